@@ -1,0 +1,109 @@
+"""The frame-group enhancement path end to end in FP64 (test infrastructure only).
+
+Per frame: unpack + pad, scene metric, extract.  Per group [a, b] (section 3.3
+grouping with n = 1 and the Interpolation, Extra-frame and Double-frame flags
+of section 3.1): fusion into HR frames at t = 0 and t = 1/2 (t = 1 too for a
+lone group), crop to twice the input size, requantise to the input's format.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import network, pixel, scene
+
+
+def weights_dict(blob, layout):
+    """{name: (w OIHW float64, b float64)} from a flat float32 blob and its layout list."""
+    out, off = {}, 0
+    for name, cout, cin, _gain in layout:
+        n = cout * cin * 9
+        w = np.asarray(blob[off:off + n], dtype=np.float64).reshape(cout, cin, 3, 3)
+        off += n
+        b = np.asarray(blob[off:off + cout], dtype=np.float64)
+        off += cout
+        out[name] = (w, b)
+    if off != len(blob):
+        raise ValueError("blob size does not match the layout")
+    return out
+
+
+def frame_rgb(Y, U, V, bits, chroma, align=8):
+    return pixel.pad(pixel.unpack(Y, U, V, bits, chroma), align)
+
+
+def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
+                  times=(0.0, 0.5, 1.0), align=8, keep=False):
+    """One frame group.  fb_planes=None means the duplicated group [a, a].
+
+    Returns {"codes": {t: (Y, Cb, Cr)}, "hr": {t: cropped float HR RGB}} plus the
+    intermediates when keep=True.
+    """
+    h, w = fa_planes[0].shape
+    rgb_a = frame_rgb(*fa_planes, bits, chroma, align)
+    fa = network.extract(rgb_a, W, res_blocks)
+    if fb_planes is None:
+        rgb_b, fb = rgb_a, fa
+    else:
+        rgb_b = frame_rgb(*fb_planes, bits, chroma, align)
+        fb = network.extract(rgb_b, W, res_blocks)
+    res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=times, keep=keep)
+    out = {"codes": {}, "hr": {}}
+    for t in times:
+        hr = res[t][:, :2 * h, :2 * w]
+        out["hr"][t] = hr
+        out["codes"][t] = pixel.pack(hr, bits, chroma)
+    if keep:
+        out.update(rgb_a=rgb_a, rgb_b=rgb_b, fa=fa, fb=fb, offsets=res["offsets"],
+                   mask=res["mask"], fmid=res["fmid"])
+    return out
+
+
+def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.SceneParams(),
+                 external=None, align=8):
+    """A whole clip in stream order.  frames: list of (Y, U, V).
+
+    Returns (cuts, outputs) where outputs is the list of 2N emitted frames, each
+    {"group": (a, b), "t": t, "codes": (Y, Cb, Cr), "hr": float RGB}.
+    """
+    cuts = scene.detect_cuts([f[0] for f in frames], bits, params, external)
+    h, w = frames[0][0].shape
+    rgb_cache, feat_cache = {}, {}
+
+    def feat(i):
+        if i not in feat_cache:
+            rgb_cache[i] = frame_rgb(*frames[i], bits, chroma, align)
+            feat_cache[i] = network.extract(rgb_cache[i], W, res_blocks)
+        return rgb_cache[i], feat_cache[i]
+
+    outputs = []
+    for a, b in scene.groups_n1(cuts):
+        rgb_a, fa = feat(a)
+        rgb_b, fb = feat(b)
+        res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=(0.0, 0.5))
+        for t in (0.0, 0.5):
+            hr = res[t][:, :2 * h, :2 * w]
+            outputs.append({"group": (a, b), "t": t, "hr": hr,
+                            "codes": pixel.pack(hr, bits, chroma)})
+        for old in [k for k in feat_cache if k < a]:
+            del feat_cache[old], rgb_cache[old]
+    return cuts, outputs
+
+
+def psnr_float(ref: np.ndarray, test: np.ndarray) -> float:
+    """PSNR of clamped RGB, peak 1.0."""
+    d = np.clip(np.asarray(ref, np.float64), 0, 1) - np.clip(np.asarray(test, np.float64), 0, 1)
+    mse = float(np.mean(d * d))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def psnr_codes(ref_planes, test_planes, bits: int) -> float:
+    """PSNR over the pooled Y, Cb, Cr samples, peak 2^bits - 1."""
+    se, n = 0.0, 0
+    for r, t in zip(ref_planes, test_planes):
+        d = np.asarray(r, np.float64) - np.asarray(t, np.float64)
+        se += float(np.sum(d * d))
+        n += d.size
+    if se == 0:
+        return float("inf")
+    peak = float((1 << bits) - 1)
+    return 10.0 * np.log10(peak * peak / (se / n))

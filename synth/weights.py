@@ -1,0 +1,81 @@
+"""Seeded weights for the generic frame-group enhancement network.
+
+The network is any extract/fusion network in the sense of the paper's
+network-integration section; this module fixes one concrete instance so that
+the oracle and the device path can be compared.  Weights are a flat float32
+blob in a fixed tensor order; every conv is 3x3 and stored OIHW followed by
+its bias.
+
+Tensor order:
+  conv_in  (C, 3)            extract, first layer
+  block r  a (C, C), b (C, C)  extract, residual blocks r = 0..R-1
+  off1     (C, 2C)           offset head, first conv
+  off2     (27G, C)          offset head, second conv (18G offsets, 9G mask logits)
+  dcn      (C, 2C)           modulated deformable alignment
+  up       (4C, C)           conv before the x2 pixel shuffle
+  hr       (3, C)            high-resolution RGB residual
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+LRELU_SLOPE = 0.1
+
+
+@dataclass(frozen=True)
+class NetConfig:
+    channels: int = 64
+    res_blocks: int = 10
+    offset_groups: int = 8
+    scale: int = 2
+    align: int = 8
+
+    def __post_init__(self):
+        if (2 * self.channels) % self.offset_groups:
+            raise ValueError("2*channels must be divisible by offset_groups")
+
+
+NET_C1 = NetConfig(32, 2, 8)
+NET_C2 = NetConfig(64, 10, 8)
+NET_C4 = NetConfig(64, 6, 8)
+
+
+def weight_layout(cfg: NetConfig):
+    """List of (name, cout, cin, gain) in blob order."""
+    C, G = cfg.channels, cfg.offset_groups
+    layers = [("conv_in", C, 3, 1.0)]
+    for r in range(cfg.res_blocks):
+        layers.append((f"block{r}.a", C, C, 1.0))
+        layers.append((f"block{r}.b", C, C, 0.1))
+    layers += [("off1", C, 2 * C, 1.0), ("off2", 27 * G, C, 1.0),
+               ("dcn", C, 2 * C, 1.0), ("up", 4 * C, C, 1.0), ("hr", 3, C, 0.1)]
+    return layers
+
+
+def gen_weights(cfg: NetConfig, seed: int = 1) -> np.ndarray:
+    """He-initialised weights (gain for LeakyReLU 0.1) and N(0, 0.01^2) biases."""
+    rng = np.random.default_rng(seed)
+    he = np.sqrt(2.0 / (1.0 + LRELU_SLOPE ** 2))
+    parts = []
+    for _name, cout, cin, gain in weight_layout(cfg):
+        std = gain * he / np.sqrt(cin * 9)
+        parts.append((rng.standard_normal((cout, cin, 3, 3)) * std).astype(np.float32).ravel())
+        parts.append((rng.standard_normal(cout) * 0.01).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def unpack_weights(cfg: NetConfig, blob: np.ndarray) -> dict:
+    """Views {name: (w OIHW, b)} into a blob."""
+    out, off = {}, 0
+    for name, cout, cin, _gain in weight_layout(cfg):
+        n = cout * cin * 9
+        w = blob[off:off + n].reshape(cout, cin, 3, 3)
+        off += n
+        b = blob[off:off + cout]
+        off += cout
+        out[name] = (w, b)
+    if off != blob.size:
+        raise ValueError(f"blob has {blob.size} floats, layout needs {off}")
+    return out
