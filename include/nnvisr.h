@@ -1,0 +1,185 @@
+/*
+ * nnvisr.h -- C-ABI of the MI355X (gfx950) frame-group enhancement library.
+ *
+ * The library implements the data path of NNVISR (Tong, Hu, Wang, "NNVISR: Bring
+ * Neural Network Video Interpolation and Super Resolution into Video Processing
+ * Framework", ACM MM 2023): Y'CbCr frames in, enhanced Y'CbCr frames out, with the
+ * frame grouping the paper describes for interpolation networks, for one generic,
+ * seeded extract/fusion network.
+ *
+ * Conventions shared by every call
+ *  - Pointers named d_* and every plane pointer are HIP device memory owned by the
+ *    caller (for example torch tensors).  Host pointers are marked as such.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.  Work
+ *    is enqueued asynchronously on it; buffers must stay valid until it completes.
+ *  - Arguments are validated on the host before anything is enqueued.  On any error
+ *    nothing is enqueued, no state changes, and nv_last_error() describes why.
+ *  - Colour is ITU-R BT.709, limited range, non-linear R'G'B'; 4:2:0 chroma is
+ *    left-sited (co-sited with even luma columns, between luma rows 2i and 2i+1).
+ *  - A context is used by one host thread at a time; calls on one context that
+ *    overlap in time are not supported.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef NNVISR_H
+#define NNVISR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NV_OK = 0,
+  NV_E_INVALID = 1,      /* bad argument: null pointer, size, format, pitch, state */
+  NV_E_UNSUPPORTED = 2,  /* valid but not implemented (e.g. a precision, a format) */
+  NV_E_NOMEM = 3,        /* device allocation failed */
+  NV_E_DEVICE = 4,       /* a HIP call failed; see nv_last_error() */
+  NV_E_BUSY = 5          /* serving queue full / admission refused */
+} nv_status;
+
+/* Arithmetic of the network's convolutions (the offset head, the bilinear sampling
+ * weights and all pixel-format stages are FP32 in every mode). */
+typedef enum { NV_FP32 = 0, NV_FP16 = 1, NV_BF16 = 2, NV_FP8_E4M3 = 3 } nv_precision;
+
+/* Network flags of the paper's network-integration section (section 3.1):
+ * Interpolation doubles the frame rate, Extra frame means the network takes n+1
+ * frames, Double frame means it emits 2n frames.  The implemented network is
+ * n = 1 with all three set. */
+enum { NV_FLAG_INTERP = 1, NV_FLAG_EXTRA = 2, NV_FLAG_DOUBLE = 4 };
+
+/* Frame format.  width/height are luma sizes (even for 4:2:0); bits is 8 (uint8
+ * samples) or 10 (uint16 little-endian samples holding the code in the low 10 bits;
+ * the upper 6 bits are ignored on input and written as zero); chroma is 420 or 444. */
+typedef struct {
+  int32_t width, height, bits, chroma;
+} nv_format;
+
+/* Planar Y, Cb, Cr.  pitch_bytes[i] is the distance between rows of plane i. */
+typedef struct {
+  void* data[3];
+  int64_t pitch_bytes[3];
+} nv_planes;
+
+/* Network shape.  channels C (multiple of 32), res_blocks R (>= 0), offset_groups G
+ * (2C divisible by G, 2C/G a multiple of 4), scale must be 2, align must be 8,
+ * flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE. */
+typedef struct {
+  int32_t channels, res_blocks, offset_groups, scale, align;
+  uint32_t flags;
+  int32_t precision;     /* nv_precision */
+} nv_net_config;
+
+/* Scene-change rule: frame t starts a scene when
+ *   SAD_t > mad_thresh_8bit * 2^(bits-8) * N   and   HD_t * hist_frac_den > 2 * N * hist_frac_num
+ * where N = width*height, SAD_t = sum |Y_t - Y_{t-1}| over luma codes and HD_t the L1
+ * distance of the 64-bin luma histograms (bin = code >> (bits-6)).  enable = 0 leaves
+ * the decision to the external per-frame flags alone. */
+typedef struct {
+  int32_t mad_thresh_8bit, hist_frac_num, hist_frac_den, enable;
+} nv_scene_params;
+
+typedef struct nv_context nv_context;
+typedef struct nv_stream nv_stream;
+
+/* ---------------------------------------------------------------- context ---- */
+
+/* Create a context on HIP device `device`.  `weights` (HOST memory, float32,
+ * n_floats long) is the flat weight blob in this tensor order, each conv 3x3 OIHW
+ * followed by its bias: conv_in (C,3), R x [block.a (C,C), block.b (C,C)],
+ * off1 (C,2C), off2 (27G,C), dcn (C,2C), up (4C,C), hr (3,C).  The library copies
+ * and repacks it; the caller may free it on return. */
+nv_status nv_context_create(int32_t device, const nv_net_config* cfg, const float* weights,
+                            size_t n_floats, nv_context** out);
+nv_status nv_context_destroy(nv_context* ctx);
+
+/* Thread-local, NUL-terminated description of the last error on this thread. */
+const char* nv_last_error(void);
+
+/* Number of floats the weight blob of `cfg` must hold (0 if cfg is invalid). */
+size_t nv_weight_count(const nv_net_config* cfg);
+
+/* ------------------------------------------------- pixel-format stages ---- */
+
+/* Unpack one frame (section 3.1, pixel formats): decode codes, upsample 4:2:0 chroma
+ * bilinearly, apply the BT.709 inverse matrix (no clamp), and write planar float32
+ * R'G'B' d_rgb[3][hp][wp] (plane stride hp*wp floats).  hp >= height and wp >= width;
+ * rows/columns beyond the frame replicate the last row/column (alignment padding). */
+nv_status nv_unpack(const nv_format* fmt, const nv_planes* in, float* d_rgb, int32_t hp,
+                    int32_t wp, void* stream);
+
+/* Requantise planar float32 R'G'B' to a frame of format `fmt`: clamp R'G'B' to [0,1],
+ * BT.709 forward matrix, 4:2:0 chroma by the (1/4,1/2,1/4) x (1/2,1/2) left-sited
+ * filter with replicated edges, code = clamp(floor(v + 1/2), 0, 2^bits - 1).  d_rgb
+ * is [3][rh][rw] (rh >= fmt->height, rw >= fmt->width); only the top-left
+ * fmt->height x fmt->width region is read (crop). */
+nv_status nv_pack(const nv_format* fmt, const float* d_rgb, int32_t rh, int32_t rw,
+                  const nv_planes* out, void* stream);
+
+/* Integer scene metric of frame `cur` against `prev` (sections 3.2 and 3.3: groups
+ * stay inside a scene).  Writes device values: *d_sad (uint64), d_hist[64] (uint32,
+ * histogram of cur), *d_hd (uint32), *d_cut (uint32, 0/1).  prev == NULL (first frame)
+ * or d_hist_prev == NULL yields sad = hd = 0 and cut = 1.  external_cut: -1 none,
+ * 0 or 1 OR-ed into the decision. */
+nv_status nv_scene_metric(const nv_format* fmt, const nv_planes* prev, const nv_planes* cur,
+                          const uint32_t* d_hist_prev, const nv_scene_params* params,
+                          int32_t external_cut, uint64_t* d_sad, uint32_t* d_hist,
+                          uint32_t* d_hd, uint32_t* d_cut, void* stream);
+
+/* --------------------------------------------------------- network ---- */
+
+/* Bytes per feature element: 4 (float32) for NV_FP32 contexts, 2 (float16 or bfloat16,
+ * matching the precision) otherwise.  Features are NHWC [hp][wp][C]. */
+int32_t nv_feature_elem_bytes(const nv_context* ctx);
+
+/* Extract stage (section 3.1: per frame, a one-level feature pyramid) from planar
+ * float32 R'G'B' d_rgb[3][hp][wp] (hp, wp multiples of 8) into NHWC features
+ * d_feat[hp][wp][C] of the context's feature type. */
+nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp, int32_t wp,
+                     void* d_feat, void* stream);
+
+/* Fusion stage of the frame group [a, b] (section 3.1).  Produces float32 HR R'G'B'
+ * planes [3][2hp][2wp] for each set bit of out_mask: bit 0 -> t = 0 (d_hr[0]),
+ * bit 1 -> t = 1/2 (d_hr[1]), bit 2 -> t = 1 (d_hr[2]).  If d_sel is not NULL and
+ * *d_sel != 0 (device uint32, e.g. a scene-cut flag) the group is [a, a]: frame b's
+ * features and pixels are replaced by frame a's (section 3.3: the last frame of a
+ * scene is duplicated).  Optional device outputs for inspection (NULL to skip):
+ * d_offsets [hp][wp][ldo] with ldo = 16*ceil(27G/16): channel 2(9g+k) dy, 2(9g+k)+1
+ * dx, 18G + 9g + k the sigmoid mask (float32); d_fmid [hp][wp][C] the aligned features
+ * (feature type). */
+nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
+                  const void* d_feat_a, const void* d_feat_b, int32_t hp, int32_t wp,
+                  const uint32_t* d_sel, uint32_t out_mask, float* const d_hr[3],
+                  float* d_offsets, void* d_fmid, void* stream);
+
+/* --------------------------------------------------------- end to end ---- */
+
+/* One frame group, two frames in, three frames out (t = 0, 1/2, 1), each of format
+ * fmt at twice the width and height. */
+nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
+                           const nv_planes out[3], void* stream);
+
+/* Clip-level streaming (section 3.2: one function from clip to enhanced clip).
+ * push(t) unpacks frame t, runs the scene metric and the extract stage, and emits the
+ * two outputs of group t-1 (frame t-1 at t = 0, then the interpolated frame), so
+ * *n_out is 0 for t = 0 and 2 afterwards.  end() emits the last group's two outputs.
+ * The cut decision stays on the device: no host synchronisation per frame. */
+nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt, const nv_scene_params* params,
+                         nv_stream** out);
+nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_t external_cut,
+                         const nv_planes out[2], int32_t* n_out, void* stream);
+nv_status nv_stream_end(nv_stream* s, const nv_planes out[2], int32_t* n_out, void* stream);
+nv_status nv_stream_close(nv_stream* s);
+
+/* Copy the device cut flags of the frames pushed so far into host memory
+ * (cuts[0..n-1], n <= frames pushed); synchronises `stream`. */
+nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n, void* stream);
+
+/* Device bytes a stream of this format keeps resident (for admission control). */
+nv_status nv_stream_footprint(const nv_context* ctx, const nv_format* fmt, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNVISR_H */

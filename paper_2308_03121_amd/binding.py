@@ -1,0 +1,236 @@
+"""Thin Python layer over the C-ABI: torch tensors provide device memory and the HIP
+stream, the library does every step of the path.  No computation happens here."""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_int32, c_size_t, c_uint32, c_void_p
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import NvFormat, NvNetConfig, NvPlanes, NvSceneParams, check
+
+PRECISIONS = {"fp32": _abi.NV_FP32, "fp16": _abi.NV_FP16, "bf16": _abi.NV_BF16,
+              "fp8": _abi.NV_FP8_E4M3}
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def fmt_struct(width: int, height: int, bits: int, chroma: int) -> NvFormat:
+    return NvFormat(width, height, bits, chroma)
+
+
+def chroma_shape(width, height, chroma):
+    return (height // 2, width // 2) if chroma == 420 else (height, width)
+
+
+def planes_struct(Y: torch.Tensor, U: torch.Tensor, V: torch.Tensor) -> NvPlanes:
+    p = NvPlanes()
+    for i, t in enumerate((Y, U, V)):
+        if t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("planes must be 2-D with unit column stride")
+        p.data[i] = t.data_ptr()
+        p.pitch_bytes[i] = t.stride(0) * t.element_size()
+    return p
+
+
+def alloc_frame(width, height, bits, chroma, device="cuda"):
+    dt = torch.uint8 if bits == 8 else torch.int16
+    hc, wc = chroma_shape(width, height, chroma)
+    return (torch.zeros((height, width), dtype=dt, device=device),
+            torch.zeros((hc, wc), dtype=dt, device=device),
+            torch.zeros((hc, wc), dtype=dt, device=device))
+
+
+def to_device_frame(Y: np.ndarray, U: np.ndarray, V: np.ndarray, device="cuda"):
+    """numpy uint8/uint16 planes -> device tensors (uint16 travels as int16 bits)."""
+    def conv(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint16:
+            a = a.view(np.int16)
+        return torch.from_numpy(a).to(device)
+    return conv(Y), conv(U), conv(V)
+
+
+def frame_to_numpy(planes, bits):
+    out = []
+    for t in planes:
+        a = t.cpu().numpy()
+        if bits == 10:
+            a = a.view(np.uint16)
+        out.append(a)
+    return tuple(out)
+
+
+def scene_params(mad=24, num=1, den=4, enable=True) -> NvSceneParams:
+    return NvSceneParams(mad, num, den, 1 if enable else 0)
+
+
+def unpack(fmt: NvFormat, planes, hp: int, wp: int, stream=None) -> torch.Tensor:
+    lib = _abi.load()
+    rgb = torch.empty((3, hp, wp), dtype=torch.float32, device=planes[0].device)
+    p = planes_struct(*planes)
+    check(lib.nv_unpack(byref(fmt), byref(p), _ptr(rgb), hp, wp, c_void_p(_stream(stream))))
+    return rgb
+
+
+def pack(fmt: NvFormat, rgb: torch.Tensor, stream=None):
+    lib = _abi.load()
+    if rgb.dtype != torch.float32 or not rgb.is_contiguous() or rgb.dim() != 3:
+        raise ValueError("rgb must be a contiguous float32 [3, H, W] tensor")
+    out = alloc_frame(fmt.width, fmt.height, fmt.bits, fmt.chroma, rgb.device)
+    p = planes_struct(*out)
+    check(lib.nv_pack(byref(fmt), _ptr(rgb), rgb.shape[1], rgb.shape[2], byref(p),
+                      c_void_p(_stream(stream))))
+    return out
+
+
+def scene_metric(fmt: NvFormat, prev, cur, hist_prev: torch.Tensor | None, params=None,
+                 external_cut: int = -1, stream=None):
+    """Returns device tensors (sad u64 as int64[1], hist int32[64], hd int32[1], cut int32[1])."""
+    lib = _abi.load()
+    dev = cur[0].device
+    sad = torch.zeros(1, dtype=torch.int64, device=dev)
+    hist = torch.zeros(64, dtype=torch.int32, device=dev)
+    hd = torch.zeros(1, dtype=torch.int32, device=dev)
+    cut = torch.zeros(1, dtype=torch.int32, device=dev)
+    pc = planes_struct(*cur)
+    pp = planes_struct(*prev) if prev is not None else None
+    check(lib.nv_scene_metric(byref(fmt), byref(pp) if pp is not None else None, byref(pc),
+                              _ptr(hist_prev), byref(params) if params is not None else None,
+                              external_cut, _ptr(sad), _ptr(hist), _ptr(hd), _ptr(cut),
+                              c_void_p(_stream(stream))))
+    return sad, hist, hd, cut
+
+
+class Context:
+    """A network context: repacked weights and workspace on one device."""
+
+    def __init__(self, channels: int, res_blocks: int, offset_groups: int, weights: np.ndarray,
+                 precision: str = "fp32", device: int = 0):
+        lib = _abi.load()
+        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8,
+                               _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | _abi.NV_FLAG_DOUBLE,
+                               PRECISIONS[precision])
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        self._h = c_void_p()
+        check(lib.nv_context_create(device, byref(self.cfg),
+                                    w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size,
+                                    byref(self._h)))
+        self.channels = channels
+        self.offset_groups = offset_groups
+        self.device = torch.device("cuda", device)
+        self.feat_dtype = {4: torch.float32, 2: torch.float16 if precision == "fp16" else torch.bfloat16}[
+            lib.nv_feature_elem_bytes(self._h)]
+        self.ldo = 16 * ((27 * offset_groups + 15) // 16)
+
+    @staticmethod
+    def weight_count(channels, res_blocks, offset_groups) -> int:
+        cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, 7, 0)
+        return int(_abi.load().nv_weight_count(byref(cfg)))
+
+    def close(self):
+        if self._h:
+            _abi.load().nv_context_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def extract(self, rgb: torch.Tensor, stream=None) -> torch.Tensor:
+        _c, hp, wp = rgb.shape
+        feat = torch.empty((hp, wp, self.channels), dtype=self.feat_dtype, device=rgb.device)
+        check(_abi.load().nv_extract(self._h, _ptr(rgb), hp, wp, _ptr(feat), c_void_p(_stream(stream))))
+        return feat
+
+    def fuse(self, rgb_a, rgb_b, feat_a, feat_b, out_mask=7, sel: torch.Tensor | None = None,
+             want_offsets=False, want_fmid=False, stream=None):
+        _c, hp, wp = rgb_a.shape
+        dev = rgb_a.device
+        hr = [torch.empty((3, 2 * hp, 2 * wp), dtype=torch.float32, device=dev)
+              if out_mask & (1 << t) else None for t in range(3)]
+        arr = (c_void_p * 3)(*[t.data_ptr() if t is not None else None for t in hr])
+        offs = torch.empty((hp, wp, self.ldo), dtype=torch.float32, device=dev) if want_offsets else None
+        fmid = torch.empty((hp, wp, self.channels), dtype=self.feat_dtype, device=dev) if want_fmid else None
+        check(_abi.load().nv_fuse(self._h, _ptr(rgb_a), _ptr(rgb_b), _ptr(feat_a), _ptr(feat_b), hp, wp,
+                                  _ptr(sel), out_mask, arr, _ptr(offs), _ptr(fmid),
+                                  c_void_p(_stream(stream))))
+        return hr, offs, fmid
+
+    def enhance_group(self, fmt: NvFormat, frame_a, frame_b, outs=None, stream=None):
+        """Two device frames in, three output frames (t = 0, 1/2, 1) at twice the size."""
+        if outs is None:
+            outs = [alloc_frame(2 * fmt.width, 2 * fmt.height, fmt.bits, fmt.chroma, frame_a[0].device)
+                    for _ in range(3)]
+        pin = (NvPlanes * 2)(planes_struct(*frame_a), planes_struct(*frame_b))
+        pout = (NvPlanes * 3)(*[planes_struct(*o) for o in outs])
+        check(_abi.load().nv_enhance_group(self._h, byref(fmt), pin, pout, c_void_p(_stream(stream))))
+        return outs
+
+    def stream_footprint(self, fmt: NvFormat) -> int:
+        n = c_size_t()
+        check(_abi.load().nv_stream_footprint(self._h, byref(fmt), byref(n)))
+        return int(n.value)
+
+    def open_stream(self, fmt: NvFormat, params: NvSceneParams | None = None) -> "Stream":
+        return Stream(self, fmt, params)
+
+
+class Stream:
+    """Clip-level streaming: push frames, get two output frames per group."""
+
+    def __init__(self, ctx: Context, fmt: NvFormat, params: NvSceneParams | None = None):
+        self.ctx = ctx
+        self.fmt = fmt
+        self._h = c_void_p()
+        check(_abi.load().nv_stream_open(ctx._h, byref(fmt), byref(params) if params is not None else None,
+                                         byref(self._h)))
+        self.n_pushed = 0
+
+    def _outs(self, outs):
+        if outs is None:
+            outs = [alloc_frame(2 * self.fmt.width, 2 * self.fmt.height, self.fmt.bits, self.fmt.chroma,
+                                self.ctx.device) for _ in range(2)]
+        return outs, (NvPlanes * 2)(*[planes_struct(*o) for o in outs])
+
+    def push(self, frame, external_cut: int = -1, outs=None, stream=None):
+        outs, pout = self._outs(outs)
+        n = c_int32()
+        check(_abi.load().nv_stream_push(self._h, byref(planes_struct(*frame)), external_cut, pout,
+                                         byref(n), c_void_p(_stream(stream))))
+        self.n_pushed += 1
+        return outs[:n.value]
+
+    def end(self, outs=None, stream=None):
+        outs, pout = self._outs(outs)
+        n = c_int32()
+        check(_abi.load().nv_stream_end(self._h, pout, byref(n), c_void_p(_stream(stream))))
+        return outs[:n.value]
+
+    def cuts(self, stream=None):
+        n = self.n_pushed
+        buf = (c_uint32 * max(n, 1))()
+        check(_abi.load().nv_stream_cuts(self._h, buf, n, c_void_p(_stream(stream))))
+        return [int(buf[i]) for i in range(n)]
+
+    def close(self):
+        if self._h:
+            _abi.load().nv_stream_close(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

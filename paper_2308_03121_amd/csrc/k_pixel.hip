@@ -1,0 +1,317 @@
+// Pixel-format and scene-change kernels (gfx950).
+//
+// Unpack: Y'CbCr codes -> planar float32 R'G'B' with alignment padding.
+// Pack:   planar float32 R'G'B' -> Y'CbCr codes with crop.
+// Scene:  integer SAD and 64-bin histogram distance, and the cut decision.
+// All three are HBM-bound streaming kernels; each thread owns a small run of
+// adjacent pixels so that row accesses coalesce.
+#include "nv_device.h"
+#include "nv_internal.h"
+
+namespace nv {
+namespace {
+
+template <int BITS>
+struct Code;
+template <>
+struct Code<8> {
+  typedef uint8_t T;
+  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
+    return (float)reinterpret_cast<const uint8_t*>(static_cast<const char*>(p) + y * pitch)[x];
+  }
+  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
+    reinterpret_cast<uint8_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint8_t)v;
+  }
+};
+template <>
+struct Code<10> {
+  typedef uint16_t T;
+  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
+    return (float)(reinterpret_cast<const uint16_t*>(static_cast<const char*>(p) + y * pitch)[x] &
+                   0x3FFu);
+  }
+  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
+    reinterpret_cast<uint16_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint16_t)v;
+  }
+};
+
+// Matrix constants, limited range.  Y' = (Y - 16s) / (219s), C' = (C - 128s) / (224s);
+// R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr'.
+struct Inv {
+  float ys, yo, cs, co, rcr, bcb, gcb, gcr;
+};
+
+__host__ Inv make_inv(int bits) {
+  const double s = double(1 << (bits - 8));
+  Inv m;
+  m.ys = float(1.0 / (219.0 * s));
+  m.yo = float(16.0 * s);
+  m.cs = float(1.0 / (224.0 * s));
+  m.co = float(128.0 * s);
+  m.rcr = float(2.0 * (1.0 - kKr));
+  m.bcb = float(2.0 * (1.0 - kKb));
+  m.gcb = float(2.0 * kKb * (1.0 - kKb) / kKg);
+  m.gcr = float(2.0 * kKr * (1.0 - kKr) / kKg);
+  return m;
+}
+
+// Each thread writes 4 consecutive padded pixels of one row of each plane.
+template <int BITS, bool C420>
+__global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
+                                                int wp) {
+  const int groups_per_row = wp >> 2;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  if (gid >= groups_per_row * hp) return;
+  const int y = gid / groups_per_row;
+  const int x0 = (gid - y * groups_per_row) << 2;
+  const int sy = min(y, f.h - 1);
+  const int hc = C420 ? (f.h >> 1) : f.h;
+  const int wc = C420 ? (f.w >> 1) : f.w;
+  // vertical chroma neighbour of this luma row (4:2:0)
+  const int ci = C420 ? (sy >> 1) : sy;
+  const int ci2 = C420 ? ((sy & 1) ? min(ci + 1, hc - 1) : max(ci - 1, 0)) : ci;
+  float r[4], g[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int sx = min(x0 + k, f.w - 1);
+    const float yv = Code<BITS>::get(f.p[0], f.pitch[0], sy, sx);
+    float cb, cr;
+    if (C420) {
+      const int cj = sx >> 1;
+      const float cb0 = 0.75f * Code<BITS>::get(f.p[1], f.pitch[1], ci, cj) +
+                        0.25f * Code<BITS>::get(f.p[1], f.pitch[1], ci2, cj);
+      const float cr0 = 0.75f * Code<BITS>::get(f.p[2], f.pitch[2], ci, cj) +
+                        0.25f * Code<BITS>::get(f.p[2], f.pitch[2], ci2, cj);
+      if (sx & 1) {
+        const int cj1 = min(cj + 1, wc - 1);
+        const float cb1 = 0.75f * Code<BITS>::get(f.p[1], f.pitch[1], ci, cj1) +
+                          0.25f * Code<BITS>::get(f.p[1], f.pitch[1], ci2, cj1);
+        const float cr1 = 0.75f * Code<BITS>::get(f.p[2], f.pitch[2], ci, cj1) +
+                          0.25f * Code<BITS>::get(f.p[2], f.pitch[2], ci2, cj1);
+        cb = 0.5f * (cb0 + cb1);
+        cr = 0.5f * (cr0 + cr1);
+      } else {
+        cb = cb0;
+        cr = cr0;
+      }
+    } else {
+      cb = Code<BITS>::get(f.p[1], f.pitch[1], ci, sx);
+      cr = Code<BITS>::get(f.p[2], f.pitch[2], ci, sx);
+    }
+    const float yn = (yv - m.yo) * m.ys;
+    const float cbn = (cb - m.co) * m.cs;
+    const float crn = (cr - m.co) * m.cs;
+    r[k] = fmaf(m.rcr, crn, yn);
+    b[k] = fmaf(m.bcb, cbn, yn);
+    g[k] = fmaf(-m.gcr, crn, fmaf(-m.gcb, cbn, yn));
+  }
+  (void)wc;
+  const size_t plane = (size_t)hp * wp;
+  float* o = rgb + (size_t)y * wp + x0;
+  st4(o, f32x4{r[0], r[1], r[2], r[3]});
+  st4(o + plane, f32x4{g[0], g[1], g[2], g[3]});
+  st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
+}
+
+struct Fwd {
+  float kr, kg, kb, cbs, crs, ys, yo, cs, co, maxc;
+};
+
+__host__ Fwd make_fwd(int bits) {
+  const double s = double(1 << (bits - 8));
+  Fwd m;
+  m.kr = float(kKr);
+  m.kg = float(kKg);
+  m.kb = float(kKb);
+  m.cbs = float(1.0 / (2.0 * (1.0 - kKb)));
+  m.crs = float(1.0 / (2.0 * (1.0 - kKr)));
+  m.ys = float(219.0 * s);
+  m.yo = float(16.0 * s);
+  m.cs = float(224.0 * s);
+  m.co = float(128.0 * s);
+  m.maxc = float((1 << bits) - 1);
+  return m;
+}
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+
+__device__ __forceinline__ int quant(float v, float maxc) {
+  return (int)fminf(fmaxf(floorf(v + 0.5f), 0.0f), maxc);
+}
+
+// 4:2:0 pack: one thread per chroma sample, i.e. one 2x2 luma block.
+template <int BITS>
+__global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float* __restrict__ rgb,
+                                                 int rh, int rw) {
+  const int wc = f.w >> 1, hc = f.h >> 1;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  if (gid >= wc * hc) return;
+  const int i = gid / wc, j = gid - i * wc;
+  const size_t plane = (size_t)rh * rw;
+  float cbs = 0.0f, crs = 0.0f;
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    const int yy = 2 * i + dy;
+    const float* row = rgb + (size_t)yy * rw;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int xx = max(2 * j + dx, 0);
+      const float R = clamp01(row[xx]);
+      const float G = clamp01(row[xx + plane]);
+      const float B = clamp01(row[xx + 2 * plane]);
+      const float Yn = fmaf(m.kb, B, fmaf(m.kg, G, m.kr * R));
+      const float wgt = dx == 0 ? 0.25f : 0.125f;
+      cbs = fmaf(wgt, (B - Yn) * m.cbs, cbs);
+      crs = fmaf(wgt, (R - Yn) * m.crs, crs);
+      if (dx >= 0) Code<BITS>::put(f.p[0], f.pitch[0], yy, xx, quant(fmaf(Yn, m.ys, m.yo), m.maxc));
+    }
+  }
+  Code<BITS>::put(f.p[1], f.pitch[1], i, j, quant(fmaf(cbs, m.cs, m.co), m.maxc));
+  Code<BITS>::put(f.p[2], f.pitch[2], i, j, quant(fmaf(crs, m.cs, m.co), m.maxc));
+}
+
+template <int BITS>
+__global__ __launch_bounds__(256) void k_pack444(FrameOut f, Fwd m, const float* __restrict__ rgb,
+                                                 int rh, int rw) {
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  if (gid >= f.w * f.h) return;
+  const int y = gid / f.w, x = gid - y * f.w;
+  const size_t plane = (size_t)rh * rw;
+  const float* px = rgb + (size_t)y * rw + x;
+  const float R = clamp01(px[0]), G = clamp01(px[plane]), B = clamp01(px[2 * plane]);
+  const float Yn = fmaf(m.kb, B, fmaf(m.kg, G, m.kr * R));
+  Code<BITS>::put(f.p[0], f.pitch[0], y, x, quant(fmaf(Yn, m.ys, m.yo), m.maxc));
+  Code<BITS>::put(f.p[1], f.pitch[1], y, x, quant(fmaf((B - Yn) * m.cbs, m.cs, m.co), m.maxc));
+  Code<BITS>::put(f.p[2], f.pitch[2], y, x, quant(fmaf((R - Yn) * m.crs, m.cs, m.co), m.maxc));
+}
+
+// ---- scene metric ----
+
+__global__ void k_scene_clear(uint64_t* sad, uint32_t* hist) {
+  const int t = threadIdx.x;
+  if (t < 64) hist[t] = 0u;
+  if (t == 0) *sad = 0ull;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Grid-stride over rows; each thread takes 4 adjacent samples per step.  Per-thread SAD
+// partial sums fit in 32 bits (at most 4 * 1023 per step and a bounded number of steps);
+// the block total is added to the 64-bit accumulator once.
+template <int BITS, bool HAS_PREV>
+__global__ __launch_bounds__(256) void k_scene_accum(Frame cur, Frame prev, uint64_t* sad,
+                                                     uint32_t* hist) {
+  __shared__ uint32_t lh[64];
+  __shared__ uint32_t lsad[4];
+  if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
+  __syncthreads();
+  const int shift = BITS - 6;
+  const int quads = (cur.w + 3) >> 2;
+  uint32_t s = 0;
+  for (int row = blockIdx.x; row < cur.h; row += gridDim.x) {
+    for (int q = threadIdx.x; q < quads; q += 256) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = 4 * q + k;
+        if (x < cur.w) {
+          const int c = (int)Code<BITS>::get(cur.p[0], cur.pitch[0], row, x);
+          atomicAdd(&lh[c >> shift], 1u);
+          if (HAS_PREV) {
+            const int pv = (int)Code<BITS>::get(prev.p[0], prev.pitch[0], row, x);
+            s += (uint32_t)abs(c - pv);
+          }
+        }
+      }
+    }
+  }
+  if (HAS_PREV) {
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lsad[threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
+  if (HAS_PREV && threadIdx.x == 0) {
+    const uint64_t tot = (uint64_t)lsad[0] + lsad[1] + lsad[2] + lsad[3];
+    if (tot) atomicAdd(reinterpret_cast<unsigned long long*>(sad), (unsigned long long)tot);
+  }
+}
+
+__global__ void k_scene_final(const uint64_t* sad, const uint32_t* hist,
+                              const uint32_t* hist_prev, int has_prev, uint64_t n_pix, int bits,
+                              SceneRule rule, int external_cut, uint32_t* hd, uint32_t* cut) {
+  __shared__ uint32_t part[64];
+  const int t = threadIdx.x;
+  uint32_t d = 0;
+  if (has_prev) d = (uint32_t)abs((int)hist[t] - (int)hist_prev[t]);
+  d = wave_sum(d);
+  (void)part;
+  if (t == 0) {
+    uint32_t c;
+    if (!has_prev) {
+      c = 1u;
+      d = 0u;
+    } else {
+      const uint64_t thr = (uint64_t)rule.mad_thresh_8bit * (uint64_t)(1u << (bits - 8)) * n_pix;
+      const bool mad_ok = *sad > thr;
+      const bool hist_ok = (uint64_t)d * (uint64_t)rule.hist_den > 2ull * n_pix * (uint64_t)rule.hist_num;
+      c = (rule.enable && mad_ok && hist_ok) ? 1u : 0u;
+    }
+    if (external_cut > 0) c = 1u;
+    *hd = d;
+    *cut = c;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s) {
+  const Inv m = make_inv(f.bits);
+  const int n = (wp >> 2) * hp;
+  const dim3 grid((n + 255) / 256), blk(256);
+  if (f.bits == 8 && f.chroma == 420) hipLaunchKernelGGL((k_unpack<8, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  else if (f.bits == 8) hipLaunchKernelGGL((k_unpack<8, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  else if (f.chroma == 420) hipLaunchKernelGGL((k_unpack<10, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  else hipLaunchKernelGGL((k_unpack<10, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipStream_t s) {
+  const Fwd m = make_fwd(f.bits);
+  if (f.chroma == 420) {
+    const int n = (f.w >> 1) * (f.h >> 1);
+    const dim3 grid((n + 255) / 256), blk(256);
+    if (f.bits == 8) hipLaunchKernelGGL((k_pack420<8>), grid, blk, 0, s, f, m, rgb, rh, rw);
+    else hipLaunchKernelGGL((k_pack420<10>), grid, blk, 0, s, f, m, rgb, rh, rw);
+  } else {
+    const int n = f.w * f.h;
+    const dim3 grid((n + 255) / 256), blk(256);
+    if (f.bits == 8) hipLaunchKernelGGL((k_pack444<8>), grid, blk, 0, s, f, m, rgb, rh, rw);
+    else hipLaunchKernelGGL((k_pack444<10>), grid, blk, 0, s, f, m, rgb, rh, rw);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* hist_prev,
+                        const SceneRule& rule, int external_cut, uint64_t* sad, uint32_t* hist,
+                        uint32_t* hd, uint32_t* cut, hipStream_t s) {
+  hipLaunchKernelGGL(k_scene_clear, dim3(1), dim3(64), 0, s, sad, hist);
+  const bool has_prev = prev != nullptr && prev->p[0] != nullptr && hist_prev != nullptr;
+  const int blocks = cur.h < 1024 ? cur.h : 1024;
+  Frame pv = has_prev ? *prev : cur;
+  if (cur.bits == 8) {
+    if (has_prev) hipLaunchKernelGGL((k_scene_accum<8, true>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+    else hipLaunchKernelGGL((k_scene_accum<8, false>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+  } else {
+    if (has_prev) hipLaunchKernelGGL((k_scene_accum<10, true>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+    else hipLaunchKernelGGL((k_scene_accum<10, false>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+  }
+  hipLaunchKernelGGL(k_scene_final, dim3(1), dim3(64), 0, s, sad, hist, hist_prev, has_prev ? 1 : 0,
+                     (uint64_t)cur.w * (uint64_t)cur.h, cur.bits, rule, external_cut, hd, cut);
+  return hipGetLastError();
+}
+
+}  // namespace nv

@@ -1,0 +1,108 @@
+"""GPU parity of the pixel-format and scene-change stages against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import pixel, scene
+from tests._helpers import max_abs, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+# FP32 unpack: the codes and the chroma resampling are exact in float32 (dyadic
+# weights, codes below 2^11); the normalisation and the matrix add at most about
+# eight roundings of quantities below 2 in magnitude: 8 * 2 * 2^-24 < 1e-6.
+UNPACK_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def B():
+    require_gpu()
+    from paper_2308_03121_amd import binding
+    return binding
+
+
+CASES = [(64, 64, 8, 420, 64, 64), (70, 36, 8, 420, 72, 40), (46, 30, 10, 420, 48, 32),
+         (40, 24, 8, 444, 40, 24), (38, 22, 10, 444, 40, 24), (960, 540, 8, 420, 960, 544)]
+
+
+@pytest.mark.parametrize("w,h,bits,chroma,wp,hp", CASES)
+def test_unpack_matches_oracle(B, w, h, bits, chroma, wp, hp):
+    say(f"unpack {w}x{h} {bits}-bit {chroma}")
+    clip = synth.gen_clip(w, h, 1, bits=bits, chroma=chroma, seed=w + h,
+                          garbage_high_bits=(bits == 10))
+    Y, U, V = clip.frame(0)
+    dev = B.to_device_frame(Y, U, V)
+    rgb = B.unpack(B.fmt_struct(w, h, bits, chroma), dev, hp, wp)
+    torch.cuda.synchronize()
+    ref = pixel.pad(pixel.unpack(Y, U, V, bits, chroma), 8)
+    ref = np.pad(ref, ((0, 0), (0, hp - ref.shape[1]), (0, wp - ref.shape[2])), mode="edge")
+    assert rgb.shape == (3, hp, wp)
+    assert max_abs(rgb.cpu().numpy(), ref) <= UNPACK_TOL
+
+
+def _tie_mask(v, bits):
+    """Where the FP64 value lies within float32 reach of a rounding tie (both codes valid)."""
+    eps = 4e-4 * (1 << (bits - 8))
+    frac = v - np.floor(v)
+    return np.abs(frac - 0.5) < eps
+
+
+@pytest.mark.parametrize("w,h,bits,chroma,rw,rh", [(128, 72, 8, 420, 136, 80), (64, 64, 10, 420, 64, 64),
+                                                    (48, 30, 8, 444, 56, 32), (30, 18, 10, 444, 32, 24),
+                                                    (1920, 1080, 8, 420, 1920, 1088)])
+def test_pack_matches_oracle(B, w, h, bits, chroma, rw, rh):
+    say(f"pack {w}x{h} {bits}-bit {chroma}")
+    rng = np.random.default_rng(w * h)
+    rgb = rng.uniform(-0.1, 1.1, (3, rh, rw)).astype(np.float32)
+    rgb[:, :8, :8] = 0.5            # neutral patch
+    rgb[:, 8:16, :8] = 1.0          # white
+    out = B.pack(B.fmt_struct(w, h, bits, chroma), torch.from_numpy(rgb).cuda())
+    torch.cuda.synchronize()
+    got = B.frame_to_numpy(out, bits)
+    crop = rgb[:, :h, :w].astype(np.float64)
+    vals = pixel.pack_values(crop, bits, chroma)
+    ref = pixel.pack(crop, bits, chroma)
+    for g, r, v in zip(got, ref, vals):
+        d = g.astype(np.int64) - r.astype(np.int64)
+        ties = _tie_mask(v, bits)
+        assert np.all(d[~ties] == 0)
+        assert np.all(np.abs(d[ties]) <= 1)
+
+
+def _scene_case(B, frames, bits, chroma, params=None, external=None):
+    h, w = frames[0][0].shape
+    fmt = B.fmt_struct(w, h, bits, chroma)
+    p = params or scene.SceneParams()
+    nvp = B.scene_params(p.mad_thresh_8bit, p.hist_frac_num, p.hist_frac_den, p.enable)
+    ref_m = scene.scene_metrics([f[0] for f in frames], bits)
+    ref_c = scene.detect_cuts([f[0] for f in frames], bits, p, external)
+    prev, hist_prev = None, None
+    for t, f in enumerate(frames):
+        cur = B.to_device_frame(*f)
+        ext = -1 if external is None or external[t] is None else external[t]
+        sad, hist, hd, cut = B.scene_metric(fmt, prev, cur, hist_prev, nvp, ext)
+        torch.cuda.synchronize()
+        assert int(sad.item()) == ref_m[t][0]
+        assert np.array_equal(hist.cpu().numpy().astype(np.int64), ref_m[t][2])
+        assert int(hd.item()) == ref_m[t][1]
+        assert int(cut.item()) == ref_c[t], t
+        prev, hist_prev = cur, hist
+
+
+def test_scene_hand_counted(B):
+    say("scene hand-counted")
+    flat = lambda v: (np.full((16, 24), v, np.uint8), np.full((8, 12), 128, np.uint8),
+                      np.full((8, 12), 128, np.uint8))
+    _scene_case(B, [flat(100)] * 3 + [flat(180)] * 3, 8, 420)
+    _scene_case(B, [flat(100), flat(124), flat(125), flat(100)], 8, 420)
+    _scene_case(B, [flat(100)] * 4, 8, 420, external=[None, -1, 1, 0])
+    _scene_case(B, [flat(100), flat(200)], 8, 420, params=scene.SceneParams(enable=False))
+
+
+@pytest.mark.parametrize("w,h,bits,chroma,n", [(160, 96, 10, 444, 24), (66, 34, 8, 420, 12)])
+def test_scene_generator_clip(B, w, h, bits, chroma, n):
+    say(f"scene clip {w}x{h}")
+    clip = synth.gen_clip(w, h, n, bits=bits, chroma=chroma, seed=9, cut_every=(4, 8),
+                          garbage_high_bits=(bits == 10))
+    _scene_case(B, [clip.frame(t) for t in range(n)], bits, chroma)
