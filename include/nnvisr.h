@@ -172,12 +172,36 @@ nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_t external_
 nv_status nv_stream_end(nv_stream* s, const nv_planes out[2], int32_t* n_out, void* stream);
 nv_status nv_stream_close(nv_stream* s);
 
+/* Restart a stream at frame 0 (a new clip of the same format) keeping its device
+ * buffers; the next push starts a new scene. */
+nv_status nv_stream_reset(nv_stream* s);
+
 /* Copy the device cut flags of the frames pushed so far into host memory
  * (cuts[0..n-1], n <= frames pushed); synchronises `stream`. */
 nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n, void* stream);
 
 /* Device bytes a stream of this format keeps resident (for admission control). */
 nv_status nv_stream_footprint(const nv_context* ctx, const nv_format* fmt, size_t* bytes);
+
+/* ------------------------------------------------------- kernel timing ---- */
+
+/* Kinds of launches the library times when profiling is on. */
+enum {
+  NV_K_UNPACK = 0, NV_K_SCENE = 1, NV_K_CONV_IN = 2, NV_K_CONV_BLOCK = 3, NV_K_OFF1 = 4,
+  NV_K_OFF2 = 5, NV_K_DCN = 6, NV_K_UP = 7, NV_K_HR = 8, NV_K_PACK = 9, NV_K_COUNT = 10
+};
+
+/* on != 0: from now on every launch the context makes (including those of its streams)
+ * is bracketed by HIP events recorded on the launch's stream; on == 0 stops recording.
+ * Enabling clears previous records. */
+nv_status nv_profile_enable(nv_context* ctx, int32_t on);
+
+/* Totals per kind since the last enable: launches[k] and device milliseconds ms[k]
+ * (HOST arrays of NV_K_COUNT entries).  Waits for the recorded events to complete. */
+nv_status nv_profile_read(nv_context* ctx, int64_t* launches, double* ms);
+
+/* Short name of a kind ("conv_block", ...), or "" when out of range. */
+const char* nv_profile_kind_name(int32_t kind);
 
 #ifdef __cplusplus
 }

@@ -60,7 +60,12 @@ _SIGS = {
     "nv_stream_close": (c_int32, [c_void_p]),
     "nv_stream_cuts": (c_int32, [c_void_p, POINTER(c_uint32), c_int32, c_void_p]),
     "nv_stream_footprint": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(c_size_t)]),
+    "nv_stream_reset": (c_int32, [c_void_p]),
+    "nv_profile_enable": (c_int32, [c_void_p, c_int32]),
+    "nv_profile_read": (c_int32, [c_void_p, POINTER(c_int64), POINTER(ctypes.c_double)]),
+    "nv_profile_kind_name": (c_char_p, [c_int32]),
 }
+NV_K_COUNT = 10
 
 _lib = None
 

@@ -186,6 +186,18 @@ class Context:
     def open_stream(self, fmt: NvFormat, params: NvSceneParams | None = None) -> "Stream":
         return Stream(self, fmt, params)
 
+    def profile(self, on: bool):
+        check(_abi.load().nv_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kind name: (launches, total device ms)} since profiling was enabled."""
+        lib = _abi.load()
+        n = _abi.NV_K_COUNT
+        launches = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        check(lib.nv_profile_read(self._h, launches, ms))
+        return {lib.nv_profile_kind_name(k).decode(): (int(launches[k]), float(ms[k])) for k in range(n)}
+
 
 class Stream:
     """Clip-level streaming: push frames, get two output frames per group."""
@@ -217,6 +229,10 @@ class Stream:
         n = c_int32()
         check(_abi.load().nv_stream_end(self._h, pout, byref(n), c_void_p(_stream(stream))))
         return outs[:n.value]
+
+    def reset(self):
+        check(_abi.load().nv_stream_reset(self._h))
+        self.n_pushed = 0
 
     def cuts(self, stream=None):
         n = self.n_pushed

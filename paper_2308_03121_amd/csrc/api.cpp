@@ -174,8 +174,29 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Launch timing: a pair of HIP events around each launch while enabled.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
 struct nv_context {
   int device = 0;
+  Profiler prof;
   nv_net_config cfg{};
   int C = 0, G = 0, ldo = 0;
   PlainConv conv_in, hr;
@@ -285,6 +306,22 @@ nv_status check_launch(hipError_t e, const char* what) {
   return NV_OK;
 }
 
+// Runs one launch; with profiling on, brackets it with events on its stream.
+template <class F>
+nv_status timed(nv_context* ctx, int kind, hipStream_t s, const char* what, F&& launch) {
+  hipEvent_t a = nullptr;
+  if (ctx && ctx->prof.on && (a = ctx->prof.next()) != nullptr) (void)hipEventRecord(a, s);
+  const hipError_t e = launch();
+  if (a) {
+    hipEvent_t b = ctx->prof.next();
+    if (b) {
+      (void)hipEventRecord(b, s);
+      ctx->prof.recs.push_back({kind, a, b});
+    }
+  }
+  return check_launch(e, what);
+}
+
 #define NV_TRY(expr)            \
   do {                          \
     nv_status s_ = (expr);      \
@@ -295,14 +332,17 @@ nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, float*
                        hipStream_t s) {
   NV_TRY(ensure_workspace(ctx, hp, wp));
   const int C = ctx->C;
-  NV_TRY(check_launch(launch_conv_in(ctx->conv_in, rgb, feat, hp, wp, s), "conv_in"));
+  NV_TRY(timed(ctx, NV_K_CONV_IN, s, "conv_in",
+               [&] { return launch_conv_in(ctx->conv_in, rgb, feat, hp, wp, s); }));
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
-    NV_TRY(check_launch(launch_conv(ctx->blocks[2 * r], EPI_LRELU, feat, nullptr, nullptr, nullptr,
-                                    nullptr, nullptr, ctx->ws.t0, C, hp, wp, 0, s),
-                        "block.a"));
-    NV_TRY(check_launch(launch_conv(ctx->blocks[2 * r + 1], EPI_RES, ctx->ws.t0, nullptr, nullptr,
-                                    nullptr, nullptr, feat, feat, C, hp, wp, 0, s),
-                        "block.b"));
+    NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.a", [&] {
+      return launch_conv(ctx->blocks[2 * r], EPI_LRELU, feat, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, ctx->ws.t0, C, hp, wp, 0, s);
+    }));
+    NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.b", [&] {
+      return launch_conv(ctx->blocks[2 * r + 1], EPI_RES, ctx->ws.t0, nullptr, nullptr, nullptr,
+                         nullptr, feat, feat, C, hp, wp, 0, s);
+    }));
   }
   return NV_OK;
 }
@@ -318,27 +358,31 @@ nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, con
   float* offs = offs_out ? offs_out : ws.offs;
   float* fmid = fmid_out ? fmid_out : ws.fmid;
   if (mask & 2u) {
-    NV_TRY(check_launch(launch_conv(ctx->off1, EPI_LRELU, fa, fb, sel, nullptr, fa, nullptr, ws.o1,
-                                    C, hp, wp, 0, s),
-                        "off1"));
-    NV_TRY(check_launch(launch_conv(ctx->off2, EPI_OFFSET, ws.o1, nullptr, nullptr, nullptr, nullptr,
-                                    nullptr, offs, ctx->ldo, hp, wp, 18 * G, s),
-                        "off2"));
-    NV_TRY(check_launch(launch_dcn(ctx->dcn, fa, fb, sel, offs, ctx->ldo, G, fmid, hp, wp, s), "dcn"));
+    NV_TRY(timed(ctx, NV_K_OFF1, s, "off1", [&] {
+      return launch_conv(ctx->off1, EPI_LRELU, fa, fb, sel, nullptr, fa, nullptr, ws.o1, C, hp, wp, 0, s);
+    }));
+    NV_TRY(timed(ctx, NV_K_OFF2, s, "off2", [&] {
+      return launch_conv(ctx->off2, EPI_OFFSET, ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs,
+                         ctx->ldo, hp, wp, 18 * G, s);
+    }));
+    NV_TRY(timed(ctx, NV_K_DCN, s, "dcn",
+                 [&] { return launch_dcn(ctx->dcn, fa, fb, sel, offs, ctx->ldo, G, fmid, hp, wp, s); }));
   }
   for (int t = 0; t < 3; ++t) {
     if (!(mask & (1u << t))) continue;
     const float* g = t == 0 ? fa : (t == 1 ? fmid : fb);
     const float* alt = t == 2 ? fa : nullptr;
     const int tsel = t == 0 ? 0 : (t == 1 ? 2 : 1);
-    NV_TRY(check_launch(launch_conv(ctx->up, EPI_SHUFFLE, g, nullptr, sel, alt, nullptr, nullptr,
-                                    ws.u, 4 * C, hp, wp, 0, s),
-                        "up"));
+    NV_TRY(timed(ctx, NV_K_UP, s, "up", [&] {
+      return launch_conv(ctx->up, EPI_SHUFFLE, g, nullptr, sel, alt, nullptr, nullptr, ws.u, 4 * C, hp,
+                         wp, 0, s);
+    }));
     float* hr = hr_out && hr_out[t] ? hr_out[t] : ws.hr;
-    NV_TRY(check_launch(launch_hr(ctx->hr, ws.u, rgb_a, rgb_b, sel, tsel, hr, hp, wp, s), "hr"));
+    NV_TRY(timed(ctx, NV_K_HR, s, "hr",
+                 [&] { return launch_hr(ctx->hr, ws.u, rgb_a, rgb_b, sel, tsel, hr, hp, wp, s); }));
     if (pack_fmt && pack_out && pack_out[t]) {
       const FrameOut fo = to_frame_out(pack_fmt, pack_out[t]);
-      NV_TRY(check_launch(launch_pack(fo, hr, 2 * hp, 2 * wp, s), "pack"));
+      NV_TRY(timed(ctx, NV_K_PACK, s, "pack", [&] { return launch_pack(fo, hr, 2 * hp, 2 * wp, s); }));
     }
   }
   return NV_OK;
@@ -428,6 +472,7 @@ extern "C" nv_status nv_context_destroy(nv_context* ctx) {
   (void)hipDeviceSynchronize();
   free_workspace(ctx->ws);
   for (void* p : ctx->allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
   delete ctx;
   return NV_OK;
 }
@@ -535,7 +580,8 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
   hipStream_t s = (hipStream_t)stream;
   Workspace& ws = ctx->ws;
   for (int i = 0; i < 2; ++i) {
-    NV_TRY(check_launch(launch_unpack(to_frame(fmt, &in[i]), ws.rgb[i], hp, wp, s), "unpack"));
+    const Frame f = to_frame(fmt, &in[i]);
+    NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
     NV_TRY(extract_impl(ctx, ws.rgb[i], hp, wp, ws.feat[i], s));
   }
   const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
@@ -654,14 +700,15 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
   hipStream_t hs = (hipStream_t)stream;
   const int cur = (int)(s->t & 1), prv = cur ^ 1;
   const Frame f = to_frame(&s->fmt, frame);
-  NV_TRY(check_launch(launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs), "unpack"));
+  NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
   Frame pf = f;
   pf.p[0] = s->luma[prv];
   pf.pitch[0] = s->luma_pitch;
   uint32_t* cut_t = s->cuts + (s->t % kCutRing);
-  NV_TRY(check_launch(launch_scene(f, s->t > 0 ? &pf : nullptr, s->t > 0 ? s->hist + 64 * prv : nullptr,
-                                   s->rule, external_cut, s->sad, s->hist + 64 * cur, s->hd, cut_t, hs),
-                      "scene"));
+  NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] {
+    return launch_scene(f, s->t > 0 ? &pf : nullptr, s->t > 0 ? s->hist + 64 * prv : nullptr, s->rule,
+                        external_cut, s->sad, s->hist + 64 * cur, s->hd, cut_t, hs);
+  }));
   HIP_TRY(hipMemcpy2DAsync(s->luma[cur], (size_t)s->luma_pitch, frame->data[0],
                            (size_t)frame->pitch_bytes[0], (size_t)s->luma_pitch, (size_t)s->fmt.height,
                            hipMemcpyDeviceToDevice, hs));
@@ -696,10 +743,52 @@ extern "C" nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n
   return NV_OK;
 }
 
+extern "C" nv_status nv_stream_reset(nv_stream* s) {
+  if (!s) return fail(NV_E_INVALID, "NULL argument");
+  s->t = 0;
+  return NV_OK;
+}
+
 extern "C" nv_status nv_stream_close(nv_stream* s) {
   if (!s) return NV_OK;
   (void)hipDeviceSynchronize();
   stream_free(s);
   delete s;
+  return NV_OK;
+}
+
+// ----------------------------------------------------------- kernel timing ----
+
+static const char* const kKindNames[NV_K_COUNT] = {"unpack", "scene", "conv_in", "conv_block", "off1",
+                                                   "off2",   "dcn",   "up",      "hr",         "pack"};
+
+extern "C" const char* nv_profile_kind_name(int32_t kind) {
+  return kind >= 0 && kind < NV_K_COUNT ? kKindNames[kind] : "";
+}
+
+extern "C" nv_status nv_profile_enable(nv_context* ctx, int32_t on) {
+  if (!ctx) return fail(NV_E_INVALID, "NULL argument");
+  if (on) {
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->prof.recs.clear();
+    ctx->prof.used = 0;
+  }
+  ctx->prof.on = on != 0;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_profile_read(nv_context* ctx, int64_t* launches, double* ms) {
+  if (!ctx || !launches || !ms) return fail(NV_E_INVALID, "NULL argument");
+  for (int k = 0; k < NV_K_COUNT; ++k) {
+    launches[k] = 0;
+    ms[k] = 0.0;
+  }
+  for (const auto& r : ctx->prof.recs) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    launches[r.kind] += 1;
+    ms[r.kind] += (double)t;
+  }
   return NV_OK;
 }
