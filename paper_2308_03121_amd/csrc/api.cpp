@@ -437,11 +437,19 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
       st = upload(ctx, std::vector<float>(w, w + (size_t)L.cout * 27), &ctx->conv_in.w);
       if (st == NV_OK) st = upload(ctx, std::vector<float>(b, b + L.cout), &ctx->conv_in.b);
     } else if (nm == "hr") {
-      // [tap][c][4], output 3 padded with a zero
-      std::vector<float> w4((size_t)9 * L.cin * 4, 0.0f);
-      for (int o = 0; o < 3; ++o)
-        for (int c = 0; c < L.cin; ++c)
-          for (int tap = 0; tap < 9; ++tap) w4[((size_t)tap * L.cin + c) * 4 + o] = w[((size_t)o * L.cin + c) * 9 + tap];
+      // fragments of the response matrix: row r = 3*tap + o (27 rows, padded to 32)
+      //   frag[((cg*2 + ob)*64 + lane)*4 + kk] = w[o][c = 16cg + 4(lane/16) + kk][tap]
+      const int nkg = L.cin / 16;
+      std::vector<float> w4((size_t)nkg * 2 * 64 * 4, 0.0f);
+      for (int cg = 0; cg < nkg; ++cg)
+        for (int ob = 0; ob < 2; ++ob)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int kk = 0; kk < 4; ++kk) {
+              const int r = 16 * ob + lane % 16;
+              if (r >= 27) continue;
+              const int tap = r / 3, o = r % 3, c = 16 * cg + 4 * (lane / 16) + kk;
+              w4[(((size_t)cg * 2 + ob) * 64 + lane) * 4 + kk] = w[((size_t)o * L.cin + c) * 9 + tap];
+            }
       ctx->hr.cin = L.cin;
       ctx->hr.cout = 3;
       st = upload(ctx, w4, &ctx->hr.w);

@@ -83,25 +83,42 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     }
     __syncthreads();
 
-    for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+    // (tap, 16-channel group) steps, software-pipelined: the A fragments (global) and
+    // B fragments (LDS) of step i+1 are in flight while the MFMAs of step i issue.
+    constexpr int NCG = CCH / 16;
+    constexpr int NIT = 9 * NCG;
+    const f32x4* wbase = a.wfrag + ((size_t)(ch * NCG) * a.obtot + obase) * 64 + lane;
+    const size_t wstride_tap = (size_t)NKG * a.obtot * 64;
+    const float* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + 4 * q];
+    f32x4 wa[OB], xb[PB];
 #pragma unroll
-      for (int cg = 0; cg < CCH / 16; ++cg) {
-        const int kg = ch * (CCH / 16) + cg;
-        const f32x4* wp = a.wfrag + ((size_t)(tap * NKG + kg) * a.obtot + obase) * 64 + lane;
-        f32x4 wa[OB];
+    for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
 #pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wa[ob] = wp[ob * 64];
-        f32x4 xb[PB];
+    for (int pb = 0; pb < PB; ++pb) xb[pb] = ld4(tbase + pb * (kTW + 2) * LDP);
+#pragma unroll 3
+    for (int it = 0; it < NIT; ++it) {
+      f32x4 wn[OB], xn[PB];
+      if (it + 1 < NIT) {
+        const int tap = (it + 1) / NCG, cg = (it + 1) - tap * NCG;
+        const int dy = tap / 3, dx = tap - 3 * dy;
+        const f32x4* wp = wbase + tap * wstride_tap + (size_t)cg * a.obtot * 64;
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) wn[ob] = wp[ob * 64];
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
-          xb[pb] = ld4(&tile[((wave * PB + pb + dy) * (kTW + 2) + j + dx) * LDP + 16 * cg + 4 * q]);
+          xn[pb] = ld4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + 16 * cg);
+      }
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int pb = 0; pb < PB; ++pb)
+        for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-            for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = mfma4(wa[ob][kk], xb[pb][kk], acc[pb][ob]);
+          for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = mfma4(wa[ob][kk], xb[pb][kk], acc[pb][ob]);
+      if (it + 1 < NIT) {
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
       }
     }
   }
@@ -282,8 +299,13 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb,
 }
 
 // ---- HR conv C -> 3 plus the bilinear x2 base, planar RGB out ----
-// Weights arrive as [tap][c][4] (fourth output zero) so each 4-channel step reads
-// 16 uniform floats.  tsel: 0 -> base of frame a, 1 -> frame b, 2 -> their mean.
+// The thin output conv is computed as "tap responses": R[3*tap + o][p] =
+// sum_c w[o][c][tap] U[c][p] is a 27-row (padded to 32) by C product on MFMA, taken over
+// every pixel of a 16x16 output tile and its one-pixel halo and kept in LDS; each
+// output pixel then sums the nine responses of its shifted neighbours:
+//   out[o][p] = b[o] + sum_tap R[3*tap + o][p + delta_tap] + base[o][p].
+// Pixels outside the map have U = 0, hence R = 0: the conv's zero padding.
+// tsel: 0 -> base of frame a, 1 -> frame b, 2 -> the mean of both.
 __device__ __forceinline__ float up2_sample(const float* pl, int H, int W, int Y, int X) {
   const int i = Y >> 1, jx = X >> 1;
   const int i2 = (Y & 1) ? min(i + 1, H - 1) : max(i - 1, 0);
@@ -293,44 +315,84 @@ __device__ __forceinline__ float up2_sample(const float* pl, int H, int W, int Y
   return 0.75f * r0 + 0.25f * r1;
 }
 
+struct HrArgs {
+  const float* u;        // [2H][2W][C]
+  const f32x4* wfrag;    // [C/16][2][64] fragments of the 32 x C response matrix
+  const float* bias;     // [3]
+  const float* rgb_a;
+  const float* rgb_b;
+  const uint32_t* sel;
+  float* dst;            // [3][2H][2W]
+  int H, W, tsel;
+};
+
 template <int C>
-__global__ __launch_bounds__(256) void k_hr(const float* __restrict__ u, const float* __restrict__ w4,
-                                            const float* __restrict__ b, const float* rgb_a,
-                                            const float* rgb_b, const uint32_t* sel, int tsel,
-                                            float* __restrict__ dst, int H, int W) {
-  const int H2 = 2 * H, W2 = 2 * W;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= H2 * W2) return;
-  const int Y = p / W2, X = p - Y * W2;
-  float s0 = b[0], s1 = b[1], s2 = b[2];
-  for (int tap = 0; tap < 9; ++tap) {
-    const int yy = Y + tap / 3 - 1, xx = X + tap % 3 - 1;
-    if (yy < 0 || yy >= H2 || xx < 0 || xx >= W2) continue;
-    const float* up = u + ((size_t)yy * W2 + xx) * C;
-    const float* wt = w4 + (size_t)tap * C * 4;
-#pragma unroll 4
-    for (int c = 0; c < C; c += 4) {
-      const f32x4 v = ld4(up + c);
+__global__ __launch_bounds__(256) void k_hr(HrArgs a) {
+  constexpr int T = 16, RW = T + 2, NP = RW * RW, NPB = (NP + 15) / 16, LDR = 33;
+  constexpr int NCG = C / 16;
+  __shared__ float R[NPB * 16 * LDR];
+  const int H2 = 2 * a.H, W2 = 2 * a.W;
+  const int tiles_x = (W2 + T - 1) / T;
+  const int ntile = tiles_x * ((H2 + T - 1) / T);
+  const int t = xcd_tile(blockIdx.x, ntile);
+  const int ty0 = (t / tiles_x) * T, tx0 = (t % tiles_x) * T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+
+  f32x4 wa[NCG][2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        s0 = fmaf(wt[(c + k) * 4 + 0], v[k], s0);
-        s1 = fmaf(wt[(c + k) * 4 + 1], v[k], s1);
-        s2 = fmaf(wt[(c + k) * 4 + 2], v[k], s2);
+  for (int cg = 0; cg < NCG; ++cg) {
+    wa[cg][0] = a.wfrag[(cg * 2 + 0) * 64 + lane];
+    wa[cg][1] = a.wfrag[(cg * 2 + 1) * 64 + lane];
+  }
+  for (int pbk = wave; pbk < NPB; pbk += 4) {
+    const int p = pbk * 16 + j;
+    const int ry = p / RW, rx = p - ry * RW;
+    const int Y = ty0 + ry - 1, X = tx0 + rx - 1;
+    const bool ok = p < NP && Y >= 0 && Y < H2 && X >= 0 && X < W2;
+    const float* up = a.u + ((size_t)(ok ? Y : 0) * W2 + (ok ? X : 0)) * C + 4 * q;
+    f32x4 acc0 = zero4(), acc1 = zero4();
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      const f32x4 xb = ok ? ld4(up + 16 * cg) : zero4();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        acc0 = mfma4(wa[cg][0][kk], xb[kk], acc0);
+        acc1 = mfma4(wa[cg][1][kk], xb[kk], acc1);
       }
     }
+    float* rp = &R[p * LDR];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      rp[4 * q + r] = acc0[r];
+      rp[16 + 4 * q + r] = acc1[r];
+    }
   }
-  const size_t lpl = (size_t)H * W, hpl = (size_t)H2 * W2;
-  const float* rb = (sel != nullptr && *sel != 0u) ? rgb_a : rgb_b;
+  __syncthreads();
+  const int ly = threadIdx.x / T, lx = threadIdx.x - ly * T;
+  const int Y = ty0 + ly, X = tx0 + lx;
+  if (Y >= H2 || X >= W2) return;
+  float s0 = a.bias[0], s1 = a.bias[1], s2 = a.bias[2];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    const float* rp = &R[((ly + dy) * RW + lx + dx) * LDR + 3 * tap];
+    s0 += rp[0];
+    s1 += rp[1];
+    s2 += rp[2];
+  }
+  const size_t lpl = (size_t)a.H * a.W, hpl = (size_t)H2 * W2;
+  const float* rb = (a.sel != nullptr && *a.sel != 0u) ? a.rgb_a : a.rgb_b;
   float base[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (tsel == 0) base[c] = up2_sample(rgb_a + c * lpl, H, W, Y, X);
-    else if (tsel == 1) base[c] = up2_sample(rb + c * lpl, H, W, Y, X);
-    else base[c] = 0.5f * (up2_sample(rgb_a + c * lpl, H, W, Y, X) + up2_sample(rb + c * lpl, H, W, Y, X));
+    if (a.tsel == 0) base[c] = up2_sample(a.rgb_a + c * lpl, a.H, a.W, Y, X);
+    else if (a.tsel == 1) base[c] = up2_sample(rb + c * lpl, a.H, a.W, Y, X);
+    else base[c] = 0.5f * (up2_sample(a.rgb_a + c * lpl, a.H, a.W, Y, X) + up2_sample(rb + c * lpl, a.H, a.W, Y, X));
   }
-  dst[(size_t)Y * W2 + X] = s0 + base[0];
-  dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
-  dst[2 * hpl + (size_t)Y * W2 + X] = s2 + base[2];
+  a.dst[(size_t)Y * W2 + X] = s0 + base[0];
+  a.dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
+  a.dst[2 * hpl + (size_t)Y * W2 + X] = s2 + base[2];
 }
 
 template <int CCH, int NCHUNK, int OB, int PB, int EPI>
@@ -426,10 +488,20 @@ hipError_t launch_dcn(const PackedConv& L, const float* fa, const float* fb, con
 
 hipError_t launch_hr(const PlainConv& L, const float* u, const float* rgb_a, const float* rgb_b,
                      const uint32_t* sel, int tsel, float* dst, int H, int W, hipStream_t s) {
-  const int n = 4 * H * W;
-  const dim3 grid((n + 255) / 256);
-  if (L.cin == 64) hipLaunchKernelGGL((k_hr<64>), grid, dim3(256), 0, s, u, L.w, L.b, rgb_a, rgb_b, sel, tsel, dst, H, W);
-  else if (L.cin == 32) hipLaunchKernelGGL((k_hr<32>), grid, dim3(256), 0, s, u, L.w, L.b, rgb_a, rgb_b, sel, tsel, dst, H, W);
+  HrArgs a;
+  a.u = u;
+  a.wfrag = reinterpret_cast<const f32x4*>(L.w);
+  a.bias = L.b;
+  a.rgb_a = rgb_a;
+  a.rgb_b = rgb_b;
+  a.sel = sel;
+  a.dst = dst;
+  a.H = H;
+  a.W = W;
+  a.tsel = tsel;
+  const int ntile = ((2 * W + 15) / 16) * ((2 * H + 15) / 16);
+  if (L.cin == 64) hipLaunchKernelGGL((k_hr<64>), dim3(ntile), dim3(256), 0, s, a);
+  else if (L.cin == 32) hipLaunchKernelGGL((k_hr<32>), dim3(ntile), dim3(256), 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
