@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS))
     ap.add_argument("--frames", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--also", default="fp16,bf16",
+                    help="other precisions timed on the same clip after the main run ('' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path needs no collective and this build runs on a "
@@ -119,18 +121,25 @@ def main():
     blob = synth.gen_weights(cfg, seed=1)
     W_, H_ = clip.width, clip.height
     fmt = B.fmt_struct(W_, H_, clip.bits, clip.chroma)
-    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=args.precision)
     frames = [B.to_device_frame(*clip.frame(t)) for t in range(clip.n_frames)]
     outs = [B.alloc_frame(2 * W_, 2 * H_, clip.bits, clip.chroma) for _ in range(2 * clip.n_frames)]
-    st = ctx.open_stream(fmt)
     hp, wp = (H_ + 7) // 8 * 8, (W_ + 7) // 8 * 8
 
-    def step():
+    def make(prec):
+        c = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+        return c, c.open_stream(fmt)
+
+    def run_clip(st):
         st.reset()
         for t in range(clip.n_frames):
             o = outs[2 * (t - 1):2 * t] if t > 0 else outs[0:2]
             st.push(frames[t], outs=o)
         st.end(outs=outs[2 * clip.n_frames - 2:])
+
+    ctx, st = make(args.precision)
+
+    def step():
+        run_clip(st)
 
     print(f"# warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -193,6 +202,28 @@ def main():
                  "frac_of_peak": round(path_flop / (ms / 1000.0) / 1e12 / PEAKS[args.precision], 4)},
         "kernels": kernels,
     }
+    others = {}
+    for prec in [p for p in args.also.split(",") if p and p != args.precision]:
+        print(f"# timing {prec}", file=sys.stderr, flush=True)
+        c2, st2 = make(prec)
+        for _ in range(max(1, args.warmup)):
+            run_clip(st2)
+        torch.cuda.synchronize()
+        c2.profile(True)
+        a0 = time.perf_counter()
+        for _ in range(args.steps):
+            run_clip(st2)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        pr = c2.profile_read()
+        ms2 = (a1 - a0) / args.steps * 1000.0
+        others[prec] = {"value": round(mpix / (ms2 / 1000.0), 3), "ms_per_step": round(ms2, 3),
+                        "speedup_vs_" + args.precision: round(ms / ms2, 3),
+                        "kernel_ms_per_step": {k: round(v[1] / args.steps, 2) for k, v in pr.items() if v[0]}}
+        st2.close()
+        c2.close()
+    if others:
+        rec["other_precisions"] = others
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(clip, blob, cfg)

@@ -62,8 +62,8 @@ typedef struct {
   int64_t pitch_bytes[3];
 } nv_planes;
 
-/* Network shape.  channels C (multiple of 32), res_blocks R (>= 0), offset_groups G
- * (2C divisible by G, 2C/G a multiple of 4), scale must be 2, align must be 8,
+/* Network shape.  channels C (32 or 64), res_blocks R (0..64), offset_groups G (even,
+ * 2C divisible by G, 2C/G a multiple of 4), scale must be 2, align must be 8,
  * flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE. */
 typedef struct {
   int32_t channels, res_blocks, offset_groups, scale, align;
@@ -182,6 +182,51 @@ nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n, void* str
 
 /* Device bytes a stream of this format keeps resident (for admission control). */
 nv_status nv_stream_footprint(const nv_context* ctx, const nv_format* fmt, size_t* bytes);
+
+/* ------------------------------------------------------------ batching ---- */
+
+enum { NV_BATCH_MAX_FRAMES = 256, NV_BATCH_MAX_GROUPS = 512, NV_BATCH_MAX_CHAIN = 16 };
+
+/* One request of a batch: n_frames (1..NV_BATCH_MAX_CHAIN) consecutive frames of one
+ * clip stream, processed exactly as n_frames calls of nv_stream_push (external_cut[j],
+ * or -1 for every frame when external_cut is NULL), followed by nv_stream_end when
+ * end_of_clip != 0.  The frames of a request share the paper's batched frame store for
+ * n = 1 (section 3.3, Fig. 1): b groups read b + 1 stored frames, none duplicated.
+ * out[] holds room for 2 * n_frames + 2 output frames (in emission order); *n_out
+ * receives the number written.  frames, external_cut, out and n_out are HOST arrays;
+ * the planes they describe are device memory. */
+typedef struct {
+  nv_stream* stream;
+  int32_t n_frames;
+  const nv_planes* frames;
+  const int32_t* external_cut;
+  const nv_planes* out;
+  int32_t* n_out;
+  int32_t end_of_clip;
+} nv_batch_req;
+
+/* Run many streams' requests (any formats and sizes) together: every stage is one
+ * persistent launch over all images of the batch, and the launch sequence is recorded
+ * once into a HIP graph and replayed for later batches (the per-batch job tables are
+ * uploaded before each replay).  Results are bit-identical to per-stream calls.  The
+ * streams of one call must be distinct and belong to ctx; at most NV_BATCH_MAX_FRAMES
+ * frames and NV_BATCH_MAX_GROUPS groups per call.  Device workspace grows to the largest
+ * batch seen (see nv_batch_footprint). */
+nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs, int32_t n, void* stream);
+
+/* on != 0 (the default): record and replay the batch graph; 0: launch directly. */
+nv_status nv_batch_graph(nv_context* ctx, int32_t on);
+
+/* Device bytes of batch workspace currently held by ctx. */
+nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes);
+
+/* Autotuner: times each candidate workgroup tile (rows per wave) of the residual-block
+ * conv, the pixel-shuffle conv and the DCN on an hp x wp frame and keeps the fastest in
+ * ctx.  When the environment variable NNVISR_TUNE_CACHE names a file, results are
+ * looked up there first (key: precision, channels, hp, wp) and appended after timing.
+ * A human-readable summary is written to report (HOST, may be NULL). */
+nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* stream, char* report,
+                      size_t report_len);
 
 /* ------------------------------------------------------- kernel timing ---- */
 

@@ -36,6 +36,12 @@ class NvSceneParams(ctypes.Structure):
                 ("hist_frac_den", c_int32), ("enable", c_int32)]
 
 
+class NvBatchReq(ctypes.Structure):
+    _fields_ = [("stream", c_void_p), ("n_frames", c_int32), ("frames", POINTER(NvPlanes)),
+                ("external_cut", POINTER(c_int32)), ("out", POINTER(NvPlanes)),
+                ("n_out", POINTER(c_int32)), ("end_of_clip", c_int32)]
+
+
 PF = POINTER(c_float)
 _SIGS = {
     "nv_context_create": (c_int32, [c_int32, POINTER(NvNetConfig), PF, c_size_t, POINTER(c_void_p)]),
@@ -64,6 +70,10 @@ _SIGS = {
     "nv_profile_enable": (c_int32, [c_void_p, c_int32]),
     "nv_profile_read": (c_int32, [c_void_p, POINTER(c_int64), POINTER(ctypes.c_double)]),
     "nv_profile_kind_name": (c_char_p, [c_int32]),
+    "nv_enhance_batch": (c_int32, [c_void_p, POINTER(NvBatchReq), c_int32, c_void_p]),
+    "nv_batch_graph": (c_int32, [c_void_p, c_int32]),
+    "nv_batch_footprint": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nv_autotune": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, ctypes.c_char_p, c_size_t]),
 }
 NV_K_COUNT = 10
 

@@ -186,6 +186,49 @@ class Context:
     def open_stream(self, fmt: NvFormat, params: NvSceneParams | None = None) -> "Stream":
         return Stream(self, fmt, params)
 
+    def enhance_batch(self, requests, stream=None):
+        """requests: list of (Stream, [device frames], external cuts or None, end_of_clip).
+        Returns, per request, the list of output frames written (emission order)."""
+        lib = _abi.load()
+        n = len(requests)
+        reqs = (_abi.NvBatchReq * max(n, 1))()
+        keep, outs_all = [], []
+        for i, (st, frames, ext, end) in enumerate(requests):
+            k = len(frames)
+            n_emit = k - (1 if st.n_pushed == 0 else 0) + (1 if end else 0)
+            outs = [alloc_frame(2 * st.fmt.width, 2 * st.fmt.height, st.fmt.bits, st.fmt.chroma, self.device)
+                    for _ in range(2 * n_emit)]
+            fr = (NvPlanes * k)(*[planes_struct(*f) for f in frames])
+            op = (NvPlanes * max(1, len(outs)))(*[planes_struct(*o) for o in outs])
+            ec = (c_int32 * k)(*ext) if ext is not None else None
+            cnt = c_int32()
+            keep += [fr, op, ec, cnt]
+            reqs[i].stream = st._h
+            reqs[i].n_frames = k
+            reqs[i].frames = ctypes.cast(fr, ctypes.POINTER(NvPlanes))
+            reqs[i].external_cut = ctypes.cast(ec, ctypes.POINTER(c_int32)) if ec is not None else None
+            reqs[i].out = ctypes.cast(op, ctypes.POINTER(NvPlanes))
+            reqs[i].n_out = ctypes.pointer(cnt)
+            reqs[i].end_of_clip = 1 if end else 0
+            outs_all.append((outs, cnt))
+        check(lib.nv_enhance_batch(self._h, reqs, n, c_void_p(_stream(stream))))
+        for i, (st, frames, _e, _end) in enumerate(requests):
+            st.n_pushed += len(frames)
+        return [outs[:cnt.value] for outs, cnt in outs_all]
+
+    def batch_graph(self, on: bool):
+        check(_abi.load().nv_batch_graph(self._h, 1 if on else 0))
+
+    def batch_footprint(self) -> int:
+        n = c_size_t()
+        check(_abi.load().nv_batch_footprint(self._h, byref(n)))
+        return int(n.value)
+
+    def autotune(self, hp: int, wp: int, stream=None) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        check(_abi.load().nv_autotune(self._h, hp, wp, c_void_p(_stream(stream)), buf, 1024))
+        return buf.value.decode()
+
     def profile(self, on: bool):
         check(_abi.load().nv_profile_enable(self._h, 1 if on else 0))
 

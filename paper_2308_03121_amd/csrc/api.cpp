@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -74,15 +75,16 @@ nv_status check_config(const nv_net_config* c) {
   if (c->res_blocks < 0 || c->res_blocks > 64)
     return fail(NV_E_INVALID, "res_blocks must be in [0, 64] (got %d)", c->res_blocks);
   const int G = c->offset_groups;
-  if (G <= 0 || (2 * c->channels) % G != 0 || ((2 * c->channels) / G) % 4 != 0)
-    return fail(NV_E_INVALID, "offset_groups must divide 2C into groups of a multiple of 4 channels");
+  if (G <= 0 || G % 2 != 0 || (2 * c->channels) % G != 0 || ((2 * c->channels) / G) % 4 != 0)
+    return fail(NV_E_INVALID,
+                "offset_groups must be even and split 2C into groups of a multiple of 4 channels");
   if (c->scale != 2) return fail(NV_E_UNSUPPORTED, "only scale 2 is implemented");
   if (c->align != 8) return fail(NV_E_UNSUPPORTED, "only align 8 is implemented");
   if (c->flags != (NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE))
     return fail(NV_E_UNSUPPORTED, "only Interpolation|Extra frame|Double frame (n = 1) is implemented");
-  if (c->precision != NV_FP32)
-    return fail(c->precision >= 0 && c->precision <= 3 ? NV_E_UNSUPPORTED : NV_E_INVALID,
-                "precision %d not available", c->precision);
+  if (c->precision < NV_FP32 || c->precision > NV_FP8_E4M3)
+    return fail(NV_E_INVALID, "precision %d is not an nv_precision", c->precision);
+  if (c->precision == NV_FP8_E4M3) return fail(NV_E_UNSUPPORTED, "FP8 precision not available");
   return NV_OK;
 }
 
@@ -163,14 +165,14 @@ void dev_free(T*& p) {
 
 struct Workspace {
   int hp = 0, wp = 0;
-  float* t0 = nullptr;    // extract temporaries [hp][wp][C]
-  float* o1 = nullptr;    // offset-head hidden  [hp][wp][C]
-  float* offs = nullptr;  // offsets + mask      [hp][wp][ldo]
-  float* fmid = nullptr;  // aligned features    [hp][wp][C]
-  float* u = nullptr;     // HR features         [2hp][2wp][C]
-  float* hr = nullptr;    // HR RGB              [3][2hp][2wp]
+  void* t0 = nullptr;     // extract temporaries [hp][wp][C]      feature type
+  float* o1 = nullptr;    // offset-head hidden  [hp][wp][C]      float
+  float* offs = nullptr;  // offsets + mask      [hp][wp][ldo]    float
+  void* fmid = nullptr;   // aligned features    [hp][wp][C]      feature type
+  void* u = nullptr;      // HR features         [2hp][2wp][C]    feature type
+  float* hr = nullptr;    // HR RGB              [3][2hp][2wp]    float
   float* rgb[2] = {nullptr, nullptr};  // group inputs [3][hp][wp]
-  float* feat[2] = {nullptr, nullptr}; // group features [hp][wp][C]
+  void* feat[2] = {nullptr, nullptr};  // group features [hp][wp][C]
   size_t bytes = 0;
 };
 
@@ -194,31 +196,76 @@ struct Profiler {
   }
 };
 
+// Tile shapes (rows per wave) of the kernels that have several; the autotuner may change
+// them per context (see nv_autotune).
+struct Tuning {
+  int pb_block = 2, pb_up = 2, pb_dcn = 2;
+};
+
+struct BatchState;
+static void batch_release(BatchState* b);
+
 struct nv_context {
   int device = 0;
   Profiler prof;
+  Tuning tune;
+  BatchState* batch = nullptr;
   nv_net_config cfg{};
   int C = 0, G = 0, ldo = 0;
-  PlainConv conv_in, hr;
+  int ft = DT_F32;                  // feature storage and bulk MFMA type
+  PlainConv conv_in;
   std::vector<PackedConv> blocks;   // a, b per residual block
-  PackedConv off1, off2, dcn, up;
+  PackedConv off1, off2, dcn, up, hr;
   Workspace ws;
   std::vector<void*> allocs;
 };
 
 namespace {
 
-// A-operand fragments of one conv for the MFMA kernels: element
-//   frag[(((tap * NKG + kg) * obtot + ob) * 64 + lane) * 4 + kk]
-//     = W[o = rowmap(16*ob + lane%16)][c = 16*kg + 4*(lane/16) + kk][tap]
-// and bias[r] = b[rowmap(r)], zero for padded rows.  rowmap is the identity except for
+// float -> bfloat16 bits, round to nearest even (no NaN inputs occur in weights)
+uint16_t to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+uint16_t to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+// One 16-byte lane fragment of an A operand: channels [c0, c0 + 16/elem) of row-vector
+// getter g(c) in the MFMA type tc.
+template <class G>
+void put_fragment(uint8_t* dst, int tc, int c0, G g) {
+  if (tc == DT_F32) {
+    for (int e = 0; e < 4; ++e) {
+      const float v = g(c0 + e);
+      std::memcpy(dst + 4 * e, &v, 4);
+    }
+  } else {
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t b = tc == DT_F16 ? to_f16_bits(g(c0 + e)) : to_bf16_bits(g(c0 + e));
+      std::memcpy(dst + 2 * e, &b, 2);
+    }
+  }
+}
+
+// A-operand fragments of one conv for the MFMA kernels, 16 bytes per lane:
+//   frag[((tap * NKG + kg) * obtot + ob) * 64 + lane]
+//     = W[o = rowmap(16*ob + lane%16)][c = KG*kg + (KG/4)*(lane/16) + e][tap], e < KG/4
+// with KG = 16 channels per group for float and 32 for 16-bit types, and
+// bias[r] = b[rowmap(r)], zero for padded rows.  rowmap is the identity except for
 // the pixel-shuffle conv, whose A row 16*ob + t carries channel 16*(ob/4) + t of
 // sub-pixel ob%4, i.e. original output channel 4*(16*(ob/4) + t) + ob%4.
 nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, int cin,
-                    bool shuffle, PackedConv* out) {
+                    bool shuffle, int tc, PackedConv* out) {
+  const int KG = tc == DT_F32 ? 16 : 32;
   const int obtot = (cout + 15) / 16;
-  const int nkg = cin / 16;
-  std::vector<float> frag((size_t)9 * nkg * obtot * 64 * 4, 0.0f);
+  const int nkg = cin / KG;
+  std::vector<uint8_t> frag((size_t)9 * nkg * obtot * 64 * 16, 0);
   std::vector<float> bias((size_t)obtot * 16, 0.0f);
   auto rowmap = [&](int r) -> int {
     if (!shuffle) return r;
@@ -228,24 +275,56 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
   for (int tap = 0; tap < 9; ++tap)
     for (int kg = 0; kg < nkg; ++kg)
       for (int ob = 0; ob < obtot; ++ob)
-        for (int lane = 0; lane < 64; ++lane)
-          for (int kk = 0; kk < 4; ++kk) {
-            const int r = 16 * ob + lane % 16;
-            if (r >= cout) continue;
-            const int o = rowmap(r);
-            const int c = 16 * kg + 4 * (lane / 16) + kk;
-            frag[((((size_t)tap * nkg + kg) * obtot + ob) * 64 + lane) * 4 + kk] =
-                w[((size_t)o * cin + c) * 9 + tap];
-          }
+        for (int lane = 0; lane < 64; ++lane) {
+          const int r = 16 * ob + lane % 16;
+          if (r >= cout) continue;
+          const int o = rowmap(r);
+          const int c0 = KG * kg + (KG / 4) * (lane / 16);
+          put_fragment(&frag[((((size_t)tap * nkg + kg) * obtot + ob) * 64 + lane) * 16], tc, c0,
+                       [&](int c) { return w[((size_t)o * cin + c) * 9 + tap]; });
+        }
   for (int r = 0; r < cout; ++r) bias[r] = b[rowmap(r)];
   out->cin = cin;
   out->cout = cout;
   out->obtot = obtot;
-  HIP_TRY(dev_alloc(&out->frag, frag.size()));
+  out->tc = tc;
+  HIP_TRY(hipMalloc(&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   HIP_TRY(dev_alloc(&out->bias, bias.size()));
   ctx->allocs.push_back(out->bias);
-  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
+  return NV_OK;
+}
+
+// Tap-response matrix of the C -> 3 HR conv: row r = 3*tap + o (27 rows, padded to 32),
+//   frag[(kg*2 + ob)*64 + lane] = Wr[r = 16*ob + lane%16][c = KG*kg + (KG/4)*(lane/16) + e]
+// with Wr[3*tap + o][c] = w[o][c][tap].
+nv_status pack_hr(nv_context* ctx, const float* w, const float* b, int cin, int tc, PackedConv* out) {
+  const int KG = tc == DT_F32 ? 16 : 32;
+  const int nkg = cin / KG;
+  std::vector<uint8_t> frag((size_t)nkg * 2 * 64 * 16, 0);
+  for (int kg = 0; kg < nkg; ++kg)
+    for (int ob = 0; ob < 2; ++ob)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int r = 16 * ob + lane % 16;
+        if (r >= 27) continue;
+        const int tap = r / 3, o = r % 3;
+        const int c0 = KG * kg + (KG / 4) * (lane / 16);
+        put_fragment(&frag[(((size_t)kg * 2 + ob) * 64 + lane) * 16], tc, c0,
+                     [&](int c) { return w[((size_t)o * cin + c) * 9 + tap]; });
+      }
+  std::vector<float> bias(16, 0.0f);
+  for (int o = 0; o < 3; ++o) bias[o] = b[o];
+  out->cin = cin;
+  out->cout = 3;
+  out->obtot = 2;
+  out->tc = tc;
+  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  ctx->allocs.push_back(out->frag);
+  HIP_TRY(dev_alloc(&out->bias, bias.size()));
+  ctx->allocs.push_back(out->bias);
+  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(out->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
   return NV_OK;
 }
@@ -257,16 +336,21 @@ nv_status upload(nv_context* ctx, const std::vector<float>& v, float** out) {
   return NV_OK;
 }
 
+void free_raw(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
 void free_workspace(Workspace& ws) {
-  dev_free(ws.t0);
+  free_raw(ws.t0);
   dev_free(ws.o1);
   dev_free(ws.offs);
-  dev_free(ws.fmid);
-  dev_free(ws.u);
+  free_raw(ws.fmid);
+  free_raw(ws.u);
   dev_free(ws.hr);
   for (int i = 0; i < 2; ++i) {
     dev_free(ws.rgb[i]);
-    dev_free(ws.feat[i]);
+    free_raw(ws.feat[i]);
   }
   ws.hp = ws.wp = 0;
   ws.bytes = 0;
@@ -282,22 +366,22 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
     HIP_TRY(hipDeviceSynchronize());
     free_workspace(ws);
   }
-  const size_t px = (size_t)nh * nw, C = ctx->C;
+  const size_t px = (size_t)nh * nw, C = ctx->C, fb = dtype_bytes(ctx->ft);
   Workspace n;
   n.hp = nh;
   n.wp = nw;
-  HIP_TRY(dev_alloc(&n.t0, px * C));
+  HIP_TRY(hipMalloc(&n.t0, px * C * fb));
   ws = n;  // from here on free_workspace() releases whatever was allocated
   HIP_TRY(dev_alloc(&ws.o1, px * C));
   HIP_TRY(dev_alloc(&ws.offs, px * ctx->ldo));
-  HIP_TRY(dev_alloc(&ws.fmid, px * C));
-  HIP_TRY(dev_alloc(&ws.u, 4 * px * C));
+  HIP_TRY(hipMalloc(&ws.fmid, px * C * fb));
+  HIP_TRY(hipMalloc(&ws.u, 4 * px * C * fb));
   HIP_TRY(dev_alloc(&ws.hr, 12 * px));
   for (int i = 0; i < 2; ++i) {
     HIP_TRY(dev_alloc(&ws.rgb[i], 3 * px));
-    HIP_TRY(dev_alloc(&ws.feat[i], px * C));
+    HIP_TRY(hipMalloc(&ws.feat[i], px * C * fb));
   }
-  ws.bytes = 4 * px * (C * 4 + ctx->ldo + 4 * C + 12 + 6 + 2 * C);
+  ws.bytes = px * (C * fb * 8 + 4 * C + 4 * (size_t)ctx->ldo + 48 + 24);
   return NV_OK;
 }
 
@@ -328,58 +412,91 @@ nv_status timed(nv_context* ctx, int kind, hipStream_t s, const char* what, F&& 
     if (s_ != NV_OK) return s_; \
   } while (0)
 
-nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, float* feat,
-                       hipStream_t s) {
+ConvImg conv_img(const void* src0, const void* src1, const uint32_t* sel, const void* alt0,
+                 const void* alt1, const void* res, void* dst, int H, int W) {
+  ConvImg im;
+  im.src0 = src0;
+  im.src1 = src1;
+  im.sel = sel;
+  im.alt0 = alt0;
+  im.alt1 = alt1;
+  im.res = res;
+  im.dst = dst;
+  im.H = H;
+  im.W = W;
+  im.item_begin = 0;
+  return im;
+}
+
+nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
   NV_TRY(ensure_workspace(ctx, hp, wp));
-  const int C = ctx->C;
+  const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
   NV_TRY(timed(ctx, NV_K_CONV_IN, s, "conv_in",
-               [&] { return launch_conv_in(ctx->conv_in, rgb, feat, hp, wp, s); }));
+               [&] { return launch_conv_in(ctx->conv_in, ft, rgb, feat, hp, wp, s); }));
+  const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->ws.t0, hp, wp);
+  const ConvImg ib = conv_img(ctx->ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.a", [&] {
-      return launch_conv(ctx->blocks[2 * r], EPI_LRELU, feat, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, ctx->ws.t0, C, hp, wp, 0, s);
+      return launch_conv(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, ia, C, 0, s);
     }));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.b", [&] {
-      return launch_conv(ctx->blocks[2 * r + 1], EPI_RES, ctx->ws.t0, nullptr, nullptr, nullptr,
-                         nullptr, feat, feat, C, hp, wp, 0, s);
+      return launch_conv(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, ib, C, 0, s);
     }));
   }
   return NV_OK;
 }
 
 // After HR output t has been written to hr_out[t], pack it into pack_out[t] when given.
-nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, const float* fa,
-                    const float* fb, int hp, int wp, const uint32_t* sel, uint32_t mask,
-                    float* const hr_out[3], float* offs_out, float* fmid_out,
+nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, const void* fa,
+                    const void* fb, int hp, int wp, const uint32_t* sel, uint32_t mask,
+                    float* const hr_out[3], float* offs_out, void* fmid_out,
                     const nv_format* pack_fmt, const nv_planes* const pack_out[3], hipStream_t s) {
   NV_TRY(ensure_workspace(ctx, hp, wp));
   Workspace& ws = ctx->ws;
-  const int C = ctx->C, G = ctx->G;
+  const int C = ctx->C, G = ctx->G, ft = ctx->ft;
   float* offs = offs_out ? offs_out : ws.offs;
-  float* fmid = fmid_out ? fmid_out : ws.fmid;
+  void* fmid = fmid_out ? fmid_out : ws.fmid;
   if (mask & 2u) {
-    NV_TRY(timed(ctx, NV_K_OFF1, s, "off1", [&] {
-      return launch_conv(ctx->off1, EPI_LRELU, fa, fb, sel, nullptr, fa, nullptr, ws.o1, C, hp, wp, 0, s);
-    }));
+    const ConvImg i1 = conv_img(fa, fb, sel, nullptr, fa, nullptr, ws.o1, hp, wp);
+    NV_TRY(timed(ctx, NV_K_OFF1, s, "off1",
+                 [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, 2, i1, C, 0, s); }));
+    const ConvImg i2 = conv_img(ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
     NV_TRY(timed(ctx, NV_K_OFF2, s, "off2", [&] {
-      return launch_conv(ctx->off2, EPI_OFFSET, ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs,
-                         ctx->ldo, hp, wp, 18 * G, s);
+      return launch_conv(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, 2, i2, ctx->ldo, 18 * G, s);
     }));
+    DcnImg di;
+    di.fa = fa;
+    di.fb = fb;
+    di.sel = sel;
+    di.offs = offs;
+    di.dst = fmid;
+    di.H = hp;
+    di.W = wp;
+    di.item_begin = 0;
     NV_TRY(timed(ctx, NV_K_DCN, s, "dcn",
-                 [&] { return launch_dcn(ctx->dcn, fa, fb, sel, offs, ctx->ldo, G, fmid, hp, wp, s); }));
+                 [&] { return launch_dcn(ctx->dcn, ft, ctx->tune.pb_dcn, di, ctx->ldo, G, s); }));
   }
   for (int t = 0; t < 3; ++t) {
     if (!(mask & (1u << t))) continue;
-    const float* g = t == 0 ? fa : (t == 1 ? fmid : fb);
-    const float* alt = t == 2 ? fa : nullptr;
+    const void* g = t == 0 ? fa : (t == 1 ? fmid : fb);
+    const void* alt = t == 2 ? fa : nullptr;
     const int tsel = t == 0 ? 0 : (t == 1 ? 2 : 1);
+    const ConvImg iu = conv_img(g, nullptr, sel, alt, nullptr, nullptr, ws.u, hp, wp);
     NV_TRY(timed(ctx, NV_K_UP, s, "up", [&] {
-      return launch_conv(ctx->up, EPI_SHUFFLE, g, nullptr, sel, alt, nullptr, nullptr, ws.u, 4 * C, hp,
-                         wp, 0, s);
+      return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, iu, 4 * C, 0, s);
     }));
     float* hr = hr_out && hr_out[t] ? hr_out[t] : ws.hr;
-    NV_TRY(timed(ctx, NV_K_HR, s, "hr",
-                 [&] { return launch_hr(ctx->hr, ws.u, rgb_a, rgb_b, sel, tsel, hr, hp, wp, s); }));
+    HrImg hi;
+    hi.u = ws.u;
+    hi.rgb_a = rgb_a;
+    hi.rgb_b = rgb_b;
+    hi.sel = sel;
+    hi.dst = hr;
+    hi.H = hp;
+    hi.W = wp;
+    hi.tsel = tsel;
+    hi.item_begin = 0;
+    NV_TRY(timed(ctx, NV_K_HR, s, "hr", [&] { return launch_hr(ctx->hr, ft, hi, s); }));
     if (pack_fmt && pack_out && pack_out[t]) {
       const FrameOut fo = to_frame_out(pack_fmt, pack_out[t]);
       NV_TRY(timed(ctx, NV_K_PACK, s, "pack", [&] { return launch_pack(fo, hr, 2 * hp, 2 * wp, s); }));
@@ -422,6 +539,7 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   ctx->C = cfg->channels;
   ctx->G = cfg->offset_groups;
   ctx->ldo = 16 * ((27 * ctx->G + 15) / 16);
+  ctx->ft = cfg->precision == NV_FP16 ? DT_F16 : (cfg->precision == NV_BF16 ? DT_BF16 : DT_F32);
   const auto specs = layer_specs(*cfg);
   const float* p = weights;
   nv_status st = NV_OK;
@@ -437,26 +555,12 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
       st = upload(ctx, std::vector<float>(w, w + (size_t)L.cout * 27), &ctx->conv_in.w);
       if (st == NV_OK) st = upload(ctx, std::vector<float>(b, b + L.cout), &ctx->conv_in.b);
     } else if (nm == "hr") {
-      // fragments of the response matrix: row r = 3*tap + o (27 rows, padded to 32)
-      //   frag[((cg*2 + ob)*64 + lane)*4 + kk] = w[o][c = 16cg + 4(lane/16) + kk][tap]
-      const int nkg = L.cin / 16;
-      std::vector<float> w4((size_t)nkg * 2 * 64 * 4, 0.0f);
-      for (int cg = 0; cg < nkg; ++cg)
-        for (int ob = 0; ob < 2; ++ob)
-          for (int lane = 0; lane < 64; ++lane)
-            for (int kk = 0; kk < 4; ++kk) {
-              const int r = 16 * ob + lane % 16;
-              if (r >= 27) continue;
-              const int tap = r / 3, o = r % 3, c = 16 * cg + 4 * (lane / 16) + kk;
-              w4[(((size_t)cg * 2 + ob) * 64 + lane) * 4 + kk] = w[((size_t)o * L.cin + c) * 9 + tap];
-            }
-      ctx->hr.cin = L.cin;
-      ctx->hr.cout = 3;
-      st = upload(ctx, w4, &ctx->hr.w);
-      if (st == NV_OK) st = upload(ctx, std::vector<float>(b, b + 3), &ctx->hr.b);
+      st = pack_hr(ctx, w, b, L.cin, ctx->ft, &ctx->hr);
     } else {
+      // the offset head stays in float in every precision
+      const int tc = (nm == "off1" || nm == "off2") ? DT_F32 : ctx->ft;
       PackedConv pc;
-      st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up", &pc);
+      st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up", tc, &pc);
       if (nm == "block.a" || nm == "block.b") ctx->blocks.push_back(pc);
       else if (nm == "off1") ctx->off1 = pc;
       else if (nm == "off2") ctx->off2 = pc;
@@ -479,6 +583,7 @@ extern "C" nv_status nv_context_destroy(nv_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_workspace(ctx->ws);
+  batch_release(ctx->batch);
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
   delete ctx;
@@ -557,7 +662,7 @@ extern "C" nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp,
                                 void* d_feat, void* stream) {
   if (!ctx || !d_rgb || !d_feat) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_dims(hp, wp));
-  return extract_impl(ctx, d_rgb, hp, wp, static_cast<float*>(d_feat), (hipStream_t)stream);
+  return extract_impl(ctx, d_rgb, hp, wp, d_feat, (hipStream_t)stream);
 }
 
 extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
@@ -569,9 +674,8 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   if (out_mask == 0 || out_mask > 7) return fail(NV_E_INVALID, "out_mask must be in 1..7");
   for (int t = 0; t < 3; ++t)
     if ((out_mask & (1u << t)) && (!d_hr || !d_hr[t])) return fail(NV_E_INVALID, "d_hr[%d] is NULL", t);
-  return fuse_impl(ctx, d_rgb_a, d_rgb_b, static_cast<const float*>(d_feat_a),
-                   static_cast<const float*>(d_feat_b), hp, wp, d_sel, out_mask, d_hr, d_offsets,
-                   static_cast<float*>(d_fmid), nullptr, nullptr, (hipStream_t)stream);
+  return fuse_impl(ctx, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets,
+                   d_fmid, nullptr, nullptr, (hipStream_t)stream);
 }
 
 extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
@@ -599,6 +703,10 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
 
 // ---------------------------------------------------------------- streams ----
 
+// Per-stream device state.  Frame t's pixels and features live in ring slot t % R
+// (R >= 2; a batch request of k frames needs R >= k + 1 so the previous call's last
+// frame survives while the new ones are written).  luma / hist hold the last pushed
+// frame's luma plane and histogram in slot *_last; the next frame writes the other.
 struct nv_stream {
   nv_context* ctx = nullptr;
   nv_format fmt{};
@@ -606,35 +714,71 @@ struct nv_stream {
   SceneRule rule{};
   int hp = 0, wp = 0;
   int64_t t = 0;                 // frames pushed
-  float* rgb[2] = {nullptr, nullptr};
-  float* feat[2] = {nullptr, nullptr};
-  void* luma[2] = {nullptr, nullptr};   // copy of each frame's luma plane (scene metric)
+  std::vector<float*> rgb;       // R slots [3][hp][wp]
+  std::vector<void*> feat;       // R slots [hp][wp][C]
+  void* luma[2] = {nullptr, nullptr};
+  int luma_last = 0;
   int64_t luma_pitch = 0;
   uint32_t* hist = nullptr;      // [2][64]
+  int hist_last = 0;
   uint64_t* sad = nullptr;
   uint32_t* hd = nullptr;
   uint32_t* cuts = nullptr;      // [kCutRing]
   size_t bytes = 0;
+  int slot(int64_t frame) const { return (int)(frame % (int64_t)rgb.size()); }
 };
 
+static size_t slot_bytes(const nv_context* ctx, int hp, int wp) {
+  return (size_t)hp * wp * (12 + (size_t)ctx->C * dtype_bytes(ctx->ft));
+}
+
 static size_t stream_bytes(const nv_context* ctx, const nv_format* f) {
-  const size_t hp = round_up(f->height, 8), wp = round_up(f->width, 8);
+  const int hp = round_up(f->height, 8), wp = round_up(f->width, 8);
   const size_t bps = f->bits == 8 ? 1 : 2;
-  return 2 * (3 * hp * wp * 4 + hp * wp * (size_t)ctx->C * 4 + (size_t)f->width * f->height * bps) +
-         2 * 64 * 4 + 8 + 4 + (size_t)kCutRing * 4;
+  return 2 * slot_bytes(ctx, hp, wp) + 2 * (size_t)f->width * f->height * bps + 2 * 64 * 4 + 8 + 4 +
+         (size_t)kCutRing * 4;
 }
 
 static void stream_free(nv_stream* s) {
-  for (int i = 0; i < 2; ++i) {
-    dev_free(s->rgb[i]);
-    dev_free(s->feat[i]);
-    if (s->luma[i]) (void)hipFree(s->luma[i]);
-    s->luma[i] = nullptr;
-  }
+  for (auto& p : s->rgb) dev_free(p);
+  for (auto& p : s->feat) free_raw(p);
+  for (int i = 0; i < 2; ++i) free_raw(s->luma[i]);
   dev_free(s->hist);
   dev_free(s->sad);
   dev_free(s->hd);
   dev_free(s->cuts);
+}
+
+// Grows the slot ring to at least r slots, keeping the last pushed frame.
+static nv_status stream_ring(nv_stream* s, int r) {
+  const int old = (int)s->rgb.size();
+  if (old >= r) return NV_OK;
+  const size_t px = (size_t)s->hp * s->wp, fbytes = px * s->ctx->C * dtype_bytes(s->ctx->ft);
+  std::vector<float*> rgb(r, nullptr);
+  std::vector<void*> feat(r, nullptr);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < r && e == hipSuccess; ++i) {
+    e = dev_alloc(&rgb[i], 3 * px);
+    if (e == hipSuccess) e = hipMalloc(&feat[i], fbytes);
+  }
+  if (e == hipSuccess && s->t > 0 && old > 0) {
+    HIP_TRY(hipDeviceSynchronize());
+    const int from = (int)((s->t - 1) % old), to = (int)((s->t - 1) % r);
+    e = hipMemcpy(rgb[to], s->rgb[from], 3 * px * 4, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(feat[to], s->feat[from], fbytes, hipMemcpyDeviceToDevice);
+  }
+  if (e != hipSuccess) {
+    for (auto& p : rgb) dev_free(p);
+    for (auto& p : feat) free_raw(p);
+    return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "stream ring: %s", hipGetErrorString(e));
+  }
+  if (old > 0) HIP_TRY(hipDeviceSynchronize());
+  for (auto& p : s->rgb) dev_free(p);
+  for (auto& p : s->feat) free_raw(p);
+  s->rgb = rgb;
+  s->feat = feat;
+  s->bytes += (size_t)(r - old) * slot_bytes(s->ctx, s->hp, s->wp);
+  return NV_OK;
 }
 
 extern "C" nv_status nv_stream_footprint(const nv_context* ctx, const nv_format* fmt, size_t* bytes) {
@@ -658,26 +802,19 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   s->rule = to_rule(params);
   s->hp = round_up(fmt->height, 8);
   s->wp = round_up(fmt->width, 8);
-  const size_t px = (size_t)s->hp * s->wp;
   s->luma_pitch = (int64_t)fmt->width * (fmt->bits == 8 ? 1 : 2);
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-    e = dev_alloc(&s->rgb[i], 3 * px);
-    if (e == hipSuccess) e = dev_alloc(&s->feat[i], px * ctx->C);
-    if (e == hipSuccess) e = hipMalloc(&s->luma[i], (size_t)s->luma_pitch * fmt->height);
-  }
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&s->luma[i], (size_t)s->luma_pitch * fmt->height);
   if (e == hipSuccess) e = dev_alloc(&s->hist, 128);
   if (e == hipSuccess) e = dev_alloc(&s->sad, 1);
   if (e == hipSuccess) e = dev_alloc(&s->hd, 1);
   if (e == hipSuccess) e = dev_alloc(&s->cuts, kCutRing);
-  if (e != hipSuccess) {
-    stream_free(s);
-    delete s;
-    return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "stream allocation: %s",
-                hipGetErrorString(e));
-  }
-  s->bytes = stream_bytes(ctx, fmt);
-  nv_status st = ensure_workspace(ctx, s->hp, s->wp);
+  nv_status st = NV_OK;
+  if (e != hipSuccess)
+    st = fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "stream allocation: %s", hipGetErrorString(e));
+  s->bytes = stream_bytes(ctx, fmt) - 2 * slot_bytes(ctx, s->hp, s->wp);
+  if (st == NV_OK) st = stream_ring(s, 2);
+  if (st == NV_OK) st = ensure_workspace(ctx, s->hp, s->wp);
   if (st != NV_OK) {
     stream_free(s);
     delete s;
@@ -706,18 +843,19 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
     for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
   }
   hipStream_t hs = (hipStream_t)stream;
-  const int cur = (int)(s->t & 1), prv = cur ^ 1;
+  const int cur = s->slot(s->t), prv = s->t > 0 ? s->slot(s->t - 1) : 0;
   const Frame f = to_frame(&s->fmt, frame);
   NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
   Frame pf = f;
-  pf.p[0] = s->luma[prv];
+  pf.p[0] = s->luma[s->luma_last];
   pf.pitch[0] = s->luma_pitch;
   uint32_t* cut_t = s->cuts + (s->t % kCutRing);
+  uint32_t* hist_new = s->hist + 64 * (s->hist_last ^ 1);
   NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] {
-    return launch_scene(f, s->t > 0 ? &pf : nullptr, s->t > 0 ? s->hist + 64 * prv : nullptr, s->rule,
-                        external_cut, s->sad, s->hist + 64 * cur, s->hd, cut_t, hs);
+    return launch_scene(f, s->t > 0 ? &pf : nullptr, s->t > 0 ? s->hist + 64 * s->hist_last : nullptr, s->rule,
+                        external_cut, s->sad, hist_new, s->hd, cut_t, hs);
   }));
-  HIP_TRY(hipMemcpy2DAsync(s->luma[cur], (size_t)s->luma_pitch, frame->data[0],
+  HIP_TRY(hipMemcpy2DAsync(s->luma[s->luma_last ^ 1], (size_t)s->luma_pitch, frame->data[0],
                            (size_t)frame->pitch_bytes[0], (size_t)s->luma_pitch, (size_t)s->fmt.height,
                            hipMemcpyDeviceToDevice, hs));
   NV_TRY(extract_impl(s->ctx, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
@@ -727,6 +865,8 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
     *n_out = 2;
   }
   s->t += 1;
+  s->luma_last ^= 1;
+  s->hist_last ^= 1;
   return NV_OK;
 }
 
@@ -736,7 +876,7 @@ extern "C" nv_status nv_stream_end(nv_stream* s, const nv_planes out[2], int32_t
   if (s->t == 0) return NV_OK;
   if (!out) return fail(NV_E_INVALID, "out is NULL");
   for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
-  const int last = (int)((s->t - 1) & 1);
+  const int last = s->slot(s->t - 1);
   NV_TRY(emit_group(s, last, last, nullptr, out, (hipStream_t)stream));
   *n_out = 2;
   return NV_OK;
@@ -762,6 +902,534 @@ extern "C" nv_status nv_stream_close(nv_stream* s) {
   (void)hipDeviceSynchronize();
   stream_free(s);
   delete s;
+  return NV_OK;
+}
+
+// ---------------------------------------------------------------- batches ----
+//
+// A batch runs every stage of many streams' frames and groups as one persistent launch
+// per stage over device job tables.  The tables live in a fixed device arena (so the
+// recorded graph never changes); each call fills a pinned host copy, uploads it on the
+// caller's stream and replays the graph.
+
+namespace {
+
+enum BatchLaunch {
+  BL_UNPACK = 0, BL_SCENE, BL_CONV_IN, BL_BLOCK, BL_OFF1, BL_OFF2, BL_DCN, BL_UP, BL_HR, BL_PACK, BL_COUNT
+};
+
+struct BatchTables {
+  int cnt[BL_COUNT][2];
+  UnpackJob unpack[NV_BATCH_MAX_FRAMES];
+  SceneJob scene[NV_BATCH_MAX_FRAMES];
+  ConvInImg convin[NV_BATCH_MAX_FRAMES];
+  ConvImg blk_a[NV_BATCH_MAX_FRAMES];
+  ConvImg blk_b[NV_BATCH_MAX_FRAMES];
+  ConvImg off1[NV_BATCH_MAX_GROUPS];
+  ConvImg off2[NV_BATCH_MAX_GROUPS];
+  DcnImg dcn[NV_BATCH_MAX_GROUPS];
+  ConvImg up[2][NV_BATCH_MAX_GROUPS];
+  HrImg hr[2][NV_BATCH_MAX_GROUPS];
+  PackJob pack[2][NV_BATCH_MAX_GROUPS];
+};
+
+struct SceneAccum {
+  uint64_t sad[NV_BATCH_MAX_FRAMES];
+  uint32_t hist[NV_BATCH_MAX_FRAMES][64];
+  uint32_t hd[NV_BATCH_MAX_FRAMES];
+};
+
+// A growable device buffer carved into per-job pieces (256-byte aligned).
+struct Pool {
+  char* base = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct BatchState {
+  BatchTables* host = nullptr;       // pinned staging copy
+  BatchTables* dev = nullptr;        // device arena
+  SceneAccum* acc = nullptr;         // device scene accumulators
+  hipEvent_t uploaded = nullptr;     // staging copy consumed
+  hipEvent_t done = nullptr;         // last batch finished with the arena
+  bool any = false;
+  Pool frame_pool, group_pool;       // per-frame and per-group workspace
+  hipStream_t cap = nullptr;         // capture stream
+  hipGraphExec_t exec = nullptr;
+  bool graph_on = true;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+nv_status pool_reserve(Pool& p, size_t bytes, bool* grew) {
+  *grew = false;
+  if (bytes <= p.cap) return NV_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  free_raw(reinterpret_cast<void*&>(p.base));
+  p.cap = 0;
+  void* b = nullptr;
+  HIP_TRY(hipMalloc(&b, bytes));
+  p.base = static_cast<char*>(b);
+  p.cap = bytes;
+  *grew = true;
+  return NV_OK;
+}
+
+}  // namespace
+
+static void batch_release(BatchState* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->host) (void)hipHostFree(b->host);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->acc) (void)hipFree(b->acc);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->done) (void)hipEventDestroy(b->done);
+  free_raw(reinterpret_cast<void*&>(b->frame_pool.base));
+  free_raw(reinterpret_cast<void*&>(b->group_pool.base));
+  delete b;
+}
+
+namespace {
+
+nv_status batch_init(nv_context* ctx) {
+  if (ctx->batch) return NV_OK;
+  BatchState* b = new (std::nothrow) BatchState;
+  if (!b) return fail(NV_E_NOMEM, "host allocation failed");
+  ctx->batch = b;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(BatchTables), hipHostMallocDefault));
+  std::memset(b->host, 0, sizeof(BatchTables));
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&b->dev), sizeof(BatchTables)));
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&b->acc), sizeof(SceneAccum)));
+  HIP_TRY(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+  HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  return NV_OK;
+}
+
+// Every batched launch of one batch, in dependency order, on stream s.
+nv_status batch_enqueue(nv_context* ctx, hipStream_t s) {
+  BatchTables* T = ctx->batch->dev;
+  const int C = ctx->C, G = ctx->G, ft = ctx->ft, pb = ctx->tune.pb_block;
+  NV_TRY(check_launch(launch_scene_batch(T->scene, T->cnt[BL_SCENE], s), "scene batch"));
+  NV_TRY(check_launch(launch_unpack_batch(T->unpack, T->cnt[BL_UNPACK], s), "unpack batch"));
+  NV_TRY(check_launch(launch_conv_in_batch(ctx->conv_in, ft, T->convin, T->cnt[BL_CONV_IN], s), "conv_in batch"));
+  for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
+    NV_TRY(check_launch(launch_conv_batch(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, T->blk_a,
+                                          T->cnt[BL_BLOCK], C, 0, s), "block.a batch"));
+    NV_TRY(check_launch(launch_conv_batch(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, T->blk_b,
+                                          T->cnt[BL_BLOCK], C, 0, s), "block.b batch"));
+  }
+  NV_TRY(check_launch(launch_conv_batch(ctx->off1, CONV_OFF1, EPI_LRELU, ft, 2, T->off1, T->cnt[BL_OFF1], C, 0, s),
+                      "off1 batch"));
+  NV_TRY(check_launch(launch_conv_batch(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, 2, T->off2, T->cnt[BL_OFF2],
+                                        ctx->ldo, 18 * G, s), "off2 batch"));
+  NV_TRY(check_launch(launch_dcn_batch(ctx->dcn, ft, ctx->tune.pb_dcn, T->dcn, T->cnt[BL_DCN], ctx->ldo, G, s),
+                      "dcn batch"));
+  for (int o = 0; o < 2; ++o) {
+    NV_TRY(check_launch(launch_conv_batch(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, T->up[o],
+                                          T->cnt[BL_UP], 4 * C, 0, s), "up batch"));
+    NV_TRY(check_launch(launch_hr_batch(ctx->hr, ft, T->hr[o], T->cnt[BL_HR], s), "hr batch"));
+    NV_TRY(check_launch(launch_pack_batch(T->pack[o], T->cnt[BL_PACK], s), "pack batch"));
+  }
+  return NV_OK;
+}
+
+struct FrameRef {          // one frame of the batch
+  nv_stream* s;
+  int64_t t;               // its index in the stream
+  const nv_planes* in;
+  int ext;
+  int first, last;         // first / last frame of its request
+};
+
+struct GroupRef {          // one emitted group
+  nv_stream* s;
+  int slot_a, slot_b;
+  const uint32_t* sel;     // cut flag of frame b, or null for [a, a]
+  const nv_planes* out;    // two output frames
+};
+
+}  // namespace
+
+extern "C" nv_status nv_batch_graph(nv_context* ctx, int32_t on) {
+  if (!ctx) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(batch_init(ctx));
+  ctx->batch->graph_on = on != 0;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(NV_E_INVALID, "NULL argument");
+  *bytes = ctx->batch ? ctx->batch->frame_pool.cap + ctx->batch->group_pool.cap + sizeof(BatchTables) +
+                            sizeof(SceneAccum)
+                      : 0;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs, int32_t n, void* stream) {
+  if (!ctx || (!reqs && n > 0) || n < 0) return fail(NV_E_INVALID, "NULL argument");
+  hipStream_t hs = (hipStream_t)stream;
+  // ---- validation (nothing is enqueued or changed before it passes) ----
+  int nframes = 0, ngroups = 0;
+  for (int i = 0; i < n; ++i) {
+    const nv_batch_req& r = reqs[i];
+    if (!r.stream || r.stream->ctx != ctx) return fail(NV_E_INVALID, "request %d: stream is NULL or of another context", i);
+    for (int k = 0; k < i; ++k)
+      if (reqs[k].stream == r.stream) return fail(NV_E_INVALID, "requests %d and %d share a stream", k, i);
+    if (r.n_frames < 1 || r.n_frames > NV_BATCH_MAX_CHAIN)
+      return fail(NV_E_INVALID, "request %d: n_frames must be 1..%d", i, (int)NV_BATCH_MAX_CHAIN);
+    if (!r.frames || !r.n_out) return fail(NV_E_INVALID, "request %d: NULL frames or n_out", i);
+    const int emitted = r.n_frames - (r.stream->t == 0 ? 1 : 0) + (r.end_of_clip ? 1 : 0);
+    if (emitted > 0 && !r.out) return fail(NV_E_INVALID, "request %d: out is NULL", i);
+    for (int j = 0; j < r.n_frames; ++j) {
+      NV_TRY(check_planes(&r.stream->fmt, &r.frames[j], "batch frame"));
+      if (r.external_cut && (r.external_cut[j] < -1 || r.external_cut[j] > 1))
+        return fail(NV_E_INVALID, "request %d: external_cut must be -1, 0 or 1", i);
+    }
+    for (int o = 0; o < 2 * emitted; ++o) NV_TRY(check_planes(&r.stream->ofmt, &r.out[o], "batch output"));
+    nframes += r.n_frames;
+    ngroups += emitted;
+  }
+  if (nframes > NV_BATCH_MAX_FRAMES || ngroups > NV_BATCH_MAX_GROUPS)
+    return fail(NV_E_INVALID, "batch of %d frames / %d groups exceeds %d / %d", nframes, ngroups,
+                (int)NV_BATCH_MAX_FRAMES, (int)NV_BATCH_MAX_GROUPS);
+  NV_TRY(batch_init(ctx));
+  BatchState* B = ctx->batch;
+  for (int i = 0; i < n; ++i) NV_TRY(stream_ring(reqs[i].stream, reqs[i].n_frames + 1));
+
+  // ---- frames and groups in emission order ----
+  std::vector<FrameRef> frames;
+  std::vector<GroupRef> groups;
+  for (int i = 0; i < n; ++i) {
+    const nv_batch_req& r = reqs[i];
+    nv_stream* s = r.stream;
+    int emitted = 0;
+    for (int j = 0; j < r.n_frames; ++j) {
+      const int64_t t = s->t + j;
+      frames.push_back({s, t, &r.frames[j], r.external_cut ? r.external_cut[j] : -1, j == 0, j == r.n_frames - 1});
+      if (t > 0) groups.push_back({s, s->slot(t - 1), s->slot(t), s->cuts + (t % kCutRing), &r.out[2 * emitted++]});
+    }
+    if (r.end_of_clip) {
+      const int last = s->slot(s->t + r.n_frames - 1);
+      groups.push_back({s, last, last, nullptr, &r.out[2 * emitted++]});
+    }
+    *r.n_out = 2 * emitted;
+  }
+
+  // ---- workspace ----
+  const int C = ctx->C, fbytes = dtype_bytes(ctx->ft);
+  size_t fneed = 0, gneed = 0;
+  for (const auto& f : frames) fneed += align256((size_t)f.s->hp * f.s->wp * C * fbytes);
+  for (const auto& g : groups) {
+    const size_t px = (size_t)g.s->hp * g.s->wp;
+    gneed += align256(px * C * 4) + align256(px * ctx->ldo * 4) + align256(px * C * fbytes) +
+             align256(4 * px * C * fbytes) + align256(12 * px * 4);
+  }
+  bool grew = false;
+  NV_TRY(pool_reserve(B->frame_pool, fneed, &grew));
+  NV_TRY(pool_reserve(B->group_pool, gneed, &grew));
+
+  // ---- job tables ----
+  if (B->any) HIP_TRY(hipEventSynchronize(B->uploaded));   // staging copy free again
+  BatchTables& T = *B->host;
+  const int pbb = ctx->tune.pb_block, pbu = ctx->tune.pb_up, pbd = ctx->tune.pb_dcn;
+  int it[BL_COUNT] = {0};
+  char* fp = B->frame_pool.base;
+  for (size_t k = 0; k < frames.size(); ++k) {
+    const FrameRef& F = frames[k];
+    nv_stream* s = F.s;
+    const int hp = s->hp, wp = s->wp, sl = s->slot(F.t);
+    const Frame fr = to_frame(&s->fmt, F.in);
+    UnpackJob& u = T.unpack[k];
+    u.f = fr;
+    u.m = make_inv(fr.bits);
+    u.rgb = s->rgb[sl];
+    u.hp = hp;
+    u.wp = wp;
+    u.item_begin = it[BL_UNPACK];
+    it[BL_UNPACK] += unpack_items(hp, wp);
+    SceneJob& sc = T.scene[k];
+    sc.cur = fr;
+    if (F.t == 0) {
+      sc.prev_y = nullptr;
+      sc.prev_pitch = 0;
+      sc.hist_prev = nullptr;
+    } else if (F.first) {
+      sc.prev_y = s->luma[s->luma_last];
+      sc.prev_pitch = s->luma_pitch;
+      sc.hist_prev = s->hist + 64 * s->hist_last;
+    } else {
+      sc.prev_y = frames[k - 1].in->data[0];
+      sc.prev_pitch = frames[k - 1].in->pitch_bytes[0];
+      sc.hist_prev = B->acc->hist[k - 1];
+    }
+    sc.sad = &B->acc->sad[k];
+    sc.hist = B->acc->hist[k];
+    sc.hd = &B->acc->hd[k];
+    sc.cut = s->cuts + (F.t % kCutRing);
+    sc.hist_save = F.last ? s->hist + 64 * (s->hist_last ^ 1) : nullptr;
+    sc.luma_save = F.last ? s->luma[s->luma_last ^ 1] : nullptr;
+    sc.luma_save_pitch = s->luma_pitch;
+    sc.rule = s->rule;
+    sc.external = F.ext;
+    sc.item_begin = it[BL_SCENE];
+    it[BL_SCENE] += scene_items(fr.h);
+    void* t0 = fp;
+    fp += align256((size_t)hp * wp * C * fbytes);
+    ConvInImg& ci = T.convin[k];
+    ci.rgb = s->rgb[sl];
+    ci.dst = s->feat[sl];
+    ci.H = hp;
+    ci.W = wp;
+    ci.item_begin = it[BL_CONV_IN];
+    it[BL_CONV_IN] += conv_in_items(hp, wp, C);
+    const int nobg = ctx->blocks.empty() ? 1 : ctx->blocks[0].obtot / conv_ob(CONV_BULK, EPI_LRELU, ctx->blocks[0].obtot);
+    T.blk_a[k] = conv_img(s->feat[sl], nullptr, nullptr, nullptr, nullptr, nullptr, t0, hp, wp);
+    T.blk_b[k] = conv_img(t0, nullptr, nullptr, nullptr, nullptr, s->feat[sl], s->feat[sl], hp, wp);
+    T.blk_a[k].item_begin = T.blk_b[k].item_begin = it[BL_BLOCK];
+    it[BL_BLOCK] += conv_items(hp, wp, pbb, nobg);
+  }
+  char* gp = B->group_pool.base;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    const GroupRef& Gr = groups[k];
+    nv_stream* s = Gr.s;
+    const int hp = s->hp, wp = s->wp;
+    const size_t px = (size_t)hp * wp;
+    float* o1 = reinterpret_cast<float*>(gp);
+    gp += align256(px * C * 4);
+    float* offs = reinterpret_cast<float*>(gp);
+    gp += align256(px * ctx->ldo * 4);
+    void* fmid = gp;
+    gp += align256(px * C * fbytes);
+    void* u = gp;
+    gp += align256(4 * px * C * fbytes);
+    float* hr = reinterpret_cast<float*>(gp);
+    gp += align256(12 * px * 4);
+    const void* fa = s->feat[Gr.slot_a];
+    const void* fb = s->feat[Gr.slot_b];
+    const float* ra = s->rgb[Gr.slot_a];
+    const float* rb = s->rgb[Gr.slot_b];
+    T.off1[k] = conv_img(fa, fb, Gr.sel, nullptr, fa, nullptr, o1, hp, wp);
+    T.off1[k].item_begin = it[BL_OFF1];
+    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot));
+    T.off2[k] = conv_img(o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
+    T.off2[k].item_begin = it[BL_OFF2];
+    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot));
+    DcnImg& d = T.dcn[k];
+    d.fa = fa;
+    d.fb = fb;
+    d.sel = Gr.sel;
+    d.offs = offs;
+    d.dst = fmid;
+    d.H = hp;
+    d.W = wp;
+    d.item_begin = it[BL_DCN];
+    it[BL_DCN] += conv_items(hp, wp, pbd, 1);
+    for (int o = 0; o < 2; ++o) {
+      T.up[o][k] = conv_img(o == 0 ? fa : fmid, nullptr, Gr.sel, nullptr, nullptr, nullptr, u, hp, wp);
+      T.up[o][k].item_begin = it[BL_UP];
+      HrImg& h = T.hr[o][k];
+      h.u = u;
+      h.rgb_a = ra;
+      h.rgb_b = rb;
+      h.sel = Gr.sel;
+      h.dst = hr;
+      h.H = hp;
+      h.W = wp;
+      h.tsel = o == 0 ? 0 : 2;
+      h.item_begin = it[BL_HR];
+      PackJob& pk = T.pack[o][k];
+      pk.f = to_frame_out(&s->ofmt, &Gr.out[o]);
+      pk.m = make_fwd(s->ofmt.bits);
+      pk.rgb = hr;
+      pk.rh = 2 * hp;
+      pk.rw = 2 * wp;
+      pk.item_begin = it[BL_PACK];
+    }
+    it[BL_UP] += conv_items(hp, wp, pbu, ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot));
+    it[BL_HR] += hr_items(hp, wp);
+    it[BL_PACK] += pack_items(s->ofmt.width, s->ofmt.height, s->ofmt.chroma);
+  }
+  const int nf = (int)frames.size(), ng = (int)groups.size();
+  const int njobs[BL_COUNT] = {nf, nf, nf, nf, ng, ng, ng, ng, ng, ng};
+  for (int k = 0; k < BL_COUNT; ++k) {
+    T.cnt[k][0] = njobs[k];
+    T.cnt[k][1] = njobs[k] > 0 ? it[k] : 0;
+  }
+
+  // ---- upload, then launch (graph replay or direct) ----
+  if (B->any) HIP_TRY(hipStreamWaitEvent(hs, B->done, 0));
+  HIP_TRY(hipMemcpyAsync(B->dev, B->host, sizeof(BatchTables), hipMemcpyHostToDevice, hs));
+  HIP_TRY(hipEventRecord(B->uploaded, hs));
+  B->any = true;
+  if (B->graph_on) {
+    if (!B->exec) {
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
+      const nv_status st = batch_enqueue(ctx, B->cap);
+      const hipError_t ec = hipStreamEndCapture(B->cap, &g);
+      if (st != NV_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      HIP_TRY(ec);
+      const hipError_t ei = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_TRY(ei);
+    }
+    HIP_TRY(hipGraphLaunch(B->exec, hs));
+  } else {
+    NV_TRY(batch_enqueue(ctx, hs));
+  }
+  HIP_TRY(hipEventRecord(B->done, hs));
+
+  // ---- stream states advance ----
+  for (int i = 0; i < n; ++i) {
+    nv_stream* s = reqs[i].stream;
+    s->t += reqs[i].n_frames;
+    s->luma_last ^= 1;
+    s->hist_last ^= 1;
+  }
+  (void)grew;
+  return NV_OK;
+}
+
+// --------------------------------------------------------------- autotuner ----
+
+namespace {
+
+template <class F>
+nv_status time_launch(hipStream_t s, int reps, float* ms, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  NV_TRY(check_launch(launch(), "autotune warmup"));
+  HIP_TRY(hipEventRecord(a, s));
+  for (int r = 0; r < reps; ++r) NV_TRY(check_launch(launch(), "autotune"));
+  HIP_TRY(hipEventRecord(b, s));
+  HIP_TRY(hipEventSynchronize(b));
+  float t = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&t, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = t / reps;
+  return NV_OK;
+}
+
+}  // namespace
+
+extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* stream, char* report,
+                                 size_t report_len) {
+  if (!ctx) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(check_dims(hp, wp));
+  const char* cache = getenv("NNVISR_TUNE_CACHE");
+  char key[128];
+  snprintf(key, sizeof key, "prec=%d C=%d R=%d size=%dx%d", ctx->cfg.precision, ctx->C, ctx->cfg.res_blocks,
+           wp, hp);
+  std::string rep;
+  bool found = false;
+  if (cache) {
+    if (FILE* f = fopen(cache, "r")) {
+      char line[256];
+      while (fgets(line, sizeof line, f)) {
+        int a = 0, b = 0, c = 0;
+        char k2[128];
+        if (sscanf(line, "%127[^|]| %d %d %d", k2, &a, &b, &c) == 4) {
+          std::string ks(k2);
+          while (!ks.empty() && ks.back() == ' ') ks.pop_back();
+          if (ks == key && a > 0 && b > 0 && c > 0) {
+            ctx->tune.pb_block = a;
+            ctx->tune.pb_up = b;
+            ctx->tune.pb_dcn = c;
+            found = true;
+          }
+        }
+      }
+      fclose(f);
+    }
+  }
+  if (!found) {
+    NV_TRY(ensure_workspace(ctx, hp, wp));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& ws = ctx->ws;
+    const int C = ctx->C, ft = ctx->ft;
+    // inputs for the timing runs: zero offsets keep every DCN sample inside the frame
+    HIP_TRY(hipMemsetAsync(ws.feat[0], 0, (size_t)hp * wp * C * dtype_bytes(ft), s));
+    HIP_TRY(hipMemsetAsync(ws.offs, 0, (size_t)hp * wp * ctx->ldo * 4, s));
+    char buf[256];
+    struct Cand {
+      const char* name;
+      int* slot;
+      std::vector<int> pbs;
+    } cands[3] = {{"block", &ctx->tune.pb_block, {1, 2, 4}}, {"up", &ctx->tune.pb_up, {1, 2, 4}},
+                  {"dcn", &ctx->tune.pb_dcn, {1, 2}}};
+    for (auto& cd : cands) {
+      float best = 1e30f;
+      int best_pb = *cd.slot;
+      rep += cd.name;
+      rep += ":";
+      for (int pb : cd.pbs) {
+        float ms = 0.0f;
+        nv_status st;
+        if (cd.slot == &ctx->tune.pb_block) {
+          const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
+          st = time_launch(s, 3, &ms, [&] {
+            return launch_conv(ctx->blocks.empty() ? ctx->up : ctx->blocks[0], CONV_BULK,
+                               ctx->blocks.empty() ? EPI_SHUFFLE : EPI_LRELU, ft, pb, im,
+                               ctx->blocks.empty() ? 4 * C : C, 0, s);
+          });
+        } else if (cd.slot == &ctx->tune.pb_up) {
+          const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.u, hp, wp);
+          st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, pb, im, 4 * C, 0, s); });
+        } else {
+          DcnImg di;
+          di.fa = ws.feat[0];
+          di.fb = ws.feat[0];
+          di.sel = nullptr;
+          di.offs = ws.offs;
+          di.dst = ws.fmid;
+          di.H = hp;
+          di.W = wp;
+          di.item_begin = 0;
+          st = time_launch(s, 3, &ms, [&] { return launch_dcn(ctx->dcn, ft, pb, di, ctx->ldo, ctx->G, s); });
+        }
+        if (st != NV_OK) return st;
+        snprintf(buf, sizeof buf, " pb%d=%.1fus", pb, 1000.0f * ms);
+        rep += buf;
+        if (ms < best) {
+          best = ms;
+          best_pb = pb;
+        }
+      }
+      *cd.slot = best_pb;
+      snprintf(buf, sizeof buf, " -> pb%d; ", best_pb);
+      rep += buf;
+    }
+    if (cache) {
+      if (FILE* f = fopen(cache, "a")) {
+        fprintf(f, "%s | %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn);
+        fclose(f);
+      }
+    }
+  } else {
+    rep = "from cache: ";
+    rep += key;
+  }
+  char tail[96];
+  snprintf(tail, sizeof tail, " [block pb%d, up pb%d, dcn pb%d]", ctx->tune.pb_block, ctx->tune.pb_up,
+           ctx->tune.pb_dcn);
+  rep += tail;
+  if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
+    HIP_TRY(hipDeviceSynchronize());
+    (void)hipGraphExecDestroy(ctx->batch->exec);
+    ctx->batch->exec = nullptr;
+  }
+  if (report && report_len > 0) snprintf(report, report_len, "%s", rep.c_str());
   return NV_OK;
 }
 

@@ -1,36 +1,26 @@
 // Network kernels (gfx950): 3x3 convolutions as implicit GEMM on MFMA, the modulated
-// deformable convolution with its bilinear gather fused into the B-operand load, and
-// the two thin convolutions (3 -> C in, C -> 3 out) on the vector ALUs.
+// deformable convolution with its bilinear gather staged through LDS, the thin output
+// conv as MFMA "tap responses", and the 3 -> C input conv on the vector ALUs.
 //
-// Activations are NHWC float32.  A workgroup owns a tile of TH x 16 output pixels
-// (TH = 4 waves x PB rows) and OB blocks of 16 output channels.  In the MFMA the
-// weights are the A operand (rows = output channels) and the activations the B
-// operand (columns = the 16 pixels of one tile row), so each lane ends up holding four
-// consecutive output channels of one pixel: one 16-byte store per accumulator.
-//
-// The reduction index K = (tap, input channel) is consumed in groups of 16 channels;
-// within a group, lane quarter q takes channels 4q..4q+3 over the four k-steps, so the
-// B operand of four MFMAs is one 16-byte LDS read and the A operand one 16-byte global
-// read (weights are pre-arranged in exactly that fragment order).
-#include "nv_device.h"
+// Activations are NHWC.  A workgroup owns a tile of TH x 16 output pixels (TH = 4 waves
+// x PB rows) and OB blocks of 16 output channels.  In the MFMA the weights are the A
+// operand (rows = output channels) and the activations the B operand (columns = the
+// 16 pixels of one tile row), so each lane ends up holding four consecutive output
+// channels of one pixel.  Storage type (TIN / TOUT) and MFMA type (TC) are template
+// parameters: float end to end, or float16 / bfloat16 storage and MFMA with float
+// accumulation; the offset head reads 16-bit features and computes in float.
 #include "nv_internal.h"
+#include "nv_mma.h"
 
 namespace nv {
 namespace {
 
 constexpr int kTW = 16;
 
-struct ConvArgs {
-  const float* src0;
-  const float* src1;
-  const uint32_t* sel;   // when non-null and *sel != 0, alt0/alt1 (if set) replace src0/src1
-  const float* alt0;
-  const float* alt1;
-  const f32x4* wfrag;
+// Arguments shared by every image of a conv launch.
+struct ConvLayer {
+  const u32x4* wfrag;
   const float* bias;
-  const float* res;
-  float* dst;
-  int H, W;
   int ldy;      // channel stride of dst / res
   int cout;     // real output channels (EPI_OFFSET stores only these)
   int sig_lo;   // EPI_OFFSET: sigmoid on channels >= sig_lo
@@ -38,20 +28,38 @@ struct ConvArgs {
   int ccout;    // EPI_SHUFFLE: channels of the high-resolution map
 };
 
-template <int CCH, int NCHUNK, int OB, int PB, int EPI>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-  constexpr int TH = 4 * PB;
-  constexpr int LDP = CCH + 4;                 // padded pixel stride in LDS (floats)
-  constexpr int NKG = NCHUNK * CCH / 16;       // 16-channel groups over all chunks
-  __shared__ __attribute__((aligned(16))) float tile[(TH + 2) * (kTW + 2) * LDP];
+// Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
+template <class J>
+__device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename TC, int CCH, int PB>
+struct ConvSmem {
+  static constexpr int TH = 4 * PB;
+  static constexpr int LDP = CCH + 16 / (int)sizeof(TC);   // LDS pixel stride (16-byte pad)
+  static constexpr int N = (TH + 2) * (kTW + 2) * LDP;
+};
+
+// One output tile: rows [ty0, ty0 + 4 PB), columns [tx0, tx0 + 16), output blocks
+// [obase, obase + OB).  Called by all 256 threads; contains block-wide barriers.
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+__device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im, int ty0, int tx0,
+                                          int obase, TC* tile) {
+  constexpr int KG = Mma<TC>::KG;           // channels per MFMA step group
+  constexpr int QE = KG / 4;                // channels per lane quarter
+  constexpr int LDP = ConvSmem<TC, CCH, PB>::LDP;
+  constexpr int NCG = CCH / KG;
+  constexpr int NKG = NCHUNK * NCG;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
-  const int tiles_x = (a.W + kTW - 1) / kTW;
-  const int ntile = tiles_x * ((a.H + TH - 1) / TH);
-  const int t = xcd_tile(blockIdx.x, ntile);
-  const int ty0 = (t / tiles_x) * TH, tx0 = (t % tiles_x) * kTW;
-  const int obase = blockIdx.y * OB;
 
   f32x4 acc[PB][OB];
 #pragma unroll
@@ -59,61 +67,59 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
 
-  const float* src0 = a.src0;
-  const float* src1 = a.src1;
-  if (a.sel != nullptr && *a.sel != 0u) {
-    if (a.alt0 != nullptr) src0 = a.alt0;
-    if (a.alt1 != nullptr) src1 = a.alt1;
+  const TIN* src0 = static_cast<const TIN*>(im.src0);
+  const TIN* src1 = static_cast<const TIN*>(im.src1);
+  if (im.sel != nullptr && *im.sel != 0u) {
+    if (im.alt0 != nullptr) src0 = static_cast<const TIN*>(im.alt0);
+    if (im.alt1 != nullptr) src1 = static_cast<const TIN*>(im.alt1);
   }
 
 #pragma unroll
   for (int ch = 0; ch < NCHUNK; ++ch) {
-    const float* src = ch == 0 ? src0 : src1;
+    const TIN* src = ch == 0 ? src0 : src1;
     if (ch) __syncthreads();
-    constexpr int V = CCH / 4;
-    constexpr int NV = (TH + 2) * (kTW + 2) * V;
+    constexpr int V = CCH / 8;
+    constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
     for (int idx = threadIdx.x; idx < NV; idx += 256) {
       const int pix = idx / V, v = idx - pix * V;
       const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
       const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-      f32x4 val = zero4();
-      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-        val = ld4(src + ((size_t)gy * a.W + gx) * CCH + 4 * v);
-      st4(&tile[pix * LDP + 4 * v], val);
+      TC* dstp = &tile[pix * LDP + 8 * v];
+      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W)
+        copy8<TIN, TC>(dstp, src + ((size_t)gy * im.W + gx) * CCH + 8 * v);
+      else
+        zero8<TC>(dstp);
     }
     __syncthreads();
 
-    // (tap, 16-channel group) steps, software-pipelined: the A fragments (global) and
+    // (tap, channel group) steps, software-pipelined: the A fragments (global) and
     // B fragments (LDS) of step i+1 are in flight while the MFMAs of step i issue.
-    constexpr int NCG = CCH / 16;
     constexpr int NIT = 9 * NCG;
-    const f32x4* wbase = a.wfrag + ((size_t)(ch * NCG) * a.obtot + obase) * 64 + lane;
-    const size_t wstride_tap = (size_t)NKG * a.obtot * 64;
-    const float* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + 4 * q];
-    f32x4 wa[OB], xb[PB];
+    const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * L.obtot + obase) * 64 + lane;
+    const size_t wstride_tap = (size_t)NKG * L.obtot * 64;
+    const TC* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + QE * q];
+    u32x4 wa[OB], xb[PB];
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) xb[pb] = ld4(tbase + pb * (kTW + 2) * LDP);
+    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(tbase + pb * (kTW + 2) * LDP);
 #pragma unroll 3
     for (int it = 0; it < NIT; ++it) {
-      f32x4 wn[OB], xn[PB];
+      u32x4 wn[OB], xn[PB];
       if (it + 1 < NIT) {
         const int tap = (it + 1) / NCG, cg = (it + 1) - tap * NCG;
         const int dy = tap / 3, dx = tap - 3 * dy;
-        const f32x4* wp = wbase + tap * wstride_tap + (size_t)cg * a.obtot * 64;
+        const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * L.obtot * 64;
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) wn[ob] = wp[ob * 64];
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
-          xn[pb] = ld4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + 16 * cg);
+          xn[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
       }
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
+      for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-          for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = mfma4(wa[ob][kk], xb[pb][kk], acc[pb][ob]);
+        for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
       if (it + 1 < NIT) {
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
@@ -123,65 +129,102 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     }
   }
 
+  TOUT* dst = static_cast<TOUT*>(im.dst);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
     const int gy = ty0 + wave * PB + pb, gx = tx0 + j;
-    if (gy >= a.H || gx >= a.W) continue;
+    if (gy >= im.H || gx >= im.W) continue;
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int row = (obase + ob) * 16 + 4 * q;
-      f32x4 v = acc[pb][ob] + ld4(a.bias + row);
+      f32x4 v = acc[pb][ob] + ld4(L.bias + row);
+      const size_t at = ((size_t)gy * im.W + gx) * L.ldy + row;
       if (EPI == EPI_LRELU) {
-        v = f32x4{lrelu(v[0]), lrelu(v[1]), lrelu(v[2]), lrelu(v[3])};
-        st4(a.dst + ((size_t)gy * a.W + gx) * a.ldy + row, v);
+        store4f<TOUT>(dst + at, lrelu4(v));
       } else if (EPI == EPI_RES) {
-        float* p = a.dst + ((size_t)gy * a.W + gx) * a.ldy + row;
-        v += ld4(a.res + ((size_t)gy * a.W + gx) * a.ldy + row);
-        st4(p, v);
+        v += load4f<TOUT>(static_cast<const TOUT*>(im.res) + at);
+        store4f<TOUT>(dst + at, v);
       } else if (EPI == EPI_OFFSET) {
-        float* p = a.dst + ((size_t)gy * a.W + gx) * a.ldy + row;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = row + r;
-          if (o < a.cout) p[r] = o >= a.sig_lo ? sigmoidf(v[r]) : v[r];
+          if (o < L.cout) dst[at + r] = (TOUT)(o >= L.sig_lo ? sigmoidf(v[r]) : v[r]);
         }
       } else {  // EPI_SHUFFLE: A row 16*ob + t is channel 16*(ob/4) + t at sub-pixel ob%4
         const int obg = obase + ob;
         const int sp = obg & 3, c = 16 * (obg >> 2) + 4 * q;
         const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
-        v = f32x4{lrelu(v[0]), lrelu(v[1]), lrelu(v[2]), lrelu(v[3])};
-        st4(a.dst + ((size_t)Y * (2 * a.W) + X) * a.ccout + c, v);
+        store4f<TOUT>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
       }
     }
   }
 }
 
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvLayer L, ConvImg im) {
+  __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
+  const int tiles_x = (im.W + kTW - 1) / kTW;
+  const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
+  const int t = xcd_tile(blockIdx.x, ntile);
+  conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
+                                                      blockIdx.y * OB, tile);
+}
+
+// Persistent form: item = (tile, output-block group) of one image of the job table.
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvImg* __restrict__ jobs,
+                                                       const int* __restrict__ count) {
+  __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
+  const int njobs = count[0], total = count[1];
+  const int nobg = L.obtot / OB;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const ConvImg im = jobs[find_job(jobs, njobs, item)];
+    const int local = item - im.item_begin;
+    const int t = local / nobg, obg = local - t * nobg;
+    const int tiles_x = (im.W + kTW - 1) / kTW;
+    conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
+                                                        obg * OB, tile);
+    __syncthreads();
+  }
+}
+
 // ---- modulated deformable conv, stride 1, pad 1, 3x3, over cat(fa, fb) ----
-struct DcnArgs {
-  const float* fa;
-  const float* fb;
-  const uint32_t* sel;
-  const float* offs;
-  const f32x4* wfrag;
+// Per tap, two phases over a TH x 16 pixel tile:
+//  gather: one work item per (pixel, offset group) computes the sampling position and
+//          the four bilinear weights once (float), reads the group's channels at the
+//          four corners (vectors of the NHWC maps), scales by the mask and writes the
+//          modulated samples S[pixel][channel] to LDS in the MFMA type;
+//  MFMA:   the tile's S (2C channels) times the tap's weights, accumulated over taps.
+struct DcnLayer {
+  const u32x4* wfrag;
   const float* bias;
-  float* dst;
-  int H, W, ldo, groups, obtot;
+  int ldo, groups, obtot;
 };
 
-template <int C, int PB>
-__global__ __launch_bounds__(256) void k_dcn(DcnArgs a) {
+template <typename TC, int C, int PB>
+struct DcnSmem {
+  static constexpr int LDS_P = 2 * C + 16 / (int)sizeof(TC);
+  static constexpr int N = 4 * PB * kTW * LDS_P;
+};
+
+template <typename TF, typename TC, int C, int PB>
+__device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, int ty0, int tx0, TC* S) {
   constexpr int TH = 4 * PB;
   constexpr int OB = C / 16;
-  constexpr int NKG = 2 * C / 16;
+  constexpr int CIN = 2 * C;
+  constexpr int KG = Mma<TC>::KG;
+  constexpr int QE = KG / 4;
+  constexpr int NKG = CIN / KG;
+  constexpr int NPX = TH * kTW;
+  constexpr int LDS_P = DcnSmem<TC, C, PB>::LDS_P;
+
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
-  const int tiles_x = (a.W + kTW - 1) / kTW;
-  const int ntile = tiles_x * ((a.H + TH - 1) / TH);
-  const int t = xcd_tile(blockIdx.x, ntile);
-  const int ty0 = (t / tiles_x) * TH, tx0 = (t % tiles_x) * kTW;
-  const int cpg = 2 * C / a.groups;          // channels per offset group
-  const int G = a.groups;
-  const float* fb = (a.sel != nullptr && *a.sel != 0u) ? a.fa : a.fb;
+  const int G = L.groups;
+  const int cpg = CIN / G;                   // channels per offset group (multiple of 4)
+  const TF* fa = static_cast<const TF*>(im.fa);
+  const TF* fb = (im.sel != nullptr && *im.sel != 0u) ? fa : static_cast<const TF*>(im.fb);
+  const float hmax = (float)im.H, wmax = (float)im.W;
 
   f32x4 acc[PB][OB];
 #pragma unroll
@@ -189,89 +232,126 @@ __global__ __launch_bounds__(256) void k_dcn(DcnArgs a) {
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
 
-  // per-pixel offset rows (clamped for rows/columns past the image; results discarded)
-  const float* orow[PB];
-  int gys[PB];
-  const int gx = tx0 + j;
-#pragma unroll
-  for (int pb = 0; pb < PB; ++pb) {
-    gys[pb] = ty0 + wave * PB + pb;
-    orow[pb] = a.offs + ((size_t)min(gys[pb], a.H - 1) * a.W + min(gx, a.W - 1)) * a.ldo;
-  }
-  const float hmax = (float)a.H, wmax = (float)a.W;
+  const TC* sbase = &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
 
   for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-#pragma unroll 2
-    for (int kg = 0; kg < NKG; ++kg) {
-      const int cgl = 16 * kg + 4 * q;                 // channel in cat(fa, fb)
-      const float* src = cgl < C ? a.fa : fb;
-      const int cl = cgl < C ? cgl : cgl - C;
-      const int g = cgl / cpg;
-      const f32x4* wp = a.wfrag + ((size_t)(tap * NKG + kg) * a.obtot) * 64 + lane;
-      f32x4 wa[OB];
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    if (tap) __syncthreads();
+    for (int item = threadIdx.x; item < NPX * G; item += 256) {
+      const int p = item / G, g = item - p * G;
+      const int gy = ty0 + p / kTW, gx = tx0 + (p % kTW);
+      TC* sp = &S[p * LDS_P + g * cpg];
+      if (gy >= im.H || gx >= im.W) {
+        for (int v = 0; v < cpg; v += 4) store4f<TC>(sp + v, zero4());
+        continue;
+      }
+      const float* orow = im.offs + ((size_t)gy * im.W + gx) * L.ldo;
+      const float dyo = orow[2 * (9 * g + tap)];
+      const float dxo = orow[2 * (9 * g + tap) + 1];
+      const float m = orow[18 * G + 9 * g + tap];
+      // beyond one pixel outside the map every sample is zero; the clamp keeps the
+      // integer conversion defined for any offset value
+      const float py = fminf(fmaxf((float)(gy + ky - 1) + dyo, -2.0f), hmax + 1.0f);
+      const float px = fminf(fmaxf((float)(gx + kx - 1) + dxo, -2.0f), wmax + 1.0f);
+      const float y0f = floorf(py), x0f = floorf(px);
+      const float ly = py - y0f, lx = px - x0f;
+      const int y0 = (int)y0f, x0 = (int)x0f;
+      const int c0 = g * cpg;
+      const TF* src = c0 < C ? fa : fb;
+      const int cl = c0 < C ? c0 : c0 - C;
+      float wgt[4];
+      const TF* cp[4];
+      int nc = 0;
 #pragma unroll
-      for (int ob = 0; ob < OB; ++ob) wa[ob] = wp[ob * 64];
-      f32x4 xb[PB];
+      for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) {
-        const float dyo = orow[pb][2 * (9 * g + tap)];
-        const float dxo = orow[pb][2 * (9 * g + tap) + 1];
-        const float m = orow[pb][18 * G + 9 * g + tap];
-        // positions beyond one pixel outside the map sample only zeros; clamp so the
-        // integer conversion below stays defined for any offset value
-        const float py = fminf(fmaxf((float)(gys[pb] + ky - 1) + dyo, -2.0f), hmax + 1.0f);
-        const float px = fminf(fmaxf((float)(gx + kx - 1) + dxo, -2.0f), wmax + 1.0f);
-        const float y0f = floorf(py), x0f = floorf(px);
-        const float ly = py - y0f, lx = px - x0f;
-        const int y0 = (int)y0f, x0 = (int)x0f;
-        f32x4 v = zero4();
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy) {
-          const int yy = y0 + cy;
-          const float wy = cy ? ly : 1.0f - ly;
-#pragma unroll
-          for (int cx = 0; cx < 2; ++cx) {
-            const int xx = x0 + cx;
-            const float wx = cx ? lx : 1.0f - lx;
-            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-              v += (wy * wx) * ld4(src + ((size_t)yy * a.W + xx) * C + cl);
+        for (int cx = 0; cx < 2; ++cx) {
+          const int yy = y0 + cy, xx = x0 + cx;
+          if (yy >= 0 && yy < im.H && xx >= 0 && xx < im.W) {
+            wgt[nc] = (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m;
+            cp[nc] = src + ((size_t)yy * im.W + xx) * C + cl;
+            ++nc;
           }
         }
-        xb[pb] = v * m;
+      for (int v = 0; v < cpg; v += 4) {
+        f32x4 val = zero4();
+        for (int k = 0; k < nc; ++k) val += wgt[k] * load4f<TF>(cp[k] + v);
+        store4f<TC>(sp + v, val);
       }
+    }
+    __syncthreads();
+
+    const u32x4* wbase = L.wfrag + ((size_t)tap * NKG * L.obtot) * 64 + lane;
+    u32x4 wa[OB];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
+    for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
+#pragma unroll 2
+    for (int kg = 0; kg < NKG; ++kg) {
+      u32x4 wn[OB];
+      if (kg + 1 < NKG) {
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
+        for (int ob = 0; ob < OB; ++ob) wn[ob] = wbase[((size_t)(kg + 1) * L.obtot + ob) * 64];
+      }
+      u32x4 xb[PB];
 #pragma unroll
-          for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = mfma4(wa[ob][kk], xb[pb][kk], acc[pb][ob]);
+      for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(sbase + pb * kTW * LDS_P + KG * kg);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
+      if (kg + 1 < NKG) {
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
+      }
     }
   }
 
+  TF* dst = static_cast<TF*>(im.dst);
+  const int gx = tx0 + j;
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
-    if (gys[pb] >= a.H || gx >= a.W) continue;
+    const int gy = ty0 + wave * PB + pb;
+    if (gy >= im.H || gx >= im.W) continue;
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int row = ob * 16 + 4 * q;
-      f32x4 v = acc[pb][ob] + ld4(a.bias + row);
-      v = f32x4{lrelu(v[0]), lrelu(v[1]), lrelu(v[2]), lrelu(v[3])};
-      st4(a.dst + ((size_t)gys[pb] * a.W + gx) * C + row, v);
+      const f32x4 v = acc[pb][ob] + ld4(L.bias + row);
+      store4f<TF>(dst + ((size_t)gy * im.W + gx) * C + row, lrelu4(v));
     }
   }
 }
 
-// ---- first conv 3 -> C on the vector ALUs: planar RGB in, NHWC out, LReLU ----
+template <typename TF, typename TC, int C, int PB>
+__global__ __launch_bounds__(256) void k_dcn(DcnLayer L, DcnImg im) {
+  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, C, PB>::N];
+  const int tiles_x = (im.W + kTW - 1) / kTW;
+  const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
+  const int t = xcd_tile(blockIdx.x, ntile);
+  dcn_tile<TF, TC, C, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
+}
+
+template <typename TF, typename TC, int C, int PB>
+__global__ __launch_bounds__(256) void k_dcn_batch(DcnLayer L, const DcnImg* __restrict__ jobs,
+                                                   const int* __restrict__ count) {
+  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, C, PB>::N];
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const DcnImg im = jobs[find_job(jobs, njobs, item)];
+    const int t = item - im.item_begin;
+    const int tiles_x = (im.W + kTW - 1) / kTW;
+    dcn_tile<TF, TC, C, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
+    __syncthreads();
+  }
+}
+
+// ---- first conv 3 -> C on the vector ALUs: planar float RGB in, NHWC out, LReLU ----
 // blockIdx.y selects 16 output channels, so every weight read is uniform (scalar loads).
-__global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb,
-                                                 const float* __restrict__ w,
-                                                 const float* __restrict__ b,
-                                                 float* __restrict__ dst, int H, int W, int C) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
+template <typename TOUT>
+__device__ __forceinline__ void conv_in_px(const float* __restrict__ rgb, const float* __restrict__ w,
+                                           const float* __restrict__ b, TOUT* __restrict__ dst, int H,
+                                           int W, int C, int p, int o0) {
   if (p >= H * W) return;
   const int y = p / W, x = p - y * W;
-  const int o0 = blockIdx.y * 16;
   const size_t plane = (size_t)H * W;
   float in[27];
 #pragma unroll
@@ -293,12 +373,38 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb,
     for (int k = 0; k < 27; ++k) s = fmaf(wo[k], in[k], s);
     out[o] = lrelu(s);
   }
-  float* d = dst + (size_t)p * C + o0;
+  TOUT* d = dst + (size_t)p * C + o0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) st4(d + 4 * v, f32x4{out[4 * v], out[4 * v + 1], out[4 * v + 2], out[4 * v + 3]});
+  for (int v = 0; v < 4; ++v)
+    store4f<TOUT>(d + 4 * v, f32x4{out[4 * v], out[4 * v + 1], out[4 * v + 2], out[4 * v + 3]});
 }
 
-// ---- HR conv C -> 3 plus the bilinear x2 base, planar RGB out ----
+template <typename TOUT>
+__global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb,
+                                                 const float* __restrict__ w,
+                                                 const float* __restrict__ b,
+                                                 TOUT* __restrict__ dst, int H, int W, int C) {
+  conv_in_px<TOUT>(rgb, w, b, dst, H, W, C, blockIdx.x * 256 + threadIdx.x, blockIdx.y * 16);
+}
+
+// Persistent form: item = (256-pixel block, 16-channel block) of one image.
+template <typename TOUT>
+__global__ __launch_bounds__(256) void k_conv_in_batch(const float* __restrict__ w,
+                                                       const float* __restrict__ b, int C,
+                                                       const ConvInImg* __restrict__ jobs,
+                                                       const int* __restrict__ count) {
+  const int njobs = count[0], total = count[1];
+  const int ncb = C / 16;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const ConvInImg& im = jobs[find_job(jobs, njobs, item)];
+    const int local = item - im.item_begin;
+    const int pblk = local / ncb, cb = local - pblk * ncb;
+    conv_in_px<TOUT>(im.rgb, w, b, static_cast<TOUT*>(im.dst), im.H, im.W, C, pblk * 256 + threadIdx.x,
+                     cb * 16);
+  }
+}
+
+// ---- HR conv C -> 3 plus the bilinear x2 base, planar float RGB out ----
 // The thin output conv is computed as "tap responses": R[3*tap + o][p] =
 // sum_c w[o][c][tap] U[c][p] is a 27-row (padded to 32) by C product on MFMA, taken over
 // every pixel of a 16x16 output tile and its one-pixel halo and kept in LDS; each
@@ -315,51 +421,42 @@ __device__ __forceinline__ float up2_sample(const float* pl, int H, int W, int Y
   return 0.75f * r0 + 0.25f * r1;
 }
 
-struct HrArgs {
-  const float* u;        // [2H][2W][C]
-  const f32x4* wfrag;    // [C/16][2][64] fragments of the 32 x C response matrix
+struct HrLayer {
+  const u32x4* wfrag;    // [C/KG][2][64] fragments of the 32 x C response matrix
   const float* bias;     // [3]
-  const float* rgb_a;
-  const float* rgb_b;
-  const uint32_t* sel;
-  float* dst;            // [3][2H][2W]
-  int H, W, tsel;
 };
 
-template <int C>
-__global__ __launch_bounds__(256) void k_hr(HrArgs a) {
-  constexpr int T = 16, RW = T + 2, NP = RW * RW, NPB = (NP + 15) / 16, LDR = 33;
-  constexpr int NCG = C / 16;
-  __shared__ float R[NPB * 16 * LDR];
-  const int H2 = 2 * a.H, W2 = 2 * a.W;
-  const int tiles_x = (W2 + T - 1) / T;
-  const int ntile = tiles_x * ((H2 + T - 1) / T);
-  const int t = xcd_tile(blockIdx.x, ntile);
-  const int ty0 = (t / tiles_x) * T, tx0 = (t % tiles_x) * T;
+constexpr int kHrT = 16, kHrRW = kHrT + 2, kHrNP = kHrRW * kHrRW, kHrNPB = (kHrNP + 15) / 16,
+              kHrLDR = 33;
+
+template <typename TU, int C>
+__device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int ty0, int tx0, float* R) {
+  constexpr int T = kHrT, RW = kHrRW, NP = kHrNP, NPB = kHrNPB, LDR = kHrLDR;
+  constexpr int KG = Mma<TU>::KG, QE = KG / 4, NCG = C / KG;
+  const int H2 = 2 * im.H, W2 = 2 * im.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
+  const TU* u = static_cast<const TU*>(im.u);
 
-  f32x4 wa[NCG][2];
+  u32x4 wa[NCG][2];
 #pragma unroll
   for (int cg = 0; cg < NCG; ++cg) {
-    wa[cg][0] = a.wfrag[(cg * 2 + 0) * 64 + lane];
-    wa[cg][1] = a.wfrag[(cg * 2 + 1) * 64 + lane];
+    wa[cg][0] = L.wfrag[(cg * 2 + 0) * 64 + lane];
+    wa[cg][1] = L.wfrag[(cg * 2 + 1) * 64 + lane];
   }
+  const u32x4 zero = {0u, 0u, 0u, 0u};
   for (int pbk = wave; pbk < NPB; pbk += 4) {
     const int p = pbk * 16 + j;
     const int ry = p / RW, rx = p - ry * RW;
     const int Y = ty0 + ry - 1, X = tx0 + rx - 1;
     const bool ok = p < NP && Y >= 0 && Y < H2 && X >= 0 && X < W2;
-    const float* up = a.u + ((size_t)(ok ? Y : 0) * W2 + (ok ? X : 0)) * C + 4 * q;
+    const TU* up = u + ((size_t)(ok ? Y : 0) * W2 + (ok ? X : 0)) * C + QE * q;
     f32x4 acc0 = zero4(), acc1 = zero4();
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
-      const f32x4 xb = ok ? ld4(up + 16 * cg) : zero4();
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        acc0 = mfma4(wa[cg][0][kk], xb[kk], acc0);
-        acc1 = mfma4(wa[cg][1][kk], xb[kk], acc1);
-      }
+      const u32x4 xb = ok ? ldu4(up + KG * cg) : zero;
+      acc0 = Mma<TU>::step(wa[cg][0], xb, acc0);
+      acc1 = Mma<TU>::step(wa[cg][1], xb, acc1);
     }
     float* rp = &R[p * LDR];
 #pragma unroll
@@ -372,7 +469,7 @@ __global__ __launch_bounds__(256) void k_hr(HrArgs a) {
   const int ly = threadIdx.x / T, lx = threadIdx.x - ly * T;
   const int Y = ty0 + ly, X = tx0 + lx;
   if (Y >= H2 || X >= W2) return;
-  float s0 = a.bias[0], s1 = a.bias[1], s2 = a.bias[2];
+  float s0 = L.bias[0], s1 = L.bias[1], s2 = L.bias[2];
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3, dx = tap - 3 * dy;
@@ -381,129 +478,276 @@ __global__ __launch_bounds__(256) void k_hr(HrArgs a) {
     s1 += rp[1];
     s2 += rp[2];
   }
-  const size_t lpl = (size_t)a.H * a.W, hpl = (size_t)H2 * W2;
-  const float* rb = (a.sel != nullptr && *a.sel != 0u) ? a.rgb_a : a.rgb_b;
+  const size_t lpl = (size_t)im.H * im.W, hpl = (size_t)H2 * W2;
+  const float* rb = (im.sel != nullptr && *im.sel != 0u) ? im.rgb_a : im.rgb_b;
   float base[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (a.tsel == 0) base[c] = up2_sample(a.rgb_a + c * lpl, a.H, a.W, Y, X);
-    else if (a.tsel == 1) base[c] = up2_sample(rb + c * lpl, a.H, a.W, Y, X);
-    else base[c] = 0.5f * (up2_sample(a.rgb_a + c * lpl, a.H, a.W, Y, X) + up2_sample(rb + c * lpl, a.H, a.W, Y, X));
+    if (im.tsel == 0) base[c] = up2_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X);
+    else if (im.tsel == 1) base[c] = up2_sample(rb + c * lpl, im.H, im.W, Y, X);
+    else base[c] = 0.5f * (up2_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X) + up2_sample(rb + c * lpl, im.H, im.W, Y, X));
   }
-  a.dst[(size_t)Y * W2 + X] = s0 + base[0];
-  a.dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
-  a.dst[2 * hpl + (size_t)Y * W2 + X] = s2 + base[2];
+  im.dst[(size_t)Y * W2 + X] = s0 + base[0];
+  im.dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
+  im.dst[2 * hpl + (size_t)Y * W2 + X] = s2 + base[2];
 }
 
-template <int CCH, int NCHUNK, int OB, int PB, int EPI>
-hipError_t run_conv(const ConvArgs& a, hipStream_t s) {
-  constexpr int TH = 4 * PB;
-  const int ntile = ((a.W + kTW - 1) / kTW) * ((a.H + TH - 1) / TH);
-  const dim3 grid(ntile, a.obtot / OB);
-  hipLaunchKernelGGL((k_conv3x3<CCH, NCHUNK, OB, PB, EPI>), grid, dim3(256), 0, s, a);
+template <typename TU, int C>
+__global__ __launch_bounds__(256) void k_hr(HrLayer L, HrImg im) {
+  __shared__ float R[kHrNPB * 16 * kHrLDR];
+  const int tiles_x = (2 * im.W + kHrT - 1) / kHrT;
+  const int ntile = tiles_x * ((2 * im.H + kHrT - 1) / kHrT);
+  const int t = xcd_tile(blockIdx.x, ntile);
+  hr_tile<TU, C>(L, im, (t / tiles_x) * kHrT, (t % tiles_x) * kHrT, R);
+}
+
+template <typename TU, int C>
+__global__ __launch_bounds__(256) void k_hr_batch(HrLayer L, const HrImg* __restrict__ jobs,
+                                                  const int* __restrict__ count) {
+  __shared__ float R[kHrNPB * 16 * kHrLDR];
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const HrImg im = jobs[find_job(jobs, njobs, item)];
+    const int t = item - im.item_begin;
+    const int tiles_x = (2 * im.W + kHrT - 1) / kHrT;
+    hr_tile<TU, C>(L, im, (t / tiles_x) * kHrT, (t % tiles_x) * kHrT, R);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- dispatch ----
+
+// A launcher for one (types, shape, epilogue) instance, single image or batched.
+struct ConvCall {
+  const ConvLayer& L;
+  const ConvImg* im;          // single image (by value into the kernel) ...
+  const ConvImg* jobs;        // ... or a device job table with its count
+  const int* count;
+  hipStream_t s;
+};
+
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+hipError_t run_conv(const ConvCall& c) {
+  if (c.im) {
+    const int ntile = ((c.im->W + kTW - 1) / kTW) * ((c.im->H + 4 * PB - 1) / (4 * PB));
+    const dim3 grid(ntile, c.L.obtot / OB);
+    hipLaunchKernelGGL((k_conv3x3<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>), grid, dim3(256), 0, c.s, c.L,
+                       *c.im);
+  } else {
+    hipLaunchKernelGGL((k_conv3x3_batch<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>), dim3(kBatchGrid), dim3(256),
+                       0, c.s, c.L, c.jobs, c.count);
+  }
   return hipGetLastError();
 }
 
-template <int CCH, int NCHUNK>
-hipError_t dispatch_epi(const ConvArgs& a, int epi, hipStream_t s) {
-  constexpr int PB = 2;
+template <typename T, int CCH, int PB>
+hipError_t conv_bulk_pb(const ConvCall& c, int epi) {
   switch (epi) {
     case EPI_LRELU:
-      if (a.obtot % 4 == 0) return run_conv<CCH, NCHUNK, 4, PB, EPI_LRELU>(a, s);
-      return run_conv<CCH, NCHUNK, 2, PB, EPI_LRELU>(a, s);
+      if (c.L.obtot % 4 == 0) return run_conv<T, T, T, CCH, 1, 4, PB, EPI_LRELU>(c);
+      return run_conv<T, T, T, CCH, 1, 2, PB, EPI_LRELU>(c);
     case EPI_RES:
-      if (a.obtot % 4 == 0) return run_conv<CCH, NCHUNK, 4, PB, EPI_RES>(a, s);
-      return run_conv<CCH, NCHUNK, 2, PB, EPI_RES>(a, s);
-    case EPI_OFFSET:
-      if (a.obtot % 7 == 0) return run_conv<CCH, NCHUNK, 7, PB, EPI_OFFSET>(a, s);
-      if (a.obtot % 4 == 0) return run_conv<CCH, NCHUNK, 4, PB, EPI_OFFSET>(a, s);
-      return run_conv<CCH, NCHUNK, 1, PB, EPI_OFFSET>(a, s);
-    case EPI_SHUFFLE: return run_conv<CCH, NCHUNK, 8, PB, EPI_SHUFFLE>(a, s);
+      if (c.L.obtot % 4 == 0) return run_conv<T, T, T, CCH, 1, 4, PB, EPI_RES>(c);
+      return run_conv<T, T, T, CCH, 1, 2, PB, EPI_RES>(c);
+    case EPI_SHUFFLE: return run_conv<T, T, T, CCH, 1, 8, PB, EPI_SHUFFLE>(c);
   }
   return hipErrorInvalidValue;
+}
+
+// Residual-block convs and the pixel-shuffle conv: storage and MFMA in T.
+template <typename T, int CCH>
+hipError_t conv_bulk(const ConvCall& c, int epi, int pb) {
+  if (pb == 1) return conv_bulk_pb<T, CCH, 1>(c, epi);
+  if (pb == 2) return conv_bulk_pb<T, CCH, 2>(c, epi);
+  if (pb == 4) return conv_bulk_pb<T, CCH, 4>(c, epi);
+  return hipErrorInvalidValue;
+}
+
+// Offset head: first conv reads the two feature maps (TIN) and computes in float.
+template <typename TIN, int CCH>
+hipError_t conv_off1(const ConvCall& c) {
+  if (c.L.obtot % 4 == 0) return run_conv<TIN, float, float, CCH, 2, 4, 2, EPI_LRELU>(c);
+  return run_conv<TIN, float, float, CCH, 2, 2, 2, EPI_LRELU>(c);
+}
+
+template <int CCH>
+hipError_t conv_off2(const ConvCall& c) {
+  if (c.L.obtot % 7 == 0) return run_conv<float, float, float, CCH, 1, 7, 2, EPI_OFFSET>(c);
+  if (c.L.obtot % 4 == 0) return run_conv<float, float, float, CCH, 1, 4, 2, EPI_OFFSET>(c);
+  return run_conv<float, float, float, CCH, 1, 1, 2, EPI_OFFSET>(c);
+}
+
+template <typename T>
+hipError_t conv_any(const ConvCall& c, int epi, int role, int cch, int pb) {
+  if (role == CONV_OFF1) {
+    if (cch == 64) return conv_off1<T, 64>(c);
+    if (cch == 32) return conv_off1<T, 32>(c);
+    return hipErrorInvalidValue;
+  }
+  if (cch == 64) return conv_bulk<T, 64>(c, epi, pb);
+  if (cch == 32) return conv_bulk<T, 32>(c, epi, pb);
+  return hipErrorInvalidValue;
+}
+
+hipError_t conv_dispatch(const PackedConv& P, int role, int epi, int tin, int pb, const ConvCall& c) {
+  if (role == CONV_OFF2) {
+    if (tin != DT_F32 || P.tc != DT_F32) return hipErrorInvalidValue;
+    if (P.cin == 64) return conv_off2<64>(c);
+    if (P.cin == 32) return conv_off2<32>(c);
+    return hipErrorInvalidValue;
+  }
+  const int cch = role == CONV_OFF1 ? P.cin / 2 : P.cin;
+  if (role == CONV_OFF1 && (P.tc != DT_F32 || pb != 2)) return hipErrorInvalidValue;
+  if (role != CONV_OFF1 && P.tc != tin) return hipErrorInvalidValue;
+  switch (tin) {
+    case DT_F32: return conv_any<float>(c, epi, role, cch, pb);
+    case DT_F16: return conv_any<f16>(c, epi, role, cch, pb);
+    case DT_BF16: return conv_any<bf16>(c, epi, role, cch, pb);
+  }
+  return hipErrorInvalidValue;
+}
+
+ConvLayer make_layer(const PackedConv& P, int ldy, int sig_lo) {
+  ConvLayer L;
+  L.wfrag = reinterpret_cast<const u32x4*>(P.frag);
+  L.bias = P.bias;
+  L.ldy = ldy;
+  L.cout = P.cout;
+  L.sig_lo = sig_lo;
+  L.obtot = P.obtot;
+  L.ccout = P.cout / 4;
+  return L;
+}
+
+template <typename TF, typename TC, int C, int PB>
+void run_dcn(const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count, hipStream_t s) {
+  if (im) {
+    const int ntile = ((im->W + kTW - 1) / kTW) * ((im->H + 4 * PB - 1) / (4 * PB));
+    hipLaunchKernelGGL((k_dcn<TF, TC, C, PB>), dim3(ntile), dim3(256), 0, s, L, *im);
+  } else {
+    hipLaunchKernelGGL((k_dcn_batch<TF, TC, C, PB>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
+  }
+}
+
+template <typename TF, int PB>
+hipError_t dcn_c(int C, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
+                 hipStream_t s) {
+  if (C == 64) run_dcn<TF, TF, 64, PB>(L, im, jobs, count, s);
+  else if (C == 32) run_dcn<TF, TF, 32, PB>(L, im, jobs, count, s);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t dcn_pb(int pb, int C, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
+                  hipStream_t s) {
+  if (pb == 1) return dcn_c<TF, 1>(C, L, im, jobs, count, s);
+  if (pb == 2) return dcn_c<TF, 2>(C, L, im, jobs, count, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t dcn_dispatch(const PackedConv& P, int tf, int pb, int ldo, int groups, const DcnImg* im,
+                        const DcnImg* jobs, const int* count, hipStream_t s) {
+  if (P.tc != tf) return hipErrorInvalidValue;
+  DcnLayer L;
+  L.wfrag = reinterpret_cast<const u32x4*>(P.frag);
+  L.bias = P.bias;
+  L.ldo = ldo;
+  L.groups = groups;
+  L.obtot = P.obtot;
+  switch (tf) {
+    case DT_F32: return dcn_pb<float>(pb, P.cout, L, im, jobs, count, s);
+    case DT_F16: return dcn_pb<f16>(pb, P.cout, L, im, jobs, count, s);
+    case DT_BF16: return dcn_pb<bf16>(pb, P.cout, L, im, jobs, count, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TU, int C>
+void run_hr(const HrLayer& L, const HrImg* im, const HrImg* jobs, const int* count, hipStream_t s) {
+  if (im) hipLaunchKernelGGL((k_hr<TU, C>), dim3(hr_items(im->H, im->W)), dim3(256), 0, s, L, *im);
+  else hipLaunchKernelGGL((k_hr_batch<TU, C>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
+}
+
+hipError_t hr_dispatch(const PackedConv& P, int tu, const HrImg* im, const HrImg* jobs, const int* count,
+                       hipStream_t s) {
+  if (P.tc != tu) return hipErrorInvalidValue;
+  HrLayer L;
+  L.wfrag = reinterpret_cast<const u32x4*>(P.frag);
+  L.bias = P.bias;
+  const int C = P.cin;
+#define NV_HR(TU) (C == 64 ? (run_hr<TU, 64>(L, im, jobs, count, s), true) : C == 32 ? (run_hr<TU, 32>(L, im, jobs, count, s), true) : false)
+  bool ok = false;
+  if (tu == DT_F32) ok = NV_HR(float);
+  else if (tu == DT_F16) ok = NV_HR(f16);
+  else if (tu == DT_BF16) ok = NV_HR(bf16);
+#undef NV_HR
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_conv_in(const PlainConv& L, const float* rgb, float* dst, int H, int W,
+int conv_ob(int role, int epi, int obtot) {
+  if (role == CONV_OFF2) return obtot % 7 == 0 ? 7 : (obtot % 4 == 0 ? 4 : 1);
+  if (role == CONV_OFF1) return obtot % 4 == 0 ? 4 : 2;
+  if (epi == EPI_SHUFFLE) return 8;
+  return obtot % 4 == 0 ? 4 : 2;
+}
+
+hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
                           hipStream_t s) {
   const dim3 grid((H * W + 255) / 256, L.cout / 16);
-  hipLaunchKernelGGL(k_conv_in, grid, dim3(256), 0, s, rgb, L.w, L.b, dst, H, W, L.cout);
+  if (tout == DT_F32)
+    hipLaunchKernelGGL((k_conv_in<float>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<float*>(dst), H, W, L.cout);
+  else if (tout == DT_F16)
+    hipLaunchKernelGGL((k_conv_in<f16>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<f16*>(dst), H, W, L.cout);
+  else if (tout == DT_BF16)
+    hipLaunchKernelGGL((k_conv_in<bf16>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<bf16*>(dst), H, W, L.cout);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_conv(const PackedConv& L, int epi, const float* src0, const float* src1,
-                       const uint32_t* sel, const float* alt0, const float* alt1,
-                       const float* res, float* dst, int ldy, int H, int W, int sig_lo,
-                       hipStream_t s) {
-  ConvArgs a;
-  a.src0 = src0;
-  a.src1 = src1;
-  a.sel = sel;
-  a.alt0 = alt0;
-  a.alt1 = alt1;
-  a.wfrag = reinterpret_cast<const f32x4*>(L.frag);
-  a.bias = L.bias;
-  a.res = res;
-  a.dst = dst;
-  a.H = H;
-  a.W = W;
-  a.ldy = ldy;
-  a.cout = L.cout;
-  a.sig_lo = sig_lo;
-  a.obtot = L.obtot;
-  a.ccout = L.cout / 4;
-  const int nchunk = src1 ? 2 : 1;
-  const int cch = L.cin / nchunk;
-  if (cch == 64 && nchunk == 1) return dispatch_epi<64, 1>(a, epi, s);
-  if (cch == 64 && nchunk == 2) return dispatch_epi<64, 2>(a, epi, s);
-  if (cch == 32 && nchunk == 1) return dispatch_epi<32, 1>(a, epi, s);
-  if (cch == 32 && nchunk == 2) return dispatch_epi<32, 2>(a, epi, s);
-  return hipErrorInvalidValue;
+hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
+                                hipStream_t s) {
+  const dim3 grid(kBatchGrid);
+  if (tout == DT_F32) hipLaunchKernelGGL((k_conv_in_batch<float>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
+  else if (tout == DT_F16) hipLaunchKernelGGL((k_conv_in_batch<f16>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
+  else if (tout == DT_BF16) hipLaunchKernelGGL((k_conv_in_batch<bf16>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
-hipError_t launch_dcn(const PackedConv& L, const float* fa, const float* fb, const uint32_t* sel,
-                      const float* offs, int ldo, int groups, float* dst, int H, int W,
+hipError_t launch_conv(const PackedConv& P, int role, int epi, int tin, int pb, const ConvImg& im,
+                       int ldy, int sig_lo, hipStream_t s) {
+  const ConvLayer L = make_layer(P, ldy, sig_lo);
+  const ConvCall c{L, &im, nullptr, nullptr, s};
+  return conv_dispatch(P, role, epi, tin, pb, c);
+}
+
+hipError_t launch_conv_batch(const PackedConv& P, int role, int epi, int tin, int pb,
+                             const ConvImg* jobs, const int* count, int ldy, int sig_lo, hipStream_t s) {
+  const ConvLayer L = make_layer(P, ldy, sig_lo);
+  const ConvCall c{L, nullptr, jobs, count, s};
+  return conv_dispatch(P, role, epi, tin, pb, c);
+}
+
+hipError_t launch_dcn(const PackedConv& P, int tf, int pb, const DcnImg& im, int ldo, int groups,
                       hipStream_t s) {
-  DcnArgs a;
-  a.fa = fa;
-  a.fb = fb;
-  a.sel = sel;
-  a.offs = offs;
-  a.wfrag = reinterpret_cast<const f32x4*>(L.frag);
-  a.bias = L.bias;
-  a.dst = dst;
-  a.H = H;
-  a.W = W;
-  a.ldo = ldo;
-  a.groups = groups;
-  a.obtot = L.obtot;
-  constexpr int PB = 2;
-  const int ntile = ((W + kTW - 1) / kTW) * ((H + 4 * PB - 1) / (4 * PB));
-  if (L.cout == 64) hipLaunchKernelGGL((k_dcn<64, PB>), dim3(ntile), dim3(256), 0, s, a);
-  else if (L.cout == 32) hipLaunchKernelGGL((k_dcn<32, PB>), dim3(ntile), dim3(256), 0, s, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  return dcn_dispatch(P, tf, pb, ldo, groups, &im, nullptr, nullptr, s);
 }
 
-hipError_t launch_hr(const PlainConv& L, const float* u, const float* rgb_a, const float* rgb_b,
-                     const uint32_t* sel, int tsel, float* dst, int H, int W, hipStream_t s) {
-  HrArgs a;
-  a.u = u;
-  a.wfrag = reinterpret_cast<const f32x4*>(L.w);
-  a.bias = L.b;
-  a.rgb_a = rgb_a;
-  a.rgb_b = rgb_b;
-  a.sel = sel;
-  a.dst = dst;
-  a.H = H;
-  a.W = W;
-  a.tsel = tsel;
-  const int ntile = ((2 * W + 15) / 16) * ((2 * H + 15) / 16);
-  if (L.cin == 64) hipLaunchKernelGGL((k_hr<64>), dim3(ntile), dim3(256), 0, s, a);
-  else if (L.cin == 32) hipLaunchKernelGGL((k_hr<32>), dim3(ntile), dim3(256), 0, s, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+hipError_t launch_dcn_batch(const PackedConv& P, int tf, int pb, const DcnImg* jobs, const int* count,
+                            int ldo, int groups, hipStream_t s) {
+  return dcn_dispatch(P, tf, pb, ldo, groups, nullptr, jobs, count, s);
+}
+
+hipError_t launch_hr(const PackedConv& P, int tu, const HrImg& im, hipStream_t s) {
+  return hr_dispatch(P, tu, &im, nullptr, nullptr, s);
+}
+
+hipError_t launch_hr_batch(const PackedConv& P, int tu, const HrImg* jobs, const int* count, hipStream_t s) {
+  return hr_dispatch(P, tu, nullptr, jobs, count, s);
 }
 
 }  // namespace nv

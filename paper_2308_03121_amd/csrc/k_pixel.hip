@@ -4,44 +4,15 @@
 // Pack:   planar float32 R'G'B' -> Y'CbCr codes with crop.
 // Scene:  integer SAD and 64-bin histogram distance, and the cut decision.
 // All three are HBM-bound streaming kernels; each thread owns a small run of
-// adjacent pixels so that row accesses coalesce.
+// adjacent pixels so that row accesses coalesce.  Every stage has a single-frame
+// launch and a batched, persistent launch over a device table of frames (possibly of
+// different sizes and formats).
 #include "nv_device.h"
 #include "nv_internal.h"
 
 namespace nv {
-namespace {
 
-template <int BITS>
-struct Code;
-template <>
-struct Code<8> {
-  typedef uint8_t T;
-  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
-    return (float)reinterpret_cast<const uint8_t*>(static_cast<const char*>(p) + y * pitch)[x];
-  }
-  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
-    reinterpret_cast<uint8_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint8_t)v;
-  }
-};
-template <>
-struct Code<10> {
-  typedef uint16_t T;
-  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
-    return (float)(reinterpret_cast<const uint16_t*>(static_cast<const char*>(p) + y * pitch)[x] &
-                   0x3FFu);
-  }
-  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
-    reinterpret_cast<uint16_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint16_t)v;
-  }
-};
-
-// Matrix constants, limited range.  Y' = (Y - 16s) / (219s), C' = (C - 128s) / (224s);
-// R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr'.
-struct Inv {
-  float ys, yo, cs, co, rcr, bcb, gcb, gcr;
-};
-
-__host__ Inv make_inv(int bits) {
+Inv make_inv(int bits) {
   const double s = double(1 << (bits - 8));
   Inv m;
   m.ys = float(1.0 / (219.0 * s));
@@ -55,19 +26,72 @@ __host__ Inv make_inv(int bits) {
   return m;
 }
 
-// Each thread writes 4 consecutive padded pixels of one row of each plane.
+Fwd make_fwd(int bits) {
+  const double s = double(1 << (bits - 8));
+  Fwd m;
+  m.kr = float(kKr);
+  m.kg = float(kKg);
+  m.kb = float(kKb);
+  m.cbs = float(1.0 / (2.0 * (1.0 - kKb)));
+  m.crs = float(1.0 / (2.0 * (1.0 - kKr)));
+  m.ys = float(219.0 * s);
+  m.yo = float(16.0 * s);
+  m.cs = float(224.0 * s);
+  m.co = float(128.0 * s);
+  m.maxc = float((1 << bits) - 1);
+  return m;
+}
+
+namespace {
+
+template <int BITS>
+struct Code;
+template <>
+struct Code<8> {
+  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
+    return (float)reinterpret_cast<const uint8_t*>(static_cast<const char*>(p) + y * pitch)[x];
+  }
+  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
+    reinterpret_cast<uint8_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint8_t)v;
+  }
+};
+template <>
+struct Code<10> {
+  static __device__ __forceinline__ float get(const void* p, int64_t pitch, int y, int x) {
+    return (float)(reinterpret_cast<const uint16_t*>(static_cast<const char*>(p) + y * pitch)[x] &
+                   0x3FFu);
+  }
+  static __device__ __forceinline__ void put(void* p, int64_t pitch, int y, int x, int v) {
+    reinterpret_cast<uint16_t*>(static_cast<char*>(p) + y * pitch)[x] = (uint16_t)v;
+  }
+};
+
+// Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
+template <class J>
+__device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- unpack: four consecutive padded pixels of one row of each plane per thread ----
+// (Y'CbCr -> R'G'B': Y' = (Y - 16s) / 219s, C' = (C - 128s) / 224s,
+//  R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr')
 template <int BITS, bool C420>
-__global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
-                                                int wp) {
+__device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp,
+                                        int wp, int gid) {
   const int groups_per_row = wp >> 2;
-  const int gid = blockIdx.x * 256 + threadIdx.x;
   if (gid >= groups_per_row * hp) return;
   const int y = gid / groups_per_row;
   const int x0 = (gid - y * groups_per_row) << 2;
   const int sy = min(y, f.h - 1);
   const int hc = C420 ? (f.h >> 1) : f.h;
   const int wc = C420 ? (f.w >> 1) : f.w;
-  // vertical chroma neighbour of this luma row (4:2:0)
+  // vertical chroma neighbour of this luma row (4:2:0, chroma sited between rows 2i, 2i+1)
   const int ci = C420 ? (sy >> 1) : sy;
   const int ci2 = C420 ? ((sy & 1) ? min(ci + 1, hc - 1) : max(ci - 1, 0)) : ci;
   float r[4], g[4], b[4];
@@ -113,38 +137,45 @@ __global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restric
   st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
 }
 
-struct Fwd {
-  float kr, kg, kb, cbs, crs, ys, yo, cs, co, maxc;
-};
-
-__host__ Fwd make_fwd(int bits) {
-  const double s = double(1 << (bits - 8));
-  Fwd m;
-  m.kr = float(kKr);
-  m.kg = float(kKg);
-  m.kb = float(kKb);
-  m.cbs = float(1.0 / (2.0 * (1.0 - kKb)));
-  m.crs = float(1.0 / (2.0 * (1.0 - kKr)));
-  m.ys = float(219.0 * s);
-  m.yo = float(16.0 * s);
-  m.cs = float(224.0 * s);
-  m.co = float(128.0 * s);
-  m.maxc = float((1 << bits) - 1);
-  return m;
+__device__ __forceinline__ void unpack4_any(const Frame& f, const Inv& m, float* rgb, int hp, int wp,
+                                            int gid) {
+  if (f.bits == 8) {
+    if (f.chroma == 420) unpack4<8, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<8, false>(f, m, rgb, hp, wp, gid);
+  } else {
+    if (f.chroma == 420) unpack4<10, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<10, false>(f, m, rgb, hp, wp, gid);
+  }
 }
 
+template <int BITS, bool C420>
+__global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
+                                                int wp) {
+  unpack4<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_unpack_batch(const UnpackJob* __restrict__ jobs,
+                                                      const int* __restrict__ count) {
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const UnpackJob& J = jobs[find_job(jobs, njobs, item)];
+    unpack4_any(J.f, J.m, J.rgb, J.hp, J.wp, (item - J.item_begin) * 256 + threadIdx.x);
+  }
+}
+
+// ---- pack ----
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 
 __device__ __forceinline__ int quant(float v, float maxc) {
   return (int)fminf(fmaxf(floorf(v + 0.5f), 0.0f), maxc);
 }
 
-// 4:2:0 pack: one thread per chroma sample, i.e. one 2x2 luma block.
+// 4:2:0: one thread per chroma sample, i.e. one 2x2 luma block and the chroma filter
+// (1/4, 1/2, 1/4) over columns 2j-1..2j+1 times (1/2, 1/2) over rows 2i, 2i+1.
 template <int BITS>
-__global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float* __restrict__ rgb,
-                                                 int rh, int rw) {
+__device__ __forceinline__ void pack420_px(const FrameOut& f, const Fwd& m,
+                                           const float* __restrict__ rgb, int rh, int rw, int gid) {
   const int wc = f.w >> 1, hc = f.h >> 1;
-  const int gid = blockIdx.x * 256 + threadIdx.x;
   if (gid >= wc * hc) return;
   const int i = gid / wc, j = gid - i * wc;
   const size_t plane = (size_t)rh * rw;
@@ -171,9 +202,8 @@ __global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float*
 }
 
 template <int BITS>
-__global__ __launch_bounds__(256) void k_pack444(FrameOut f, Fwd m, const float* __restrict__ rgb,
-                                                 int rh, int rw) {
-  const int gid = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pack444_px(const FrameOut& f, const Fwd& m,
+                                           const float* __restrict__ rgb, int rh, int rw, int gid) {
   if (gid >= f.w * f.h) return;
   const int y = gid / f.w, x = gid - y * f.w;
   const size_t plane = (size_t)rh * rw;
@@ -185,13 +215,39 @@ __global__ __launch_bounds__(256) void k_pack444(FrameOut f, Fwd m, const float*
   Code<BITS>::put(f.p[2], f.pitch[2], y, x, quant(fmaf((R - Yn) * m.crs, m.cs, m.co), m.maxc));
 }
 
-// ---- scene metric ----
-
-__global__ void k_scene_clear(uint64_t* sad, uint32_t* hist) {
-  const int t = threadIdx.x;
-  if (t < 64) hist[t] = 0u;
-  if (t == 0) *sad = 0ull;
+__device__ __forceinline__ void pack_any(const FrameOut& f, const Fwd& m, const float* rgb, int rh,
+                                         int rw, int gid) {
+  if (f.chroma == 420) {
+    if (f.bits == 8) pack420_px<8>(f, m, rgb, rh, rw, gid);
+    else pack420_px<10>(f, m, rgb, rh, rw, gid);
+  } else {
+    if (f.bits == 8) pack444_px<8>(f, m, rgb, rh, rw, gid);
+    else pack444_px<10>(f, m, rgb, rh, rw, gid);
+  }
 }
+
+template <int BITS>
+__global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float* __restrict__ rgb,
+                                                 int rh, int rw) {
+  pack420_px<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
+}
+
+template <int BITS>
+__global__ __launch_bounds__(256) void k_pack444(FrameOut f, Fwd m, const float* __restrict__ rgb,
+                                                 int rh, int rw) {
+  pack444_px<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_pack_batch(const PackJob* __restrict__ jobs,
+                                                    const int* __restrict__ count) {
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const PackJob& J = jobs[find_job(jobs, njobs, item)];
+    pack_any(J.f, J.m, J.rgb, J.rh, J.rw, (item - J.item_begin) * 256 + threadIdx.x);
+  }
+}
+
+// ---- scene metric ----
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
@@ -199,9 +255,46 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// Grid-stride over rows; each thread takes 4 adjacent samples per step.  Per-thread SAD
-// partial sums fit in 32 bits (at most 4 * 1023 per step and a bounded number of steps);
-// the block total is added to the 64-bit accumulator once.
+__global__ void k_scene_clear(uint64_t* sad, uint32_t* hist) {
+  const int t = threadIdx.x;
+  if (t < 64) hist[t] = 0u;
+  if (t == 0) *sad = 0ull;
+}
+
+// Rows [r0, r1) of one frame: luma histogram into lh (LDS), SAD against the previous
+// frame's luma, optionally a copy of the rows into luma_save.  Returns the thread's SAD.
+// Per-thread partial sums fit in 32 bits for the frame sizes the library accepts.
+template <int BITS>
+__device__ __forceinline__ uint32_t scene_rows(const Frame& cur, const void* prev_y, int64_t prev_pitch,
+                                               void* luma_save, int64_t save_pitch, int r0, int r1,
+                                               uint32_t* lh) {
+  const int shift = BITS - 6;
+  uint32_t s = 0;
+  for (int row = r0; row < r1; ++row) {
+    for (int x = threadIdx.x; x < cur.w; x += 256) {
+      const int c = (int)Code<BITS>::get(cur.p[0], cur.pitch[0], row, x);
+      atomicAdd(&lh[c >> shift], 1u);
+      if (prev_y != nullptr) s += (uint32_t)abs(c - (int)Code<BITS>::get(prev_y, prev_pitch, row, x));
+      if (luma_save != nullptr) Code<BITS>::put(luma_save, save_pitch, row, x, c);
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ void scene_flush(uint32_t s, bool has_prev, uint32_t* lh, uint32_t* lsad,
+                                            uint64_t* sad, uint32_t* hist) {
+  if (has_prev) {
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lsad[threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
+  if (has_prev && threadIdx.x == 0) {
+    const uint64_t tot = (uint64_t)lsad[0] + lsad[1] + lsad[2] + lsad[3];
+    if (tot) atomicAdd(reinterpret_cast<unsigned long long*>(sad), (unsigned long long)tot);
+  }
+}
+
 template <int BITS, bool HAS_PREV>
 __global__ __launch_bounds__(256) void k_scene_accum(Frame cur, Frame prev, uint64_t* sad,
                                                      uint32_t* hist) {
@@ -209,46 +302,22 @@ __global__ __launch_bounds__(256) void k_scene_accum(Frame cur, Frame prev, uint
   __shared__ uint32_t lsad[4];
   if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
   __syncthreads();
-  const int shift = BITS - 6;
-  const int quads = (cur.w + 3) >> 2;
   uint32_t s = 0;
-  for (int row = blockIdx.x; row < cur.h; row += gridDim.x) {
-    for (int q = threadIdx.x; q < quads; q += 256) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = 4 * q + k;
-        if (x < cur.w) {
-          const int c = (int)Code<BITS>::get(cur.p[0], cur.pitch[0], row, x);
-          atomicAdd(&lh[c >> shift], 1u);
-          if (HAS_PREV) {
-            const int pv = (int)Code<BITS>::get(prev.p[0], prev.pitch[0], row, x);
-            s += (uint32_t)abs(c - pv);
-          }
-        }
-      }
-    }
-  }
-  if (HAS_PREV) {
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) lsad[threadIdx.x >> 6] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64 && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
-  if (HAS_PREV && threadIdx.x == 0) {
-    const uint64_t tot = (uint64_t)lsad[0] + lsad[1] + lsad[2] + lsad[3];
-    if (tot) atomicAdd(reinterpret_cast<unsigned long long*>(sad), (unsigned long long)tot);
-  }
+  for (int row = blockIdx.x; row < cur.h; row += gridDim.x)
+    s += scene_rows<BITS>(cur, HAS_PREV ? prev.p[0] : nullptr, prev.pitch[0], nullptr, 0, row, row + 1, lh);
+  scene_flush(s, HAS_PREV, lh, lsad, sad, hist);
 }
 
-__global__ void k_scene_final(const uint64_t* sad, const uint32_t* hist,
-                              const uint32_t* hist_prev, int has_prev, uint64_t n_pix, int bits,
-                              SceneRule rule, int external_cut, uint32_t* hd, uint32_t* cut) {
-  __shared__ uint32_t part[64];
+// Frame t starts a scene when SAD > T * 2^(bits-8) * N and HD * den > 2 N num.
+__device__ __forceinline__ void scene_decide(const uint64_t* sad, const uint32_t* hist,
+                                             const uint32_t* hist_prev, int has_prev, uint64_t n_pix,
+                                             int bits, const SceneRule& rule, int external_cut,
+                                             uint32_t* hd, uint32_t* cut, uint32_t* hist_save) {
   const int t = threadIdx.x;
   uint32_t d = 0;
   if (has_prev) d = (uint32_t)abs((int)hist[t] - (int)hist_prev[t]);
   d = wave_sum(d);
-  (void)part;
+  if (hist_save != nullptr) hist_save[t] = hist[t];
   if (t == 0) {
     uint32_t c;
     if (!has_prev) {
@@ -263,6 +332,50 @@ __global__ void k_scene_final(const uint64_t* sad, const uint32_t* hist,
     if (external_cut > 0) c = 1u;
     *hd = d;
     *cut = c;
+  }
+}
+
+__global__ void k_scene_final(const uint64_t* sad, const uint32_t* hist, const uint32_t* hist_prev,
+                              int has_prev, uint64_t n_pix, int bits, SceneRule rule, int external_cut,
+                              uint32_t* hd, uint32_t* cut) {
+  scene_decide(sad, hist, hist_prev, has_prev, n_pix, bits, rule, external_cut, hd, cut, nullptr);
+}
+
+// Batched scene metric: clear every job's accumulators, accumulate row chunks, decide.
+__global__ __launch_bounds__(64) void k_scene_clear_batch(const SceneJob* __restrict__ jobs,
+                                                          const int* __restrict__ count) {
+  for (int j = blockIdx.x; j < count[0]; j += gridDim.x) {
+    jobs[j].hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) *jobs[j].sad = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scene_accum_batch(const SceneJob* __restrict__ jobs,
+                                                           const int* __restrict__ count) {
+  __shared__ uint32_t lh[64];
+  __shared__ uint32_t lsad[4];
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const SceneJob& J = jobs[find_job(jobs, njobs, item)];
+    const int r0 = (item - J.item_begin) * kSceneRowsPerItem;
+    const int r1 = min(r0 + kSceneRowsPerItem, J.cur.h);
+    if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t s = J.cur.bits == 8
+        ? scene_rows<8>(J.cur, J.prev_y, J.prev_pitch, J.luma_save, J.luma_save_pitch, r0, r1, lh)
+        : scene_rows<10>(J.cur, J.prev_y, J.prev_pitch, J.luma_save, J.luma_save_pitch, r0, r1, lh);
+    scene_flush(s, J.prev_y != nullptr, lh, lsad, J.sad, J.hist);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_scene_final_batch(const SceneJob* __restrict__ jobs,
+                                                          const int* __restrict__ count) {
+  for (int j = blockIdx.x; j < count[0]; j += gridDim.x) {
+    const SceneJob& J = jobs[j];
+    const int has_prev = J.prev_y != nullptr && J.hist_prev != nullptr;
+    scene_decide(J.sad, J.hist, J.hist_prev, has_prev, (uint64_t)J.cur.w * (uint64_t)J.cur.h, J.cur.bits,
+                 J.rule, J.external, J.hd, J.cut, J.hist_save);
   }
 }
 
@@ -311,6 +424,23 @@ hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* his
   }
   hipLaunchKernelGGL(k_scene_final, dim3(1), dim3(64), 0, s, sad, hist, hist_prev, has_prev ? 1 : 0,
                      (uint64_t)cur.w * (uint64_t)cur.h, cur.bits, rule, external_cut, hd, cut);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_batch(const UnpackJob* jobs, const int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack_batch, dim3(kBatchGrid), dim3(256), 0, s, jobs, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(const PackJob* jobs, const int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_batch, dim3(kBatchGrid), dim3(256), 0, s, jobs, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_scene_batch(const SceneJob* jobs, const int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_scene_clear_batch, dim3(256), dim3(64), 0, s, jobs, count);
+  hipLaunchKernelGGL(k_scene_accum_batch, dim3(kBatchGrid), dim3(256), 0, s, jobs, count);
+  hipLaunchKernelGGL(k_scene_final_batch, dim3(256), dim3(64), 0, s, jobs, count);
   return hipGetLastError();
 }
 

@@ -23,6 +23,17 @@ struct SceneRule {
   int mad_thresh_8bit, hist_num, hist_den, enable;
 };
 
+// Limited-range BT.709 constants of the inverse (unpack) and forward (pack) matrices for
+// one bit depth; every derived coefficient is formed in double and rounded once.
+struct Inv {
+  float ys, yo, cs, co, rcr, bcb, gcb, gcr;
+};
+struct Fwd {
+  float kr, kg, kb, cbs, crs, ys, yo, cs, co, maxc;
+};
+Inv make_inv(int bits);
+Fwd make_fwd(int bits);
+
 // ---- pixel-format stages (k_pixel.hip) ----
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s);
 hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipStream_t s);
@@ -31,16 +42,75 @@ hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* his
                         const SceneRule& rule, int external_cut, uint64_t* sad,
                         uint32_t* hist, uint32_t* hd, uint32_t* cut, hipStream_t s);
 
-// ---- network (k_net.hip) ----
-// Packed weights of one 3x3 conv for the MFMA kernels: fragment-ordered A operands
-// [tap][kgroup][oblock][lane] x 4 floats, and the bias per A row.
-struct PackedConv {
-  float* frag = nullptr;   // device
-  float* bias = nullptr;   // device, obtot*16 floats
-  int cin = 0, cout = 0, obtot = 0;
+// ---- batched (multi-image, persistent) launches ----
+// Each batched kernel walks a device table of jobs.  Job j owns the work items
+// [item_begin_j, item_begin_{j+1}); count[0] is the number of jobs and count[1] the
+// total number of items, both read on the device, so one captured graph serves any
+// batch that fits the tables.  Blocks grid-stride over the items.
+constexpr int kBatchGrid = 2048;          // persistent workgroups per batched launch
+constexpr int kUnpackPerItem = 1024;      // 256 threads x 4 pixels
+constexpr int kSceneRowsPerItem = 8;
+
+struct UnpackJob {
+  Frame f;
+  Inv m;
+  float* rgb;
+  int hp, wp;
+  int item_begin;
 };
 
-// Small convs done on the vector ALUs keep their plain layout.
+struct PackJob {
+  FrameOut f;
+  Fwd m;
+  const float* rgb;
+  int rh, rw;
+  int item_begin;
+};
+
+struct SceneJob {
+  Frame cur;
+  const void* prev_y;          // previous frame's luma, or null for a stream's first frame
+  int64_t prev_pitch;
+  const uint32_t* hist_prev;
+  uint64_t* sad;
+  uint32_t* hist;              // histogram of cur (accumulator)
+  uint32_t* hd;
+  uint32_t* cut;
+  uint32_t* hist_save;         // when set, the final pass copies hist there
+  void* luma_save;             // when set, the accumulate pass copies cur's luma rows there
+  int64_t luma_save_pitch;
+  SceneRule rule;
+  int external;
+  int item_begin;              // in row chunks of kSceneRowsPerItem
+};
+
+inline int unpack_items(int hp, int wp) { return ((wp / 4) * hp + 255) / 256; }
+inline int pack_items(int w, int h, int chroma) {
+  const int n = chroma == 420 ? (w / 2) * (h / 2) : w * h;
+  return (n + 255) / 256;
+}
+inline int scene_items(int h) { return (h + kSceneRowsPerItem - 1) / kSceneRowsPerItem; }
+
+hipError_t launch_unpack_batch(const UnpackJob* jobs, const int* count, hipStream_t s);
+hipError_t launch_pack_batch(const PackJob* jobs, const int* count, hipStream_t s);
+// count: {njobs, accumulate items}
+hipError_t launch_scene_batch(const SceneJob* jobs, const int* count, hipStream_t s);
+
+// ---- network (k_net.hip) ----
+enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+inline int dtype_bytes(int dt) { return dt == DT_F32 ? 4 : 2; }
+
+// Packed weights of one conv for the MFMA kernels: fragment-ordered A operands
+// [tap][kgroup][oblock][lane] x 16 bytes in the MFMA type tc, and the float bias per
+// A row.  For the HR conv the fragments hold the 32 x C tap-response matrix.
+struct PackedConv {
+  void* frag = nullptr;    // device
+  float* bias = nullptr;   // device, obtot*16 floats
+  int cin = 0, cout = 0, obtot = 0, tc = DT_F32;
+};
+
+// The 3 -> C input conv runs on the vector ALUs with the plain OIHW layout.
 struct PlainConv {
   float* w = nullptr;      // device
   float* b = nullptr;      // device
@@ -48,21 +118,78 @@ struct PlainConv {
 };
 
 enum ConvEpi { EPI_LRELU = 0, EPI_RES = 1, EPI_OFFSET = 2, EPI_SHUFFLE = 3 };
+// Role of a conv: bulk (residual blocks, pixel-shuffle conv; storage = MFMA type), the
+// offset head's first conv (two 16- or 32-bit inputs, float MFMA), its second conv (float).
+enum ConvRole { CONV_BULK = 0, CONV_OFF1 = 1, CONV_OFF2 = 2 };
 
-hipError_t launch_conv_in(const PlainConv& L, const float* rgb, float* dst, int H, int W,
+// Per-image arguments of a conv launch (one job of a batched launch).  When sel is
+// non-null and *sel != 0 on the device, alt0 / alt1 (where non-null) replace src0 /
+// src1 -- the device-side selection of a duplicated frame at a scene cut.
+struct ConvImg {
+  const void* src0;
+  const void* src1;
+  const uint32_t* sel;
+  const void* alt0;
+  const void* alt1;
+  const void* res;
+  void* dst;
+  int H, W;
+  int item_begin;
+};
+
+struct ConvInImg {
+  const float* rgb;
+  void* dst;
+  int H, W;
+  int item_begin;              // in 256-pixel blocks x (C/16) channel blocks
+};
+
+struct DcnImg {
+  const void* fa;
+  const void* fb;
+  const uint32_t* sel;
+  const float* offs;
+  void* dst;
+  int H, W;
+  int item_begin;
+};
+
+struct HrImg {
+  const void* u;
+  const float* rgb_a;
+  const float* rgb_b;
+  const uint32_t* sel;
+  float* dst;
+  int H, W, tsel;
+  int item_begin;
+};
+
+// Output blocks per workgroup chosen by the conv dispatch for a role / epilogue.
+int conv_ob(int role, int epi, int obtot);
+inline int conv_items(int H, int W, int pb, int nobg) {
+  return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
+}
+inline int hr_items(int H, int W) { return ((2 * W + 15) / 16) * ((2 * H + 15) / 16); }
+inline int conv_in_items(int H, int W, int C) { return ((H * W + 255) / 256) * (C / 16); }
+
+hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
                           hipStream_t s);
-// dst (and res) NHWC with channel stride ldy.  src1 may be null (single source).  When
-// sel is non-null and *sel != 0 on the device, alt0 / alt1 (where non-null) replace
-// src0 / src1 -- the device-side selection of a duplicated frame at a scene cut.
-hipError_t launch_conv(const PackedConv& L, int epi, const float* src0, const float* src1,
-                       const uint32_t* sel, const float* alt0, const float* alt1,
-                       const float* res, float* dst, int ldy, int H, int W, int sig_lo,
-                       hipStream_t s);
-hipError_t launch_dcn(const PackedConv& L, const float* fa, const float* fb,
-                      const uint32_t* sel, const float* offs, int ldo, int groups,
-                      float* dst, int H, int W, hipStream_t s);
-// HR conv C->3 plus the bilinear x2 base of frame a (tb = 0), b (tb = 1) or their mean.
-hipError_t launch_hr(const PlainConv& L, const float* u, const float* rgb_a, const float* rgb_b,
-                     const uint32_t* sel, int tsel, float* dst, int H, int W, hipStream_t s);
+// dst (and res) NHWC with channel stride ldy.  src1 only for CONV_OFF1.  pb = rows per
+// wave of the workgroup tile (1, 2 or 4 for bulk convs; 2 for the offset head).
+hipError_t launch_conv(const PackedConv& L, int role, int epi, int tin, int pb, const ConvImg& im,
+                       int ldy, int sig_lo, hipStream_t s);
+hipError_t launch_dcn(const PackedConv& L, int tf, int pb, const DcnImg& im, int ldo, int groups,
+                      hipStream_t s);
+// HR conv C->3 plus the bilinear x2 base of frame a (tsel 0), b (1) or their mean (2).
+hipError_t launch_hr(const PackedConv& L, int tu, const HrImg& im, hipStream_t s);
+
+hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
+                                hipStream_t s);
+hipError_t launch_conv_batch(const PackedConv& L, int role, int epi, int tin, int pb,
+                             const ConvImg* jobs, const int* count, int ldy, int sig_lo, hipStream_t s);
+hipError_t launch_dcn_batch(const PackedConv& L, int tf, int pb, const DcnImg* jobs, const int* count,
+                            int ldo, int groups, hipStream_t s);
+hipError_t launch_hr_batch(const PackedConv& L, int tu, const HrImg* jobs, const int* count,
+                           hipStream_t s);
 
 }  // namespace nv

@@ -80,6 +80,7 @@ def test_context_rejects_bad_config(lib):
     for cfg, code in [((48, 2, 8, 2, 8, 7, 0), _abi.NV_E_INVALID),
                       ((96, 2, 8, 2, 8, 7, 0), _abi.NV_E_UNSUPPORTED),
                       ((64, 2, 7, 2, 8, 7, 0), _abi.NV_E_INVALID),
+                      ((64, 2, 1, 2, 8, 7, 0), _abi.NV_E_INVALID),
                       ((64, 2, 8, 3, 8, 7, 0), _abi.NV_E_UNSUPPORTED),
                       ((64, 2, 8, 2, 8, 1, 0), _abi.NV_E_UNSUPPORTED),
                       ((64, 2, 8, 2, 8, 7, 9), _abi.NV_E_INVALID)]:

@@ -1,0 +1,157 @@
+"""Batched execution (one persistent launch per stage over many streams, replayed from a
+HIP graph) against per-stream calls and the oracle.
+
+The batched kernels run the same per-pixel arithmetic in the same order as the
+per-stream kernels (a tile's shape only changes which workgroup computes a pixel, not
+the order of its K accumulation), so the bar is bit-identity with the per-stream
+results, for every precision, with the graph on and off, and with autotuned tiles.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import pipeline
+from tests._helpers import oracle_weights, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+# (width, height, bits, chroma, scene starts) of the clips mixed in one batch
+CLIPS = [(64, 48, 8, 420, [3]), (48, 32, 10, 444, []), (80, 40, 8, 444, [2, 4]), (40, 24, 10, 420, [1])]
+N_FRAMES = 6
+
+
+@pytest.fixture(scope="module")
+def B():
+    require_gpu()
+    from paper_2308_03121_amd import binding
+    return binding
+
+
+def _clips():
+    return [synth.gen_clip(w, h, N_FRAMES, bits=b, chroma=c, seed=20 + i, scene_starts=s)
+            for i, (w, h, b, c, s) in enumerate(CLIPS)]
+
+
+def _per_stream(B, ctx, clips, dev_frames):
+    res = []
+    for clip, frames in zip(clips, dev_frames):
+        st = ctx.open_stream(B.fmt_struct(clip.width, clip.height, clip.bits, clip.chroma))
+        outs = []
+        for f in frames:
+            outs += st.push(f)
+        outs += st.end()
+        torch.cuda.synchronize()
+        res.append(([B.frame_to_numpy(o, clip.bits) for o in outs], st.cuts()))
+        st.close()
+    return res
+
+
+def _batched(B, ctx, clips, dev_frames, chains):
+    """Push every clip through one stream per clip in batch calls; chains[i] = list of
+    request sizes per call (the last call ends the clip)."""
+    streams = [ctx.open_stream(B.fmt_struct(c.width, c.height, c.bits, c.chroma)) for c in clips]
+    pos = [0] * len(clips)
+    outs = [[] for _ in clips]
+    ncalls = max(len(ch) for ch in chains)
+    for call in range(ncalls):
+        reqs, idx = [], []
+        for i, ch in enumerate(chains):
+            if call >= len(ch):
+                continue
+            k = ch[call]
+            frames = dev_frames[i][pos[i]:pos[i] + k]
+            end = call == len(ch) - 1
+            reqs.append((streams[i], frames, None, end))
+            idx.append(i)
+            pos[i] += k
+        got = ctx.enhance_batch(reqs)
+        for i, o in zip(idx, got):
+            outs[i] += o
+    torch.cuda.synchronize()
+    res = [([B.frame_to_numpy(o, c.bits) for o in outs[i]], streams[i].cuts()) for i, c in enumerate(clips)]
+    for s in streams:
+        s.close()
+    return res
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for (oa, ca), (ob, cb) in zip(a, b):
+        assert ca == cb
+        assert len(oa) == len(ob)
+        for fa, fb in zip(oa, ob):
+            for pa, pb in zip(fa, fb):
+                assert np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_batch_bit_identical_to_streams(B, prec):
+    say(f"batch vs streams {prec}")
+    cfg = synth.NetConfig(32, 1, 8)
+    blob = synth.gen_weights(cfg, seed=4)
+    clips = _clips()
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    ref = _per_stream(B, ctx, clips, dev)
+    assert [[t for t, c in enumerate(r[1]) if c] for r in ref] == [c.scene_starts for c in clips]
+    chains = [[3, 3], [1, 2, 3], [6], [2, 2, 2]]
+    _same(_batched(B, ctx, clips, dev, chains), ref)          # recorded graph
+    _same(_batched(B, ctx, clips, dev, [[2, 4], [4, 2], [5, 1], [1, 5]]), ref)   # replayed graph
+    ctx.batch_graph(False)
+    _same(_batched(B, ctx, clips, dev, chains), ref)          # direct launches
+    ctx.close()
+
+
+def test_batch_autotuned_tiles_keep_results(B):
+    say("batch autotune")
+    cfg = synth.NetConfig(64, 2, 8)
+    blob = synth.gen_weights(cfg, seed=5)
+    clips = _clips()[:2]
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision="fp16")
+    ref = _per_stream(B, ctx, clips, dev)
+    rep = ctx.autotune(48, 64)
+    print("  autotune:", rep, flush=True)
+    assert "block" in rep and "dcn" in rep
+    _same(_batched(B, ctx, clips, dev, [[3, 3], [2, 4]]), ref)
+    ctx.close()
+
+
+def test_batch_matches_oracle(B):
+    say("batch vs oracle")
+    cfg = synth.NetConfig(32, 1, 8)
+    blob = synth.gen_weights(cfg, seed=6)
+    clips = _clips()[1:3]
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob)
+    got = _batched(B, ctx, clips, dev, [[4, 2], [2, 4]])
+    W = oracle_weights(cfg, blob)
+    for clip, (outs, cuts) in zip(clips, got):
+        frames = [clip.frame(t) for t in range(N_FRAMES)]
+        ref_cuts, ref_out = pipeline.enhance_clip(frames, clip.bits, clip.chroma, W, cfg.res_blocks,
+                                                  cfg.offset_groups)
+        assert cuts == ref_cuts
+        assert len(outs) == 2 * N_FRAMES
+        for g, r in zip(outs, ref_out):
+            d = max(int(np.abs(a.astype(np.int64) - b.astype(np.int64)).max()) for a, b in zip(g, r["codes"]))
+            assert d <= 1 and pipeline.psnr_codes(r["codes"], g, clip.bits) >= 50.0
+    ctx.close()
+
+
+def test_batch_rejects_bad_requests(B):
+    cfg = synth.NetConfig(32, 1, 8)
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, synth.gen_weights(cfg))
+    clip = _clips()[0]
+    st = ctx.open_stream(B.fmt_struct(clip.width, clip.height, clip.bits, clip.chroma))
+    f = B.to_device_frame(*clip.frame(0))
+    from paper_2308_03121_amd import NvError
+    with pytest.raises(NvError):
+        ctx.enhance_batch([(st, [f] * 17, None, False)])          # chain too long
+    with pytest.raises(NvError):
+        ctx.enhance_batch([(st, [f], None, False), (st, [f], None, False)])   # same stream twice
+    assert st.n_pushed == 0
+    out = ctx.enhance_batch([(st, [f], None, False)])
+    assert out == [[]]
+    st.close()
+    ctx.close()

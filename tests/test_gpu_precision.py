@@ -1,0 +1,134 @@
+"""GPU parity of the 16-bit network modes against the FP64 oracle.
+
+FP16 / BF16 modes store features in the 16-bit type and run the bulk convolutions
+(residual blocks, DCN contraction, pixel-shuffle conv, HR conv) on 16-bit MFMA with
+float accumulation; the offset head and the bilinear sampling weights stay float.
+
+Tolerances.  The spec bar is PSNR >= 50 dB against FP64 for every float output
+frame.  The max-abs bounds follow from the storage rounding: a value of magnitude up
+to ~3 stored in FP16 (unit roundoff 2^-11) or BF16 (2^-8) carries 1.5e-3 / 1.2e-2 of
+error, about 21 stored layers compound it by sqrt(21) ~ 4.6 in the features, and the
+HR output sees it through the 0.1-gain output conv (residual std ~0.05): ~3e-4 / 2.5e-3
+typical, with a 6x peak factor: FP16 <= 2e-3, BF16 <= 1.5e-2 on HR R'G'B'.  Offsets
+(float head on 16-bit features) are reported, not bounded.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import network, pipeline
+from tests._helpers import max_abs, nhwc_to_chw, oracle_weights, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+HR_TOL = {"fp16": 2e-3, "bf16": 1.5e-2}
+PSNR_MIN = 50.0
+
+
+@pytest.fixture(scope="module")
+def B():
+    require_gpu()
+    from paper_2308_03121_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("cfg,hp,wp", [(synth.NET_C1, 40, 72), (synth.NetConfig(64, 4, 8), 64, 48)],
+                         ids=["C32R2", "C64R4"])
+def test_network_16bit_against_oracle(B, prec, cfg, hp, wp):
+    say(f"precision {prec} C={cfg.channels} R={cfg.res_blocks} {wp}x{hp}")
+    blob = synth.gen_weights(cfg, seed=1)
+    W = oracle_weights(cfg, blob)
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    assert ctx.feat_dtype == (torch.float16 if prec == "fp16" else torch.bfloat16)
+    rng = np.random.default_rng(hp + wp)
+    rgb_a = rng.uniform(0, 1, (3, hp, wp)).astype(np.float32)
+    rgb_b = np.clip(rgb_a + rng.normal(0, 0.05, rgb_a.shape), 0, 1).astype(np.float32)
+    ta, tb = torch.from_numpy(rgb_a).cuda(), torch.from_numpy(rgb_b).cuda()
+    fa, fb = ctx.extract(ta), ctx.extract(tb)
+    hr, offs, _ = ctx.fuse(ta, tb, fa, fb, 7, want_offsets=True)
+    torch.cuda.synchronize()
+    ra, rb = rgb_a.astype(np.float64), rgb_b.astype(np.float64)
+    ofa, ofb = network.extract(ra, W, cfg.res_blocks), network.extract(rb, W, cfg.res_blocks)
+    full = network.fuse(ra, rb, ofa, ofb, W, cfg.offset_groups, keep=True)
+    G = cfg.offset_groups
+    off_err = max_abs(nhwc_to_chw(offs)[:18 * G], full["offsets"])
+    feat_err = max_abs(nhwc_to_chw(fa), ofa)
+    print(f"  {prec}: feature max-abs {feat_err:.2e}, offset max-abs {off_err:.2e}", flush=True)
+    for t, key in enumerate((0.0, 0.5, 1.0)):
+        got = hr[t].cpu().numpy()
+        err = max_abs(got, full[key])
+        p = pipeline.psnr_float(full[key], got)
+        print(f"  t={key}: HR max-abs {err:.2e}, PSNR {p:.1f} dB", flush=True)
+        assert err <= HR_TOL[prec] and p >= PSNR_MIN, (key, err, p)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_stream_16bit_codes(B, prec):
+    say(f"stream {prec}")
+    cfg = synth.NetConfig(32, 2, 8)
+    blob = synth.gen_weights(cfg, seed=3)
+    clip = synth.gen_clip(48, 32, 6, bits=10, chroma=420, seed=5, scene_starts=[3])
+    frames = [clip.frame(t) for t in range(clip.n_frames)]
+    ref_cuts, ref_out = pipeline.enhance_clip(frames, 10, 420, oracle_weights(cfg, blob),
+                                              cfg.res_blocks, cfg.offset_groups)
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    st = ctx.open_stream(B.fmt_struct(48, 32, 10, 420))
+    got = []
+    for f in frames:
+        got += st.push(B.to_device_frame(*f))
+    got += st.end()
+    torch.cuda.synchronize()
+    assert st.cuts() == ref_cuts
+    for g, r in zip(got, ref_out):
+        codes = B.frame_to_numpy(g, 10)
+        p = pipeline.psnr_codes(r["codes"], codes, 10)
+        d = max(int(np.abs(a.astype(np.int64) - b.astype(np.int64)).max()) for a, b in zip(codes, r["codes"]))
+        assert p >= PSNR_MIN, (p, d)
+    st.close()
+    ctx.close()
+
+
+MARGIN = 32
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_full_size_c3_windows(B, prec):
+    """1920x1080 10-bit frames through the C=64, R=10 network in each precision, checked
+    against the oracle on 112x112 windows (corner with the frame edge, bottom-right with
+    the alignment padding, centre)."""
+    say(f"full-size C3 {prec}")
+    cfg = synth.NET_C2
+    blob = synth.gen_weights(cfg, seed=1)
+    W = oracle_weights(cfg, blob)
+    clip = synth.gen_clip(1920, 1080, 2, bits=10, chroma=420, seed=0, scene_starts=[])
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    fmt = B.fmt_struct(1920, 1080, 10, 420)
+    ra_t = B.unpack(fmt, B.to_device_frame(*clip.frame(0)), 1088, 1920)
+    rb_t = B.unpack(fmt, B.to_device_frame(*clip.frame(1)), 1088, 1920)
+    fa, fb = ctx.extract(ra_t), ctx.extract(rb_t)
+    hr, _, _ = ctx.fuse(ra_t, rb_t, fa, fb, 3)
+    torch.cuda.synchronize()
+    hr_np = [hr[0].cpu().numpy(), hr[1].cpu().numpy()]
+    ra, rb = ra_t.cpu().numpy().astype(np.float64), rb_t.cpu().numpy().astype(np.float64)
+    tol = {"fp32": 1e-4}.get(prec, HR_TOL.get(prec))
+    H, Wd = 1088, 1920
+    for (y0, x0) in [(0, 0), (H - 112, Wd - 112), (488, 904)]:
+        ca, cb = ra[:, y0:y0 + 112, x0:x0 + 112], rb[:, y0:y0 + 112, x0:x0 + 112]
+        res = network.fuse(ca, cb, network.extract(ca, W, cfg.res_blocks),
+                           network.extract(cb, W, cfg.res_blocks), W, cfg.offset_groups,
+                           times=(0.0, 0.5), keep=True)
+        ylo, yhi = (y0 if y0 == 0 else y0 + MARGIN), (y0 + 112 if y0 + 112 == H else y0 + 112 - MARGIN)
+        xlo, xhi = (x0 if x0 == 0 else x0 + MARGIN), (x0 + 112 if x0 + 112 == Wd else x0 + 112 - MARGIN)
+        inner = res["offsets"][:, ylo - y0:yhi - y0, xlo - x0:xhi - x0]
+        assert np.abs(inner).max() < MARGIN - 26
+        for i, t in enumerate((0.0, 0.5)):
+            ref = res[t][:, 2 * (ylo - y0):2 * (yhi - y0), 2 * (xlo - x0):2 * (xhi - x0)]
+            got = hr_np[i][:, 2 * ylo:2 * yhi, 2 * xlo:2 * xhi]
+            err, p = max_abs(got, ref), pipeline.psnr_float(ref, got)
+            print(f"  window ({y0},{x0}) t={t}: max-abs {err:.2e} PSNR {p:.1f} dB", flush=True)
+            assert err <= tol and p >= PSNR_MIN
+    ctx.close()
