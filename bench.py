@@ -16,6 +16,8 @@ from __future__ import annotations
 import argparse
 import json
 import os
+
+import numpy as np
 import sys
 import time
 
@@ -90,6 +92,117 @@ def cpu_baseline(clip, blob, cfg, budget_s=20.0):
     return best
 
 
+def _frame_bank(B, synth, w, h, bits, chroma, scenes=2, per=4, seed=0):
+    """Device frames of a few scenes of one format (synthetic clip, cut between scenes)."""
+    clip = synth.gen_clip(w, h, scenes * per, bits=bits, chroma=chroma, seed=seed,
+                          scene_starts=[per * k for k in range(1, scenes)])
+    frames = [B.to_device_frame(*clip.frame(t)) for t in range(clip.n_frames)]
+    return [frames[k * per:(k + 1) * per] for k in range(scenes)]
+
+
+def batching_bench(B, synth, torch, reps=3):
+    """64 frame groups from 16 clips (4 consecutive groups each, the frame store of a
+    5-frame chain) of mixed sizes and formats in one batched call, FP16 network C=64, R=6,
+    tiles from the autotuner, graph replay; against the same groups one at a time in FP32."""
+    rng = np.random.default_rng(2)
+    sizes = [(640, 360), (960, 540), (1280, 720)]
+    fmts = [(8, 420), (10, 420), (8, 444), (10, 444)]
+    clips = []
+    for i in range(16):
+        w, h = sizes[rng.integers(3)]
+        b, c = fmts[rng.integers(4)]
+        clips.append((w, h, b, c))
+    banks = {}
+    for (w, h, b, c) in set(clips):
+        banks[(w, h, b, c)] = _frame_bank(B, synth, w, h, b, c, scenes=1, per=5, seed=w + b + c)[0]
+    cfg = synth.NET_C4
+    blob = synth.gen_weights(cfg, seed=1)
+    res = {}
+    mpix = sum(4 * 2 * (2 * w) * (2 * h) for (w, h, _b, _c) in clips) / 1e6
+    for prec in ("fp16", "fp32"):
+        ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+        tune = ctx.autotune(544, 960)
+        streams = [ctx.open_stream(B.fmt_struct(w, h, b, c)) for (w, h, b, c) in clips]
+
+        def one_batch():
+            for st in streams:
+                st.reset()
+                st.n_pushed = 0
+            ctx.enhance_batch([(st, banks[k], None, False) for st, k in zip(streams, clips)])
+
+        def one_at_a_time():
+            for st, k in zip(streams, clips):
+                st.reset()
+                st.n_pushed = 0
+                for f in banks[k]:
+                    st.push(f)
+
+        runs = {"batched_graph": one_batch} if prec == "fp16" else {"one_at_a_time": one_at_a_time}
+        if prec == "fp16":
+            runs["one_at_a_time"] = one_at_a_time
+        for name, fn in runs.items():
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res[f"{prec}_{name}"] = {"ms": round(dt * 1000, 2), "mpix_per_s": round(mpix / dt, 1)}
+        if prec == "fp16":
+            res["fp16_tuning"] = tune
+            res["batch_workspace_gb"] = round(ctx.batch_footprint() / 2 ** 30, 2)
+        for st in streams:
+            st.close()
+        ctx.close()
+    res["groups"] = 64
+    res["output_mpix"] = round(mpix, 2)
+    res["clips"] = [f"{w}x{h} {b}-bit {c}" for (w, h, b, c) in clips]
+    res["speedup_fp16_batched_vs_fp32_single"] = round(
+        res["fp32_one_at_a_time"]["ms"] / res["fp16_batched_graph"]["ms"], 2)
+    return res
+
+
+def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=120, max_batch_mpx=16.0):
+    """16 streams (540p/1080p, 8/10-bit 4:2:0, 30-300 frames, cuts every 10-60 frames)
+    whose frames arrive as Poisson processes totalling `rate` groups/s, truncated at
+    `duration` seconds of arrivals; FP16 network C=64, R=10; admission by HBM footprint."""
+    from paper_2308_03121_amd.serving import GpuExecutor, Server, poisson_workload
+
+    specs = poisson_workload(n_streams=16, rate_total=rate, seed=3, max_time=duration)
+    fmts = {(s.width, s.height, s.bits, s.chroma) for s in specs}
+    banks = {f: _frame_bank(B, synth, *f, scenes=2, per=4, seed=sum(f)) for f in fmts}
+
+    def source(spec, t):
+        k = sum(1 for c in spec.scene_starts if c <= t)
+        start = ([0] + [c for c in spec.scene_starts if c <= t])[-1]
+        bank = banks[(spec.width, spec.height, spec.bits, spec.chroma)]
+        scene = bank[(k + spec.sid) % len(bank)]
+        return scene[(t - start) % len(scene)]
+
+    cfg = synth.NET_C2
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, synth.gen_weights(cfg, seed=1),
+                    precision="fp16")
+    ctx.autotune(544, 960)
+    out = {}
+    for label, sp in (("poisson", specs), ("saturation", [type(s)(s.sid, s.width, s.height, s.bits, s.chroma,
+                                                                    [0.0] * s.n_frames, s.scene_starts)
+                                                               for s in specs])):
+        ex = GpuExecutor(ctx, source, batch_share_per_px=0, max_chain=4)
+        srv = Server(ex, hbm_budget=int(budget_gb * 2 ** 30), max_chain=4, max_batch_px=int(max_batch_mpx * 1e6))
+        rep = srv.run(sp)
+        torch.cuda.synchronize()
+        ex.shutdown()
+        out[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}
+    out["streams"] = len(specs)
+    out["frames"] = sum(s.n_frames for s in specs)
+    out["arrival_rate_groups_per_s"] = rate
+    out["hbm_budget_gb"] = budget_gb
+    out["max_batch_lr_mpx"] = max_batch_mpx
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,13 +213,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--also", default="fp16,bf16",
                     help="other precisions timed on the same clip after the main run ('' for none)")
+    ap.add_argument("--no-batching", action="store_true", help="skip the 64-group batching run")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path needs no collective and this build runs on a "
               f"single MI355X (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
@@ -224,6 +339,21 @@ def main():
         c2.close()
     if others:
         rec["other_precisions"] = others
+        print("# other precisions: " + json.dumps(others), file=sys.stderr, flush=True)
+    if not args.no_batching:
+        print("# batching: 64 groups of mixed clips", file=sys.stderr, flush=True)
+        try:
+            rec["batching"] = batching_bench(B, synth, torch)
+        except Exception as e:  # report, keep the main measurement
+            rec["batching"] = {"error": f"{type(e).__name__}: {e}"}
+        print("# batching: " + json.dumps(rec["batching"]), file=sys.stderr, flush=True)
+    if not args.no_serving:
+        print("# serving: Poisson arrivals of 16 streams", file=sys.stderr, flush=True)
+        try:
+            rec["serving"] = serving_bench(B, synth, torch, duration=args.serving_seconds)
+        except Exception as e:
+            rec["serving"] = {"error": f"{type(e).__name__}: {e}"}
+        print("# serving: " + json.dumps(rec["serving"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(clip, blob, cfg)

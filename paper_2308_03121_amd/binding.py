@@ -45,9 +45,9 @@ def planes_struct(Y: torch.Tensor, U: torch.Tensor, V: torch.Tensor) -> NvPlanes
 def alloc_frame(width, height, bits, chroma, device="cuda"):
     dt = torch.uint8 if bits == 8 else torch.int16
     hc, wc = chroma_shape(width, height, chroma)
-    return (torch.zeros((height, width), dtype=dt, device=device),
-            torch.zeros((hc, wc), dtype=dt, device=device),
-            torch.zeros((hc, wc), dtype=dt, device=device))
+    return (torch.empty((height, width), dtype=dt, device=device),
+            torch.empty((hc, wc), dtype=dt, device=device),
+            torch.empty((hc, wc), dtype=dt, device=device))
 
 
 def to_device_frame(Y: np.ndarray, U: np.ndarray, V: np.ndarray, device="cuda"):
