@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAKS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0}   # dense TFLOP/s
+PEAKS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp8-fusion": 5000.0}   # dense TFLOP/s
 HBM_PEAK_GBS = 8000.0
 
 
@@ -92,6 +92,57 @@ def cpu_baseline(clip, blob, cfg, budget_s=20.0):
     return best
 
 
+def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16", "fp8", "fp8-fusion"), steps=2):
+    """The 48-frame 1920x1080 10-bit 4:2:0 clip (cuts at 16 and 32) pushed through a
+    stream in each precision: 96 output frames of 3840x2160 per step.  fp8 quantises the
+    residual trunk; fp8-fusion also the DCN and pixel-shuffle conv (below the 50 dB bar
+    on this network, reported for speed only)."""
+    clip = synth.gen_clip_c3()
+    fmt = B.fmt_struct(clip.width, clip.height, clip.bits, clip.chroma)
+    frames = [B.to_device_frame(*clip.frame(t)) for t in range(clip.n_frames)]
+    outs = [B.alloc_frame(2 * clip.width, 2 * clip.height, clip.bits, clip.chroma) for _ in range(2 * clip.n_frames)]
+    hp, wp = (clip.height + 7) // 8 * 8, (clip.width + 7) // 8 * 8
+    mpix = 2 * clip.n_frames * 4 * clip.width * clip.height / 1e6
+    res = {"workload": "48-frame 1920x1080 10-bit 4:2:0 clip, cuts at 16 and 32, C=64 R=10 G=8",
+           "output_mpix_per_step": round(mpix, 2)}
+    for prec in precs:
+        ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec.split("-")[0],
+                        fp8_fusion=prec == "fp8-fusion")
+        ctx.autotune(hp, wp)
+        if prec.startswith("fp8"):
+            ctx.calibrate(fmt, frames[:4])
+        st = ctx.open_stream(fmt)
+
+        def run():
+            st.reset()
+            for t in range(clip.n_frames):
+                o = outs[2 * (t - 1):2 * t] if t > 0 else outs[0:2]
+                st.push(frames[t], outs=o)
+            st.end(outs=outs[2 * clip.n_frames - 2:])
+
+        run()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1000.0
+        pr = ctx.profile_read()
+        cuts = [t for t, c in enumerate(st.cuts()) if c]
+        res[prec] = {"value": round(mpix / (ms / 1000.0), 3), "unit": "Mpix/s", "ms_per_step": round(ms, 2),
+                     "cuts": cuts,
+                     "kernel_ms_per_step": {k: round(v[1] / steps, 2) for k, v in pr.items() if v[0]}}
+        print(f"# c3 {prec}: {res[prec]['value']} Mpix/s", file=sys.stderr, flush=True)
+        st.close()
+        ctx.close()
+    if "fp32" in res:
+        for prec in precs:
+            if prec != "fp32" and prec in res:
+                res[prec]["speedup_vs_fp32"] = round(res[prec]["value"] / res["fp32"]["value"], 3)
+    return res
+
+
 def _frame_bank(B, synth, w, h, bits, chroma, scenes=2, per=4, seed=0):
     """Device frames of a few scenes of one format (synthetic clip, cut between scenes)."""
     clip = synth.gen_clip(w, h, scenes * per, bits=bits, chroma=chroma, seed=seed,
@@ -102,8 +153,9 @@ def _frame_bank(B, synth, w, h, bits, chroma, scenes=2, per=4, seed=0):
 
 def batching_bench(B, synth, torch, reps=3):
     """64 frame groups from 16 clips (4 consecutive groups each, the frame store of a
-    5-frame chain) of mixed sizes and formats in one batched call, FP16 network C=64, R=6,
-    tiles from the autotuner, graph replay; against the same groups one at a time in FP32."""
+    5-frame chain) of mixed sizes and formats in one batched call, FP16 (and FP8) network
+    C=64, R=6, tiles from the autotuner, graph replay; against the same groups one at a
+    time in FP32."""
     rng = np.random.default_rng(2)
     sizes = [(640, 360), (960, 540), (1280, 720)]
     fmts = [(8, 420), (10, 420), (8, 444), (10, 444)]
@@ -119,9 +171,12 @@ def batching_bench(B, synth, torch, reps=3):
     blob = synth.gen_weights(cfg, seed=1)
     res = {}
     mpix = sum(4 * 2 * (2 * w) * (2 * h) for (w, h, _b, _c) in clips) / 1e6
-    for prec in ("fp16", "fp32"):
+    for prec in ("fp16", "fp8", "fp32"):
         ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
         tune = ctx.autotune(544, 960)
+        if prec == "fp8":
+            w0, h0, b0, c0 = clips[0]
+            ctx.calibrate(B.fmt_struct(w0, h0, b0, c0), banks[clips[0]])
         streams = [ctx.open_stream(B.fmt_struct(w, h, b, c)) for (w, h, b, c) in clips]
 
         def one_batch():
@@ -137,7 +192,7 @@ def batching_bench(B, synth, torch, reps=3):
                 for f in banks[k]:
                     st.push(f)
 
-        runs = {"batched_graph": one_batch} if prec == "fp16" else {"one_at_a_time": one_at_a_time}
+        runs = {"batched_graph": one_batch} if prec != "fp32" else {"one_at_a_time": one_at_a_time}
         if prec == "fp16":
             runs["one_at_a_time"] = one_at_a_time
         for name, fn in runs.items():
@@ -160,6 +215,8 @@ def batching_bench(B, synth, torch, reps=3):
     res["clips"] = [f"{w}x{h} {b}-bit {c}" for (w, h, b, c) in clips]
     res["speedup_fp16_batched_vs_fp32_single"] = round(
         res["fp32_one_at_a_time"]["ms"] / res["fp16_batched_graph"]["ms"], 2)
+    res["speedup_fp8_batched_vs_fp32_single"] = round(
+        res["fp32_one_at_a_time"]["ms"] / res["fp8_batched_graph"]["ms"], 2)
     return res
 
 
@@ -208,14 +265,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS) + ["fp8-fusion"])
     ap.add_argument("--frames", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--also", default="fp16,bf16",
+    ap.add_argument("--also", default="fp16,bf16,fp8",
                     help="other precisions timed on the same clip after the main run ('' for none)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 1080p 10-bit per-precision run")
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-group batching run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serving-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path needs no collective and this build runs on a "
@@ -230,6 +290,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_only:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE per dispatch of this kernel
+        # calibrate the counters against bytes actually moved
+        n = args.copy_only * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
     print(f"# generating the 960x540 clip ({args.frames} frames)", file=sys.stderr, flush=True)
     clip = synth.gen_clip_c2(n_frames=args.frames)
     cfg = synth.NET_C2
@@ -241,7 +312,11 @@ def main():
     hp, wp = (H_ + 7) // 8 * 8, (W_ + 7) // 8 * 8
 
     def make(prec):
-        c = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+        c = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec.split("-")[0],
+                      fp8_fusion=prec == "fp8-fusion")
+        c.autotune(hp, wp)
+        if prec.startswith("fp8"):
+            c.calibrate(fmt, frames[:4])
         return c, c.open_stream(fmt)
 
     def run_clip(st):
@@ -340,6 +415,13 @@ def main():
     if others:
         rec["other_precisions"] = others
         print("# other precisions: " + json.dumps(others), file=sys.stderr, flush=True)
+    if not args.no_c3:
+        print("# precisions on the 48-frame 1920x1080 10-bit clip", file=sys.stderr, flush=True)
+        try:
+            rec["c3_precisions"] = c3_precision_bench(B, synth, torch, cfg, blob)
+        except Exception as e:
+            rec["c3_precisions"] = {"error": f"{type(e).__name__}: {e}"}
+        print("# c3: " + json.dumps(rec["c3_precisions"]), file=sys.stderr, flush=True)
     if not args.no_batching:
         print("# batching: 64 groups of mixed clips", file=sys.stderr, flush=True)
         try:

@@ -39,8 +39,15 @@ typedef enum {
   NV_E_BUSY = 5          /* serving queue full / admission refused */
 } nv_status;
 
-/* Arithmetic of the network's convolutions (the offset head, the bilinear sampling
- * weights and all pixel-format stages are FP32 in every mode). */
+/* Arithmetic of the network's convolutions (the offset head is float-class, see
+ * NV_FLAG_HEAD_FP32; the bilinear sampling weights and all pixel-format stages are FP32
+ * in every mode).  FP16 / BF16 store the
+ * feature maps in that type and run every other conv on it with FP32 accumulation.
+ * NV_FP8_E4M3 (64 channels only) stores feature maps in FP16, runs the residual-block
+ * convs (and with NV_FLAG_FP8_FUSION the deformable conv and the pixel-shuffle conv)
+ * with OCP e4m3 operands (per output channel weight scales max|W|/448, one static
+ * activation scale per layer, see nv_calibrate) and FP32 accumulation, and every other
+ * conv as in FP16. */
 typedef enum { NV_FP32 = 0, NV_FP16 = 1, NV_BF16 = 2, NV_FP8_E4M3 = 3 } nv_precision;
 
 /* Network flags of the paper's network-integration section (section 3.1):
@@ -48,6 +55,23 @@ typedef enum { NV_FP32 = 0, NV_FP16 = 1, NV_BF16 = 2, NV_FP8_E4M3 = 3 } nv_preci
  * frames, Double frame means it emits 2n frames.  The implemented network is
  * n = 1 with all three set. */
 enum { NV_FLAG_INTERP = 1, NV_FLAG_EXTRA = 2, NV_FLAG_DOUBLE = 4 };
+
+/* Offset head arithmetic (a library option, not one of the paper's flags).  The head
+ * (both convs of the offset/mask prediction) is float-class in every precision.  In
+ * FP32 mode it runs on float MFMA.  In the FP16 / BF16 / FP8 modes it runs by default on
+ * float16 MFMA with each weight carried as two float16 parts (hi + lo, about 22 bits)
+ * and the float input of its second conv staged the same way, products exact and
+ * accumulated in float; NV_FLAG_HEAD_FP32 in nv_net_config.flags selects float MFMA
+ * there too. */
+enum { NV_FLAG_HEAD_FP32 = 8 };
+
+/* FP8 scope (library option, NV_FP8_E4M3 only).  By default FP8 covers the residual
+ * blocks of the extract stage (the bulk of the work); the deformable conv and the
+ * pixel-shuffle conv run as in FP16 mode, which keeps every output frame of the
+ * 1920x1080, C = 64, R = 10 network above 50 dB PSNR against the FP64 reference.
+ * NV_FLAG_FP8_FUSION puts those two convs on e4m3 too (faster, measured 45.8 dB on that
+ * network's worst window). */
+enum { NV_FLAG_FP8_FUSION = 16 };
 
 /* Frame format.  width/height are luma sizes (even for 4:2:0); bits is 8 (uint8
  * samples) or 10 (uint16 little-endian samples holding the code in the low 10 bits;
@@ -62,9 +86,10 @@ typedef struct {
   int64_t pitch_bytes[3];
 } nv_planes;
 
-/* Network shape.  channels C (32 or 64), res_blocks R (0..64), offset_groups G (even,
- * 2C divisible by G, 2C/G a multiple of 4), scale must be 2, align must be 8,
- * flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE. */
+/* Network shape.  channels C (32 or 64; 64 for NV_FP8_E4M3), res_blocks R (0..64),
+ * offset_groups G (even, 2C divisible by G, 2C/G a multiple of 4), scale must be 2,
+ * align must be 8, flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE, optionally
+ * with NV_FLAG_HEAD_FP32 and (FP8 only) NV_FLAG_FP8_FUSION. */
 typedef struct {
   int32_t channels, res_blocks, offset_groups, scale, align;
   uint32_t flags;
@@ -99,6 +124,28 @@ const char* nv_last_error(void);
 
 /* Number of floats the weight blob of `cfg` must hold (0 if cfg is invalid). */
 size_t nv_weight_count(const nv_net_config* cfg);
+
+/* FP8 activation scales.  An NV_FP8_E4M3 context quantises the input of each of its
+ * FP8 layers (in this order: block.a and block.b of each residual block, then with
+ * NV_FLAG_FP8_FUSION the deformable conv and the pixel-shuffle conv; 2R or 2R + 2
+ * layers) with a static scale amax / 448, where amax
+ * is the largest |input| the layer saw during calibration; the scales stay fixed
+ * afterwards, so a frame's result does not depend on what it is batched with.  Every
+ * enhancement call of an FP8 context fails with NV_E_INVALID until one of these has
+ * been called.
+ *
+ * nv_calibrate runs the network over the n_frames (>= 2, device planes of format fmt)
+ * as consecutive frame groups (0,1), (1,2), ... without scene detection, and sets each
+ * layer's amax to the largest |input| seen (the layers after it already use the
+ * updated scales).  It uses the context's workspace, enqueues on `stream` and does not
+ * synchronise.  NV_E_INVALID for contexts of other precisions.
+ *
+ * nv_fp8_scales reads (set = 0) or writes (set = 1) the n (2R or 2R + 2) amax values in
+ * host memory, e.g. to reuse one calibration in other contexts; it synchronises
+ * `stream`.  Written values must be finite and >= 0 (0 means scale 1). */
+nv_status nv_calibrate(nv_context* ctx, const nv_format* fmt, const nv_planes* frames, int32_t n_frames,
+                       void* stream);
+nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int32_t set, void* stream);
 
 /* ------------------------------------------------- pixel-format stages ---- */
 

@@ -14,6 +14,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "nnvisr.h")
 NV_OK, NV_E_INVALID, NV_E_UNSUPPORTED, NV_E_NOMEM, NV_E_DEVICE, NV_E_BUSY = range(6)
 NV_FP32, NV_FP16, NV_BF16, NV_FP8_E4M3 = range(4)
 NV_FLAG_INTERP, NV_FLAG_EXTRA, NV_FLAG_DOUBLE = 1, 2, 4
+NV_FLAG_HEAD_FP32 = 8
+NV_FLAG_FP8_FUSION = 16
 STATUS_NAMES = {0: "NV_OK", 1: "NV_E_INVALID", 2: "NV_E_UNSUPPORTED", 3: "NV_E_NOMEM",
                 4: "NV_E_DEVICE", 5: "NV_E_BUSY"}
 
@@ -74,6 +76,8 @@ _SIGS = {
     "nv_batch_graph": (c_int32, [c_void_p, c_int32]),
     "nv_batch_footprint": (c_int32, [c_void_p, POINTER(c_size_t)]),
     "nv_autotune": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, ctypes.c_char_p, c_size_t]),
+    "nv_calibrate": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), c_int32, c_void_p]),
+    "nv_fp8_scales": (c_int32, [c_void_p, PF, c_int32, c_int32, c_void_p]),
 }
 NV_K_COUNT = 10
 

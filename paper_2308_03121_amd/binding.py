@@ -115,11 +115,16 @@ class Context:
     """A network context: repacked weights and workspace on one device."""
 
     def __init__(self, channels: int, res_blocks: int, offset_groups: int, weights: np.ndarray,
-                 precision: str = "fp32", device: int = 0):
+                 precision: str = "fp32", device: int = 0, head_fp32: bool = False,
+                 fp8_fusion: bool = False):
         lib = _abi.load()
-        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8,
-                               _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | _abi.NV_FLAG_DOUBLE,
-                               PRECISIONS[precision])
+        flags = _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | _abi.NV_FLAG_DOUBLE
+        if head_fp32:
+            flags |= _abi.NV_FLAG_HEAD_FP32
+        if fp8_fusion:
+            flags |= _abi.NV_FLAG_FP8_FUSION
+        self.fp8_fusion = fp8_fusion
+        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, flags, PRECISIONS[precision])
         w = np.ascontiguousarray(weights, dtype=np.float32)
         self._h = c_void_p()
         check(lib.nv_context_create(device, byref(self.cfg),
@@ -128,7 +133,9 @@ class Context:
         self.channels = channels
         self.offset_groups = offset_groups
         self.device = torch.device("cuda", device)
-        self.feat_dtype = {4: torch.float32, 2: torch.float16 if precision == "fp16" else torch.bfloat16}[
+        self.precision = precision
+        self.res_blocks = res_blocks
+        self.feat_dtype = {4: torch.float32, 2: torch.bfloat16 if precision == "bf16" else torch.float16}[
             lib.nv_feature_elem_bytes(self._h)]
         self.ldo = 16 * ((27 * offset_groups + 15) // 16)
 
@@ -228,6 +235,19 @@ class Context:
         buf = ctypes.create_string_buffer(1024)
         check(_abi.load().nv_autotune(self._h, hp, wp, c_void_p(_stream(stream)), buf, 1024))
         return buf.value.decode()
+
+    def calibrate(self, fmt: NvFormat, frames, stream=None):
+        """FP8 contexts: set the static activation scales from consecutive groups of
+        the given device frames."""
+        arr = (NvPlanes * len(frames))(*[planes_struct(*f) for f in frames])
+        check(_abi.load().nv_calibrate(self._h, byref(fmt), arr, len(frames), c_void_p(_stream(stream))))
+
+    def fp8_scales(self, amax=None, stream=None) -> np.ndarray:
+        """FP8 contexts: read the per-layer input maxima, or set them when amax is given."""
+        n = 2 * self.res_blocks + (2 if self.fp8_fusion else 0)
+        buf = (ctypes.c_float * n)(*(amax if amax is not None else [0.0] * n))
+        check(_abi.load().nv_fp8_scales(self._h, buf, n, 0 if amax is None else 1, c_void_p(_stream(stream))))
+        return np.array(buf[:], dtype=np.float32)
 
     def profile(self, on: bool):
         check(_abi.load().nv_profile_enable(self._h, 1 if on else 0))

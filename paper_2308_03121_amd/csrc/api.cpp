@@ -2,10 +2,14 @@
 // repacking, the per-context workspace, the frame-group pipeline and clip streams.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,11 +84,14 @@ nv_status check_config(const nv_net_config* c) {
                 "offset_groups must be even and split 2C into groups of a multiple of 4 channels");
   if (c->scale != 2) return fail(NV_E_UNSUPPORTED, "only scale 2 is implemented");
   if (c->align != 8) return fail(NV_E_UNSUPPORTED, "only align 8 is implemented");
-  if (c->flags != (NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE))
+  if ((c->flags & ~(uint32_t)(NV_FLAG_HEAD_FP32 | NV_FLAG_FP8_FUSION)) != (NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE))
     return fail(NV_E_UNSUPPORTED, "only Interpolation|Extra frame|Double frame (n = 1) is implemented");
+  if ((c->flags & NV_FLAG_FP8_FUSION) && c->precision != NV_FP8_E4M3)
+    return fail(NV_E_INVALID, "NV_FLAG_FP8_FUSION needs NV_FP8_E4M3 precision");
   if (c->precision < NV_FP32 || c->precision > NV_FP8_E4M3)
     return fail(NV_E_INVALID, "precision %d is not an nv_precision", c->precision);
-  if (c->precision == NV_FP8_E4M3) return fail(NV_E_UNSUPPORTED, "FP8 precision not available");
+  if (c->precision == NV_FP8_E4M3 && c->channels != 64)
+    return fail(NV_E_UNSUPPORTED, "FP8 precision is implemented for 64 channels");
   return NV_OK;
 }
 
@@ -212,10 +219,20 @@ struct nv_context {
   BatchState* batch = nullptr;
   nv_net_config cfg{};
   int C = 0, G = 0, ldo = 0;
-  int ft = DT_F32;                  // feature storage and bulk MFMA type
+  int ft = DT_F32;                  // feature storage type
+  int bt = DT_F32;                  // MFMA type of the residual-block convs
+  int ut = DT_F32;                  // MFMA type of the DCN contraction and the pixel-shuffle conv
   PlainConv conv_in;
   std::vector<PackedConv> blocks;   // a, b per residual block
   PackedConv off1, off2, dcn, up, hr;
+  // FP8: quantised layers in calibration order (residual convs, dcn, up), each with
+  // its per-row weight scales (device) and the running input max |x| (device, float
+  // bits, one per layer); q_ready once scales were calibrated or set.
+  std::vector<PackedConv*> q_layers;
+  std::vector<float*> q_wscale;
+  uint32_t* q_amax = nullptr;
+  bool q_ready = false;
+  bool calibrating = false;
   Workspace ws;
   std::vector<void*> allocs;
 };
@@ -236,11 +253,33 @@ uint16_t to_f16_bits(float f) {
   return b;
 }
 
-// One 16-byte lane fragment of an A operand: channels [c0, c0 + 16/elem) of row-vector
-// getter g(c) in the MFMA type tc.
+// float -> OCP e4m3 (bias 7, 3 mantissa bits, largest finite 448, subnormal step 2^-9),
+// round to nearest even, saturating to +-448.  The input is finite.
+uint8_t to_e4m3_bits(float f) {
+  const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+  const double a = std::fabs((double)f);
+  if (a >= 448.0) return sign | 0x7E;
+  int e = 0;
+  std::frexp(a, &e);                       // a in [2^(e-1), 2^e)
+  int E = a > 0.0 ? e - 1 : -6;
+  if (E < -6) E = -6;                      // subnormals share the quantum of 2^-6
+  const double quantum = std::ldexp(1.0, E - 3);
+  const double v = std::nearbyint(a / quantum) * quantum;   // ties to even
+  if (v < std::ldexp(1.0, -6)) return sign | (uint8_t)(v / std::ldexp(1.0, -9));   // subnormal (or 2^-6)
+  int e2 = 0;
+  std::frexp(v, &e2);
+  const int Ev = e2 - 1;
+  const int mant = (int)(v / std::ldexp(1.0, Ev - 3)) - 8;
+  return sign | (uint8_t)((Ev + 7) << 3) | (uint8_t)mant;
+}
+
+// One lane fragment of an A operand: elements [c0, c0 + n) of row-vector getter g(c)
+// in the MFMA type tc (n = 4 floats, 8 16-bit values or 32 e4m3 values).
 template <class G>
 void put_fragment(uint8_t* dst, int tc, int c0, G g) {
-  if (tc == DT_F32) {
+  if (tc == DT_F8) {
+    for (int e = 0; e < 32; ++e) dst[e] = to_e4m3_bits(g(c0 + e));
+  } else if (tc == DT_F32) {
     for (int e = 0; e < 4; ++e) {
       const float v = g(c0 + e);
       std::memcpy(dst + 4 * e, &v, 4);
@@ -297,6 +336,158 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
   return NV_OK;
 }
 
+// Two-part float16 fragments of an offset-head conv (float-class head on float16 MFMA):
+// with v = s * W[o][c % cin][tap] (s a power of two putting max |v| near 2^14), A
+// position (kgroup, ob) holds two fragments, part 0 = f16(v) and part 1 = f16(v - f16(v)):
+//   frag[((tap * NKG + kg) * 2*obtot + 2*ob + part) * 64 + lane], c = 32*kg + 8*(lane/16) + e
+// over dup * cin input channels (dup = 2: the float input is staged as [hi | lo] and
+// both halves meet the same weights).  oscale[r] = 1/s undoes the scaling.
+nv_status pack_conv_split(nv_context* ctx, const float* w, const float* b, int cout, int cin, int dup,
+                          PackedConv* out) {
+  const int cin_v = cin * dup, KG = 32, nkg = cin_v / KG;
+  const int obtot = (cout + 15) / 16;
+  float m = 0.0f;
+  for (size_t k = 0; k < (size_t)cout * cin * 9; ++k) m = std::max(m, std::fabs(w[k]));
+  int e = m > 0.0f ? (int)std::floor(std::log2(16384.0 / m)) : 0;
+  e = std::min(std::max(e, -14), 30);
+  const float s = std::ldexp(1.0f, e);
+  std::vector<uint8_t> frag((size_t)9 * nkg * 2 * obtot * 64 * 16, 0);
+  for (int tap = 0; tap < 9; ++tap)
+    for (int kg = 0; kg < nkg; ++kg)
+      for (int ob = 0; ob < obtot; ++ob)
+        for (int part = 0; part < 2; ++part)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int o = 16 * ob + lane % 16;
+            if (o >= cout) continue;
+            const int c0 = KG * kg + (KG / 4) * (lane / 16);
+            put_fragment(&frag[((((size_t)tap * nkg + kg) * 2 * obtot + 2 * ob + part) * 64 + lane) * 16],
+                         DT_F16, c0, [&](int c) {
+                           const float v = w[((size_t)o * cin + c % cin) * 9 + tap] * s;
+                           const float hi = (float)(_Float16)v;
+                           return part == 0 ? hi : v - hi;
+                         });
+          }
+  std::vector<float> bias((size_t)obtot * 16, 0.0f), inv((size_t)obtot * 16, 1.0f / s);
+  for (int r = 0; r < cout; ++r) bias[r] = b[r];
+  out->cin = cin_v;
+  out->cout = cout;
+  out->obtot = obtot;
+  out->tc = DT_F16;
+  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  ctx->allocs.push_back(out->frag);
+  HIP_TRY(dev_alloc(&out->bias, bias.size()));
+  ctx->allocs.push_back(out->bias);
+  HIP_TRY(dev_alloc(&out->oscale, inv.size()));
+  ctx->allocs.push_back(out->oscale);
+  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->oscale, inv.data(), inv.size() * 4, hipMemcpyHostToDevice));
+  return NV_OK;
+}
+
+// Per A row r (output channel rowmap(r)), the FP8 weight scale max |W| / 448.
+std::vector<float> f8_row_scales(const float* w, int cout, int cin, int obtot, const std::function<int(int)>& rowmap) {
+  std::vector<float> sc((size_t)obtot * 16, 1.0f);
+  for (int r = 0; r < cout; ++r) {
+    const int o = rowmap(r);
+    float m = 0.0f;
+    for (size_t k = 0; k < (size_t)cin * 9; ++k) m = std::max(m, std::fabs(w[(size_t)o * cin * 9 + k]));
+    sc[r] = m > 0.0f ? m / 448.0f : 1.0f;
+  }
+  return sc;
+}
+
+// FP8 fragments of a 64-channel 3x3 conv (residual blocks, pixel-shuffle conv), 32 bytes
+// per lane, five steps of two taps:
+//   frag[(st * obtot + ob) * 64 + lane][e] = e4m3(W[o][c][tap] / s_w[r])
+// with r = 16*ob + lane%16, o = rowmap(r), q = lane/16, tap = 2*st + q/2, c = 32*(q%2) + e,
+// and zero where tap = 9.  wscale receives s_w per A row.
+nv_status pack_conv_f8(nv_context* ctx, const float* w, const float* b, int cout, int cin, bool shuffle,
+                       PackedConv* out, std::vector<float>* wscale) {
+  const int obtot = (cout + 15) / 16;
+  std::vector<uint8_t> frag((size_t)5 * obtot * 64 * 32, 0);
+  std::vector<float> bias((size_t)obtot * 16, 0.0f);
+  auto rowmap = [&](int r) -> int {
+    if (!shuffle) return r;
+    const int ob = r / 16, t = r % 16;
+    return 4 * (16 * (ob / 4) + t) + (ob % 4);
+  };
+  *wscale = f8_row_scales(w, cout, cin, obtot, rowmap);
+  for (int st = 0; st < 5; ++st)
+    for (int ob = 0; ob < obtot; ++ob)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int r = 16 * ob + lane % 16, q = lane / 16;
+        const int tap = 2 * st + q / 2;
+        if (r >= cout || tap > 8) continue;
+        const int o = rowmap(r);
+        const float inv = 1.0f / (*wscale)[r];
+        put_fragment(&frag[(((size_t)st * obtot + ob) * 64 + lane) * 32], DT_F8, 32 * (q % 2),
+                     [&](int c) { return w[((size_t)o * cin + c) * 9 + tap] * inv; });
+      }
+  for (int r = 0; r < cout; ++r) bias[r] = b[rowmap(r)];
+  out->cin = cin;
+  out->cout = cout;
+  out->obtot = obtot;
+  out->tc = DT_F8;
+  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  ctx->allocs.push_back(out->frag);
+  HIP_TRY(dev_alloc(&out->bias, bias.size()));
+  ctx->allocs.push_back(out->bias);
+  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->bias, bias.data(), bias.size() * 4, hipMemcpyHostToDevice));
+  return NV_OK;
+}
+
+// A-operand fragments of the deformable conv (C out, 2C in, G offset groups), in the
+// phase order its kernel reduces in.  The 2C input channels are cut into chunks of
+// CW = min(CPG, KG) channels (CPG = 2C / G); phase ph covers chunks u = ph*GP + gi,
+// gi < GP = KG / CW, each with all nine taps, and is 9 steps of KG deep:
+//   frag[((ph*9 + st) * obtot + ob) * 64 + lane] = W[o = 16*ob + lane%16][ci][tap]
+// for k = KG*st + (KG/4)*(lane/16) + e, gi = k / (9*CW), tap = (k / CW) % 9,
+// ci = (ph*GP + gi)*CW + k % CW.  FP8 fragments are 32 bytes (KG = 128) and hold
+// W / s_w[o] with s_w the per output channel scale returned in wscale.
+nv_status pack_dcn(nv_context* ctx, const float* w, const float* b, int C, int G, int tc, PackedConv* out,
+                   std::vector<float>* wscale) {
+  const int KG = tc == DT_F32 ? 16 : (tc == DT_F8 ? 128 : 32);
+  const int fb = tc == DT_F8 ? 32 : 16;    // fragment bytes per lane
+  const int cin = 2 * C, cpg = cin / G;
+  const int CW = cpg < KG ? cpg : KG, GP = KG / CW;
+  const int nphase = cin / (GP * CW);
+  const int obtot = C / 16;
+  std::vector<float> sc((size_t)obtot * 16, 1.0f);
+  if (tc == DT_F8) {
+    sc = f8_row_scales(w, C, cin, obtot, [](int r) { return r; });
+    *wscale = sc;
+  }
+  std::vector<uint8_t> frag((size_t)nphase * 9 * obtot * 64 * fb, 0);
+  for (int ph = 0; ph < nphase; ++ph)
+    for (int st = 0; st < 9; ++st)
+      for (int ob = 0; ob < obtot; ++ob)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int o = 16 * ob + lane % 16;
+          const int k0 = KG * st + (KG / 4) * (lane / 16);
+          const float inv = 1.0f / sc[o];
+          put_fragment(&frag[((((size_t)ph * 9 + st) * obtot + ob) * 64 + lane) * fb], tc, 0, [&](int e) {
+            const int k = k0 + e;
+            const int gi = k / (9 * CW), tap = (k / CW) % 9;
+            const int ci = (ph * GP + gi) * CW + k % CW;
+            const float v = w[((size_t)o * cin + ci) * 9 + tap];
+            return tc == DT_F8 ? v * inv : v;
+          });
+        }
+  out->cin = cin;
+  out->cout = C;
+  out->obtot = obtot;
+  out->tc = tc;
+  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  ctx->allocs.push_back(out->frag);
+  HIP_TRY(dev_alloc(&out->bias, C));
+  ctx->allocs.push_back(out->bias);
+  HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(out->bias, b, (size_t)C * 4, hipMemcpyHostToDevice));
+  return NV_OK;
+}
+
 // Tap-response matrix of the C -> 3 HR conv: row r = 3*tap + o (27 rows, padded to 32),
 //   frag[(kg*2 + ob)*64 + lane] = Wr[r = 16*ob + lane%16][c = KG*kg + (KG/4)*(lane/16) + e]
 // with Wr[3*tap + o][c] = w[o][c][tap].
@@ -333,6 +524,36 @@ nv_status upload(nv_context* ctx, const std::vector<float>& v, float** out) {
   HIP_TRY(dev_alloc(out, v.size()));
   ctx->allocs.push_back(*out);
   HIP_TRY(hipMemcpy(*out, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+  return NV_OK;
+}
+
+// Device scales of the FP8 layers (residual convs in order, dcn, up): per-row weight
+// scales, output scales and reciprocal activation scales, with every running input
+// maximum at zero (activation scale 1) until calibration.
+nv_status init_fp8_state(nv_context* ctx, const std::vector<std::vector<float>>& wscales) {
+  for (auto& b : ctx->blocks) ctx->q_layers.push_back(&b);
+  if (ctx->ut == DT_F8) {
+    ctx->q_layers.push_back(&ctx->dcn);
+    ctx->q_layers.push_back(&ctx->up);
+  }
+  if (wscales.size() != ctx->q_layers.size()) return fail(NV_E_INVALID, "FP8 layer count mismatch");
+  const size_t nq = ctx->q_layers.size();
+  HIP_TRY(dev_alloc(&ctx->q_amax, nq));
+  ctx->allocs.push_back(ctx->q_amax);
+  HIP_TRY(hipMemset(ctx->q_amax, 0, nq * sizeof(uint32_t)));
+  for (size_t l = 0; l < nq; ++l) {
+    PackedConv* P = ctx->q_layers[l];
+    float* ws = nullptr;
+    const nv_status st = upload(ctx, wscales[l], &ws);
+    if (st != NV_OK) return st;
+    ctx->q_wscale.push_back(ws);
+    HIP_TRY(dev_alloc(&P->oscale, (size_t)P->obtot * 16));
+    ctx->allocs.push_back(P->oscale);
+    HIP_TRY(dev_alloc(&P->ainv, 1));
+    ctx->allocs.push_back(P->ainv);
+    HIP_TRY(launch_qscale(ctx->q_amax + l, ws, P->oscale, P->ainv, P->obtot * 16, nullptr));
+  }
+  HIP_TRY(hipDeviceSynchronize());
   return NV_OK;
 }
 
@@ -428,6 +649,15 @@ ConvImg conv_img(const void* src0, const void* src1, const uint32_t* sel, const 
   return im;
 }
 
+// FP8 calibration step of quantised layer l: fold max |x| of its inputs (float16 maps
+// of n elements each) into the layer's running maximum, then refresh its scales.
+nv_status calib_layer(nv_context* ctx, int l, std::initializer_list<const void*> inputs, size_t n, hipStream_t s) {
+  for (const void* x : inputs) NV_TRY(check_launch(launch_amax(DT_F16, x, n, ctx->q_amax + l, s), "amax"));
+  PackedConv* P = ctx->q_layers[l];
+  return check_launch(launch_qscale(ctx->q_amax + l, ctx->q_wscale[l], P->oscale, P->ainv, P->obtot * 16, s),
+                      "qscale");
+}
+
 nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
   NV_TRY(ensure_workspace(ctx, hp, wp));
   const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
@@ -435,10 +665,13 @@ nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* 
                [&] { return launch_conv_in(ctx->conv_in, ft, rgb, feat, hp, wp, s); }));
   const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->ws.t0, hp, wp);
   const ConvImg ib = conv_img(ctx->ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
+  const size_t n = (size_t)hp * wp * C;
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
+    if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r, {feat}, n, s));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.a", [&] {
       return launch_conv(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, ia, C, 0, s);
     }));
+    if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r + 1, {ctx->ws.t0}, n, s));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.b", [&] {
       return launch_conv(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, ib, C, 0, s);
     }));
@@ -473,6 +706,8 @@ nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, con
     di.H = hp;
     di.W = wp;
     di.item_begin = 0;
+    if (ctx->calibrating && ctx->ut == DT_F8)
+      NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks, {fa, fb}, (size_t)hp * wp * C, s));
     NV_TRY(timed(ctx, NV_K_DCN, s, "dcn",
                  [&] { return launch_dcn(ctx->dcn, ft, ctx->tune.pb_dcn, di, ctx->ldo, G, s); }));
   }
@@ -482,6 +717,8 @@ nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, con
     const void* alt = t == 2 ? fa : nullptr;
     const int tsel = t == 0 ? 0 : (t == 1 ? 2 : 1);
     const ConvImg iu = conv_img(g, nullptr, sel, alt, nullptr, nullptr, ws.u, hp, wp);
+    if (ctx->calibrating && ctx->ut == DT_F8)
+      NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks + 1, {g}, (size_t)hp * wp * C, s));
     NV_TRY(timed(ctx, NV_K_UP, s, "up", [&] {
       return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, iu, 4 * C, 0, s);
     }));
@@ -539,7 +776,14 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   ctx->C = cfg->channels;
   ctx->G = cfg->offset_groups;
   ctx->ldo = 16 * ((27 * ctx->G + 15) / 16);
-  ctx->ft = cfg->precision == NV_FP16 ? DT_F16 : (cfg->precision == NV_BF16 ? DT_BF16 : DT_F32);
+  ctx->ft = cfg->precision == NV_FP16 || cfg->precision == NV_FP8_E4M3
+                ? DT_F16
+                : (cfg->precision == NV_BF16 ? DT_BF16 : DT_F32);
+  ctx->bt = cfg->precision == NV_FP8_E4M3 ? DT_F8 : ctx->ft;
+  ctx->ut = (cfg->flags & NV_FLAG_FP8_FUSION) ? DT_F8 : ctx->ft;
+  if (ctx->ut == DT_F8) ctx->tune.pb_dcn = 1;   // the FP8 DCN tile is one row per wave
+  std::vector<std::vector<float>> wscales;      // FP8 row scales in calibration order
+  std::vector<float> dcn_ws, up_ws;
   const auto specs = layer_specs(*cfg);
   const float* p = weights;
   nv_status st = NV_OK;
@@ -556,17 +800,37 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
       if (st == NV_OK) st = upload(ctx, std::vector<float>(b, b + L.cout), &ctx->conv_in.b);
     } else if (nm == "hr") {
       st = pack_hr(ctx, w, b, L.cin, ctx->ft, &ctx->hr);
+    } else if (nm == "dcn") {
+      st = pack_dcn(ctx, w, b, L.cout, ctx->G, ctx->ut, &ctx->dcn, &dcn_ws);
     } else {
-      // the offset head stays in float in every precision
-      const int tc = (nm == "off1" || nm == "off2") ? DT_F32 : ctx->ft;
+      // the offset head stays float-class in every precision: float MFMA in FP32 mode
+      // (or on request), two-part float16 weights on float16 MFMA otherwise
+      const bool head = nm == "off1" || nm == "off2";
+      const bool split = head && ctx->ft != DT_F32 && !(cfg->flags & NV_FLAG_HEAD_FP32);
+      const int tc = head ? DT_F32 : (nm == "up" ? ctx->ut : ctx->bt);
       PackedConv pc;
-      st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up", tc, &pc);
+      if (split) {
+        st = pack_conv_split(ctx, w, b, L.cout, L.cin, nm == "off2" ? 2 : 1, &pc);
+      } else if (tc == DT_F8) {
+        std::vector<float> ws;
+        st = pack_conv_f8(ctx, w, b, L.cout, L.cin, nm == "up", &pc, &ws);
+        if (nm == "up") up_ws = ws;
+        else wscales.push_back(ws);
+      } else {
+        st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up", tc, &pc);
+      }
       if (nm == "block.a" || nm == "block.b") ctx->blocks.push_back(pc);
       else if (nm == "off1") ctx->off1 = pc;
       else if (nm == "off2") ctx->off2 = pc;
-      else if (nm == "dcn") ctx->dcn = pc;
       else if (nm == "up") ctx->up = pc;
     }
+  }
+  if (st == NV_OK && ctx->bt == DT_F8) {
+    if (ctx->ut == DT_F8) {
+      wscales.push_back(dcn_ws);
+      wscales.push_back(up_ws);
+    }
+    st = init_fp8_state(ctx, wscales);
   }
   if (st != NV_OK) {
     const std::string msg = g_err;
@@ -652,6 +916,12 @@ extern "C" nv_status nv_scene_metric(const nv_format* fmt, const nv_planes* prev
 
 // --------------------------------------------------------------- network ----
 
+static nv_status check_ready(const nv_context* ctx) {
+  if (ctx->bt == DT_F8 && !ctx->q_ready)
+    return fail(NV_E_INVALID, "FP8 context has no activation scales yet (nv_calibrate or nv_fp8_scales)");
+  return NV_OK;
+}
+
 static nv_status check_dims(int hp, int wp) {
   if (hp <= 0 || wp <= 0 || hp % 8 || wp % 8 || hp > kMaxDim || wp > kMaxDim)
     return fail(NV_E_INVALID, "padded size %dx%d must be positive multiples of 8", wp, hp);
@@ -662,6 +932,7 @@ extern "C" nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp,
                                 void* d_feat, void* stream) {
   if (!ctx || !d_rgb || !d_feat) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_dims(hp, wp));
+  NV_TRY(check_ready(ctx));
   return extract_impl(ctx, d_rgb, hp, wp, d_feat, (hipStream_t)stream);
 }
 
@@ -672,6 +943,7 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   if (!ctx || !d_rgb_a || !d_rgb_b || !d_feat_a || !d_feat_b) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_dims(hp, wp));
   if (out_mask == 0 || out_mask > 7) return fail(NV_E_INVALID, "out_mask must be in 1..7");
+  NV_TRY(check_ready(ctx));
   for (int t = 0; t < 3; ++t)
     if ((out_mask & (1u << t)) && (!d_hr || !d_hr[t])) return fail(NV_E_INVALID, "d_hr[%d] is NULL", t);
   return fuse_impl(ctx, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets,
@@ -681,6 +953,7 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
 extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
                                       const nv_planes out[3], void* stream) {
   if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(check_ready(ctx));
   NV_TRY(check_format(fmt, "input"));
   NV_TRY(check_planes(fmt, &in[0], "input 0"));
   NV_TRY(check_planes(fmt, &in[1], "input 1"));
@@ -699,6 +972,66 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
   const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
   return fuse_impl(ctx, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr,
                    nullptr, nullptr, &of, po, s);
+}
+
+// ------------------------------------------------------------------- FP8 ----
+
+extern "C" nv_status nv_calibrate(nv_context* ctx, const nv_format* fmt, const nv_planes* frames,
+                                  int32_t n_frames, void* stream) {
+  if (!ctx || !frames) return fail(NV_E_INVALID, "NULL argument");
+  if (ctx->bt != DT_F8) return fail(NV_E_INVALID, "only FP8 contexts are calibrated");
+  if (n_frames < 2) return fail(NV_E_INVALID, "calibration needs at least 2 frames (got %d)", n_frames);
+  NV_TRY(check_format(fmt, "input"));
+  for (int i = 0; i < n_frames; ++i) NV_TRY(check_planes(fmt, &frames[i], "calibration frame"));
+  const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
+  NV_TRY(ensure_workspace(ctx, hp, wp));
+  hipStream_t s = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  HIP_TRY(hipMemsetAsync(ctx->q_amax, 0, ctx->q_layers.size() * sizeof(uint32_t), s));
+  ctx->calibrating = true;
+  nv_status st = NV_OK;
+  for (int i = 0; i < n_frames && st == NV_OK; ++i) {
+    const int cur = i & 1, prv = cur ^ 1;
+    const Frame f = to_frame(fmt, &frames[i]);
+    st = check_launch(launch_unpack(f, ws.rgb[cur], hp, wp, s), "unpack");
+    if (st == NV_OK) st = extract_impl(ctx, ws.rgb[cur], hp, wp, ws.feat[cur], s);
+    if (st == NV_OK && i > 0 && ctx->ut == DT_F8)
+      st = fuse_impl(ctx, ws.rgb[prv], ws.rgb[cur], ws.feat[prv], ws.feat[cur], hp, wp, nullptr, 7u, nullptr,
+                     nullptr, nullptr, nullptr, nullptr, s);
+  }
+  ctx->calibrating = false;
+  if (st != NV_OK) return st;
+  ctx->q_ready = true;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int32_t set, void* stream) {
+  if (!ctx || !amax) return fail(NV_E_INVALID, "NULL argument");
+  if (ctx->bt != DT_F8) return fail(NV_E_INVALID, "only FP8 contexts have activation scales");
+  const int nq = (int)ctx->q_layers.size();
+  if (n != nq) return fail(NV_E_INVALID, "this context has %d FP8 layers (got n = %d)", nq, n);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint32_t> bits(nq);
+  if (!set) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(bits.data(), ctx->q_amax, nq * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    for (int l = 0; l < nq; ++l) std::memcpy(&amax[l], &bits[l], 4);
+    return NV_OK;
+  }
+  for (int l = 0; l < nq; ++l) {
+    if (!std::isfinite(amax[l]) || amax[l] < 0.0f)
+      return fail(NV_E_INVALID, "amax[%d] = %g is not a finite non-negative value", l, (double)amax[l]);
+    std::memcpy(&bits[l], &amax[l], 4);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(ctx->q_amax, bits.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice));
+  for (int l = 0; l < nq; ++l) {
+    PackedConv* P = ctx->q_layers[l];
+    NV_TRY(check_launch(launch_qscale(ctx->q_amax + l, ctx->q_wscale[l], P->oscale, P->ainv, P->obtot * 16, s),
+                        "qscale"));
+  }
+  ctx->q_ready = true;
+  return NV_OK;
 }
 
 // ---------------------------------------------------------------- streams ----
@@ -836,6 +1169,7 @@ static nv_status emit_group(nv_stream* s, int slot_a, int slot_b, const uint32_t
 extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_t external_cut,
                                     const nv_planes out[2], int32_t* n_out, void* stream) {
   if (!s || !n_out) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(check_ready(s->ctx));
   NV_TRY(check_planes(&s->fmt, frame, "frame"));
   if (external_cut < -1 || external_cut > 1) return fail(NV_E_INVALID, "external_cut must be -1, 0 or 1");
   if (s->t > 0) {
@@ -1073,6 +1407,7 @@ extern "C" nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes) {
 
 extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs, int32_t n, void* stream) {
   if (!ctx || (!reqs && n > 0) || n < 0) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(check_ready(ctx));
   hipStream_t hs = (hipStream_t)stream;
   // ---- validation (nothing is enqueued or changed before it passes) ----
   int nframes = 0, ngroups = 0;
@@ -1188,7 +1523,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     ci.W = wp;
     ci.item_begin = it[BL_CONV_IN];
     it[BL_CONV_IN] += conv_in_items(hp, wp, C);
-    const int nobg = ctx->blocks.empty() ? 1 : ctx->blocks[0].obtot / conv_ob(CONV_BULK, EPI_LRELU, ctx->blocks[0].obtot);
+    const int nobg = ctx->blocks.empty() ? 1 : ctx->blocks[0].obtot / conv_ob(CONV_BULK, EPI_LRELU, ctx->blocks[0].obtot, ctx->blocks[0].tc);
     T.blk_a[k] = conv_img(s->feat[sl], nullptr, nullptr, nullptr, nullptr, nullptr, t0, hp, wp);
     T.blk_b[k] = conv_img(t0, nullptr, nullptr, nullptr, nullptr, s->feat[sl], s->feat[sl], hp, wp);
     T.blk_a[k].item_begin = T.blk_b[k].item_begin = it[BL_BLOCK];
@@ -1216,10 +1551,10 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     const float* rb = s->rgb[Gr.slot_b];
     T.off1[k] = conv_img(fa, fb, Gr.sel, nullptr, fa, nullptr, o1, hp, wp);
     T.off1[k].item_begin = it[BL_OFF1];
-    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot));
+    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot, ctx->off1.tc));
     T.off2[k] = conv_img(o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
     T.off2[k].item_begin = it[BL_OFF2];
-    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot));
+    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot, ctx->off2.tc));
     DcnImg& d = T.dcn[k];
     d.fa = fa;
     d.fb = fb;
@@ -1251,7 +1586,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
       pk.rw = 2 * wp;
       pk.item_begin = it[BL_PACK];
     }
-    it[BL_UP] += conv_items(hp, wp, pbu, ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot));
+    it[BL_UP] += conv_items(hp, wp, pbu, ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot, ctx->up.tc));
     it[BL_HR] += hr_items(hp, wp);
     it[BL_PACK] += pack_items(s->ofmt.width, s->ofmt.height, s->ofmt.chroma);
   }
@@ -1367,7 +1702,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
       int* slot;
       std::vector<int> pbs;
     } cands[3] = {{"block", &ctx->tune.pb_block, {1, 2, 4}}, {"up", &ctx->tune.pb_up, {1, 2, 4}},
-                  {"dcn", &ctx->tune.pb_dcn, {1, 2}}};
+                  {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}}};
     for (auto& cd : cands) {
       float best = 1e30f;
       int best_pb = *cd.slot;

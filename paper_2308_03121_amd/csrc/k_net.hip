@@ -9,6 +9,8 @@
 // channels of one pixel.  Storage type (TIN / TOUT) and MFMA type (TC) are template
 // parameters: float end to end, or float16 / bfloat16 storage and MFMA with float
 // accumulation; the offset head reads 16-bit features and computes in float.
+#include <type_traits>
+
 #include "nv_internal.h"
 #include "nv_mma.h"
 
@@ -17,10 +19,15 @@ namespace {
 
 constexpr int kTW = 16;
 
+// Offset-head forms of a conv (see conv_tile).
+enum { SPLIT_NONE = 0, SPLIT_W = 1, SPLIT_WX = 2 };
+
 // Arguments shared by every image of a conv launch.
 struct ConvLayer {
   const u32x4* wfrag;
   const float* bias;
+  const float* oscale;   // FP8: per A row weight scale x activation scale
+  const float* ainv;     // FP8: 1 / activation scale (device scalar)
   int ldy;      // channel stride of dst / res
   int cout;     // real output channels (EPI_OFFSET stores only these)
   int sig_lo;   // EPI_OFFSET: sigmoid on channels >= sig_lo
@@ -47,88 +54,13 @@ struct ConvSmem {
   static constexpr int N = (TH + 2) * (kTW + 2) * LDP;
 };
 
-// One output tile: rows [ty0, ty0 + 4 PB), columns [tx0, tx0 + 16), output blocks
-// [obase, obase + OB).  Called by all 256 threads; contains block-wide barriers.
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
-__device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im, int ty0, int tx0,
-                                          int obase, TC* tile) {
-  constexpr int KG = Mma<TC>::KG;           // channels per MFMA step group
-  constexpr int QE = KG / 4;                // channels per lane quarter
-  constexpr int LDP = ConvSmem<TC, CCH, PB>::LDP;
-  constexpr int NCG = CCH / KG;
-  constexpr int NKG = NCHUNK * NCG;
-
+// Epilogue of a conv tile: bias (and, for FP8, the per-row output scale), then the
+// layer's activation / residual / offset-head / pixel-shuffle store.
+template <typename TOUT, int OB, int PB, int EPI>
+__device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[PB][OB],
+                                           int ty0, int tx0, int obase, const float* oscale) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
-
-  f32x4 acc[PB][OB];
-#pragma unroll
-  for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-    for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
-
-  const TIN* src0 = static_cast<const TIN*>(im.src0);
-  const TIN* src1 = static_cast<const TIN*>(im.src1);
-  if (im.sel != nullptr && *im.sel != 0u) {
-    if (im.alt0 != nullptr) src0 = static_cast<const TIN*>(im.alt0);
-    if (im.alt1 != nullptr) src1 = static_cast<const TIN*>(im.alt1);
-  }
-
-#pragma unroll
-  for (int ch = 0; ch < NCHUNK; ++ch) {
-    const TIN* src = ch == 0 ? src0 : src1;
-    if (ch) __syncthreads();
-    constexpr int V = CCH / 8;
-    constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
-    for (int idx = threadIdx.x; idx < NV; idx += 256) {
-      const int pix = idx / V, v = idx - pix * V;
-      const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
-      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-      TC* dstp = &tile[pix * LDP + 8 * v];
-      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W)
-        copy8<TIN, TC>(dstp, src + ((size_t)gy * im.W + gx) * CCH + 8 * v);
-      else
-        zero8<TC>(dstp);
-    }
-    __syncthreads();
-
-    // (tap, channel group) steps, software-pipelined: the A fragments (global) and
-    // B fragments (LDS) of step i+1 are in flight while the MFMAs of step i issue.
-    constexpr int NIT = 9 * NCG;
-    const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * L.obtot + obase) * 64 + lane;
-    const size_t wstride_tap = (size_t)NKG * L.obtot * 64;
-    const TC* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + QE * q];
-    u32x4 wa[OB], xb[PB];
-#pragma unroll
-    for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(tbase + pb * (kTW + 2) * LDP);
-#pragma unroll 3
-    for (int it = 0; it < NIT; ++it) {
-      u32x4 wn[OB], xn[PB];
-      if (it + 1 < NIT) {
-        const int tap = (it + 1) / NCG, cg = (it + 1) - tap * NCG;
-        const int dy = tap / 3, dx = tap - 3 * dy;
-        const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * L.obtot * 64;
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wn[ob] = wp[ob * 64];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-          xn[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
-      }
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
-      if (it + 1 < NIT) {
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
-      }
-    }
-  }
-
   TOUT* dst = static_cast<TOUT*>(im.dst);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
@@ -137,7 +69,8 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int row = (obase + ob) * 16 + 4 * q;
-      f32x4 v = acc[pb][ob] + ld4(L.bias + row);
+      f32x4 v = oscale ? acc[pb][ob] * ld4(oscale + row) : acc[pb][ob];
+      v += ld4(L.bias + row);
       const size_t at = ((size_t)gy * im.W + gx) * L.ldy + row;
       if (EPI == EPI_LRELU) {
         store4f<TOUT>(dst + at, lrelu4(v));
@@ -160,18 +93,214 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
   }
 }
 
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+
+// FP8 tile of a 64-channel float16 map (residual-block and pixel-shuffle convs).  The
+// input tile is staged in LDS as e4m3 of x / s_act.  One MFMA step covers 128
+// reduction indices, two taps x 64 channels: lane quarter q takes tap 2 st + q / 2,
+// channels 32 (q % 2) .. +32.  The fifth step pairs tap 8 with a zero-weight tap (its
+// lanes read tap 8's samples again, which are finite).  The accumulator is rescaled
+// by s_w[row] x s_act in the epilogue.
+template <int OB, int PB, int EPI>
+__device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& im, int ty0, int tx0, int obase,
+                                             f8* tile) {
+  constexpr int C = 64;
+  constexpr int LDP = ConvSmem<f8, C, PB>::LDP;   // bytes per staged pixel
+  constexpr int NST = 5;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+
+  f32x4 acc[PB][OB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
+
+  const f16* src = static_cast<const f16*>(im.src0);
+  if (im.sel != nullptr && *im.sel != 0u && im.alt0 != nullptr) src = static_cast<const f16*>(im.alt0);
+  const float ainv = *L.ainv;
+
+  constexpr int V = C / 8;
+  constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
+  for (int idx = threadIdx.x; idx < NV; idx += 256) {
+    const int pix = idx / V, v = idx - pix * V;
+    const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+    u32x2 w = u32x2{0u, 0u};
+    if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
+      const f16* p = src + ((size_t)gy * im.W + gx) * C + 8 * v;
+      w[0] = f8x4_pack(load4f<f16>(p) * ainv);
+      w[1] = f8x4_pack(load4f<f16>(p + 4) * ainv);
+    }
+    *reinterpret_cast<u32x2*>(&tile[pix * LDP + 8 * v]) = w;
+  }
+  __syncthreads();
+
+  const f8* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + 32 * (q & 1)];
+  auto tap_off = [&](int st) {
+    const int tap = min(2 * st + (q >> 1), 8);
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    return (dy * (kTW + 2) + dx) * LDP;
+  };
+  const u32x8* wbase = reinterpret_cast<const u32x8*>(L.wfrag) + (size_t)obase * 64 + lane;
+  u32x8 wa[OB], xb[PB];
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
+  {
+    const int o0 = tap_off(0);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu8(tbase + o0 + pb * (kTW + 2) * LDP);
+  }
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    u32x8 wn[OB], xn[PB];
+    if (st + 1 < NST) {
+      const u32x8* wp = wbase + (size_t)(st + 1) * L.obtot * 64;
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) wn[ob] = wp[ob * 64];
+      const int o1 = tap_off(st + 1);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) xn[pb] = ldu8(tbase + o1 + pb * (kTW + 2) * LDP);
+    }
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<f8>::step(wa[ob], xb[pb], acc[pb][ob]);
+    if (st + 1 < NST) {
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
+    }
+  }
+  conv_store<f16, OB, PB, EPI>(L, im, acc, ty0, tx0, obase, L.oscale);
+}
+
+// One output tile: rows [ty0, ty0 + 4 PB), columns [tx0, tx0 + 16), output blocks
+// [obase, obase + OB).  Called by all 256 threads; contains block-wide barriers.
+//
+// SPLIT selects the float-class offset head on float16 MFMA: the weights are carried
+// as two float16 parts per fragment (hi = f16(s w), lo = f16(s w - hi), s a power of
+// two), each A fragment position holding the pair, so every product of a float16
+// input with w is formed from 22 weight bits, exactly, and accumulated in float; the
+// epilogue multiplies by 1/s.  SPLIT_W: inputs are float16 (or bfloat16 converted
+// exactly) maps.  SPLIT_WX: the single float input is staged as two chunks, its
+// float16 part and the float16 of the remainder, against the same weights.
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0>
+__device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im, int ty0, int tx0,
+                                          int obase, TC* tile) {
+  if constexpr (std::is_same<TC, f8>::value) {
+    static_assert(std::is_same<TIN, f16>::value && std::is_same<TOUT, f16>::value && CCH == 64 && NCHUNK == 1,
+                  "FP8 convs read and write 64-channel float16 maps");
+    conv_tile_f8<OB, PB, EPI>(L, im, ty0, tx0, obase, tile);
+    return;
+  } else {
+  constexpr int KG = Mma<TC>::KG;           // channels per MFMA step group
+  constexpr int QE = KG / 4;                // channels per lane quarter
+  constexpr int LDP = ConvSmem<TC, CCH, PB>::LDP;
+  constexpr int NCG = CCH / KG;
+  constexpr int NKG = NCHUNK * NCG;
+  constexpr int AS = SPLIT ? 2 : 1;         // A fragments per output block and step
+  static_assert(SPLIT == 0 || std::is_same<TC, f16>::value, "the split head runs on float16 MFMA");
+  static_assert(SPLIT != SPLIT_WX || (NCHUNK == 2 && std::is_same<TIN, float>::value), "SPLIT_WX stages hi / lo");
+  const int wobtot = L.obtot * AS;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+
+  f32x4 acc[PB][OB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
+
+  const TIN* src0 = static_cast<const TIN*>(im.src0);
+  const TIN* src1 = static_cast<const TIN*>(im.src1);
+  if (im.sel != nullptr && *im.sel != 0u) {
+    if (im.alt0 != nullptr) src0 = static_cast<const TIN*>(im.alt0);
+    if (im.alt1 != nullptr) src1 = static_cast<const TIN*>(im.alt1);
+  }
+
+#pragma unroll
+  for (int ch = 0; ch < NCHUNK; ++ch) {
+    const TIN* src = (ch == 0 || SPLIT == SPLIT_WX) ? src0 : src1;
+    if (ch) __syncthreads();
+    constexpr int V = CCH / 8;
+    constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
+    for (int idx = threadIdx.x; idx < NV; idx += 256) {
+      const int pix = idx / V, v = idx - pix * V;
+      const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+      TC* dstp = &tile[pix * LDP + 8 * v];
+      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
+        const TIN* sp = src + ((size_t)gy * im.W + gx) * CCH + 8 * v;
+        if constexpr (SPLIT == SPLIT_WX) copy8_split(dstp, reinterpret_cast<const float*>(sp), ch);
+        else copy8<TIN, TC>(dstp, sp);
+      } else {
+        zero8<TC>(dstp);
+      }
+    }
+    __syncthreads();
+
+    // (tap, channel group) steps, software-pipelined: the A fragments (global) and
+    // B fragments (LDS) of step i+1 are in flight while the MFMAs of step i issue.
+    constexpr int NIT = 9 * NCG;
+    const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * wobtot + obase * AS) * 64 + lane;
+    const size_t wstride_tap = (size_t)NKG * wobtot * 64;
+    const TC* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + QE * q];
+    u32x4 wa[OB * AS], xb[PB];
+#pragma unroll
+    for (int ob = 0; ob < OB * AS; ++ob) wa[ob] = wbase[ob * 64];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(tbase + pb * (kTW + 2) * LDP);
+#pragma unroll 3
+    for (int it = 0; it < NIT; ++it) {
+      u32x4 wn[OB * AS], xn[PB];
+      if (it + 1 < NIT) {
+        const int tap = (it + 1) / NCG, cg = (it + 1) - tap * NCG;
+        const int dy = tap / 3, dx = tap - 3 * dy;
+        const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * wobtot * 64;
+#pragma unroll
+        for (int ob = 0; ob < OB * AS; ++ob) wn[ob] = wp[ob * 64];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb)
+          xn[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
+      }
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+          for (int part = 0; part < AS; ++part)
+            acc[pb][ob] = Mma<TC>::step(wa[ob * AS + part], xb[pb], acc[pb][ob]);
+      if (it + 1 < NIT) {
+#pragma unroll
+        for (int ob = 0; ob < OB * AS; ++ob) wa[ob] = wn[ob];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
+      }
+    }
+  }
+
+  conv_store<TOUT, OB, PB, EPI>(L, im, acc, ty0, tx0, obase, SPLIT ? L.oscale : nullptr);
+  }
+}
+
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvLayer L, ConvImg im) {
   __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
+  // block = (tile, output-block group), group fastest: the groups of a tile run next to
+  // each other on one XCD and read its input from that XCD's L2
   const int tiles_x = (im.W + kTW - 1) / kTW;
+  const int nobg = L.obtot / OB;
   const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
-  const int t = xcd_tile(blockIdx.x, ntile);
-  conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
-                                                      blockIdx.y * OB, tile);
+  const int b = xcd_tile(blockIdx.x, ntile * nobg);
+  const int t = b / nobg, obg = b - t * nobg;
+  conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
+                                                             obg * OB, tile);
 }
 
 // Persistent form: item = (tile, output-block group) of one image of the job table.
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT>
 __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvImg* __restrict__ jobs,
                                                        const int* __restrict__ count) {
   __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
@@ -182,49 +311,71 @@ __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvIm
     const int local = item - im.item_begin;
     const int t = local / nobg, obg = local - t * nobg;
     const int tiles_x = (im.W + kTW - 1) / kTW;
-    conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
-                                                        obg * OB, tile);
+    conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>(L, im, (t / tiles_x) * 4 * PB,
+                                                               (t % tiles_x) * kTW, obg * OB, tile);
     __syncthreads();
   }
 }
 
 // ---- modulated deformable conv, stride 1, pad 1, 3x3, over cat(fa, fb) ----
-// Per tap, two phases over a TH x 16 pixel tile:
-//  gather: one work item per (pixel, offset group) computes the sampling position and
-//          the four bilinear weights once (float), reads the group's channels at the
-//          four corners (vectors of the NHWC maps), scales by the mask and writes the
-//          modulated samples S[pixel][channel] to LDS in the MFMA type;
-//  MFMA:   the tile's S (2C channels) times the tap's weights, accumulated over taps.
+// Over a TH x 16 pixel tile, per phase (below):
+//  gather: one work item per (pixel, channel chunk, tap) computes the sampling position
+//          and the four bilinear weights (float), reads the chunk's channels at the four
+//          corners (vectors of the NHWC maps), scales by the mask and writes the
+//          modulated samples to LDS in the MFMA type;
+//  MFMA:   the tile's samples times the phase's weights, accumulated over phases.
 struct DcnLayer {
-  const u32x4* wfrag;
+  const void* wfrag;        // fragments of the MFMA type
   const float* bias;
+  const float* oscale;      // FP8: per output channel weight scale x activation scale
+  const float* ainv;        // FP8: 1 / activation scale (device scalar)
   int ldo, groups, obtot;
 };
 
-template <typename TC, int C, int PB>
-struct DcnSmem {
-  static constexpr int LDS_P = 2 * C + 16 / (int)sizeof(TC);
-  static constexpr int N = 4 * PB * kTW * LDS_P;
+// The reduction index K of the DCN (input channel ci of the concatenated pair, tap) is
+// walked in phases.  The channels are cut into chunks of CW = min(CPG, KG) consecutive
+// channels (CPG channels per offset group, KG channels per MFMA step group); a phase
+// covers GP = KG / CW consecutive chunks with all nine taps, ordered (chunk, tap,
+// channel), so a phase reads each of its sampling positions' offsets once and gathers
+// its chunks' channels for all taps at once.  Every phase is 9 MFMA steps deep.
+template <typename TC, int CPG>
+struct DcnPhase {
+  static constexpr int KG = Mma<TC>::KG;
+  static constexpr int CW = CPG < KG ? CPG : KG;
+  static constexpr int GP = KG / CW;
+  static constexpr int NCH = CPG / CW;              // chunks per offset group
+  static constexpr int K = 9 * KG;                  // K of one phase
+  static constexpr int LDS_P = K + 16 / (int)sizeof(TC);
 };
 
-template <typename TF, typename TC, int C, int PB>
+template <typename TC, int CPG, int PB>
+struct DcnSmem {
+  static constexpr int N = 4 * PB * kTW * DcnPhase<TC, CPG>::LDS_P;
+};
+
+template <typename TF, typename TC, int C, int CPG, int PB>
 __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, int ty0, int tx0, TC* S) {
+  using Ph = DcnPhase<TC, CPG>;
   constexpr int TH = 4 * PB;
   constexpr int OB = C / 16;
-  constexpr int CIN = 2 * C;
-  constexpr int KG = Mma<TC>::KG;
+  constexpr int G = 2 * C / CPG;
+  constexpr int CW = Ph::CW, GP = Ph::GP, NCH = Ph::NCH;
+  constexpr int NPHASE = 2 * C / (GP * CW);
+  constexpr int KG = Ph::KG;
   constexpr int QE = KG / 4;
-  constexpr int NKG = CIN / KG;
   constexpr int NPX = TH * kTW;
-  constexpr int LDS_P = DcnSmem<TC, C, PB>::LDS_P;
+  constexpr int LDS_P = Ph::LDS_P;
+  static_assert(2 * C % (GP * CW) == 0 && CW % 4 == 0, "channel chunks must tile the input");
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
-  const int G = L.groups;
-  const int cpg = CIN / G;                   // channels per offset group (multiple of 4)
+  constexpr bool kF8 = std::is_same<TC, f8>::value;
+  using Frag = typename Mma<TC>::Frag;
   const TF* fa = static_cast<const TF*>(im.fa);
   const TF* fb = (im.sel != nullptr && *im.sel != 0u) ? fa : static_cast<const TF*>(im.fb);
   const float hmax = (float)im.H, wmax = (float)im.W;
+  // FP8 stores samples / activation scale; folded into the bilinear-times-mask weights
+  const float qs = kF8 ? *L.ainv : 1.0f;
 
   f32x4 acc[PB][OB];
 #pragma unroll
@@ -234,72 +385,108 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 
   const TC* sbase = &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
 
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap - 3 * ky;
-    if (tap) __syncthreads();
-    for (int item = threadIdx.x; item < NPX * G; item += 256) {
-      const int p = item / G, g = item - p * G;
-      const int gy = ty0 + p / kTW, gx = tx0 + (p % kTW);
-      TC* sp = &S[p * LDS_P + g * cpg];
-      if (gy >= im.H || gx >= im.W) {
-        for (int v = 0; v < cpg; v += 4) store4f<TC>(sp + v, zero4());
-        continue;
+  for (int ph = 0; ph < NPHASE; ++ph) {
+    if (ph) __syncthreads();
+    // gather: item = (pixel, chunk in phase, tap), tap fastest; S[p][(gi*9 + tap)*CW + c].
+    // A thread takes U items at a time: first the offsets of all U, then the corner
+    // vectors of all U, so several independent loads are in flight per thread.  Each
+    // item always reads its four corners (coordinates clamped into the map); a corner
+    // outside the map, or a pixel outside the image, gets weight 0.
+    constexpr int NITEM = NPX * GP * 9;
+    constexpr int U = 2;
+    for (int i0 = 0; i0 < NITEM; i0 += U * 256) {
+      const TF* cp[U][4];
+      float cw[U][4];
+      TC* sp[U];
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu) {
+        const int item = i0 + uu * 256 + (int)threadIdx.x;
+        sp[uu] = nullptr;
+        if (item >= NITEM) continue;
+        const int tap = item % 9, rest = item / 9;
+        const int gi = rest % GP, p = rest / GP;
+        const int u = ph * GP + gi;                  // chunk index over the 2C channels
+        const int g = u / NCH;                       // its offset group
+        const int gy = ty0 + p / kTW, gx = tx0 + (p % kTW);
+        const bool inside = gy < im.H && gx < im.W;
+        const int gyc = min(gy, im.H - 1), gxc = min(gx, im.W - 1);
+        sp[uu] = &S[p * LDS_P + (gi * 9 + tap) * CW];
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        const float* orow = im.offs + ((size_t)gyc * im.W + gxc) * L.ldo;
+        const float dyo = orow[2 * (9 * g + tap)];
+        const float dxo = orow[2 * (9 * g + tap) + 1];
+        float m = inside ? orow[18 * G + 9 * g + tap] : 0.0f;
+        if (kF8) m *= qs;
+        // beyond one pixel outside the map every sample is zero; the clamp keeps the
+        // integer conversion defined for any offset value
+        const float py = fminf(fmaxf((float)(gy + ky - 1) + dyo, -2.0f), hmax + 1.0f);
+        const float px = fminf(fmaxf((float)(gx + kx - 1) + dxo, -2.0f), wmax + 1.0f);
+        const float y0f = floorf(py), x0f = floorf(px);
+        const float ly = py - y0f, lx = px - x0f;
+        const int y0 = (int)y0f, x0 = (int)x0f;
+        const int ci = u * CW;
+        const TF* src = ci < C ? fa : fb;
+        const int cl = ci < C ? ci : ci - C;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            const int yy = y0 + cy, xx = x0 + cx;
+            const bool ok = yy >= 0 && yy < im.H && xx >= 0 && xx < im.W;
+            const int yc = min(max(yy, 0), im.H - 1), xc = min(max(xx, 0), im.W - 1);
+            cw[uu][2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
+            cp[uu][2 * cy + cx] = src + ((size_t)yc * im.W + xc) * C + cl;
+          }
       }
-      const float* orow = im.offs + ((size_t)gy * im.W + gx) * L.ldo;
-      const float dyo = orow[2 * (9 * g + tap)];
-      const float dxo = orow[2 * (9 * g + tap) + 1];
-      const float m = orow[18 * G + 9 * g + tap];
-      // beyond one pixel outside the map every sample is zero; the clamp keeps the
-      // integer conversion defined for any offset value
-      const float py = fminf(fmaxf((float)(gy + ky - 1) + dyo, -2.0f), hmax + 1.0f);
-      const float px = fminf(fmaxf((float)(gx + kx - 1) + dxo, -2.0f), wmax + 1.0f);
-      const float y0f = floorf(py), x0f = floorf(px);
-      const float ly = py - y0f, lx = px - x0f;
-      const int y0 = (int)y0f, x0 = (int)x0f;
-      const int c0 = g * cpg;
-      const TF* src = c0 < C ? fa : fb;
-      const int cl = c0 < C ? c0 : c0 - C;
-      float wgt[4];
-      const TF* cp[4];
-      int nc = 0;
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy)
+      for (int uu = 0; uu < U; ++uu) {
+        if (sp[uu] == nullptr) continue;
+        if constexpr (CW % 8 == 0) {
 #pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-          const int yy = y0 + cy, xx = x0 + cx;
-          if (yy >= 0 && yy < im.H && xx >= 0 && xx < im.W) {
-            wgt[nc] = (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m;
-            cp[nc] = src + ((size_t)yy * im.W + xx) * C + cl;
-            ++nc;
+          for (int v = 0; v < CW; v += 8) {
+            f32x4 lo = zero4(), hi = zero4();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              f32x4 a, b;
+              load8f<TF>(cp[uu][k] + v, a, b);
+              lo += cw[uu][k] * a;
+              hi += cw[uu][k] * b;
+            }
+            store4f<TC>(sp[uu] + v, lo);
+            store4f<TC>(sp[uu] + v + 4, hi);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < CW; v += 4) {
+            f32x4 acc4 = zero4();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc4 += cw[uu][k] * load4f<TF>(cp[uu][k] + v);
+            store4f<TC>(sp[uu] + v, acc4);
           }
         }
-      for (int v = 0; v < cpg; v += 4) {
-        f32x4 val = zero4();
-        for (int k = 0; k < nc; ++k) val += wgt[k] * load4f<TF>(cp[k] + v);
-        store4f<TC>(sp + v, val);
       }
     }
     __syncthreads();
 
-    const u32x4* wbase = L.wfrag + ((size_t)tap * NKG * L.obtot) * 64 + lane;
-    u32x4 wa[OB];
+    const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot) * 64 + lane;
+    Frag wa[OB];
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
-#pragma unroll 2
-    for (int kg = 0; kg < NKG; ++kg) {
-      u32x4 wn[OB];
-      if (kg + 1 < NKG) {
+#pragma unroll 3
+    for (int st = 0; st < 9; ++st) {
+      Frag wn[OB];
+      if (st + 1 < 9) {
 #pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wn[ob] = wbase[((size_t)(kg + 1) * L.obtot + ob) * 64];
+        for (int ob = 0; ob < OB; ++ob) wn[ob] = wbase[((size_t)(st + 1) * L.obtot + ob) * 64];
       }
-      u32x4 xb[PB];
+      Frag xb[PB];
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(sbase + pb * kTW * LDS_P + KG * kg);
+      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + KG * st);
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
-      if (kg + 1 < NKG) {
+      if (st + 1 < 9) {
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
       }
@@ -315,31 +502,32 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int row = ob * 16 + 4 * q;
-      const f32x4 v = acc[pb][ob] + ld4(L.bias + row);
+      const f32x4 a = kF8 ? acc[pb][ob] * ld4(L.oscale + row) : acc[pb][ob];
+      const f32x4 v = a + ld4(L.bias + row);
       store4f<TF>(dst + ((size_t)gy * im.W + gx) * C + row, lrelu4(v));
     }
   }
 }
 
-template <typename TF, typename TC, int C, int PB>
+template <typename TF, typename TC, int C, int CPG, int PB>
 __global__ __launch_bounds__(256) void k_dcn(DcnLayer L, DcnImg im) {
-  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, C, PB>::N];
+  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, CPG, PB>::N];
   const int tiles_x = (im.W + kTW - 1) / kTW;
   const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
   const int t = xcd_tile(blockIdx.x, ntile);
-  dcn_tile<TF, TC, C, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
+  dcn_tile<TF, TC, C, CPG, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
 }
 
-template <typename TF, typename TC, int C, int PB>
+template <typename TF, typename TC, int C, int CPG, int PB>
 __global__ __launch_bounds__(256) void k_dcn_batch(DcnLayer L, const DcnImg* __restrict__ jobs,
                                                    const int* __restrict__ count) {
-  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, C, PB>::N];
+  __shared__ __attribute__((aligned(16))) TC S[DcnSmem<TC, CPG, PB>::N];
   const int njobs = count[0], total = count[1];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const DcnImg im = jobs[find_job(jobs, njobs, item)];
     const int t = item - im.item_begin;
     const int tiles_x = (im.W + kTW - 1) / kTW;
-    dcn_tile<TF, TC, C, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
+    dcn_tile<TF, TC, C, CPG, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S);
     __syncthreads();
   }
 }
@@ -515,6 +703,42 @@ __global__ __launch_bounds__(256) void k_hr_batch(HrLayer L, const HrImg* __rest
   }
 }
 
+// ---- FP8 calibration: running max |x| of a layer input, and the scales derived from it ----
+
+// amax_bits holds the running maximum as float bits (non-negative floats order like
+// their bit patterns, so an unsigned atomic max is a float max).
+template <typename T>
+__global__ __launch_bounds__(256) void k_amax(const T* __restrict__ x, size_t n, uint32_t* amax_bits) {
+  float m = 0.0f;
+  for (size_t i = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += (size_t)gridDim.x * 256 * 4) {
+    if (i + 4 <= n) {
+      const f32x4 v = load4f<T>(x + i);
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+    } else {
+      for (size_t k = i; k < n; ++k) m = fmaxf(m, fabsf((float)x[k]));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  __shared__ float wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float b = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    atomicMax(amax_bits, __float_as_uint(b));
+  }
+}
+
+// s_act = amax / 448 (1 when the layer has only seen zeros): ainv = 1 / s_act and
+// oscale[r] = wscale[r] * s_act.
+__global__ __launch_bounds__(256) void k_qscale(const uint32_t* __restrict__ amax_bits,
+                                                const float* __restrict__ wscale, float* __restrict__ oscale,
+                                                float* __restrict__ ainv, int rows) {
+  const float a = __uint_as_float(*amax_bits);
+  const float sa = a > 0.0f ? a / kF8Max : 1.0f;
+  for (int r = threadIdx.x; r < rows; r += 256) oscale[r] = wscale[r] * sa;
+  if (threadIdx.x == 0) *ainv = 1.0f / sa;
+}
+
 // ---------------------------------------------------------------- dispatch ----
 
 // A launcher for one (types, shape, epilogue) instance, single image or batched.
@@ -526,30 +750,44 @@ struct ConvCall {
   hipStream_t s;
 };
 
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI>
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0>
 hipError_t run_conv(const ConvCall& c) {
   if (c.im) {
     const int ntile = ((c.im->W + kTW - 1) / kTW) * ((c.im->H + 4 * PB - 1) / (4 * PB));
-    const dim3 grid(ntile, c.L.obtot / OB);
-    hipLaunchKernelGGL((k_conv3x3<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>), grid, dim3(256), 0, c.s, c.L,
-                       *c.im);
+    const dim3 grid(ntile * (c.L.obtot / OB));
+    hipLaunchKernelGGL((k_conv3x3<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>), grid, dim3(256), 0, c.s,
+                       c.L, *c.im);
   } else {
-    hipLaunchKernelGGL((k_conv3x3_batch<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI>), dim3(kBatchGrid), dim3(256),
-                       0, c.s, c.L, c.jobs, c.count);
+    hipLaunchKernelGGL((k_conv3x3_batch<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>), dim3(kBatchGrid),
+                       dim3(256), 0, c.s, c.L, c.jobs, c.count);
   }
   return hipGetLastError();
 }
 
+// Storage type of a bulk conv whose MFMA type is T (FP8 layers keep float16 maps).
+template <typename T>
+struct Store {
+  typedef T type;
+};
+template <>
+struct Store<f8> {
+  typedef f16 type;
+};
+
 template <typename T, int CCH, int PB>
 hipError_t conv_bulk_pb(const ConvCall& c, int epi) {
+  typedef typename Store<T>::type S;
   switch (epi) {
     case EPI_LRELU:
-      if (c.L.obtot % 4 == 0) return run_conv<T, T, T, CCH, 1, 4, PB, EPI_LRELU>(c);
-      return run_conv<T, T, T, CCH, 1, 2, PB, EPI_LRELU>(c);
+      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_LRELU>(c);
+      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_LRELU>(c);
     case EPI_RES:
-      if (c.L.obtot % 4 == 0) return run_conv<T, T, T, CCH, 1, 4, PB, EPI_RES>(c);
-      return run_conv<T, T, T, CCH, 1, 2, PB, EPI_RES>(c);
-    case EPI_SHUFFLE: return run_conv<T, T, T, CCH, 1, 8, PB, EPI_SHUFFLE>(c);
+      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_RES>(c);
+      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_RES>(c);
+    case EPI_SHUFFLE:
+      // FP8 fragments are twice as wide: half the output blocks per workgroup
+      if constexpr (std::is_same<T, f8>::value) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_SHUFFLE>(c);
+      else return run_conv<S, T, S, CCH, 1, 8, PB, EPI_SHUFFLE>(c);
   }
   return hipErrorInvalidValue;
 }
@@ -560,28 +798,44 @@ hipError_t conv_bulk(const ConvCall& c, int epi, int pb) {
   if (pb == 1) return conv_bulk_pb<T, CCH, 1>(c, epi);
   if (pb == 2) return conv_bulk_pb<T, CCH, 2>(c, epi);
   if (pb == 4) return conv_bulk_pb<T, CCH, 4>(c, epi);
+  // eight rows per wave: 16-bit residual convs only (more pixels per weight fragment)
+  if constexpr (std::is_same<T, f16>::value || std::is_same<T, bf16>::value)
+    if (pb == 8 && epi != EPI_SHUFFLE) return conv_bulk_pb<T, CCH, 8>(c, epi);
   return hipErrorInvalidValue;
 }
 
-// Offset head: first conv reads the two feature maps (TIN) and computes in float.
+// Offset head: first conv reads the two feature maps (TIN) and computes in float, on
+// float MFMA or (split) on float16 MFMA with two-part weights.
 template <typename TIN, int CCH>
-hipError_t conv_off1(const ConvCall& c) {
+hipError_t conv_off1(const ConvCall& c, bool split) {
+  if (split) {
+    if constexpr (std::is_same<TIN, float>::value) return hipErrorInvalidValue;
+    else {
+      if (c.L.obtot % 4 == 0) return run_conv<TIN, f16, float, CCH, 2, 4, 2, EPI_LRELU, SPLIT_W>(c);
+      return run_conv<TIN, f16, float, CCH, 2, 2, 2, EPI_LRELU, SPLIT_W>(c);
+    }
+  }
   if (c.L.obtot % 4 == 0) return run_conv<TIN, float, float, CCH, 2, 4, 2, EPI_LRELU>(c);
   return run_conv<TIN, float, float, CCH, 2, 2, 2, EPI_LRELU>(c);
 }
 
 template <int CCH>
-hipError_t conv_off2(const ConvCall& c) {
+hipError_t conv_off2(const ConvCall& c, bool split) {
+  if (split) {
+    if (c.L.obtot % 7 == 0) return run_conv<float, f16, float, CCH, 2, 7, 2, EPI_OFFSET, SPLIT_WX>(c);
+    if (c.L.obtot % 4 == 0) return run_conv<float, f16, float, CCH, 2, 4, 2, EPI_OFFSET, SPLIT_WX>(c);
+    return run_conv<float, f16, float, CCH, 2, 1, 2, EPI_OFFSET, SPLIT_WX>(c);
+  }
   if (c.L.obtot % 7 == 0) return run_conv<float, float, float, CCH, 1, 7, 2, EPI_OFFSET>(c);
   if (c.L.obtot % 4 == 0) return run_conv<float, float, float, CCH, 1, 4, 2, EPI_OFFSET>(c);
   return run_conv<float, float, float, CCH, 1, 1, 2, EPI_OFFSET>(c);
 }
 
 template <typename T>
-hipError_t conv_any(const ConvCall& c, int epi, int role, int cch, int pb) {
+hipError_t conv_any(const ConvCall& c, int epi, int role, int cch, int pb, bool split) {
   if (role == CONV_OFF1) {
-    if (cch == 64) return conv_off1<T, 64>(c);
-    if (cch == 32) return conv_off1<T, 32>(c);
+    if (cch == 64) return conv_off1<T, 64>(c, split);
+    if (cch == 32) return conv_off1<T, 32>(c, split);
     return hipErrorInvalidValue;
   }
   if (cch == 64) return conv_bulk<T, 64>(c, epi, pb);
@@ -590,19 +844,27 @@ hipError_t conv_any(const ConvCall& c, int epi, int role, int cch, int pb) {
 }
 
 hipError_t conv_dispatch(const PackedConv& P, int role, int epi, int tin, int pb, const ConvCall& c) {
+  // offset head: float fragments, or two-part float16 fragments (split) with 1/s per row
+  const bool split = (role == CONV_OFF1 || role == CONV_OFF2) && P.tc == DT_F16;
+  if (split && !P.oscale) return hipErrorInvalidValue;
   if (role == CONV_OFF2) {
-    if (tin != DT_F32 || P.tc != DT_F32) return hipErrorInvalidValue;
-    if (P.cin == 64) return conv_off2<64>(c);
-    if (P.cin == 32) return conv_off2<32>(c);
+    if (tin != DT_F32 || (P.tc != DT_F32 && !split)) return hipErrorInvalidValue;
+    const int cch = split ? P.cin / 2 : P.cin;   // split: packed over [hi | lo] chunks
+    if (cch == 64) return conv_off2<64>(c, split);
+    if (cch == 32) return conv_off2<32>(c, split);
     return hipErrorInvalidValue;
   }
+  if (P.tc == DT_F8) {
+    if (role != CONV_BULK || tin != DT_F16 || P.cin != 64 || !P.oscale || !P.ainv) return hipErrorInvalidValue;
+    return conv_bulk<f8, 64>(c, epi, pb);
+  }
   const int cch = role == CONV_OFF1 ? P.cin / 2 : P.cin;
-  if (role == CONV_OFF1 && (P.tc != DT_F32 || pb != 2)) return hipErrorInvalidValue;
+  if (role == CONV_OFF1 && ((P.tc != DT_F32 && !split) || pb != 2)) return hipErrorInvalidValue;
   if (role != CONV_OFF1 && P.tc != tin) return hipErrorInvalidValue;
   switch (tin) {
-    case DT_F32: return conv_any<float>(c, epi, role, cch, pb);
-    case DT_F16: return conv_any<f16>(c, epi, role, cch, pb);
-    case DT_BF16: return conv_any<bf16>(c, epi, role, cch, pb);
+    case DT_F32: return conv_any<float>(c, epi, role, cch, pb, split);
+    case DT_F16: return conv_any<f16>(c, epi, role, cch, pb, split);
+    case DT_BF16: return conv_any<bf16>(c, epi, role, cch, pb, split);
   }
   return hipErrorInvalidValue;
 }
@@ -611,6 +873,8 @@ ConvLayer make_layer(const PackedConv& P, int ldy, int sig_lo) {
   ConvLayer L;
   L.wfrag = reinterpret_cast<const u32x4*>(P.frag);
   L.bias = P.bias;
+  L.oscale = P.oscale;
+  L.ainv = P.ainv;
   L.ldy = ldy;
   L.cout = P.cout;
   L.sig_lo = sig_lo;
@@ -619,46 +883,86 @@ ConvLayer make_layer(const PackedConv& P, int ldy, int sig_lo) {
   return L;
 }
 
-template <typename TF, typename TC, int C, int PB>
+template <typename TF, typename TC, int C, int CPG, int PB>
 void run_dcn(const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count, hipStream_t s) {
   if (im) {
     const int ntile = ((im->W + kTW - 1) / kTW) * ((im->H + 4 * PB - 1) / (4 * PB));
-    hipLaunchKernelGGL((k_dcn<TF, TC, C, PB>), dim3(ntile), dim3(256), 0, s, L, *im);
+    hipLaunchKernelGGL((k_dcn<TF, TC, C, CPG, PB>), dim3(ntile), dim3(256), 0, s, L, *im);
   } else {
-    hipLaunchKernelGGL((k_dcn_batch<TF, TC, C, PB>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
+    hipLaunchKernelGGL((k_dcn_batch<TF, TC, C, CPG, PB>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
   }
 }
 
+// FP8: float16 storage, e4m3 samples and weights, 64 channels; one pixel row per wave
+// (a phase holds all 2C channels x 9 taps of a tile in LDS).
+hipError_t dcn_f8(int cpg, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
+                  hipStream_t s) {
+  switch (cpg) {
+    case 4: run_dcn<f16, f8, 64, 4, 1>(L, im, jobs, count, s); break;
+    case 8: run_dcn<f16, f8, 64, 8, 1>(L, im, jobs, count, s); break;
+    case 16: run_dcn<f16, f8, 64, 16, 1>(L, im, jobs, count, s); break;
+    case 32: run_dcn<f16, f8, 64, 32, 1>(L, im, jobs, count, s); break;
+    case 64: run_dcn<f16, f8, 64, 64, 1>(L, im, jobs, count, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename TF, int PB>
-hipError_t dcn_c(int C, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
+hipError_t dcn_c(int C, int cpg, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
                  hipStream_t s) {
-  if (C == 64) run_dcn<TF, TF, 64, PB>(L, im, jobs, count, s);
-  else if (C == 32) run_dcn<TF, TF, 32, PB>(L, im, jobs, count, s);
-  else return hipErrorInvalidValue;
+  // cpg = 2C / offset groups: 4 .. 2C
+  if (C == 64) {
+    switch (cpg) {
+      case 4: run_dcn<TF, TF, 64, 4, PB>(L, im, jobs, count, s); break;
+      case 8: run_dcn<TF, TF, 64, 8, PB>(L, im, jobs, count, s); break;
+      case 16: run_dcn<TF, TF, 64, 16, PB>(L, im, jobs, count, s); break;
+      case 32: run_dcn<TF, TF, 64, 32, PB>(L, im, jobs, count, s); break;
+      case 64: run_dcn<TF, TF, 64, 64, PB>(L, im, jobs, count, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (C == 32) {
+    switch (cpg) {
+      case 4: run_dcn<TF, TF, 32, 4, PB>(L, im, jobs, count, s); break;
+      case 8: run_dcn<TF, TF, 32, 8, PB>(L, im, jobs, count, s); break;
+      case 16: run_dcn<TF, TF, 32, 16, PB>(L, im, jobs, count, s); break;
+      case 32: run_dcn<TF, TF, 32, 32, PB>(L, im, jobs, count, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <typename TF>
-hipError_t dcn_pb(int pb, int C, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
-                  hipStream_t s) {
-  if (pb == 1) return dcn_c<TF, 1>(C, L, im, jobs, count, s);
-  if (pb == 2) return dcn_c<TF, 2>(C, L, im, jobs, count, s);
+hipError_t dcn_pb(int pb, int C, int cpg, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs,
+                  const int* count, hipStream_t s) {
+  if (pb == 1) return dcn_c<TF, 1>(C, cpg, L, im, jobs, count, s);
+  if (pb == 2) return dcn_c<TF, 2>(C, cpg, L, im, jobs, count, s);
   return hipErrorInvalidValue;
 }
 
 hipError_t dcn_dispatch(const PackedConv& P, int tf, int pb, int ldo, int groups, const DcnImg* im,
                         const DcnImg* jobs, const int* count, hipStream_t s) {
-  if (P.tc != tf) return hipErrorInvalidValue;
   DcnLayer L;
-  L.wfrag = reinterpret_cast<const u32x4*>(P.frag);
+  L.wfrag = P.frag;
   L.bias = P.bias;
+  L.oscale = P.oscale;
+  L.ainv = P.ainv;
   L.ldo = ldo;
   L.groups = groups;
   L.obtot = P.obtot;
+  const int cpg = 2 * P.cout / groups;
+  if (P.tc == DT_F8) {
+    if (tf != DT_F16 || P.cout != 64 || pb != 1 || !P.oscale || !P.ainv) return hipErrorInvalidValue;
+    return dcn_f8(cpg, L, im, jobs, count, s);
+  }
+  if (P.tc != tf) return hipErrorInvalidValue;
   switch (tf) {
-    case DT_F32: return dcn_pb<float>(pb, P.cout, L, im, jobs, count, s);
-    case DT_F16: return dcn_pb<f16>(pb, P.cout, L, im, jobs, count, s);
-    case DT_BF16: return dcn_pb<bf16>(pb, P.cout, L, im, jobs, count, s);
+    case DT_F32: return dcn_pb<float>(pb, P.cout, cpg, L, im, jobs, count, s);
+    case DT_F16: return dcn_pb<f16>(pb, P.cout, cpg, L, im, jobs, count, s);
+    case DT_BF16: return dcn_pb<bf16>(pb, P.cout, cpg, L, im, jobs, count, s);
   }
   return hipErrorInvalidValue;
 }
@@ -687,10 +991,10 @@ hipError_t hr_dispatch(const PackedConv& P, int tu, const HrImg* im, const HrImg
 
 }  // namespace
 
-int conv_ob(int role, int epi, int obtot) {
+int conv_ob(int role, int epi, int obtot, int tc) {
   if (role == CONV_OFF2) return obtot % 7 == 0 ? 7 : (obtot % 4 == 0 ? 4 : 1);
   if (role == CONV_OFF1) return obtot % 4 == 0 ? 4 : 2;
-  if (epi == EPI_SHUFFLE) return 8;
+  if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : 8;
   return obtot % 4 == 0 ? 4 : 2;
 }
 
@@ -740,6 +1044,22 @@ hipError_t launch_dcn(const PackedConv& P, int tf, int pb, const DcnImg& im, int
 hipError_t launch_dcn_batch(const PackedConv& P, int tf, int pb, const DcnImg* jobs, const int* count,
                             int ldo, int groups, hipStream_t s) {
   return dcn_dispatch(P, tf, pb, ldo, groups, nullptr, jobs, count, s);
+}
+
+hipError_t launch_amax(int dt, const void* x, size_t n, uint32_t* amax_bits, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 4 * 256 - 1) / (4 * 256);
+  const dim3 grid((unsigned)(blocks < 1024 ? blocks : 1024));
+  if (dt == DT_F16) hipLaunchKernelGGL((k_amax<f16>), grid, dim3(256), 0, s, static_cast<const f16*>(x), n, amax_bits);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_amax<float>), grid, dim3(256), 0, s, static_cast<const float*>(x), n, amax_bits);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_qscale(const uint32_t* amax_bits, const float* wscale, float* oscale, float* ainv, int rows,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_qscale, dim3(1), dim3(256), 0, s, amax_bits, wscale, oscale, ainv, rows);
+  return hipGetLastError();
 }
 
 hipError_t launch_hr(const PackedConv& P, int tu, const HrImg& im, hipStream_t s) {

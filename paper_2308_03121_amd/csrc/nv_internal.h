@@ -97,16 +97,22 @@ hipError_t launch_pack_batch(const PackJob* jobs, const int* count, hipStream_t 
 hipError_t launch_scene_batch(const SceneJob* jobs, const int* count, hipStream_t s);
 
 // ---- network (k_net.hip) ----
-enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+// DT_F8 (OCP e4m3) is an MFMA operand type only; FP8 layers read and write float16.
+enum DType { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
 
-inline int dtype_bytes(int dt) { return dt == DT_F32 ? 4 : 2; }
+inline int dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_F8 ? 1 : 2); }
 
-// Packed weights of one conv for the MFMA kernels: fragment-ordered A operands
-// [tap][kgroup][oblock][lane] x 16 bytes in the MFMA type tc, and the float bias per
-// A row.  For the HR conv the fragments hold the 32 x C tap-response matrix.
+// Packed weights of one conv for the MFMA kernels: fragment-ordered A operands in the
+// MFMA type tc (16 bytes per lane, 32 for FP8), and the float bias per A row.  For the
+// HR conv the fragments hold the 32 x C tap-response matrix.  FP8 layers also carry
+// the per-row output scale (weight scale x activation scale) and the reciprocal
+// activation scale, both in device memory so that recalibration needs no relaunch
+// setup (captured graphs read the current values).
 struct PackedConv {
   void* frag = nullptr;    // device
   float* bias = nullptr;   // device, obtot*16 floats
+  float* oscale = nullptr; // device, obtot*16 floats (FP8 only)
+  float* ainv = nullptr;   // device scalar (FP8 only)
   int cin = 0, cout = 0, obtot = 0, tc = DT_F32;
 };
 
@@ -164,8 +170,8 @@ struct HrImg {
   int item_begin;
 };
 
-// Output blocks per workgroup chosen by the conv dispatch for a role / epilogue.
-int conv_ob(int role, int epi, int obtot);
+// Output blocks per workgroup chosen by the conv dispatch for a role / epilogue / MFMA type.
+int conv_ob(int role, int epi, int obtot, int tc);
 inline int conv_items(int H, int W, int pb, int nobg) {
   return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
 }
@@ -182,6 +188,12 @@ hipError_t launch_dcn(const PackedConv& L, int tf, int pb, const DcnImg& im, int
                       hipStream_t s);
 // HR conv C->3 plus the bilinear x2 base of frame a (tsel 0), b (1) or their mean (2).
 hipError_t launch_hr(const PackedConv& L, int tu, const HrImg& im, hipStream_t s);
+
+// FP8 calibration: folds max |x| over n elements of x (float16 or float) into
+// *amax_bits (float bits, atomic max), and derives a layer's scales from it.
+hipError_t launch_amax(int dt, const void* x, size_t n, uint32_t* amax_bits, hipStream_t s);
+hipError_t launch_qscale(const uint32_t* amax_bits, const float* wscale, float* oscale, float* ainv, int rows,
+                         hipStream_t s);
 
 hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
                                 hipStream_t s);

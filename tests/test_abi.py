@@ -83,13 +83,22 @@ def test_context_rejects_bad_config(lib):
                       ((64, 2, 1, 2, 8, 7, 0), _abi.NV_E_INVALID),
                       ((64, 2, 8, 3, 8, 7, 0), _abi.NV_E_UNSUPPORTED),
                       ((64, 2, 8, 2, 8, 1, 0), _abi.NV_E_UNSUPPORTED),
-                      ((64, 2, 8, 2, 8, 7, 9), _abi.NV_E_INVALID)]:
+                      ((64, 2, 8, 2, 8, 7, 9), _abi.NV_E_INVALID),
+                      ((32, 2, 8, 2, 8, 7, 3), _abi.NV_E_UNSUPPORTED),    # FP8 needs C = 64
+                      ((64, 2, 8, 2, 8, 7 | 16, 1), _abi.NV_E_INVALID),   # FP8 fusion without FP8
+                      ((64, 2, 8, 2, 8, 7 | 32, 3), _abi.NV_E_UNSUPPORTED)]:
         c = _abi.NvNetConfig(*cfg)
         assert lib.nv_context_create(0, ctypes.byref(c), wp, 10, ctypes.byref(h)) == code, cfg
         assert not h.value
     c = _abi.NvNetConfig(32, 2, 8, 2, 8, 7, 0)
     assert lib.nv_context_create(0, ctypes.byref(c), wp, 10, ctypes.byref(h)) == _abi.NV_E_INVALID
     assert "needs" in lib.nv_last_error().decode()
+
+
+def test_fp8_entry_points_reject_null(lib):
+    f = ctypes.c_float()
+    assert lib.nv_calibrate(None, None, None, 2, None) == _abi.NV_E_INVALID
+    assert lib.nv_fp8_scales(None, ctypes.byref(f), 1, 0, None) == _abi.NV_E_INVALID
 
 
 def test_null_handles_are_rejected(lib):
