@@ -151,7 +151,8 @@ nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int32_t set, vo
 
 /* Unpack one frame (section 3.1, pixel formats): decode codes, upsample 4:2:0 chroma
  * bilinearly, apply the BT.709 inverse matrix (no clamp), and write planar float32
- * R'G'B' d_rgb[3][hp][wp] (plane stride hp*wp floats).  hp >= height and wp >= width;
+ * R'G'B' d_rgb[3][hp][wp] (plane stride hp*wp floats).  hp >= height and wp >= width, wp a
+ * multiple of 4, d_rgb 16-byte aligned;
  * rows/columns beyond the frame replicate the last row/column (alignment padding). */
 nv_status nv_unpack(const nv_format* fmt, const nv_planes* in, float* d_rgb, int32_t hp,
                     int32_t wp, void* stream);
@@ -159,8 +160,8 @@ nv_status nv_unpack(const nv_format* fmt, const nv_planes* in, float* d_rgb, int
 /* Requantise planar float32 R'G'B' to a frame of format `fmt`: clamp R'G'B' to [0,1],
  * BT.709 forward matrix, 4:2:0 chroma by the (1/4,1/2,1/4) x (1/2,1/2) left-sited
  * filter with replicated edges, code = clamp(floor(v + 1/2), 0, 2^bits - 1).  d_rgb
- * is [3][rh][rw] (rh >= fmt->height, rw >= fmt->width); only the top-left
- * fmt->height x fmt->width region is read (crop). */
+ * is [3][rh][rw] (rh >= fmt->height, rw >= fmt->width, rw a multiple of 4, d_rgb
+ * 16-byte aligned); only the top-left fmt->height x fmt->width region is read (crop). */
 nv_status nv_pack(const nv_format* fmt, const float* d_rgb, int32_t rh, int32_t rw,
                   const nv_planes* out, void* stream);
 

@@ -82,11 +82,12 @@ def unpack(fmt: NvFormat, planes, hp: int, wp: int, stream=None) -> torch.Tensor
     return rgb
 
 
-def pack(fmt: NvFormat, rgb: torch.Tensor, stream=None):
+def pack(fmt: NvFormat, rgb: torch.Tensor, out=None, stream=None):
     lib = _abi.load()
     if rgb.dtype != torch.float32 or not rgb.is_contiguous() or rgb.dim() != 3:
         raise ValueError("rgb must be a contiguous float32 [3, H, W] tensor")
-    out = alloc_frame(fmt.width, fmt.height, fmt.bits, fmt.chroma, rgb.device)
+    if out is None:
+        out = alloc_frame(fmt.width, fmt.height, fmt.bits, fmt.chroma, rgb.device)
     p = planes_struct(*out)
     check(lib.nv_pack(byref(fmt), _ptr(rgb), rgb.shape[1], rgb.shape[2], byref(p),
                       c_void_p(_stream(stream))))

@@ -877,8 +877,9 @@ extern "C" nv_status nv_pack(const nv_format* fmt, const float* d_rgb, int32_t r
   NV_TRY(check_format(fmt, "output"));
   NV_TRY(check_planes(fmt, out, "output"));
   if (!d_rgb) return fail(NV_E_INVALID, "d_rgb is NULL");
-  if (rh < fmt->height || rw < fmt->width || rh > 2 * kMaxDim || rw > 2 * kMaxDim)
-    return fail(NV_E_INVALID, "RGB size %dx%d smaller than the frame", rw, rh);
+  if (rh < fmt->height || rw < fmt->width || rh > 2 * kMaxDim || rw > 2 * kMaxDim || (rw & 3))
+    return fail(NV_E_INVALID, "RGB size %dx%d must cover the frame and rw be a multiple of 4", rw, rh);
+  if ((reinterpret_cast<uintptr_t>(d_rgb) & 15) != 0) return fail(NV_E_INVALID, "d_rgb must be 16-byte aligned");
   return check_launch(launch_pack(to_frame_out(fmt, out), d_rgb, rh, rw, (hipStream_t)stream), "pack");
 }
 

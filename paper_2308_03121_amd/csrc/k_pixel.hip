@@ -66,6 +66,64 @@ struct Code<10> {
   }
 };
 
+// N consecutive codes of row y starting at column x0 (N = 4 or 8), columns clamped to
+// w - 1.  A run inside the row whose address is aligned to its size is one vector load.
+template <int BITS, int N>
+__device__ __forceinline__ void code_run(const void* base, int64_t pitch, int y, int x0, int w, float (&v)[N]) {
+  constexpr int SB = BITS == 8 ? 1 : 2;      // bytes per sample
+  constexpr int VB = N * SB;                 // 4, 8 or 16 bytes
+  constexpr uint32_t mask = BITS == 8 ? 0xFFu : 0x3FFu;
+  const char* row = static_cast<const char*>(base) + y * pitch;
+  const char* at = row + (size_t)x0 * SB;
+  if (x0 + N <= w && (reinterpret_cast<uintptr_t>(at) & (VB - 1)) == 0) {
+    uint32_t wd[VB / 4];
+    if constexpr (VB == 4) {
+      wd[0] = *reinterpret_cast<const uint32_t*>(at);
+    } else if constexpr (VB == 8) {
+      const u32x2 t = *reinterpret_cast<const u32x2*>(at);
+      wd[0] = t[0];
+      wd[1] = t[1];
+    } else {
+      const u32x4 t = *reinterpret_cast<const u32x4*>(at);
+      wd[0] = t[0];
+      wd[1] = t[1];
+      wd[2] = t[2];
+      wd[3] = t[3];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      constexpr int PER = 4 / SB;            // samples per 32-bit word
+      v[k] = (float)((wd[k / PER] >> (8 * SB * (k % PER))) & mask);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = Code<BITS>::get(base, pitch, y, min(x0 + k, w - 1));
+  }
+}
+
+// N codes written to row y from column x0 (all inside the row): one vector store when
+// aligned, else one store per sample.
+template <int BITS, int N>
+__device__ __forceinline__ void code_store(void* base, int64_t pitch, int y, int x0, const int (&c)[N]) {
+  constexpr int SB = BITS == 8 ? 1 : 2;
+  constexpr int VB = N * SB;
+  char* at = static_cast<char*>(base) + y * pitch + (size_t)x0 * SB;
+  if ((reinterpret_cast<uintptr_t>(at) & (VB - 1)) == 0) {
+    constexpr int PER = 4 / SB;
+    uint32_t wd[VB / 4];
+#pragma unroll
+    for (int i = 0; i < VB / 4; ++i) wd[i] = 0u;
+#pragma unroll
+    for (int k = 0; k < N; ++k) wd[k / PER] |= (uint32_t)c[k] << (8 * SB * (k % PER));
+    if constexpr (VB == 4) *reinterpret_cast<uint32_t*>(at) = wd[0];
+    else if constexpr (VB == 8) *reinterpret_cast<u32x2*>(at) = u32x2{wd[0], wd[1]};
+    else *reinterpret_cast<u32x4*>(at) = u32x4{wd[0], wd[1], wd[2], wd[3]};
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) Code<BITS>::put(base, pitch, y, x0 + k, c[k]);
+  }
+}
+
 // Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
 template <class J>
 __device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
@@ -82,12 +140,8 @@ __device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
 // (Y'CbCr -> R'G'B': Y' = (Y - 16s) / 219s, C' = (C - 128s) / 224s,
 //  R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr')
 template <int BITS, bool C420>
-__device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp,
-                                        int wp, int gid) {
-  const int groups_per_row = wp >> 2;
-  if (gid >= groups_per_row * hp) return;
-  const int y = gid / groups_per_row;
-  const int x0 = (gid - y * groups_per_row) << 2;
+__device__ __forceinline__ void unpack_px4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp,
+                                           int wp, int y, int x0) {
   const int sy = min(y, f.h - 1);
   const int hc = C420 ? (f.h >> 1) : f.h;
   const int wc = C420 ? (f.w >> 1) : f.w;
@@ -137,21 +191,82 @@ __device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __r
   st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
 }
 
-__device__ __forceinline__ void unpack4_any(const Frame& f, const Inv& m, float* rgb, int hp, int wp,
-                                            int gid) {
-  if (f.bits == 8) {
-    if (f.chroma == 420) unpack4<8, true>(f, m, rgb, hp, wp, gid);
-    else unpack4<8, false>(f, m, rgb, hp, wp, gid);
+// Eight consecutive padded pixels of row y per thread (four in the last group of a row
+// when wp is not a multiple of 8).  Runs fully inside the frame
+// read each plane row with vector loads (luma 8 samples; 4:2:0 chroma the 4 + 1
+// samples the bilinear filter needs from rows ci and ci2); runs that reach into the
+// padding use the per-pixel form.
+template <int BITS, bool C420>
+__device__ __forceinline__ void unpack8(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp, int wp,
+                                        int gid) {
+  const int groups_per_row = (wp + 7) >> 3;   // wp is a multiple of 4
+  if (gid >= groups_per_row * hp) return;
+  const int y = gid / groups_per_row;
+  const int x0 = (gid - y * groups_per_row) << 3;
+  if (x0 + 8 > f.w || x0 + 8 > wp) {
+    unpack_px4<BITS, C420>(f, m, rgb, hp, wp, y, x0);
+    if (x0 + 4 < wp) unpack_px4<BITS, C420>(f, m, rgb, hp, wp, y, x0 + 4);
+    return;
+  }
+  const int sy = min(y, f.h - 1);
+  float yv[8], cb[8], cr[8];
+  code_run<BITS, 8>(f.p[0], f.pitch[0], sy, x0, f.w, yv);
+  if (C420) {
+    const int hc = f.h >> 1, wc = f.w >> 1;
+    const int ci = sy >> 1;
+    const int ci2 = (sy & 1) ? min(ci + 1, hc - 1) : max(ci - 1, 0);
+    const int c0 = x0 >> 1, c4 = min(c0 + 4, wc - 1);
+#pragma unroll
+    for (int pl = 1; pl <= 2; ++pl) {
+      float top[4], bot[4], vb[5];
+      code_run<BITS, 4>(f.p[pl], f.pitch[pl], ci, c0, wc, top);
+      code_run<BITS, 4>(f.p[pl], f.pitch[pl], ci2, c0, wc, bot);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) vb[i] = 0.75f * top[i] + 0.25f * bot[i];
+      vb[4] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, c4) +
+              0.25f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci2, c4);
+      float* c = pl == 1 ? cb : cr;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) c[k] = (k & 1) ? 0.5f * (vb[k >> 1] + vb[(k >> 1) + 1]) : vb[k >> 1];
+    }
   } else {
-    if (f.chroma == 420) unpack4<10, true>(f, m, rgb, hp, wp, gid);
-    else unpack4<10, false>(f, m, rgb, hp, wp, gid);
+    code_run<BITS, 8>(f.p[1], f.pitch[1], sy, x0, f.w, cb);
+    code_run<BITS, 8>(f.p[2], f.pitch[2], sy, x0, f.w, cr);
+  }
+  float r[8], g[8], b[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float yn = (yv[k] - m.yo) * m.ys;
+    const float cbn = (cb[k] - m.co) * m.cs;
+    const float crn = (cr[k] - m.co) * m.cs;
+    r[k] = fmaf(m.rcr, crn, yn);
+    b[k] = fmaf(m.bcb, cbn, yn);
+    g[k] = fmaf(-m.gcr, crn, fmaf(-m.gcb, cbn, yn));
+  }
+  const size_t plane = (size_t)hp * wp;
+  float* o = rgb + (size_t)y * wp + x0;
+  st4(o, f32x4{r[0], r[1], r[2], r[3]});
+  st4(o + 4, f32x4{r[4], r[5], r[6], r[7]});
+  st4(o + plane, f32x4{g[0], g[1], g[2], g[3]});
+  st4(o + plane + 4, f32x4{g[4], g[5], g[6], g[7]});
+  st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
+  st4(o + 2 * plane + 4, f32x4{b[4], b[5], b[6], b[7]});
+}
+
+__device__ __forceinline__ void unpack_any(const Frame& f, const Inv& m, float* rgb, int hp, int wp, int gid) {
+  if (f.bits == 8) {
+    if (f.chroma == 420) unpack8<8, true>(f, m, rgb, hp, wp, gid);
+    else unpack8<8, false>(f, m, rgb, hp, wp, gid);
+  } else {
+    if (f.chroma == 420) unpack8<10, true>(f, m, rgb, hp, wp, gid);
+    else unpack8<10, false>(f, m, rgb, hp, wp, gid);
   }
 }
 
 template <int BITS, bool C420>
 __global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
                                                 int wp) {
-  unpack4<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
+  unpack8<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_unpack_batch(const UnpackJob* __restrict__ jobs,
@@ -159,7 +274,7 @@ __global__ __launch_bounds__(256) void k_unpack_batch(const UnpackJob* __restric
   const int njobs = count[0], total = count[1];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const UnpackJob& J = jobs[find_job(jobs, njobs, item)];
-    unpack4_any(J.f, J.m, J.rgb, J.hp, J.wp, (item - J.item_begin) * 256 + threadIdx.x);
+    unpack_any(J.f, J.m, J.rgb, J.hp, J.wp, (item - J.item_begin) * 256 + threadIdx.x);
   }
 }
 
@@ -215,27 +330,127 @@ __device__ __forceinline__ void pack444_px(const FrameOut& f, const Fwd& m,
   Code<BITS>::put(f.p[2], f.pitch[2], y, x, quant(fmaf((R - Yn) * m.crs, m.cs, m.co), m.maxc));
 }
 
+// Four chroma samples of chroma row i per thread (a 2 x 8 luma block): each R'G'B' row
+// is read as two float4 vectors plus the left neighbour, the codes are written as
+// vector runs.  Blocks that reach past the frame width use the per-sample form.
+template <int BITS>
+__device__ __forceinline__ void pack420_x4(const FrameOut& f, const Fwd& m, const float* __restrict__ rgb,
+                                           int rh, int rw, int gid) {
+  const int wc = f.w >> 1, hc = f.h >> 1;
+  const int gpr = (wc + 3) >> 2;
+  if (gid >= gpr * hc) return;
+  const int i = gid / gpr, j0 = (gid - i * gpr) << 2;
+  if (j0 + 4 > wc) {
+    for (int j = j0; j < wc; ++j) pack420_px<BITS>(f, m, rgb, rh, rw, i * wc + j);
+    return;
+  }
+  const size_t plane = (size_t)rh * rw;
+  const int x0 = 2 * j0;
+  float cbs[4] = {0.0f, 0.0f, 0.0f, 0.0f}, crs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    const int yy = 2 * i + dy;
+    const float* row = rgb + (size_t)yy * rw;
+    float R[9], G[9], B[9];           // columns x0 - 1 .. x0 + 7
+    const int xl = max(x0 - 1, 0);
+    R[0] = row[xl];
+    G[0] = row[xl + plane];
+    B[0] = row[xl + 2 * plane];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x4 r4 = ld4(row + x0 + 4 * h), g4 = ld4(row + plane + x0 + 4 * h),
+                  b4 = ld4(row + 2 * plane + x0 + 4 * h);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        R[1 + 4 * h + k] = r4[k];
+        G[1 + 4 * h + k] = g4[k];
+        B[1 + 4 * h + k] = b4[k];
+      }
+    }
+    float Yn[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      R[c] = clamp01(R[c]);
+      G[c] = clamp01(G[c]);
+      B[c] = clamp01(B[c]);
+      Yn[c] = fmaf(m.kb, B[c], fmaf(m.kg, G[c], m.kr * R[c]));
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int c = 1 + 2 * jj + dx;
+        const float wgt = dx == 0 ? 0.25f : 0.125f;
+        cbs[jj] = fmaf(wgt, (B[c] - Yn[c]) * m.cbs, cbs[jj]);
+        crs[jj] = fmaf(wgt, (R[c] - Yn[c]) * m.crs, crs[jj]);
+      }
+    int yc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) yc[k] = quant(fmaf(Yn[1 + k], m.ys, m.yo), m.maxc);
+    code_store<BITS, 8>(f.p[0], f.pitch[0], yy, x0, yc);
+  }
+  int cbc[4], crc[4];
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    cbc[jj] = quant(fmaf(cbs[jj], m.cs, m.co), m.maxc);
+    crc[jj] = quant(fmaf(crs[jj], m.cs, m.co), m.maxc);
+  }
+  code_store<BITS, 4>(f.p[1], f.pitch[1], i, j0, cbc);
+  code_store<BITS, 4>(f.p[2], f.pitch[2], i, j0, crc);
+}
+
+// Eight consecutive pixels of row y per thread.
+template <int BITS>
+__device__ __forceinline__ void pack444_x8(const FrameOut& f, const Fwd& m, const float* __restrict__ rgb,
+                                           int rh, int rw, int gid) {
+  const int gpr = (f.w + 7) >> 3;
+  if (gid >= gpr * f.h) return;
+  const int y = gid / gpr, x0 = (gid - y * gpr) << 3;
+  if (x0 + 8 > f.w) {
+    for (int x = x0; x < f.w; ++x) pack444_px<BITS>(f, m, rgb, rh, rw, y * f.w + x);
+    return;
+  }
+  const size_t plane = (size_t)rh * rw;
+  const float* row = rgb + (size_t)y * rw + x0;
+  int yc[8], cbc[8], crc[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const f32x4 r4 = ld4(row + 4 * h), g4 = ld4(row + plane + 4 * h), b4 = ld4(row + 2 * plane + 4 * h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float R = clamp01(r4[k]), G = clamp01(g4[k]), B = clamp01(b4[k]);
+      const float Yn = fmaf(m.kb, B, fmaf(m.kg, G, m.kr * R));
+      yc[4 * h + k] = quant(fmaf(Yn, m.ys, m.yo), m.maxc);
+      cbc[4 * h + k] = quant(fmaf((B - Yn) * m.cbs, m.cs, m.co), m.maxc);
+      crc[4 * h + k] = quant(fmaf((R - Yn) * m.crs, m.cs, m.co), m.maxc);
+    }
+  }
+  code_store<BITS, 8>(f.p[0], f.pitch[0], y, x0, yc);
+  code_store<BITS, 8>(f.p[1], f.pitch[1], y, x0, cbc);
+  code_store<BITS, 8>(f.p[2], f.pitch[2], y, x0, crc);
+}
+
 __device__ __forceinline__ void pack_any(const FrameOut& f, const Fwd& m, const float* rgb, int rh,
                                          int rw, int gid) {
   if (f.chroma == 420) {
-    if (f.bits == 8) pack420_px<8>(f, m, rgb, rh, rw, gid);
-    else pack420_px<10>(f, m, rgb, rh, rw, gid);
+    if (f.bits == 8) pack420_x4<8>(f, m, rgb, rh, rw, gid);
+    else pack420_x4<10>(f, m, rgb, rh, rw, gid);
   } else {
-    if (f.bits == 8) pack444_px<8>(f, m, rgb, rh, rw, gid);
-    else pack444_px<10>(f, m, rgb, rh, rw, gid);
+    if (f.bits == 8) pack444_x8<8>(f, m, rgb, rh, rw, gid);
+    else pack444_x8<10>(f, m, rgb, rh, rw, gid);
   }
 }
 
 template <int BITS>
 __global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float* __restrict__ rgb,
                                                  int rh, int rw) {
-  pack420_px<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
+  pack420_x4<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
 }
 
 template <int BITS>
 __global__ __launch_bounds__(256) void k_pack444(FrameOut f, Fwd m, const float* __restrict__ rgb,
                                                  int rh, int rw) {
-  pack444_px<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
+  pack444_x8<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_pack_batch(const PackJob* __restrict__ jobs,
@@ -383,7 +598,7 @@ __global__ __launch_bounds__(64) void k_scene_final_batch(const SceneJob* __rest
 
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s) {
   const Inv m = make_inv(f.bits);
-  const int n = (wp >> 2) * hp;
+  const int n = ((wp + 7) >> 3) * hp;
   const dim3 grid((n + 255) / 256), blk(256);
   if (f.bits == 8 && f.chroma == 420) hipLaunchKernelGGL((k_unpack<8, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
   else if (f.bits == 8) hipLaunchKernelGGL((k_unpack<8, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
@@ -395,12 +610,12 @@ hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t
 hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipStream_t s) {
   const Fwd m = make_fwd(f.bits);
   if (f.chroma == 420) {
-    const int n = (f.w >> 1) * (f.h >> 1);
+    const int n = (((f.w >> 1) + 3) >> 2) * (f.h >> 1);
     const dim3 grid((n + 255) / 256), blk(256);
     if (f.bits == 8) hipLaunchKernelGGL((k_pack420<8>), grid, blk, 0, s, f, m, rgb, rh, rw);
     else hipLaunchKernelGGL((k_pack420<10>), grid, blk, 0, s, f, m, rgb, rh, rw);
   } else {
-    const int n = f.w * f.h;
+    const int n = ((f.w + 7) >> 3) * f.h;
     const dim3 grid((n + 255) / 256), blk(256);
     if (f.bits == 8) hipLaunchKernelGGL((k_pack444<8>), grid, blk, 0, s, f, m, rgb, rh, rw);
     else hipLaunchKernelGGL((k_pack444<10>), grid, blk, 0, s, f, m, rgb, rh, rw);

@@ -48,7 +48,6 @@ hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* his
 // total number of items, both read on the device, so one captured graph serves any
 // batch that fits the tables.  Blocks grid-stride over the items.
 constexpr int kBatchGrid = 2048;          // persistent workgroups per batched launch
-constexpr int kUnpackPerItem = 1024;      // 256 threads x 4 pixels
 constexpr int kSceneRowsPerItem = 8;
 
 struct UnpackJob {
@@ -84,9 +83,9 @@ struct SceneJob {
   int item_begin;              // in row chunks of kSceneRowsPerItem
 };
 
-inline int unpack_items(int hp, int wp) { return ((wp / 4) * hp + 255) / 256; }
+inline int unpack_items(int hp, int wp) { return (((wp + 7) / 8) * hp + 255) / 256; }
 inline int pack_items(int w, int h, int chroma) {
-  const int n = chroma == 420 ? (w / 2) * (h / 2) : w * h;
+  const int n = chroma == 420 ? ((w / 2 + 3) / 4) * (h / 2) : ((w + 7) / 8) * h;
   return (n + 255) / 256;
 }
 inline int scene_items(int h) { return (h + kSceneRowsPerItem - 1) / kSceneRowsPerItem; }

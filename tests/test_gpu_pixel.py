@@ -22,8 +22,11 @@ def B():
     return binding
 
 
+# sizes cover: aligned rows (vector loads), odd pitches (per-sample loads), padded widths
+# that are multiples of 4 but not 8, frames narrower than their padding
 CASES = [(64, 64, 8, 420, 64, 64), (70, 36, 8, 420, 72, 40), (46, 30, 10, 420, 48, 32),
-         (40, 24, 8, 444, 40, 24), (38, 22, 10, 444, 40, 24), (960, 540, 8, 420, 960, 544)]
+         (40, 24, 8, 444, 40, 24), (38, 22, 10, 444, 40, 24), (960, 540, 8, 420, 960, 544),
+         (60, 20, 8, 444, 60, 20), (44, 20, 10, 420, 44, 24)]
 
 
 @pytest.mark.parametrize("w,h,bits,chroma,wp,hp", CASES)
@@ -41,6 +44,42 @@ def test_unpack_matches_oracle(B, w, h, bits, chroma, wp, hp):
     assert max_abs(rgb.cpu().numpy(), ref) <= UNPACK_TOL
 
 
+def _offset_planes(B, planes, off):
+    """Device copies of the planes whose rows start `off` samples into wider rows (so
+    plane addresses and pitches are not vector aligned)."""
+    import torch as T
+    out = []
+    for p in B.to_device_frame(*planes):
+        big = T.zeros((p.shape[0], p.shape[1] + off + 3), dtype=p.dtype, device=p.device)
+        big[:, off:off + p.shape[1]] = p
+        out.append(big[:, off:off + p.shape[1]])
+    return tuple(out)
+
+
+@pytest.mark.parametrize("bits,chroma", [(8, 420), (10, 444)])
+def test_unpack_pack_misaligned_planes(B, bits, chroma):
+    say(f"unpack/pack misaligned planes {bits}-bit {chroma}")
+    w, h = 64, 32
+    clip = synth.gen_clip(w, h, 1, bits=bits, chroma=chroma, seed=3, garbage_high_bits=(bits == 10))
+    Y, U, V = clip.frame(0)
+    fmt = B.fmt_struct(w, h, bits, chroma)
+    rgb = B.unpack(fmt, _offset_planes(B, (Y, U, V), 1), h, w)
+    torch.cuda.synchronize()
+    ref = pixel.unpack(Y, U, V, bits, chroma)
+    assert max_abs(rgb.cpu().numpy(), ref) <= UNPACK_TOL
+    # pack into outputs at odd offsets and compare with packing into aligned outputs
+    dt = torch.uint8 if bits == 8 else torch.int16
+    hc, wc = (h // 2, w // 2) if chroma == 420 else (h, w)
+    outs = _offset_planes(B, (np.zeros((h, w), np.uint8 if bits == 8 else np.uint16),
+                               np.zeros((hc, wc), np.uint8 if bits == 8 else np.uint16),
+                               np.zeros((hc, wc), np.uint8 if bits == 8 else np.uint16)), 1)
+    assert outs[0].dtype == dt
+    got = B.frame_to_numpy(B.pack(fmt, rgb, out=outs), bits)
+    want = B.frame_to_numpy(B.pack(fmt, rgb), bits)
+    for g, r in zip(got, want):
+        assert np.array_equal(g, r)
+
+
 def _tie_mask(v, bits):
     """Where the FP64 value lies within float32 reach of a rounding tie (both codes valid)."""
     eps = 4e-4 * (1 << (bits - 8))
@@ -50,7 +89,7 @@ def _tie_mask(v, bits):
 
 @pytest.mark.parametrize("w,h,bits,chroma,rw,rh", [(128, 72, 8, 420, 136, 80), (64, 64, 10, 420, 64, 64),
                                                     (48, 30, 8, 444, 56, 32), (30, 18, 10, 444, 32, 24),
-                                                    (1920, 1080, 8, 420, 1920, 1088)])
+                                                    (52, 20, 8, 420, 56, 24), (1920, 1080, 8, 420, 1920, 1088)])
 def test_pack_matches_oracle(B, w, h, bits, chroma, rw, rh):
     say(f"pack {w}x{h} {bits}-bit {chroma}")
     rng = np.random.default_rng(w * h)
