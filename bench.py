@@ -311,10 +311,12 @@ def main():
     outs = [B.alloc_frame(2 * W_, 2 * H_, clip.bits, clip.chroma) for _ in range(2 * clip.n_frames)]
     hp, wp = (H_ + 7) // 8 * 8, (W_ + 7) // 8 * 8
 
+    tuning = {}
+
     def make(prec):
         c = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec.split("-")[0],
                       fp8_fusion=prec == "fp8-fusion")
-        c.autotune(hp, wp)
+        tuning[prec] = c.autotune(hp, wp)
         if prec.startswith("fp8"):
             c.calibrate(fmt, frames[:4])
         return c, c.open_stream(fmt)
@@ -412,6 +414,7 @@ def main():
                         "kernel_ms_per_step": {k: round(v[1] / args.steps, 2) for k, v in pr.items() if v[0]}}
         st2.close()
         c2.close()
+    rec["tuning"] = tuning
     if others:
         rec["other_precisions"] = others
         print("# other precisions: " + json.dumps(others), file=sys.stderr, flush=True)

@@ -203,7 +203,8 @@ struct Profiler {
   }
 };
 
-// Tile shapes (rows per wave) of the kernels that have several; the autotuner may change
+// Tile shapes of the kernels that have several (bulk convs: tile codes, see tile_code;
+// DCN: rows per wave); the autotuner may change
 // them per context (see nv_autotune).
 struct Tuning {
   int pb_block = 2, pb_up = 2, pb_dcn = 2;
@@ -1528,7 +1529,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     T.blk_a[k] = conv_img(s->feat[sl], nullptr, nullptr, nullptr, nullptr, nullptr, t0, hp, wp);
     T.blk_b[k] = conv_img(t0, nullptr, nullptr, nullptr, nullptr, s->feat[sl], s->feat[sl], hp, wp);
     T.blk_a[k].item_begin = T.blk_b[k].item_begin = it[BL_BLOCK];
-    it[BL_BLOCK] += conv_items(hp, wp, pbb, nobg);
+    it[BL_BLOCK] += conv_items(hp, wp, tile_pb(pbb), nobg);
   }
   char* gp = B->group_pool.base;
   for (size_t k = 0; k < groups.size(); ++k) {
@@ -1587,7 +1588,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
       pk.rw = 2 * wp;
       pk.item_begin = it[BL_PACK];
     }
-    it[BL_UP] += conv_items(hp, wp, pbu, ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot, ctx->up.tc));
+    it[BL_UP] += conv_items(hp, wp, tile_pb(pbu), ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot, ctx->up.tc));
     it[BL_HR] += hr_items(hp, wp);
     it[BL_PACK] += pack_items(s->ofmt.width, s->ofmt.height, s->ofmt.chroma);
   }
@@ -1638,6 +1639,13 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
 // --------------------------------------------------------------- autotuner ----
 
 namespace {
+
+std::string tile_name(int code) {
+  char b[32];
+  if (tile_wo(code) == 1) snprintf(b, sizeof b, "pb%d", tile_pb(code));
+  else snprintf(b, sizeof b, "pb%dw%d", tile_pb(code), tile_wo(code));
+  return b;
+}
 
 template <class F>
 nv_status time_launch(hipStream_t s, int reps, float* ms, F&& launch) {
@@ -1698,11 +1706,16 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     HIP_TRY(hipMemsetAsync(ws.feat[0], 0, (size_t)hp * wp * C * dtype_bytes(ft), s));
     HIP_TRY(hipMemsetAsync(ws.offs, 0, (size_t)hp * wp * ctx->ldo * 4, s));
     char buf[256];
+    // bulk conv tiles: rows per wave 1, 2, 4, and for 16-bit / FP8 also with two waves
+    // along the output blocks
+    std::vector<int> bulk_tiles = {1, 2, 4};
+    if (ft != DT_F32)
+      for (int pb : {1, 2, 4}) bulk_tiles.push_back(tile_code(pb, 2));
     struct Cand {
       const char* name;
       int* slot;
       std::vector<int> pbs;
-    } cands[3] = {{"block", &ctx->tune.pb_block, {1, 2, 4}}, {"up", &ctx->tune.pb_up, {1, 2, 4}},
+    } cands[3] = {{"block", &ctx->tune.pb_block, bulk_tiles}, {"up", &ctx->tune.pb_up, bulk_tiles},
                   {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}}};
     for (auto& cd : cands) {
       float best = 1e30f;
@@ -1735,7 +1748,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
           st = time_launch(s, 3, &ms, [&] { return launch_dcn(ctx->dcn, ft, pb, di, ctx->ldo, ctx->G, s); });
         }
         if (st != NV_OK) return st;
-        snprintf(buf, sizeof buf, " pb%d=%.1fus", pb, 1000.0f * ms);
+        snprintf(buf, sizeof buf, " %s=%.1fus", tile_name(pb).c_str(), 1000.0f * ms);
         rep += buf;
         if (ms < best) {
           best = ms;
@@ -1743,7 +1756,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
         }
       }
       *cd.slot = best_pb;
-      snprintf(buf, sizeof buf, " -> pb%d; ", best_pb);
+      snprintf(buf, sizeof buf, " -> %s; ", tile_name(best_pb).c_str());
       rep += buf;
     }
     if (cache) {
@@ -1757,8 +1770,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     rep += key;
   }
   char tail[96];
-  snprintf(tail, sizeof tail, " [block pb%d, up pb%d, dcn pb%d]", ctx->tune.pb_block, ctx->tune.pb_up,
-           ctx->tune.pb_dcn);
+  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d]", tile_name(ctx->tune.pb_block).c_str(),
+           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn);
   rep += tail;
   if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
     HIP_TRY(hipDeviceSynchronize());

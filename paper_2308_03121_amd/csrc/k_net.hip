@@ -54,17 +54,18 @@ struct ConvSmem {
   static constexpr int N = (TH + 2) * (kTW + 2) * LDP;
 };
 
-// Epilogue of a conv tile: bias (and, for FP8, the per-row output scale), then the
-// layer's activation / residual / offset-head / pixel-shuffle store.
+// Epilogue of a wave's part of a conv tile (rows y0 .. y0 + PB, output blocks obase ..
+// obase + OB): bias (and, for FP8, the per-row output scale), then the layer's
+// activation / residual / offset-head / pixel-shuffle store.
 template <typename TOUT, int OB, int PB, int EPI>
 __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[PB][OB],
-                                           int ty0, int tx0, int obase, const float* oscale) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                           int y0, int tx0, int obase, const float* oscale) {
+  const int lane = threadIdx.x & 63;
   const int q = lane >> 4, j = lane & 15;
   TOUT* dst = static_cast<TOUT*>(im.dst);
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
-    const int gy = ty0 + wave * PB + pb, gx = tx0 + j;
+    const int gy = y0 + pb, gx = tx0 + j;
     if (gy >= im.H || gx >= im.W) continue;
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
@@ -100,20 +101,23 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
 // channels 32 (q % 2) .. +32.  The fifth step pairs tap 8 with a zero-weight tap (its
 // lanes read tap 8's samples again, which are finite).  The accumulator is rescaled
 // by s_w[row] x s_act in the epilogue.
-template <int OB, int PB, int EPI>
+template <int OB, int PB, int EPI, int WO>
 __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& im, int ty0, int tx0, int obase,
                                              f8* tile) {
   constexpr int C = 64;
   constexpr int LDP = ConvSmem<f8, C, PB>::LDP;   // bytes per staged pixel
   constexpr int NST = 5;
+  constexpr int RW = PB * WO, OBW = OB / WO;     // this wave's rows and output blocks
+  static_assert(OB % WO == 0, "output blocks split evenly over the waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
+  const int wo = wave % WO, wr = wave / WO;
 
-  f32x4 acc[PB][OB];
+  f32x4 acc[RW][OBW];
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb)
+  for (int pb = 0; pb < RW; ++pb)
 #pragma unroll
-    for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
+    for (int ob = 0; ob < OBW; ++ob) acc[pb][ob] = zero4();
 
   const f16* src = static_cast<const f16*>(im.src0);
   if (im.sel != nullptr && *im.sel != 0u && im.alt0 != nullptr) src = static_cast<const f16*>(im.alt0);
@@ -121,58 +125,69 @@ __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& 
 
   constexpr int V = C / 8;
   constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
-  for (int idx = threadIdx.x; idx < NV; idx += 256) {
-    const int pix = idx / V, v = idx - pix * V;
-    const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
-    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-    u32x2 w = u32x2{0u, 0u};
-    if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-      const f16* p = src + ((size_t)gy * im.W + gx) * C + 8 * v;
-      w[0] = f8x4_pack(load4f<f16>(p) * ainv);
-      w[1] = f8x4_pack(load4f<f16>(p + 4) * ainv);
+  constexpr int SB = 8;                     // loads in flight per thread while staging
+  for (int i0 = 0; i0 < NV; i0 += SB * 256) {
+    Raw8<f16> rb[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      rb[u].zero();
+      if (idx < NV) {
+        const int pix = idx / V, v = idx - pix * V;
+        const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+        const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+        if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) rb[u].load(src + ((size_t)gy * im.W + gx) * C + 8 * v);
+      }
     }
-    *reinterpret_cast<u32x2*>(&tile[pix * LDP + 8 * v]) = w;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      if (idx < NV) {
+        const int pix = idx / V, v = idx - pix * V;
+        f32x4 lo, hi;
+        rb[u].to_f32(lo, hi);
+        *reinterpret_cast<u32x2*>(&tile[pix * LDP + 8 * v]) = u32x2{f8x4_pack(lo * ainv), f8x4_pack(hi * ainv)};
+      }
+    }
   }
   __syncthreads();
 
-  const f8* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + 32 * (q & 1)];
+  // the step loop stays rolled: unrolled, the compiler hoists all five steps' 32-byte
+  // weight fragments (160 registers) and occupancy drops to one or two waves per SIMD
+  const f8* tbase = &tile[((wr * RW) * (kTW + 2) + j) * LDP + 32 * (q & 1)];
   auto tap_off = [&](int st) {
     const int tap = min(2 * st + (q >> 1), 8);
     const int dy = tap / 3, dx = tap - 3 * dy;
     return (dy * (kTW + 2) + dx) * LDP;
   };
-  const u32x8* wbase = reinterpret_cast<const u32x8*>(L.wfrag) + (size_t)obase * 64 + lane;
-  u32x8 wa[OB], xb[PB];
+  const u32x8* wbase = reinterpret_cast<const u32x8*>(L.wfrag) + (size_t)(obase + wo * OBW) * 64 + lane;
+  u32x8 wa0[OBW], xb0[RW], wa1[OBW], xb1[RW];
+  auto fetch = [&](int st, u32x8 (&wa)[OBW], u32x8 (&xb)[RW]) {
+    const u32x8* wp = wbase + (size_t)st * L.obtot * 64;
 #pragma unroll
-  for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
-  {
-    const int o0 = tap_off(0);
+    for (int ob = 0; ob < OBW; ++ob) wa[ob] = wp[ob * 64];
+    const int o = tap_off(st);
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu8(tbase + o0 + pb * (kTW + 2) * LDP);
-  }
+    for (int pb = 0; pb < RW; ++pb) xb[pb] = ldu8(tbase + o + pb * (kTW + 2) * LDP);
+  };
+  auto mma = [&](const u32x8 (&wa)[OBW], const u32x8 (&xb)[RW]) {
 #pragma unroll
-  for (int st = 0; st < NST; ++st) {
-    u32x8 wn[OB], xn[PB];
+    for (int pb = 0; pb < RW; ++pb)
+#pragma unroll
+      for (int ob = 0; ob < OBW; ++ob) acc[pb][ob] = Mma<f8>::step(wa[ob], xb[pb], acc[pb][ob]);
+  };
+  // two register buffers, step i+1 loading while step i multiplies (see conv_tile)
+  fetch(0, wa0, xb0);
+#pragma unroll 1
+  for (int st = 0; st < NST; st += 2) {
+    if (st + 1 < NST) fetch(st + 1, wa1, xb1);
+    mma(wa0, xb0);
     if (st + 1 < NST) {
-      const u32x8* wp = wbase + (size_t)(st + 1) * L.obtot * 64;
-#pragma unroll
-      for (int ob = 0; ob < OB; ++ob) wn[ob] = wp[ob * 64];
-      const int o1 = tap_off(st + 1);
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xn[pb] = ldu8(tbase + o1 + pb * (kTW + 2) * LDP);
-    }
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-      for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<f8>::step(wa[ob], xb[pb], acc[pb][ob]);
-    if (st + 1 < NST) {
-#pragma unroll
-      for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
+      if (st + 2 < NST) fetch(st + 2, wa0, xb0);
+      mma(wa1, xb1);
     }
   }
-  conv_store<f16, OB, PB, EPI>(L, im, acc, ty0, tx0, obase, L.oscale);
+  conv_store<f16, OBW, RW, EPI>(L, im, acc, ty0 + wr * RW, tx0, obase + wo * OBW, L.oscale);
 }
 
 // One output tile: rows [ty0, ty0 + 4 PB), columns [tx0, tx0 + 16), output blocks
@@ -184,14 +199,20 @@ __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& 
 // input with w is formed from 22 weight bits, exactly, and accumulated in float; the
 // epilogue multiplies by 1/s.  SPLIT_W: inputs are float16 (or bfloat16 converted
 // exactly) maps.  SPLIT_WX: the single float input is staged as two chunks, its
-// float16 part and the float16 of the remainder, against the same weights.
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0>
+// float16 part and the float16 of the remainder, against the same weights (the
+// remainder against their hi part only).
+//
+// WO splits the workgroup's four waves over the output blocks: each wave takes OB / WO
+// blocks and PB * WO rows, so per MFMA a wave fetches 1/(PB WO) weight fragments from
+// L1/L2 and 1/(OB/WO) activation fragments from LDS (WO = 2 balances the two).
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0,
+          int WO = 1>
 __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im, int ty0, int tx0,
                                           int obase, TC* tile) {
   if constexpr (std::is_same<TC, f8>::value) {
     static_assert(std::is_same<TIN, f16>::value && std::is_same<TOUT, f16>::value && CCH == 64 && NCHUNK == 1,
                   "FP8 convs read and write 64-channel float16 maps");
-    conv_tile_f8<OB, PB, EPI>(L, im, ty0, tx0, obase, tile);
+    conv_tile_f8<OB, PB, EPI, WO>(L, im, ty0, tx0, obase, tile);
     return;
   } else {
   constexpr int KG = Mma<TC>::KG;           // channels per MFMA step group
@@ -200,18 +221,21 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
   constexpr int NCG = CCH / KG;
   constexpr int NKG = NCHUNK * NCG;
   constexpr int AS = SPLIT ? 2 : 1;         // A fragments per output block and step
+  constexpr int RW = PB * WO, OBW = OB / WO;  // this wave's rows and output blocks
   static_assert(SPLIT == 0 || std::is_same<TC, f16>::value, "the split head runs on float16 MFMA");
   static_assert(SPLIT != SPLIT_WX || (NCHUNK == 2 && std::is_same<TIN, float>::value), "SPLIT_WX stages hi / lo");
+  static_assert(OB % WO == 0, "output blocks split evenly over the waves");
   const int wobtot = L.obtot * AS;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
+  const int wo = wave % WO, wr = wave / WO;
 
-  f32x4 acc[PB][OB];
+  f32x4 acc[RW][OBW];
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb)
+  for (int pb = 0; pb < RW; ++pb)
 #pragma unroll
-    for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
+    for (int ob = 0; ob < OBW; ++ob) acc[pb][ob] = zero4();
 
   const TIN* src0 = static_cast<const TIN*>(im.src0);
   const TIN* src1 = static_cast<const TIN*>(im.src1);
@@ -224,68 +248,87 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
   for (int ch = 0; ch < NCHUNK; ++ch) {
     const TIN* src = (ch == 0 || SPLIT == SPLIT_WX) ? src0 : src1;
     if (ch) __syncthreads();
+    // staging: a thread loads up to SB vectors of 8 channels before storing any of
+    // them, so its global loads are in flight together
     constexpr int V = CCH / 8;
     constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
-    for (int idx = threadIdx.x; idx < NV; idx += 256) {
-      const int pix = idx / V, v = idx - pix * V;
-      const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
-      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
-      TC* dstp = &tile[pix * LDP + 8 * v];
-      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-        const TIN* sp = src + ((size_t)gy * im.W + gx) * CCH + 8 * v;
-        if constexpr (SPLIT == SPLIT_WX) copy8_split(dstp, reinterpret_cast<const float*>(sp), ch);
-        else copy8<TIN, TC>(dstp, sp);
-      } else {
-        zero8<TC>(dstp);
+    constexpr int SB = std::is_same<TIN, float>::value ? 4 : 8;
+    for (int i0 = 0; i0 < NV; i0 += SB * 256) {
+      Raw8<TIN> rb[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 256 + (int)threadIdx.x;
+        rb[u].zero();
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+          const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+          if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) rb[u].load(src + ((size_t)gy * im.W + gx) * CCH + 8 * v);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 256 + (int)threadIdx.x;
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          TC* dstp = &tile[pix * LDP + 8 * v];
+          if constexpr (SPLIT == SPLIT_WX) copy8_split(dstp, rb[u], ch);
+          else raw8_store<TIN, TC>(dstp, rb[u]);
+        }
       }
     }
     __syncthreads();
 
-    // (tap, channel group) steps, software-pipelined: the A fragments (global) and
-    // B fragments (LDS) of step i+1 are in flight while the MFMAs of step i issue.
+    // (tap, channel group) steps, software-pipelined over two register buffers: the
+    // A fragments (global) and B fragments (LDS) of step i+1 load into one buffer
+    // while the MFMAs of step i read the other, so no fragment is ever copied between
+    // registers (a copy would wait for the loads it was meant to overlap).
     constexpr int NIT = 9 * NCG;
-    const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * wobtot + obase * AS) * 64 + lane;
+    const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * wobtot + (obase + wo * OBW) * AS) * 64 + lane;
     const size_t wstride_tap = (size_t)NKG * wobtot * 64;
-    const TC* tbase = &tile[((wave * PB) * (kTW + 2) + j) * LDP + QE * q];
-    u32x4 wa[OB * AS], xb[PB];
+    const TC* tbase = &tile[((wr * RW) * (kTW + 2) + j) * LDP + QE * q];
+    u32x4 wa0[OBW * AS], xb0[RW], wa1[OBW * AS], xb1[RW];
+    // the remainder chunk of SPLIT_WX meets only the hi weights (lo x lo is below the
+    // weights' own 22-bit representation)
+    const int np = (SPLIT == SPLIT_WX && ch == 1) ? 1 : AS;
+    auto fetch = [&](int it, u32x4 (&wa)[OBW * AS], u32x4 (&xb)[RW]) {
+      const int tap = it / NCG, cg = it - tap * NCG;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * wobtot * 64;
 #pragma unroll
-    for (int ob = 0; ob < OB * AS; ++ob) wa[ob] = wbase[ob * 64];
+      for (int ob = 0; ob < OBW; ++ob)
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) xb[pb] = ldu4(tbase + pb * (kTW + 2) * LDP);
-#pragma unroll 3
-    for (int it = 0; it < NIT; ++it) {
-      u32x4 wn[OB * AS], xn[PB];
-      if (it + 1 < NIT) {
-        const int tap = (it + 1) / NCG, cg = (it + 1) - tap * NCG;
-        const int dy = tap / 3, dx = tap - 3 * dy;
-        const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * wobtot * 64;
+        for (int part = 0; part < AS; ++part)
+          if (part < np) wa[ob * AS + part] = wp[(ob * AS + part) * 64];
 #pragma unroll
-        for (int ob = 0; ob < OB * AS; ++ob) wn[ob] = wp[ob * 64];
+      for (int pb = 0; pb < RW; ++pb) xb[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
+    };
+    auto mma = [&](const u32x4 (&wa)[OBW * AS], const u32x4 (&xb)[RW]) {
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-          xn[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
-      }
+      for (int pb = 0; pb < RW; ++pb)
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob)
+        for (int ob = 0; ob < OBW; ++ob)
 #pragma unroll
           for (int part = 0; part < AS; ++part)
-            acc[pb][ob] = Mma<TC>::step(wa[ob * AS + part], xb[pb], acc[pb][ob]);
+            if (part < np) acc[pb][ob] = Mma<TC>::step(wa[ob * AS + part], xb[pb], acc[pb][ob]);
+    };
+    fetch(0, wa0, xb0);
+#pragma unroll 1
+    for (int it = 0; it < NIT; it += 2) {
+      if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
+      mma(wa0, xb0);
       if (it + 1 < NIT) {
-#pragma unroll
-        for (int ob = 0; ob < OB * AS; ++ob) wa[ob] = wn[ob];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) xb[pb] = xn[pb];
+        if (it + 2 < NIT) fetch(it + 2, wa0, xb0);
+        mma(wa1, xb1);
       }
     }
   }
 
-  conv_store<TOUT, OB, PB, EPI>(L, im, acc, ty0, tx0, obase, SPLIT ? L.oscale : nullptr);
+  conv_store<TOUT, OBW, RW, EPI>(L, im, acc, ty0 + wr * RW, tx0, obase + wo * OBW, SPLIT ? L.oscale : nullptr);
   }
 }
 
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT>
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT, int WO>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvLayer L, ConvImg im) {
   __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
   // block = (tile, output-block group), group fastest: the groups of a tile run next to
@@ -295,12 +338,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvLayer L, ConvImg im) {
   const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
   const int b = xcd_tile(blockIdx.x, ntile * nobg);
   const int t = b / nobg, obg = b - t * nobg;
-  conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
-                                                             obg * OB, tile);
+  conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT, WO>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW,
+                                                                 obg * OB, tile);
 }
 
 // Persistent form: item = (tile, output-block group) of one image of the job table.
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT>
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT, int WO>
 __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvImg* __restrict__ jobs,
                                                        const int* __restrict__ count) {
   __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
@@ -311,8 +354,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvIm
     const int local = item - im.item_begin;
     const int t = local / nobg, obg = local - t * nobg;
     const int tiles_x = (im.W + kTW - 1) / kTW;
-    conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>(L, im, (t / tiles_x) * 4 * PB,
-                                                               (t % tiles_x) * kTW, obg * OB, tile);
+    conv_tile<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT, WO>(L, im, (t / tiles_x) * 4 * PB,
+                                                                   (t % tiles_x) * kTW, obg * OB, tile);
     __syncthreads();
   }
 }
@@ -452,8 +495,7 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
               lo += cw[uu][k] * a;
               hi += cw[uu][k] * b;
             }
-            store4f<TC>(sp[uu] + v, lo);
-            store4f<TC>(sp[uu] + v + 4, hi);
+            store8f<TC>(sp[uu] + v, lo, hi);
           }
         } else {
 #pragma unroll
@@ -469,26 +511,28 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
     __syncthreads();
 
     const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot) * 64 + lane;
-    Frag wa[OB];
+    // nine steps over two register buffers (see conv_tile)
+    Frag wa0[OB], xb0[PB], wa1[OB], xb1[PB];
+    auto fetch = [&](int st, Frag (&wa)[OB], Frag (&xb)[PB]) {
 #pragma unroll
-    for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[ob * 64];
-#pragma unroll 3
-    for (int st = 0; st < 9; ++st) {
-      Frag wn[OB];
-      if (st + 1 < 9) {
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wn[ob] = wbase[((size_t)(st + 1) * L.obtot + ob) * 64];
-      }
-      Frag xb[PB];
+      for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[((size_t)st * L.obtot + ob) * 64];
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + KG * st);
+    };
+    auto mma = [&](const Frag (&wa)[OB], const Frag (&xb)[PB]) {
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
+    };
+    fetch(0, wa0, xb0);
+#pragma unroll 1
+    for (int st = 0; st < 9; st += 2) {
+      if (st + 1 < 9) fetch(st + 1, wa1, xb1);
+      mma(wa0, xb0);
       if (st + 1 < 9) {
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) wa[ob] = wn[ob];
+        if (st + 2 < 9) fetch(st + 2, wa0, xb0);
+        mma(wa1, xb1);
       }
     }
   }
@@ -750,15 +794,16 @@ struct ConvCall {
   hipStream_t s;
 };
 
-template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0>
+template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT = 0,
+          int WO = 1>
 hipError_t run_conv(const ConvCall& c) {
   if (c.im) {
     const int ntile = ((c.im->W + kTW - 1) / kTW) * ((c.im->H + 4 * PB - 1) / (4 * PB));
     const dim3 grid(ntile * (c.L.obtot / OB));
-    hipLaunchKernelGGL((k_conv3x3<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>), grid, dim3(256), 0, c.s,
+    hipLaunchKernelGGL((k_conv3x3<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT, WO>), grid, dim3(256), 0, c.s,
                        c.L, *c.im);
   } else {
-    hipLaunchKernelGGL((k_conv3x3_batch<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT>), dim3(kBatchGrid),
+    hipLaunchKernelGGL((k_conv3x3_batch<TIN, TC, TOUT, CCH, NCHUNK, OB, PB, EPI, SPLIT, WO>), dim3(kBatchGrid),
                        dim3(256), 0, c.s, c.L, c.jobs, c.count);
   }
   return hipGetLastError();
@@ -774,33 +819,41 @@ struct Store<f8> {
   typedef f16 type;
 };
 
-template <typename T, int CCH, int PB>
-hipError_t conv_bulk_pb(const ConvCall& c, int epi) {
+template <typename T, int CCH, int PB, int WO>
+hipError_t conv_bulk_pbw(const ConvCall& c, int epi) {
   typedef typename Store<T>::type S;
   switch (epi) {
     case EPI_LRELU:
-      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_LRELU>(c);
-      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_LRELU>(c);
+      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_LRELU, SPLIT_NONE, WO>(c);
+      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_LRELU, SPLIT_NONE, WO>(c);
     case EPI_RES:
-      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_RES>(c);
-      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_RES>(c);
+      if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_RES, SPLIT_NONE, WO>(c);
+      return run_conv<S, T, S, CCH, 1, 2, PB, EPI_RES, SPLIT_NONE, WO>(c);
     case EPI_SHUFFLE:
       // FP8 fragments are twice as wide: half the output blocks per workgroup
-      if constexpr (std::is_same<T, f8>::value) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_SHUFFLE>(c);
-      else return run_conv<S, T, S, CCH, 1, 8, PB, EPI_SHUFFLE>(c);
+      if constexpr (std::is_same<T, f8>::value) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
+      else return run_conv<S, T, S, CCH, 1, 8, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
   }
   return hipErrorInvalidValue;
 }
 
-// Residual-block convs and the pixel-shuffle conv: storage and MFMA in T.
+template <typename T, int CCH, int PB>
+hipError_t conv_bulk_pb(const ConvCall& c, int epi, int wo) {
+  if (wo == 1) return conv_bulk_pbw<T, CCH, PB, 1>(c, epi);
+  // two waves along the output blocks: 16-bit and FP8 MFMA types
+  if constexpr (!std::is_same<T, float>::value)
+    if (wo == 2) return conv_bulk_pbw<T, CCH, PB, 2>(c, epi);
+  return hipErrorInvalidValue;
+}
+
+// Residual-block convs and the pixel-shuffle conv: storage and MFMA in T; tile is a
+// tile code (rows per wave, waves along the output blocks).
 template <typename T, int CCH>
-hipError_t conv_bulk(const ConvCall& c, int epi, int pb) {
-  if (pb == 1) return conv_bulk_pb<T, CCH, 1>(c, epi);
-  if (pb == 2) return conv_bulk_pb<T, CCH, 2>(c, epi);
-  if (pb == 4) return conv_bulk_pb<T, CCH, 4>(c, epi);
-  // eight rows per wave: 16-bit residual convs only (more pixels per weight fragment)
-  if constexpr (std::is_same<T, f16>::value || std::is_same<T, bf16>::value)
-    if (pb == 8 && epi != EPI_SHUFFLE) return conv_bulk_pb<T, CCH, 8>(c, epi);
+hipError_t conv_bulk(const ConvCall& c, int epi, int tile) {
+  const int pb = tile_pb(tile), wo = tile_wo(tile);
+  if (pb == 1) return conv_bulk_pb<T, CCH, 1>(c, epi, wo);
+  if (pb == 2) return conv_bulk_pb<T, CCH, 2>(c, epi, wo);
+  if (pb == 4) return conv_bulk_pb<T, CCH, 4>(c, epi, wo);
   return hipErrorInvalidValue;
 }
 

@@ -169,6 +169,13 @@ struct HrImg {
   int item_begin;
 };
 
+// Tile shape of a bulk conv launch: rows per wave pb (1, 2, 4; a workgroup covers 4 pb
+// rows) and waves along the output blocks wo (1, 2; each wave then takes pb * wo rows
+// and 1/wo of the workgroup's output blocks), packed in one int.
+inline int tile_code(int pb, int wo) { return pb | ((wo - 1) << 8); }
+inline int tile_pb(int code) { return code & 0xFF; }
+inline int tile_wo(int code) { return 1 + (code >> 8); }
+
 // Output blocks per workgroup chosen by the conv dispatch for a role / epilogue / MFMA type.
 int conv_ob(int role, int epi, int obtot, int tc);
 inline int conv_items(int H, int W, int pb, int nobg) {
@@ -179,8 +186,8 @@ inline int conv_in_items(int H, int W, int C) { return ((H * W + 255) / 256) * (
 
 hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
                           hipStream_t s);
-// dst (and res) NHWC with channel stride ldy.  src1 only for CONV_OFF1.  pb = rows per
-// wave of the workgroup tile (1, 2 or 4 for bulk convs; 2 for the offset head).
+// dst (and res) NHWC with channel stride ldy.  src1 only for CONV_OFF1.  pb = tile code
+// of bulk convs (tile_code), 2 for the offset head.
 hipError_t launch_conv(const PackedConv& L, int role, int epi, int tin, int pb, const ConvImg& im,
                        int ldy, int sig_lo, hipStream_t s);
 hipError_t launch_dcn(const PackedConv& L, int tf, int pb, const DcnImg& im, int ldo, int groups,

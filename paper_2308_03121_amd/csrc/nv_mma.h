@@ -10,6 +10,8 @@
 // B (activations) use the same split, so the K pairing is consistent; the output
 // D[i][j] sits in lane j + 16 * (i / 4), item i % 4, for all four instructions.
 #pragma once
+#include <type_traits>
+
 #include "nv_device.h"
 
 namespace nv {
@@ -150,6 +152,27 @@ __device__ __forceinline__ void store4f<f8>(f8* p, f32x4 v) {
   *reinterpret_cast<uint32_t*>(p) = f8x4_pack(v);
 }
 
+// Eight values stored as eight consecutive TC with one store where they fit 16 bytes.
+template <typename TC>
+__device__ __forceinline__ void store8f(TC* p, f32x4 lo, f32x4 hi) {
+  store4f<TC>(p, lo);
+  store4f<TC>(p + 4, hi);
+}
+template <>
+__device__ __forceinline__ void store8f<f16>(f16* p, f32x4 lo, f32x4 hi) {
+  *reinterpret_cast<f16x8*>(p) = f16x8{(f16)lo[0], (f16)lo[1], (f16)lo[2], (f16)lo[3],
+                                       (f16)hi[0], (f16)hi[1], (f16)hi[2], (f16)hi[3]};
+}
+template <>
+__device__ __forceinline__ void store8f<bf16>(bf16* p, f32x4 lo, f32x4 hi) {
+  *reinterpret_cast<bf16x8*>(p) = bf16x8{(bf16)lo[0], (bf16)lo[1], (bf16)lo[2], (bf16)lo[3],
+                                         (bf16)hi[0], (bf16)hi[1], (bf16)hi[2], (bf16)hi[3]};
+}
+template <>
+__device__ __forceinline__ void store8f<f8>(f8* p, f32x4 lo, f32x4 hi) {
+  *reinterpret_cast<u32x2*>(p) = u32x2{f8x4_pack(lo), f8x4_pack(hi)};
+}
+
 // Eight consecutive elements of type TIN, converted, stored as eight TC at q (LDS).
 template <typename TIN, typename TC>
 __device__ __forceinline__ void copy8(TC* q, const TIN* p) {
@@ -162,10 +185,50 @@ __device__ __forceinline__ void copy8<f16, f16>(f16* q, const f16* p) { stu4(q, 
 template <>
 __device__ __forceinline__ void copy8<bf16, bf16>(bf16* q, const bf16* p) { stu4(q, ldu4(p)); }
 
+// Eight consecutive elements held as loaded (so that a thread can issue all of its
+// staging loads before the first LDS store), then converted to the LDS type.
+template <typename T>
+struct Raw8 {
+  u32x4 v;                                  // 16-bit types: 8 x 2 bytes
+  __device__ __forceinline__ void load(const T* p) { v = ldu4(p); }
+  __device__ __forceinline__ void zero() { v = u32x4{0u, 0u, 0u, 0u}; }
+  __device__ __forceinline__ void to_f32(f32x4& lo, f32x4& hi) const {
+    typedef T T8 __attribute__((ext_vector_type(8)));
+    const T8 e = __builtin_bit_cast(T8, v);
+    lo = f32x4{(float)e[0], (float)e[1], (float)e[2], (float)e[3]};
+    hi = f32x4{(float)e[4], (float)e[5], (float)e[6], (float)e[7]};
+  }
+};
+template <>
+struct Raw8<float> {
+  f32x4 lo, hi;
+  __device__ __forceinline__ void load(const float* p) {
+    lo = ld4(p);
+    hi = ld4(p + 4);
+  }
+  __device__ __forceinline__ void zero() { lo = hi = zero4(); }
+  __device__ __forceinline__ void to_f32(f32x4& a, f32x4& b) const {
+    a = lo;
+    b = hi;
+  }
+};
+
+template <typename TIN, typename TC>
+__device__ __forceinline__ void raw8_store(TC* q, const Raw8<TIN>& r) {
+  if constexpr (std::is_same<TIN, TC>::value && !std::is_same<TIN, float>::value) {
+    stu4(q, r.v);
+  } else {
+    f32x4 lo, hi;
+    r.to_f32(lo, hi);
+    store4f<TC>(q, lo);
+    store4f<TC>(q + 4, hi);
+  }
+}
+
 // Eight floats staged as float16: part 0 the rounded values, part 1 the float16 of
 // what the rounding left out (x = hi + lo to about 22 bits).
-__device__ __forceinline__ void copy8_split(f16* q, const float* p, int part) {
-  f32x4 v[2] = {ld4(p), ld4(p + 4)};
+__device__ __forceinline__ void copy8_split(f16* q, const Raw8<float>& r, int part) {
+  f32x4 v[2] = {r.lo, r.hi};
   f16x8 o;
 #pragma unroll
   for (int h = 0; h < 2; ++h)

@@ -38,8 +38,8 @@ def test_unpack_matches_oracle(B, w, h, bits, chroma, wp, hp):
     dev = B.to_device_frame(Y, U, V)
     rgb = B.unpack(B.fmt_struct(w, h, bits, chroma), dev, hp, wp)
     torch.cuda.synchronize()
-    ref = pixel.pad(pixel.unpack(Y, U, V, bits, chroma), 8)
-    ref = np.pad(ref, ((0, 0), (0, hp - ref.shape[1]), (0, wp - ref.shape[2])), mode="edge")
+    # replicate padding to (hp, wp), which need not be multiples of 8
+    ref = np.pad(pixel.unpack(Y, U, V, bits, chroma), ((0, 0), (0, hp - h), (0, wp - w)), mode="edge")
     assert rgb.shape == (3, hp, wp)
     assert max_abs(rgb.cpu().numpy(), ref) <= UNPACK_TOL
 
