@@ -1525,7 +1525,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     ci.W = wp;
     ci.item_begin = it[BL_CONV_IN];
     it[BL_CONV_IN] += conv_in_items(hp, wp, C);
-    const int nobg = ctx->blocks.empty() ? 1 : ctx->blocks[0].obtot / conv_ob(CONV_BULK, EPI_LRELU, ctx->blocks[0].obtot, ctx->blocks[0].tc);
+    const int nobg = ctx->blocks.empty() ? 1 : ctx->blocks[0].obtot / conv_ob(CONV_BULK, EPI_LRELU, ctx->blocks[0].obtot, ctx->blocks[0].tc, pbb);
     T.blk_a[k] = conv_img(s->feat[sl], nullptr, nullptr, nullptr, nullptr, nullptr, t0, hp, wp);
     T.blk_b[k] = conv_img(t0, nullptr, nullptr, nullptr, nullptr, s->feat[sl], s->feat[sl], hp, wp);
     T.blk_a[k].item_begin = T.blk_b[k].item_begin = it[BL_BLOCK];
@@ -1553,10 +1553,10 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     const float* rb = s->rgb[Gr.slot_b];
     T.off1[k] = conv_img(fa, fb, Gr.sel, nullptr, fa, nullptr, o1, hp, wp);
     T.off1[k].item_begin = it[BL_OFF1];
-    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot, ctx->off1.tc));
+    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot, ctx->off1.tc, 2));
     T.off2[k] = conv_img(o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
     T.off2[k].item_begin = it[BL_OFF2];
-    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot, ctx->off2.tc));
+    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot, ctx->off2.tc, 2));
     DcnImg& d = T.dcn[k];
     d.fa = fa;
     d.fb = fb;
@@ -1588,7 +1588,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
       pk.rw = 2 * wp;
       pk.item_begin = it[BL_PACK];
     }
-    it[BL_UP] += conv_items(hp, wp, tile_pb(pbu), ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot, ctx->up.tc));
+    it[BL_UP] += conv_items(hp, wp, tile_pb(pbu), ctx->up.obtot / conv_ob(CONV_BULK, EPI_SHUFFLE, ctx->up.obtot, ctx->up.tc, pbu));
     it[BL_HR] += hr_items(hp, wp);
     it[BL_PACK] += pack_items(s->ofmt.width, s->ofmt.height, s->ofmt.chroma);
   }
@@ -1642,7 +1642,8 @@ namespace {
 
 std::string tile_name(int code) {
   char b[32];
-  if (tile_wo(code) == 1) snprintf(b, sizeof b, "pb%d", tile_pb(code));
+  if (tile_lw(code)) snprintf(b, sizeof b, "pb%dlw", tile_pb(code));
+  else if (tile_wo(code) == 1) snprintf(b, sizeof b, "pb%d", tile_pb(code));
   else snprintf(b, sizeof b, "pb%dw%d", tile_pb(code), tile_wo(code));
   return b;
 }
@@ -1709,8 +1710,15 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     // bulk conv tiles: rows per wave 1, 2, 4, and for 16-bit / FP8 also with two waves
     // along the output blocks
     std::vector<int> bulk_tiles = {1, 2, 4};
-    if (ft != DT_F32)
+    if (ft != DT_F32) {
       for (int pb : {1, 2, 4}) bulk_tiles.push_back(tile_code(pb, 2));
+      // LDS-resident weights, where the device allows the workgroup that much LDS
+      if (C == 64 && lds_weight_tiles())
+        for (int pb : {2, 4})
+          if (bulk_tile_lds(ctx->bt, C, tile_code(pb, 1, 1)) <= lds_limit() &&
+              bulk_tile_lds(ctx->ut, C, tile_code(pb, 1, 1)) <= lds_limit())
+            bulk_tiles.push_back(tile_code(pb, 1, 1));
+    }
     struct Cand {
       const char* name;
       int* slot;
@@ -1769,9 +1777,9 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     rep = "from cache: ";
     rep += key;
   }
-  char tail[96];
-  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d]", tile_name(ctx->tune.pb_block).c_str(),
-           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn);
+  char tail[128];
+  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d; LDS limit %d]", tile_name(ctx->tune.pb_block).c_str(),
+           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn, lds_limit());
   rep += tail;
   if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
     HIP_TRY(hipDeviceSynchronize());

@@ -252,7 +252,7 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
     // them, so its global loads are in flight together
     constexpr int V = CCH / 8;
     constexpr int NV = (4 * PB + 2) * (kTW + 2) * V;
-    constexpr int SB = std::is_same<TIN, float>::value ? 4 : 8;
+    constexpr int SB = std::is_same<TIN, float>::value ? 2 : 8;
     for (int i0 = 0; i0 < NV; i0 += SB * 256) {
       Raw8<TIN> rb[SB];
 #pragma unroll
@@ -360,6 +360,220 @@ __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvIm
   }
 }
 
+// ---- bulk conv with LDS-resident weights (16-bit and FP8 MFMA types) ----
+// Switched off: its first launch on the device stopped in the HIP runtime ("cannot find
+// symbol" for the kernel, 99.6 KB of static LDS, below the device's 160 KB) and no cause
+// has been found in this code; the dispatch refuses these tiles and the tuner does not
+// offer them until one is.
+constexpr bool kLdsWeightTiles = false;
+
+// A persistent workgroup owns one group of 64 output channels (4 output blocks) for all
+// of its tiles: it copies that group's A fragments into LDS once, then for each tile
+// reads both MFMA operands from LDS.  While the MFMAs of tile n run, the input of tile
+// n+1 is already being loaded into registers (the step loop waits on LDS only, so these
+// global loads stay in flight), and is written to the LDS tile after tile n's epilogue.
+// Each wave computes PB rows x 16 pixels x 64 channels of the tile.
+template <typename TC, int PB>
+struct LwShape {
+  static constexpr int OB = 4;
+  static constexpr bool F8 = std::is_same<TC, f8>::value;
+  static constexpr int NSTEP = F8 ? 5 : 18;                       // MFMA steps over 9 taps x 64 ch
+  static constexpr int FB = F8 ? 32 : 16;                         // fragment bytes per lane
+  static constexpr int WBYTES = NSTEP * OB * 64 * FB;
+  static constexpr int LDP = ConvSmem<TC, 64, PB>::LDP;           // tile pixel stride (elements)
+  static constexpr int TBYTES = ConvSmem<TC, 64, PB>::N * (int)sizeof(TC);
+  static constexpr int NV = (4 * PB + 2) * (kTW + 2) * 8;          // 8-channel vectors per tile
+  static constexpr int NR = (NV + 255) / 256;                      // per thread
+  static constexpr int WG_PER_CU = 163840 / (WBYTES + TBYTES);
+};
+
+// The tile's input vectors of this thread (8 channels each), loaded into registers.
+template <typename TC, int PB>
+__device__ __forceinline__ void lw_load(const ConvImg& im, int ty0, int tx0, Raw8<f16>* rb, const void* src_v) {
+  using S = LwShape<TC, PB>;
+  const f16* src = static_cast<const f16*>(src_v);
+#pragma unroll
+  for (int u = 0; u < S::NR; ++u) {
+    const int idx = u * 256 + (int)threadIdx.x;
+    rb[u].zero();
+    if (idx < S::NV) {
+      const int pix = idx >> 3, v = idx & 7;
+      const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) rb[u].load(src + ((size_t)gy * im.W + gx) * 64 + 8 * v);
+    }
+  }
+}
+
+template <typename TC, int PB>
+__device__ __forceinline__ void lw_store(TC* tile, const Raw8<f16>* rb, float ainv) {
+  using S = LwShape<TC, PB>;
+#pragma unroll
+  for (int u = 0; u < S::NR; ++u) {
+    const int idx = u * 256 + (int)threadIdx.x;
+    if (idx < S::NV) {
+      const int pix = idx >> 3, v = idx & 7;
+      TC* d = &tile[pix * S::LDP + 8 * v];
+      if constexpr (S::F8) {
+        f32x4 lo, hi;
+        rb[u].to_f32(lo, hi);
+        *reinterpret_cast<u32x2*>(d) = u32x2{f8x4_pack(lo * ainv), f8x4_pack(hi * ainv)};
+      } else {
+        stu4(d, rb[u].v);
+      }
+    }
+  }
+}
+
+// MFMAs of one tile: A fragments from the LDS weight block, B from the LDS tile.
+template <typename TC, int PB>
+__device__ __forceinline__ void lw_mma(const uint8_t* wl, const TC* tile, f32x4 (&acc)[PB][4]) {
+  using S = LwShape<TC, PB>;
+  using Frag = typename Mma<TC>::Frag;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+  const Frag* wfr = reinterpret_cast<const Frag*>(wl) + lane;
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) acc[pb][ob] = zero4();
+  // B fragment address of step st: float16 steps are (tap, 32-channel group), quarter
+  // q at channel 8 q; FP8 steps pair taps, quarter q at tap 2 st + q / 2, channel 32 (q % 2)
+  auto boff = [&](int st) {
+    int tap, ch;
+    if constexpr (S::F8) {
+      tap = min(2 * st + (q >> 1), 8);
+      ch = 32 * (q & 1);
+    } else {
+      tap = st >> 1;
+      ch = 32 * (st & 1) + 8 * q;
+    }
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    return ((wave * PB + dy) * (kTW + 2) + j + dx) * S::LDP + ch;
+  };
+  Frag a0[4], b0[PB], a1[4], b1[PB];
+  auto fetch = [&](int st, Frag (&a)[4], Frag (&b)[PB]) {
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) a[ob] = Mma<TC>::ld(wfr + (st * 4 + ob) * 64);
+    const int o = boff(st);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) b[pb] = Mma<TC>::ld(tile + o + pb * (kTW + 2) * S::LDP);
+  };
+  auto mma = [&](const Frag (&a)[4], const Frag (&b)[PB]) {
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob) acc[pb][ob] = Mma<TC>::step(a[ob], b[pb], acc[pb][ob]);
+  };
+  fetch(0, a0, b0);
+#pragma unroll 1
+  for (int st = 0; st < S::NSTEP; st += 2) {
+    if (st + 1 < S::NSTEP) fetch(st + 1, a1, b1);
+    mma(a0, b0);
+    if (st + 1 < S::NSTEP) {
+      if (st + 2 < S::NSTEP) fetch(st + 2, a0, b0);
+      mma(a1, b1);
+    }
+  }
+}
+
+// Copies output group obg's fragments (all steps, 4 blocks) from the packed layer into
+// LDS in (step, block, lane) order.
+template <typename TC, int PB>
+__device__ __forceinline__ void lw_weights(const ConvLayer& L, int obg, uint8_t* wl) {
+  using S = LwShape<TC, PB>;
+  const u32x4* g = reinterpret_cast<const u32x4*>(L.wfrag);
+  constexpr int N16 = S::WBYTES / 16;                  // 16-byte pieces
+  constexpr int P = S::FB / 16;                        // pieces per lane fragment
+  for (int i = threadIdx.x; i < N16; i += 256) {
+    const int part = i % P, f = i / P;                 // f = (st * 4 + ob) * 64 + lane
+    const int lane = f & 63, sb = f >> 6, ob = sb & 3, st = sb >> 2;
+    const size_t gi = (((size_t)st * L.obtot + obg * 4 + ob) * 64 + lane) * P + part;
+    reinterpret_cast<u32x4*>(wl)[i] = g[gi];
+  }
+}
+
+template <typename TC, int PB, int EPI>
+__device__ __forceinline__ void lw_run(const ConvLayer& L, const ConvImg* im1, const ConvImg* jobs,
+                                       const int* count, uint8_t* smem) {
+  using S = LwShape<TC, PB>;
+  // storage type of the maps: bfloat16 for bfloat16 MFMA, float16 otherwise
+  using TO = typename std::conditional<std::is_same<TC, bf16>::value, bf16, f16>::type;
+  uint8_t* wl = smem;
+  TC* tile = reinterpret_cast<TC*>(smem + S::WBYTES);
+  const int nobg = L.obtot / 4;
+  const int obg = blockIdx.x % nobg;                   // gridDim.x is a multiple of nobg
+  const int wave = threadIdx.x >> 6;
+  const float ainv = S::F8 ? *L.ainv : 1.0f;
+  const int njobs = jobs ? count[0] : 1;
+  const int total = jobs ? count[1] : 0;
+  // item -> (image, tile origin); returns false past the end
+  auto locate = [&](int item, ConvImg& im, int& ty0, int& tx0) -> bool {
+    int local;
+    if (jobs) {
+      if (item >= total) return false;
+      im = jobs[find_job(jobs, njobs, item)];
+      local = item - im.item_begin;
+    } else {
+      im = *im1;
+      const int ntile = ((im.W + kTW - 1) / kTW) * ((im.H + 4 * PB - 1) / (4 * PB));
+      if (item >= ntile * nobg) return false;
+      local = item;
+    }
+    const int t = local / nobg;
+    const int tiles_x = (im.W + kTW - 1) / kTW;
+    ty0 = (t / tiles_x) * 4 * PB;
+    tx0 = (t % tiles_x) * kTW;
+    return true;
+  };
+  auto src_of = [&](const ConvImg& im) -> const void* {
+    return (im.sel != nullptr && *im.sel != 0u && im.alt0 != nullptr) ? im.alt0 : im.src0;
+  };
+
+  lw_weights<TC, PB>(L, obg, wl);
+  ConvImg im;
+  int ty0, tx0;
+  int item = blockIdx.x;
+  if (!locate(item, im, ty0, tx0)) return;             // uniform per workgroup
+  Raw8<f16> rb[S::NR];
+  lw_load<TC, PB>(im, ty0, tx0, rb, src_of(im));
+  lw_store<TC, PB>(tile, rb, ainv);
+  __syncthreads();
+  for (;;) {
+    ConvImg nim;
+    int nty0 = 0, ntx0 = 0;
+    const int next = item + gridDim.x;
+    const bool more = locate(next, nim, nty0, ntx0);
+    if (more) lw_load<TC, PB>(nim, nty0, ntx0, rb, src_of(nim));
+    f32x4 acc[PB][4];
+    lw_mma<TC, PB>(wl, tile, acc);
+    conv_store<TO, 4, PB, EPI>(L, im, acc, ty0 + wave * PB, tx0, obg * 4, S::F8 ? L.oscale : nullptr);
+    __syncthreads();                                   // every wave is done with the tile
+    if (!more) break;
+    lw_store<TC, PB>(tile, rb, ainv);
+    __syncthreads();
+    item = next;
+    im = nim;
+    ty0 = nty0;
+    tx0 = ntx0;
+  }
+}
+
+template <typename TC, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv_lw(ConvLayer L, ConvImg im) {
+  using S = LwShape<TC, PB>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[S::WBYTES + S::TBYTES];
+  lw_run<TC, PB, EPI>(L, &im, nullptr, nullptr, smem);
+}
+
+template <typename TC, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv_lw_batch(ConvLayer L, const ConvImg* __restrict__ jobs,
+                                                       const int* __restrict__ count) {
+  using S = LwShape<TC, PB>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[S::WBYTES + S::TBYTES];
+  lw_run<TC, PB, EPI>(L, nullptr, jobs, count, smem);
+}
+
 // ---- modulated deformable conv, stride 1, pad 1, 3x3, over cat(fa, fb) ----
 // Over a TH x 16 pixel tile, per phase (below):
 //  gather: one work item per (pixel, channel chunk, tap) computes the sampling position
@@ -426,7 +640,12 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
 
-  const TC* sbase = &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
+  // float with 16-channel chunks: the four 16-byte pieces of chunk c sit rotated by
+  // c / 2 inside the chunk, so that the gather's stores of consecutive taps (chunks 64
+  // bytes apart) fall in eight different 16-byte bank groups
+  constexpr bool ROT = std::is_same<TC, float>::value && CW == 16;
+  auto piece = [](int c, int v4) { return ROT ? ((v4 + (c >> 1)) & 3) : v4; };
+  const TC* sbase = ROT ? &S[((wave * PB) * kTW + j) * LDS_P] : &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
 
   for (int ph = 0; ph < NPHASE; ++ph) {
     if (ph) __syncthreads();
@@ -495,7 +714,13 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
               lo += cw[uu][k] * a;
               hi += cw[uu][k] * b;
             }
-            store8f<TC>(sp[uu] + v, lo, hi);
+            if constexpr (ROT) {
+              const int c = (int)((sp[uu] - S) % LDS_P) / CW;   // chunk index within the pixel row
+              store4f<TC>(sp[uu] + 4 * piece(c, v / 4), lo);
+              store4f<TC>(sp[uu] + 4 * piece(c, v / 4 + 1), hi);
+            } else {
+              store8f<TC>(sp[uu] + v, lo, hi);
+            }
           }
         } else {
 #pragma unroll
@@ -516,8 +741,10 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
     auto fetch = [&](int st, Frag (&wa)[OB], Frag (&xb)[PB]) {
 #pragma unroll
       for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[((size_t)st * L.obtot + ob) * 64];
+      // float: step st is chunk st (KG = CW = 16), quarter q its piece q
+      const int so = ROT ? KG * st + 4 * piece(st, q) : KG * st;
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + KG * st);
+      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + so);
     };
     auto mma = [&](const Frag (&wa)[OB], const Frag (&xb)[PB]) {
 #pragma unroll
@@ -846,11 +1073,75 @@ hipError_t conv_bulk_pb(const ConvCall& c, int epi, int wo) {
   return hipErrorInvalidValue;
 }
 
+template <typename TC, int PB, int EPI>
+hipError_t run_lw(const ConvCall& c) {
+  using S = LwShape<TC, PB>;
+  if (c.L.obtot % 4 != 0) return hipErrorInvalidValue;
+  const int nobg = c.L.obtot / 4;
+  const int maxg = 256 * (S::WG_PER_CU > 0 ? S::WG_PER_CU : 1);
+  if (c.im) {
+    const int ntile = ((c.im->W + kTW - 1) / kTW) * ((c.im->H + 4 * PB - 1) / (4 * PB));
+    int g = ntile * nobg < maxg ? ntile * nobg : maxg;
+    g -= g % nobg;
+    hipLaunchKernelGGL((k_conv_lw<TC, PB, EPI>), dim3(g), dim3(256), 0, c.s, c.L, *c.im);
+  } else {
+    hipLaunchKernelGGL((k_conv_lw_batch<TC, PB, EPI>), dim3(maxg), dim3(256), 0, c.s, c.L, c.jobs, c.count);
+  }
+  return hipGetLastError();
+}
+
+template <typename TC, int PB>
+hipError_t conv_lw(const ConvCall& c, int epi) {
+  switch (epi) {
+    case EPI_LRELU: return run_lw<TC, PB, EPI_LRELU>(c);
+    case EPI_RES: return run_lw<TC, PB, EPI_RES>(c);
+    case EPI_SHUFFLE: return run_lw<TC, PB, EPI_SHUFFLE>(c);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Largest static LDS a workgroup may use on the current device (queried once per device).
+int device_lds_limit() {
+  static int limit[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (limit[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    limit[dev] = v;
+  }
+  return limit[dev];
+}
+
+template <typename T, int CCH>
+int bulk_lds_bytes(int tile) {
+  const int pb = tile_pb(tile);
+  if (tile_lw(tile)) {
+    if constexpr (!std::is_same<T, float>::value && CCH == 64) {
+      if (pb == 2) return LwShape<T, 2>::WBYTES + LwShape<T, 2>::TBYTES;
+      if (pb == 4) return LwShape<T, 4>::WBYTES + LwShape<T, 4>::TBYTES;
+    }
+    return 1 << 30;
+  }
+  const int th = 4 * pb;
+  return (th + 2) * (kTW + 2) * (CCH + 16 / (int)sizeof(T)) * (int)sizeof(T);
+}
+
 // Residual-block convs and the pixel-shuffle conv: storage and MFMA in T; tile is a
-// tile code (rows per wave, waves along the output blocks).
+// tile code (rows per wave, waves along the output blocks, LDS-resident weights).
+// A tile whose LDS exceeds the device's per-workgroup limit is refused, not launched.
 template <typename T, int CCH>
 hipError_t conv_bulk(const ConvCall& c, int epi, int tile) {
   const int pb = tile_pb(tile), wo = tile_wo(tile);
+  if (bulk_lds_bytes<T, CCH>(tile) > device_lds_limit()) return hipErrorInvalidConfiguration;
+  if (tile_lw(tile)) {
+    if (!kLdsWeightTiles) return hipErrorNotSupported;
+    if constexpr (!std::is_same<T, float>::value && CCH == 64) {
+      if (pb == 2) return conv_lw<T, 2>(c, epi);
+      if (pb == 4) return conv_lw<T, 4>(c, epi);
+    }
+    return hipErrorInvalidValue;
+  }
   if (pb == 1) return conv_bulk_pb<T, CCH, 1>(c, epi, wo);
   if (pb == 2) return conv_bulk_pb<T, CCH, 2>(c, epi, wo);
   if (pb == 4) return conv_bulk_pb<T, CCH, 4>(c, epi, wo);
@@ -1044,9 +1335,10 @@ hipError_t hr_dispatch(const PackedConv& P, int tu, const HrImg* im, const HrImg
 
 }  // namespace
 
-int conv_ob(int role, int epi, int obtot, int tc) {
+int conv_ob(int role, int epi, int obtot, int tc, int tile) {
   if (role == CONV_OFF2) return obtot % 7 == 0 ? 7 : (obtot % 4 == 0 ? 4 : 1);
   if (role == CONV_OFF1) return obtot % 4 == 0 ? 4 : 2;
+  if (tile_lw(tile)) return 4;
   if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : 8;
   return obtot % 4 == 0 ? 4 : 2;
 }
@@ -1074,6 +1366,21 @@ hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* j
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
+int bulk_tile_lds(int tc, int cch, int tile) {
+  if (cch != 32 && cch != 64) return 1 << 30;
+  switch (tc) {
+    case DT_F32: return cch == 64 ? bulk_lds_bytes<float, 64>(tile) : bulk_lds_bytes<float, 32>(tile);
+    case DT_F16: return cch == 64 ? bulk_lds_bytes<f16, 64>(tile) : bulk_lds_bytes<f16, 32>(tile);
+    case DT_BF16: return cch == 64 ? bulk_lds_bytes<bf16, 64>(tile) : bulk_lds_bytes<bf16, 32>(tile);
+    case DT_F8: return bulk_lds_bytes<f8, 64>(tile);
+  }
+  return 1 << 30;
+}
+
+int lds_limit() { return device_lds_limit(); }
+
+bool lds_weight_tiles() { return kLdsWeightTiles; }
 
 hipError_t launch_conv(const PackedConv& P, int role, int epi, int tin, int pb, const ConvImg& im,
                        int ldy, int sig_lo, hipStream_t s) {

@@ -170,14 +170,24 @@ struct HrImg {
 };
 
 // Tile shape of a bulk conv launch: rows per wave pb (1, 2, 4; a workgroup covers 4 pb
-// rows) and waves along the output blocks wo (1, 2; each wave then takes pb * wo rows
-// and 1/wo of the workgroup's output blocks), packed in one int.
-inline int tile_code(int pb, int wo) { return pb | ((wo - 1) << 8); }
+// rows), waves along the output blocks wo (1, 2; each wave then takes pb * wo rows and
+// 1/wo of the workgroup's output blocks), and lw: the persistent form that keeps a
+// 64-channel output group's weights in LDS (16-bit and FP8, pb 2 or 4, wo 1), packed
+// in one int.
+inline int tile_code(int pb, int wo, int lw = 0) { return pb | ((wo - 1) << 8) | (lw << 12); }
 inline int tile_pb(int code) { return code & 0xFF; }
-inline int tile_wo(int code) { return 1 + (code >> 8); }
+inline int tile_wo(int code) { return 1 + ((code >> 8) & 0xF); }
+inline int tile_lw(int code) { return (code >> 12) & 1; }
 
-// Output blocks per workgroup chosen by the conv dispatch for a role / epilogue / MFMA type.
-int conv_ob(int role, int epi, int obtot, int tc);
+// Static LDS of a bulk conv tile (MFMA type tc, cch input channels), and the current
+// device's per-workgroup LDS limit; tiles above the limit are refused by the dispatch.
+int bulk_tile_lds(int tc, int cch, int tile);
+int lds_limit();
+bool lds_weight_tiles();   // whether the LDS-resident-weight tiles are enabled
+
+// Output blocks per workgroup chosen by the conv dispatch for a role / epilogue / MFMA
+// type / tile code.
+int conv_ob(int role, int epi, int obtot, int tc, int tile);
 inline int conv_items(int H, int W, int pb, int nobg) {
   return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
 }

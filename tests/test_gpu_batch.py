@@ -155,3 +155,48 @@ def test_batch_rejects_bad_requests(B):
     assert out == [[]]
     st.close()
     ctx.close()
+
+
+@pytest.mark.skip(reason="the LDS-resident-weight conv tile stopped in the HIP runtime on its first launch "
+                         "(kernel symbol not found) and no cause has been found in the code yet; the tile is "
+                         "switched off in the library and kept off the GPU until one is shown")
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp8"])
+def test_lds_weight_tiles_bit_identical(B, prec, tmp_path, monkeypatch):
+    """The persistent conv form that keeps a 64-channel output group's weights in LDS
+    (forced through the tuner's cache file) accumulates every output in the same order
+    as the default tiles: per-stream and batched results are bit-identical."""
+    say(f"LDS-weight conv tiles {prec}")
+    cfg = synth.NetConfig(64, 1, 8)
+    blob = synth.gen_weights(cfg, seed=7)
+    clips = _clips()
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+
+    def context():
+        ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+        if prec == "fp8":
+            c0 = clips[0]
+            ctx.calibrate(B.fmt_struct(c0.width, c0.height, c0.bits, c0.chroma), dev[0][:4])
+        return ctx
+
+    ref_ctx = context()
+    ref = _per_stream(B, ref_ctx, clips, dev)
+    ref_ctx.close()
+    code = {"fp16": 1, "bf16": 2, "fp8": 3}[prec]
+    lw = lambda pb: pb | (1 << 12)                      # rows per wave, LDS-resident weights
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"prec={code} C=64 R=1 size=64x48 | {lw(2)} {lw(4)} 1\n")
+    monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+    ctx = context()
+    monkeypatch.delenv("NNVISR_TUNE_CACHE")
+    probe = ctx.autotune(48, 64)                        # timed: offers only tiles that fit
+    print("  tuner:", probe, flush=True)
+    if "lw=" not in probe:
+        ctx.close()
+        pytest.skip("the device's per-workgroup LDS limit admits no LDS-weight tile for " + prec)
+    monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+    rep = ctx.autotune(48, 64)
+    print("  tiles:", rep, flush=True)
+    assert "from cache" in rep
+    _same(_per_stream(B, ctx, clips, dev), ref)
+    _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
+    ctx.close()
