@@ -53,6 +53,55 @@ def kernel_work(kind, hp, wp, C, G, bits_out_bytes):
     return None, None
 
 
+def pixel_bytes(kind, w, h, bits, chroma):
+    """Algorithmic HBM bytes of one launch of a pixel-format / scene stage on a w x h
+    input frame: unpack reads the codes and writes float R'G'B' at the padded size; the
+    scene metric reads the luma of the frame and of its predecessor; pack reads the float
+    R'G'B' of one 2w x 2h output frame and writes its codes."""
+    bps = 1 if bits == 8 else 2
+    per_px = 1.5 if chroma == 420 else 3.0
+    hp, wp = (h + 7) // 8 * 8, (w + 7) // 8 * 8
+    if kind == "unpack":
+        return w * h * bps * per_px + 12 * hp * wp
+    if kind == "scene":
+        return 2 * w * h * bps
+    if kind == "pack":
+        return 4 * w * h * (12 + bps * per_px)
+    return None
+
+
+def pixel_rates(prof, steps, w, h, bits, chroma):
+    """GB/s and fraction of the 8 TB/s HBM peak of the pixel stages from a profile."""
+    out = {}
+    for kind in ("unpack", "scene", "pack"):
+        n, tot = prof.get(kind, (0, 0.0))
+        if not n:
+            continue
+        us = 1000.0 * tot / n
+        gbs = pixel_bytes(kind, w, h, bits, chroma) / (us * 1e3)
+        out[kind] = {"avg_us": round(us, 2), "bytes_per_launch": int(pixel_bytes(kind, w, h, bits, chroma)),
+                     "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def device_copy_gbs(torch, mib=1024, reps=10):
+    """Measured device-to-device copy rate (read + write bytes per second), the
+    achievable HBM figure quoted beside the 8 TB/s specification."""
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1000.0 / reps
+    del a, b
+    return round(2 * mib * (1 << 20) / s / 1e9, 1)
+
+
 def group_flops_per_px(C, R, G):
     """Network flops per padded LR pixel of one stream group (one extract, two outputs)."""
     extract = 2 * 9 * 3 * C + R * 2 * (2 * 9 * C * C)
@@ -133,6 +182,8 @@ def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16"
         res[prec] = {"value": round(mpix / (ms / 1000.0), 3), "unit": "Mpix/s", "ms_per_step": round(ms, 2),
                      "cuts": cuts,
                      "kernel_ms_per_step": {k: round(v[1] / steps, 2) for k, v in pr.items() if v[0]}}
+        if "pixel_stages" not in res:
+            res["pixel_stages"] = pixel_rates(pr, steps, clip.width, clip.height, clip.bits, clip.chroma)
         print(f"# c3 {prec}: {res[prec]['value']} Mpix/s", file=sys.stderr, flush=True)
         st.close()
         ctx.close()
@@ -393,6 +444,8 @@ def main():
                  "tflops": round(path_flop / (ms / 1000.0) / 1e12, 2),
                  "frac_of_peak": round(path_flop / (ms / 1000.0) / 1e12 / PEAKS[args.precision], 4)},
         "kernels": kernels,
+        "pixel_stages": pixel_rates(prof, args.steps, W_, H_, clip.bits, clip.chroma),
+        "hbm_copy_gbs": device_copy_gbs(torch),
     }
     others = {}
     for prec in [p for p in args.also.split(",") if p and p != args.precision]:

@@ -909,11 +909,18 @@ extern "C" nv_status nv_scene_metric(const nv_format* fmt, const nv_planes* prev
   if (external_cut < -1 || external_cut > 1) return fail(NV_E_INVALID, "external_cut must be -1, 0 or 1");
   if (!d_sad || !d_hist || !d_hd || !d_cut) return fail(NV_E_INVALID, "output pointers must be set");
   if (reinterpret_cast<uintptr_t>(d_sad) & 7) return fail(NV_E_INVALID, "d_sad must be 8-byte aligned");
-  const Frame c = to_frame(fmt, cur);
-  Frame p = to_frame(fmt, prev);
-  return check_launch(launch_scene(c, prev ? &p : nullptr, d_hist_prev, to_rule(params), external_cut,
-                                   d_sad, d_hist, d_hd, d_cut, (hipStream_t)stream),
-                      "scene");
+  SceneJob J{};
+  J.cur = to_frame(fmt, cur);
+  J.prev_y = prev ? prev->data[0] : nullptr;
+  J.prev_pitch = prev ? prev->pitch_bytes[0] : 0;
+  J.hist_prev = d_hist_prev;
+  J.sad = d_sad;
+  J.hist = d_hist;
+  J.hd = d_hd;
+  J.cut = d_cut;
+  J.rule = to_rule(params);
+  J.external = external_cut;
+  return check_launch(launch_scene(J, true, (hipStream_t)stream), "scene");
 }
 
 // --------------------------------------------------------------- network ----
@@ -1042,6 +1049,13 @@ extern "C" nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int3
 // (R >= 2; a batch request of k frames needs R >= k + 1 so the previous call's last
 // frame survives while the new ones are written).  luma / hist hold the last pushed
 // frame's luma plane and histogram in slot *_last; the next frame writes the other.
+struct SceneAcc {
+  uint64_t sad;
+  uint32_t hist[64];
+};
+
+static int64_t luma_pitch(const nv_format* f) { return round_up(f->width * (f->bits == 8 ? 1 : 2), 64); }
+
 struct nv_stream {
   nv_context* ctx = nullptr;
   nv_format fmt{};
@@ -1059,6 +1073,7 @@ struct nv_stream {
   uint64_t* sad = nullptr;
   uint32_t* hd = nullptr;
   uint32_t* cuts = nullptr;      // [kCutRing]
+  SceneAcc* acc = nullptr;       // scene accumulators, zero between frames
   size_t bytes = 0;
   int slot(int64_t frame) const { return (int)(frame % (int64_t)rgb.size()); }
 };
@@ -1069,9 +1084,8 @@ static size_t slot_bytes(const nv_context* ctx, int hp, int wp) {
 
 static size_t stream_bytes(const nv_context* ctx, const nv_format* f) {
   const int hp = round_up(f->height, 8), wp = round_up(f->width, 8);
-  const size_t bps = f->bits == 8 ? 1 : 2;
-  return 2 * slot_bytes(ctx, hp, wp) + 2 * (size_t)f->width * f->height * bps + 2 * 64 * 4 + 8 + 4 +
-         (size_t)kCutRing * 4;
+  return 2 * slot_bytes(ctx, hp, wp) + 2 * (size_t)luma_pitch(f) * f->height + 2 * 64 * 4 + 8 + 4 +
+         (size_t)kCutRing * 4 + sizeof(SceneAcc);
 }
 
 static void stream_free(nv_stream* s) {
@@ -1082,6 +1096,7 @@ static void stream_free(nv_stream* s) {
   dev_free(s->sad);
   dev_free(s->hd);
   dev_free(s->cuts);
+  dev_free(s->acc);
 }
 
 // Grows the slot ring to at least r slots, keeping the last pushed frame.
@@ -1137,13 +1152,15 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   s->rule = to_rule(params);
   s->hp = round_up(fmt->height, 8);
   s->wp = round_up(fmt->width, 8);
-  s->luma_pitch = (int64_t)fmt->width * (fmt->bits == 8 ? 1 : 2);
+  s->luma_pitch = luma_pitch(fmt);
   hipError_t e = hipSuccess;
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&s->luma[i], (size_t)s->luma_pitch * fmt->height);
   if (e == hipSuccess) e = dev_alloc(&s->hist, 128);
   if (e == hipSuccess) e = dev_alloc(&s->sad, 1);
   if (e == hipSuccess) e = dev_alloc(&s->hd, 1);
   if (e == hipSuccess) e = dev_alloc(&s->cuts, kCutRing);
+  if (e == hipSuccess) e = dev_alloc(&s->acc, 1);
+  if (e == hipSuccess) e = hipMemset(s->acc, 0, sizeof(SceneAcc));
   nv_status st = NV_OK;
   if (e != hipSuccess)
     st = fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "stream allocation: %s", hipGetErrorString(e));
@@ -1182,18 +1199,24 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
   const int cur = s->slot(s->t), prv = s->t > 0 ? s->slot(s->t - 1) : 0;
   const Frame f = to_frame(&s->fmt, frame);
   NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
-  Frame pf = f;
-  pf.p[0] = s->luma[s->luma_last];
-  pf.pitch[0] = s->luma_pitch;
   uint32_t* cut_t = s->cuts + (s->t % kCutRing);
-  uint32_t* hist_new = s->hist + 64 * (s->hist_last ^ 1);
-  NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] {
-    return launch_scene(f, s->t > 0 ? &pf : nullptr, s->t > 0 ? s->hist + 64 * s->hist_last : nullptr, s->rule,
-                        external_cut, s->sad, hist_new, s->hd, cut_t, hs);
-  }));
-  HIP_TRY(hipMemcpy2DAsync(s->luma[s->luma_last ^ 1], (size_t)s->luma_pitch, frame->data[0],
-                           (size_t)frame->pitch_bytes[0], (size_t)s->luma_pitch, (size_t)s->fmt.height,
-                           hipMemcpyDeviceToDevice, hs));
+  SceneJob J{};
+  J.cur = f;
+  J.prev_y = s->t > 0 ? s->luma[s->luma_last] : nullptr;
+  J.prev_pitch = s->luma_pitch;
+  J.hist_prev = s->t > 0 ? s->hist + 64 * s->hist_last : nullptr;
+  J.sad = &s->acc->sad;
+  J.hist = s->acc->hist;
+  J.reset = 1;
+  J.hd = s->hd;
+  J.cut = cut_t;
+  J.hist_save = s->hist + 64 * (s->hist_last ^ 1);
+  J.sad_save = s->sad;
+  J.luma_save = s->luma[s->luma_last ^ 1];
+  J.luma_save_pitch = s->luma_pitch;
+  J.rule = s->rule;
+  J.external = external_cut;
+  NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] { return launch_scene(J, false, hs); }));
   NV_TRY(extract_impl(s->ctx, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
   *n_out = 0;
   if (s->t > 0) {
@@ -1512,6 +1535,8 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     sc.hist_save = F.last ? s->hist + 64 * (s->hist_last ^ 1) : nullptr;
     sc.luma_save = F.last ? s->luma[s->luma_last ^ 1] : nullptr;
     sc.luma_save_pitch = s->luma_pitch;
+    sc.sad_save = nullptr;
+    sc.reset = 0;
     sc.rule = s->rule;
     sc.external = F.ext;
     sc.item_begin = it[BL_SCENE];

@@ -313,13 +313,29 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
             if (part < np) acc[pb][ob] = Mma<TC>::step(wa[ob * AS + part], xb[pb], acc[pb][ob]);
     };
     fetch(0, wa0, xb0);
+    if constexpr (std::is_same<TC, float>::value) {
+      // float: four MFMAs per fragment pair leave the loads enough time to land, and
+      // the unrolled form (the copies fold into register renaming) schedules best
+#pragma unroll 3
+      for (int it = 0; it < NIT; ++it) {
+        if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
+        mma(wa0, xb0);
+        if (it + 1 < NIT) {
+#pragma unroll
+          for (int ob = 0; ob < OBW * AS; ++ob) wa0[ob] = wa1[ob];
+#pragma unroll
+          for (int pb = 0; pb < RW; ++pb) xb0[pb] = xb1[pb];
+        }
+      }
+    } else {
 #pragma unroll 1
-    for (int it = 0; it < NIT; it += 2) {
-      if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
-      mma(wa0, xb0);
-      if (it + 1 < NIT) {
-        if (it + 2 < NIT) fetch(it + 2, wa0, xb0);
-        mma(wa1, xb1);
+      for (int it = 0; it < NIT; it += 2) {
+        if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
+        mma(wa0, xb0);
+        if (it + 1 < NIT) {
+          if (it + 2 < NIT) fetch(it + 2, wa0, xb0);
+          mma(wa1, xb1);
+        }
       }
     }
   }

@@ -191,51 +191,66 @@ __device__ __forceinline__ void unpack_px4(const Frame& f, const Inv& m, float* 
   st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
 }
 
-// Eight consecutive padded pixels of row y per thread (four in the last group of a row
-// when wp is not a multiple of 8).  Runs fully inside the frame
-// read each plane row with vector loads (luma 8 samples; 4:2:0 chroma the 4 + 1
-// samples the bilinear filter needs from rows ci and ci2); runs that reach into the
+// Two codes of row y from column x0 (x0 even, x0 + 1 < w): one load when aligned.
+template <int BITS>
+__device__ __forceinline__ void code_pair(const void* base, int64_t pitch, int y, int x0, float (&v)[2]) {
+  constexpr uint32_t mask = BITS == 8 ? 0xFFu : 0x3FFu;
+  const char* at = static_cast<const char*>(base) + y * pitch + (size_t)x0 * (BITS == 8 ? 1 : 2);
+  if ((reinterpret_cast<uintptr_t>(at) & (BITS == 8 ? 1 : 3)) == 0) {
+    const uint32_t wd = BITS == 8 ? (uint32_t)*reinterpret_cast<const uint16_t*>(at)
+                                  : *reinterpret_cast<const uint32_t*>(at);
+    v[0] = (float)(wd & mask);
+    v[1] = (float)((wd >> (BITS == 8 ? 8 : 16)) & mask);
+  } else {
+    v[0] = Code<BITS>::get(base, pitch, y, x0);
+    v[1] = Code<BITS>::get(base, pitch, y, x0 + 1);
+  }
+}
+
+// Four consecutive padded pixels of row y per thread, so that each of the wave's
+// float4 stores covers one contiguous kilobyte of an output plane.  Runs fully inside
+// the frame read each plane row with vector loads (luma 4 codes; 4:2:0 chroma the 2 + 1
+// codes the bilinear filter needs from rows ci and ci2); runs that reach into the
 // padding use the per-pixel form.
 template <int BITS, bool C420>
-__device__ __forceinline__ void unpack8(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp, int wp,
+__device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp, int wp,
                                         int gid) {
-  const int groups_per_row = (wp + 7) >> 3;   // wp is a multiple of 4
+  const int groups_per_row = wp >> 2;   // wp is a multiple of 4
   if (gid >= groups_per_row * hp) return;
   const int y = gid / groups_per_row;
-  const int x0 = (gid - y * groups_per_row) << 3;
-  if (x0 + 8 > f.w || x0 + 8 > wp) {
+  const int x0 = (gid - y * groups_per_row) << 2;
+  if (x0 + 4 > f.w) {
     unpack_px4<BITS, C420>(f, m, rgb, hp, wp, y, x0);
-    if (x0 + 4 < wp) unpack_px4<BITS, C420>(f, m, rgb, hp, wp, y, x0 + 4);
     return;
   }
   const int sy = min(y, f.h - 1);
-  float yv[8], cb[8], cr[8];
-  code_run<BITS, 8>(f.p[0], f.pitch[0], sy, x0, f.w, yv);
+  float yv[4], cb[4], cr[4];
+  code_run<BITS, 4>(f.p[0], f.pitch[0], sy, x0, f.w, yv);
   if (C420) {
     const int hc = f.h >> 1, wc = f.w >> 1;
     const int ci = sy >> 1;
     const int ci2 = (sy & 1) ? min(ci + 1, hc - 1) : max(ci - 1, 0);
-    const int c0 = x0 >> 1, c4 = min(c0 + 4, wc - 1);
+    const int c0 = x0 >> 1, c2 = min(c0 + 2, wc - 1);
 #pragma unroll
     for (int pl = 1; pl <= 2; ++pl) {
-      float top[4], bot[4], vb[5];
-      code_run<BITS, 4>(f.p[pl], f.pitch[pl], ci, c0, wc, top);
-      code_run<BITS, 4>(f.p[pl], f.pitch[pl], ci2, c0, wc, bot);
+      float top[2], bot[2], vb[3];
+      code_pair<BITS>(f.p[pl], f.pitch[pl], ci, c0, top);
+      code_pair<BITS>(f.p[pl], f.pitch[pl], ci2, c0, bot);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) vb[i] = 0.75f * top[i] + 0.25f * bot[i];
-      vb[4] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, c4) +
-              0.25f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci2, c4);
+      for (int i = 0; i < 2; ++i) vb[i] = 0.75f * top[i] + 0.25f * bot[i];
+      vb[2] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, c2) +
+              0.25f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci2, c2);
       float* c = pl == 1 ? cb : cr;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) c[k] = (k & 1) ? 0.5f * (vb[k >> 1] + vb[(k >> 1) + 1]) : vb[k >> 1];
+      for (int k = 0; k < 4; ++k) c[k] = (k & 1) ? 0.5f * (vb[k >> 1] + vb[(k >> 1) + 1]) : vb[k >> 1];
     }
   } else {
-    code_run<BITS, 8>(f.p[1], f.pitch[1], sy, x0, f.w, cb);
-    code_run<BITS, 8>(f.p[2], f.pitch[2], sy, x0, f.w, cr);
+    code_run<BITS, 4>(f.p[1], f.pitch[1], sy, x0, f.w, cb);
+    code_run<BITS, 4>(f.p[2], f.pitch[2], sy, x0, f.w, cr);
   }
-  float r[8], g[8], b[8];
+  float r[4], g[4], b[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 4; ++k) {
     const float yn = (yv[k] - m.yo) * m.ys;
     const float cbn = (cb[k] - m.co) * m.cs;
     const float crn = (cr[k] - m.co) * m.cs;
@@ -246,27 +261,24 @@ __device__ __forceinline__ void unpack8(const Frame& f, const Inv& m, float* __r
   const size_t plane = (size_t)hp * wp;
   float* o = rgb + (size_t)y * wp + x0;
   st4(o, f32x4{r[0], r[1], r[2], r[3]});
-  st4(o + 4, f32x4{r[4], r[5], r[6], r[7]});
   st4(o + plane, f32x4{g[0], g[1], g[2], g[3]});
-  st4(o + plane + 4, f32x4{g[4], g[5], g[6], g[7]});
   st4(o + 2 * plane, f32x4{b[0], b[1], b[2], b[3]});
-  st4(o + 2 * plane + 4, f32x4{b[4], b[5], b[6], b[7]});
 }
 
 __device__ __forceinline__ void unpack_any(const Frame& f, const Inv& m, float* rgb, int hp, int wp, int gid) {
   if (f.bits == 8) {
-    if (f.chroma == 420) unpack8<8, true>(f, m, rgb, hp, wp, gid);
-    else unpack8<8, false>(f, m, rgb, hp, wp, gid);
+    if (f.chroma == 420) unpack4<8, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<8, false>(f, m, rgb, hp, wp, gid);
   } else {
-    if (f.chroma == 420) unpack8<10, true>(f, m, rgb, hp, wp, gid);
-    else unpack8<10, false>(f, m, rgb, hp, wp, gid);
+    if (f.chroma == 420) unpack4<10, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<10, false>(f, m, rgb, hp, wp, gid);
   }
 }
 
 template <int BITS, bool C420>
 __global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
                                                 int wp) {
-  unpack8<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
+  unpack4<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_unpack_batch(const UnpackJob* __restrict__ jobs,
@@ -463,6 +475,11 @@ __global__ __launch_bounds__(256) void k_pack_batch(const PackJob* __restrict__ 
 }
 
 // ---- scene metric ----
+// A thread takes runs of 16 adjacent luma codes of one row (one or two 16-byte loads
+// where the row allows): it adds |Y_t - Y_{t-1}| into a register sum and bins the run
+// into the workgroup's LDS histogram, one LDS atomic per stretch of equal bins
+// (neighbouring codes of natural images mostly share a bin).  Workgroups then add their
+// partial sums into the frame's accumulators with one global atomic per used bin.
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
@@ -470,32 +487,103 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-__global__ void k_scene_clear(uint64_t* sad, uint32_t* hist) {
-  const int t = threadIdx.x;
-  if (t < 64) hist[t] = 0u;
-  if (t == 0) *sad = 0ull;
+constexpr int kRun = 16;   // luma codes per thread and step
+
+// Codes x0 .. x0+15 of row y (zero past the row end w).
+template <int BITS>
+__device__ __forceinline__ void luma_run(const void* base, int64_t pitch, int y, int x0, int w,
+                                         uint32_t (&c)[kRun]) {
+  constexpr int SB = BITS == 8 ? 1 : 2;
+  constexpr uint32_t mask = BITS == 8 ? 0xFFu : 0x3FFu;
+  const char* at = static_cast<const char*>(base) + y * pitch + (size_t)x0 * SB;
+  if (x0 + kRun <= w && (reinterpret_cast<uintptr_t>(at) & 15) == 0) {
+    uint32_t wd[kRun * SB / 4];
+#pragma unroll
+    for (int v = 0; v < SB; ++v) {
+      const u32x4 t = reinterpret_cast<const u32x4*>(at)[v];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wd[4 * v + i] = t[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+      constexpr int PER = 4 / SB;
+      c[k] = (wd[k / PER] >> (8 * SB * (k % PER))) & mask;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) c[k] = x0 + k < w ? (uint32_t)Code<BITS>::get(base, pitch, y, x0 + k) : 0u;
+  }
 }
 
-// Rows [r0, r1) of one frame: luma histogram into lh (LDS), SAD against the previous
-// frame's luma, optionally a copy of the rows into luma_save.  Returns the thread's SAD.
-// Per-thread partial sums fit in 32 bits for the frame sizes the library accepts.
+// Codes x0 .. x0+n-1 (n = min(16, w - x0)) written to row y of a luma copy.
 template <int BITS>
-__device__ __forceinline__ uint32_t scene_rows(const Frame& cur, const void* prev_y, int64_t prev_pitch,
-                                               void* luma_save, int64_t save_pitch, int r0, int r1,
-                                               uint32_t* lh) {
-  const int shift = BITS - 6;
-  uint32_t s = 0;
-  for (int row = r0; row < r1; ++row) {
-    for (int x = threadIdx.x; x < cur.w; x += 256) {
-      const int c = (int)Code<BITS>::get(cur.p[0], cur.pitch[0], row, x);
-      atomicAdd(&lh[c >> shift], 1u);
-      if (prev_y != nullptr) s += (uint32_t)abs(c - (int)Code<BITS>::get(prev_y, prev_pitch, row, x));
-      if (luma_save != nullptr) Code<BITS>::put(luma_save, save_pitch, row, x, c);
+__device__ __forceinline__ void luma_run_store(void* base, int64_t pitch, int y, int x0, int w,
+                                               const uint32_t (&c)[kRun]) {
+  constexpr int SB = BITS == 8 ? 1 : 2;
+  char* at = static_cast<char*>(base) + y * pitch + (size_t)x0 * SB;
+  if (x0 + kRun <= w && (reinterpret_cast<uintptr_t>(at) & 15) == 0) {
+    constexpr int PER = 4 / SB;
+    uint32_t wd[kRun / PER];
+#pragma unroll
+    for (int i = 0; i < kRun / PER; ++i) wd[i] = 0u;
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) wd[k / PER] |= c[k] << (8 * SB * (k % PER));
+#pragma unroll
+    for (int v = 0; v < SB; ++v)
+      reinterpret_cast<u32x4*>(at)[v] = u32x4{wd[4 * v], wd[4 * v + 1], wd[4 * v + 2], wd[4 * v + 3]};
+  } else {
+#pragma unroll
+    for (int k = 0; k < kRun; ++k)
+      if (x0 + k < w) Code<BITS>::put(base, pitch, y, x0 + k, (int)c[k]);
+  }
+}
+
+// One run: SAD against the previous luma into *s, histogram into lh, optional copy.
+template <int BITS>
+__device__ __forceinline__ void scene_run(const Frame& cur, const void* prev_y, int64_t prev_pitch,
+                                          void* luma_save, int64_t save_pitch, int y, int x0,
+                                          uint32_t* lh, uint32_t& s) {
+  constexpr int SH = BITS - 6;
+  uint32_t c[kRun];
+  luma_run<BITS>(cur.p[0], cur.pitch[0], y, x0, cur.w, c);
+  if (prev_y != nullptr) {
+    uint32_t p[kRun];
+    luma_run<BITS>(prev_y, prev_pitch, y, x0, cur.w, p);
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) s += (uint32_t)abs((int)c[k] - (int)p[k]);   // zero past the row end
+  }
+  const int n = min(kRun, cur.w - x0);
+  uint32_t bin = c[0] >> SH, cnt = 1u;
+#pragma unroll
+  for (int k = 1; k < kRun; ++k) {
+    if (k < n) {
+      const uint32_t bk = c[k] >> SH;
+      if (bk == bin) {
+        ++cnt;
+      } else {
+        atomicAdd(&lh[bin], cnt);
+        bin = bk;
+        cnt = 1u;
+      }
     }
+  }
+  atomicAdd(&lh[bin], cnt);
+  if (luma_save != nullptr) luma_run_store<BITS>(luma_save, save_pitch, y, x0, cur.w, c);
+}
+
+// Runs [r0, r1) of a frame whose rows hold nrun runs each, strided over the workgroup.
+template <int BITS>
+__device__ __forceinline__ uint32_t scene_runs(const SceneJob& J, int nrun, int r0, int r1, int stride,
+                                               uint32_t* lh) {
+  uint32_t s = 0u;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += stride) {
+    const int y = r / nrun, x0 = (r - y * nrun) * kRun;
+    scene_run<BITS>(J.cur, J.prev_y, J.prev_pitch, J.luma_save, J.luma_save_pitch, y, x0, lh, s);
   }
   return s;
 }
 
+// Adds the workgroup's partial SAD and histogram to the frame's accumulators.
 __device__ __forceinline__ void scene_flush(uint32_t s, bool has_prev, uint32_t* lh, uint32_t* lsad,
                                             uint64_t* sad, uint32_t* hist) {
   if (has_prev) {
@@ -510,53 +598,70 @@ __device__ __forceinline__ void scene_flush(uint32_t s, bool has_prev, uint32_t*
   }
 }
 
-template <int BITS, bool HAS_PREV>
-__global__ __launch_bounds__(256) void k_scene_accum(Frame cur, Frame prev, uint64_t* sad,
-                                                     uint32_t* hist) {
-  __shared__ uint32_t lh[64];
-  __shared__ uint32_t lsad[4];
-  if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
-  __syncthreads();
-  uint32_t s = 0;
-  for (int row = blockIdx.x; row < cur.h; row += gridDim.x)
-    s += scene_rows<BITS>(cur, HAS_PREV ? prev.p[0] : nullptr, prev.pitch[0], nullptr, 0, row, row + 1, lh);
-  scene_flush(s, HAS_PREV, lh, lsad, sad, hist);
-}
-
-// Frame t starts a scene when SAD > T * 2^(bits-8) * N and HD * den > 2 N num.
-__device__ __forceinline__ void scene_decide(const uint64_t* sad, const uint32_t* hist,
-                                             const uint32_t* hist_prev, int has_prev, uint64_t n_pix,
-                                             int bits, const SceneRule& rule, int external_cut,
-                                             uint32_t* hd, uint32_t* cut, uint32_t* hist_save) {
+// Frame t starts a scene when SAD > T * 2^(bits-8) * N and HD * den > 2 N num.  Run by
+// one wave of 64 lanes (lane = histogram bin) after the accumulating launch.
+__device__ __forceinline__ void scene_decide(const SceneJob& J, bool has_prev) {
   const int t = threadIdx.x;
+  const uint64_t n_pix = (uint64_t)J.cur.w * (uint64_t)J.cur.h;
+  const uint32_t h = J.hist[t];
   uint32_t d = 0;
-  if (has_prev) d = (uint32_t)abs((int)hist[t] - (int)hist_prev[t]);
+  if (has_prev) d = (uint32_t)abs((int)h - (int)J.hist_prev[t]);
   d = wave_sum(d);
-  if (hist_save != nullptr) hist_save[t] = hist[t];
+  if (J.hist_save != nullptr) J.hist_save[t] = h;
   if (t == 0) {
+    const uint64_t sad = *J.sad;
     uint32_t c;
     if (!has_prev) {
       c = 1u;
       d = 0u;
     } else {
-      const uint64_t thr = (uint64_t)rule.mad_thresh_8bit * (uint64_t)(1u << (bits - 8)) * n_pix;
-      const bool mad_ok = *sad > thr;
-      const bool hist_ok = (uint64_t)d * (uint64_t)rule.hist_den > 2ull * n_pix * (uint64_t)rule.hist_num;
-      c = (rule.enable && mad_ok && hist_ok) ? 1u : 0u;
+      const uint64_t thr = (uint64_t)J.rule.mad_thresh_8bit * (uint64_t)(1u << (J.cur.bits - 8)) * n_pix;
+      const bool mad_ok = sad > thr;
+      const bool hist_ok = (uint64_t)d * (uint64_t)J.rule.hist_den > 2ull * n_pix * (uint64_t)J.rule.hist_num;
+      c = (J.rule.enable && mad_ok && hist_ok) ? 1u : 0u;
     }
-    if (external_cut > 0) c = 1u;
-    *hd = d;
-    *cut = c;
+    if (J.external > 0) c = 1u;
+    if (J.sad_save != nullptr) *J.sad_save = sad;
+    *J.hd = d;
+    *J.cut = c;
   }
 }
 
-__global__ void k_scene_final(const uint64_t* sad, const uint32_t* hist, const uint32_t* hist_prev,
-                              int has_prev, uint64_t n_pix, int bits, SceneRule rule, int external_cut,
-                              uint32_t* hd, uint32_t* cut) {
-  scene_decide(sad, hist, hist_prev, has_prev, n_pix, bits, rule, external_cut, hd, cut, nullptr);
+__global__ void k_scene_clear(uint64_t* sad, uint32_t* hist) {
+  const int t = threadIdx.x;
+  if (t < 64) hist[t] = 0u;
+  if (t == 0) *sad = 0ull;
+}
+
+// One frame: the workgroups split the frame's runs into contiguous shares and add into
+// the accumulators.  (A grid-wide "last workgroup decides" tail would need a device
+// fence per workgroup, which writes back the L2 and costs more than a second launch.)
+template <int BITS, bool HAS_PREV>
+__global__ __launch_bounds__(256) void k_scene(SceneJob J) {
+  __shared__ uint32_t lh[64];
+  __shared__ uint32_t lsad[4];
+  if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
+  __syncthreads();
+  const int nrun = (J.cur.w + kRun - 1) / kRun, total = nrun * J.cur.h;
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = min(total, (int)blockIdx.x * per), r1 = min(total, r0 + per);
+  uint32_t s = 0u;
+  for (int b = r0; b < r1; b += 256) s += scene_runs<BITS>(J, nrun, b, min(r1, b + 256), 256, lh);
+  scene_flush(s, HAS_PREV, lh, lsad, J.sad, J.hist);
+}
+
+// The decision, then (J.reset) the accumulators back to zero for the next frame.
+__global__ void k_scene_final(SceneJob J, int has_prev) {
+  scene_decide(J, has_prev != 0);
+  if (J.reset) {
+    J.hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) *J.sad = 0ull;
+  }
 }
 
 // Batched scene metric: clear every job's accumulators, accumulate row chunks, decide.
+// (A frame's decision may read the previous frame's histogram from the same batch, so
+// the decisions wait for the whole accumulate launch.)
 __global__ __launch_bounds__(64) void k_scene_clear_batch(const SceneJob* __restrict__ jobs,
                                                           const int* __restrict__ count) {
   for (int j = blockIdx.x; j < count[0]; j += gridDim.x) {
@@ -572,13 +677,13 @@ __global__ __launch_bounds__(256) void k_scene_accum_batch(const SceneJob* __res
   const int njobs = count[0], total = count[1];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const SceneJob& J = jobs[find_job(jobs, njobs, item)];
-    const int r0 = (item - J.item_begin) * kSceneRowsPerItem;
-    const int r1 = min(r0 + kSceneRowsPerItem, J.cur.h);
+    const int nrun = (J.cur.w + kRun - 1) / kRun;
+    const int y0 = (item - J.item_begin) * kSceneRowsPerItem;
+    const int r0 = y0 * nrun, r1 = min(y0 + kSceneRowsPerItem, J.cur.h) * nrun;
     if (threadIdx.x < 64) lh[threadIdx.x] = 0u;
     __syncthreads();
-    const uint32_t s = J.cur.bits == 8
-        ? scene_rows<8>(J.cur, J.prev_y, J.prev_pitch, J.luma_save, J.luma_save_pitch, r0, r1, lh)
-        : scene_rows<10>(J.cur, J.prev_y, J.prev_pitch, J.luma_save, J.luma_save_pitch, r0, r1, lh);
+    const uint32_t s = J.cur.bits == 8 ? scene_runs<8>(J, nrun, r0, r1, 256, lh)
+                                       : scene_runs<10>(J, nrun, r0, r1, 256, lh);
     scene_flush(s, J.prev_y != nullptr, lh, lsad, J.sad, J.hist);
     __syncthreads();
   }
@@ -588,9 +693,7 @@ __global__ __launch_bounds__(64) void k_scene_final_batch(const SceneJob* __rest
                                                           const int* __restrict__ count) {
   for (int j = blockIdx.x; j < count[0]; j += gridDim.x) {
     const SceneJob& J = jobs[j];
-    const int has_prev = J.prev_y != nullptr && J.hist_prev != nullptr;
-    scene_decide(J.sad, J.hist, J.hist_prev, has_prev, (uint64_t)J.cur.w * (uint64_t)J.cur.h, J.cur.bits,
-                 J.rule, J.external, J.hd, J.cut, J.hist_save);
+    scene_decide(J, J.prev_y != nullptr && J.hist_prev != nullptr);
   }
 }
 
@@ -598,7 +701,7 @@ __global__ __launch_bounds__(64) void k_scene_final_batch(const SceneJob* __rest
 
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s) {
   const Inv m = make_inv(f.bits);
-  const int n = ((wp + 7) >> 3) * hp;
+  const int n = (wp >> 2) * hp;
   const dim3 grid((n + 255) / 256), blk(256);
   if (f.bits == 8 && f.chroma == 420) hipLaunchKernelGGL((k_unpack<8, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
   else if (f.bits == 8) hipLaunchKernelGGL((k_unpack<8, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
@@ -623,22 +726,22 @@ hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* hist_prev,
-                        const SceneRule& rule, int external_cut, uint64_t* sad, uint32_t* hist,
-                        uint32_t* hd, uint32_t* cut, hipStream_t s) {
-  hipLaunchKernelGGL(k_scene_clear, dim3(1), dim3(64), 0, s, sad, hist);
-  const bool has_prev = prev != nullptr && prev->p[0] != nullptr && hist_prev != nullptr;
-  const int blocks = cur.h < 1024 ? cur.h : 1024;
-  Frame pv = has_prev ? *prev : cur;
-  if (cur.bits == 8) {
-    if (has_prev) hipLaunchKernelGGL((k_scene_accum<8, true>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
-    else hipLaunchKernelGGL((k_scene_accum<8, false>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+hipError_t launch_scene(const SceneJob& job, bool clear, hipStream_t s) {
+  if (clear) hipLaunchKernelGGL(k_scene_clear, dim3(1), dim3(64), 0, s, job.sad, job.hist);
+  const bool has_prev = job.prev_y != nullptr && job.hist_prev != nullptr;
+  const int64_t runs = (int64_t)((job.cur.w + kRun - 1) / kRun) * job.cur.h;
+  // about four runs per thread, at most 1024 workgroups
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (runs + 1023) / 1024));
+  SceneJob J = job;
+  if (!has_prev) J.prev_y = nullptr;
+  if (job.cur.bits == 8) {
+    if (has_prev) hipLaunchKernelGGL((k_scene<8, true>), dim3(blocks), dim3(256), 0, s, J);
+    else hipLaunchKernelGGL((k_scene<8, false>), dim3(blocks), dim3(256), 0, s, J);
   } else {
-    if (has_prev) hipLaunchKernelGGL((k_scene_accum<10, true>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
-    else hipLaunchKernelGGL((k_scene_accum<10, false>), dim3(blocks), dim3(256), 0, s, cur, pv, sad, hist);
+    if (has_prev) hipLaunchKernelGGL((k_scene<10, true>), dim3(blocks), dim3(256), 0, s, J);
+    else hipLaunchKernelGGL((k_scene<10, false>), dim3(blocks), dim3(256), 0, s, J);
   }
-  hipLaunchKernelGGL(k_scene_final, dim3(1), dim3(64), 0, s, sad, hist, hist_prev, has_prev ? 1 : 0,
-                     (uint64_t)cur.w * (uint64_t)cur.h, cur.bits, rule, external_cut, hd, cut);
+  hipLaunchKernelGGL(k_scene_final, dim3(1), dim3(64), 0, s, J, has_prev ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -37,10 +37,10 @@ Fwd make_fwd(int bits);
 // ---- pixel-format stages (k_pixel.hip) ----
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s);
 hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipStream_t s);
-// prev may have null p[0] (first frame).  hist_prev may be null.
-hipError_t launch_scene(const Frame& cur, const Frame* prev, const uint32_t* hist_prev,
-                        const SceneRule& rule, int external_cut, uint64_t* sad,
-                        uint32_t* hist, uint32_t* hd, uint32_t* cut, hipStream_t s);
+struct SceneJob;
+// One frame's scene metric: accumulate, then decide (after a clear of job.sad / hist when
+// `clear`; otherwise they must be zero, as a previous call with job.reset leaves them).
+hipError_t launch_scene(const SceneJob& job, bool clear, hipStream_t s);
 
 // ---- batched (multi-image, persistent) launches ----
 // Each batched kernel walks a device table of jobs.  Job j owns the work items
@@ -66,6 +66,9 @@ struct PackJob {
   int item_begin;
 };
 
+// The scene metric of one frame.  sad / hist accumulate over the frame (zero at the
+// start); the decision writes hd and cut and, when set, copies hist to hist_save and
+// the SAD to sad_save.
 struct SceneJob {
   Frame cur;
   const void* prev_y;          // previous frame's luma, or null for a stream's first frame
@@ -75,15 +78,17 @@ struct SceneJob {
   uint32_t* hist;              // histogram of cur (accumulator)
   uint32_t* hd;
   uint32_t* cut;
-  uint32_t* hist_save;         // when set, the final pass copies hist there
+  uint32_t* hist_save;
+  uint64_t* sad_save;
   void* luma_save;             // when set, the accumulate pass copies cur's luma rows there
   int64_t luma_save_pitch;
   SceneRule rule;
   int external;
-  int item_begin;              // in row chunks of kSceneRowsPerItem
+  int reset;                   // single-frame launch: zero sad and hist after the decision
+  int item_begin;              // batched launch: first item, in row chunks of kSceneRowsPerItem
 };
 
-inline int unpack_items(int hp, int wp) { return (((wp + 7) / 8) * hp + 255) / 256; }
+inline int unpack_items(int hp, int wp) { return ((wp / 4) * hp + 255) / 256; }
 inline int pack_items(int w, int h, int chroma) {
   const int n = chroma == 420 ? ((w / 2 + 3) / 4) * (h / 2) : ((w + 7) / 8) * h;
   return (n + 255) / 256;

@@ -145,3 +145,14 @@ def test_scene_generator_clip(B, w, h, bits, chroma, n):
     clip = synth.gen_clip(w, h, n, bits=bits, chroma=chroma, seed=9, cut_every=(4, 8),
                           garbage_high_bits=(bits == 10))
     _scene_case(B, [clip.frame(t) for t in range(n)], bits, chroma)
+
+
+@pytest.mark.parametrize("w,h,bits,chroma", [(1920, 1080, 10, 420), (1000, 540, 8, 444)])
+def test_scene_full_size(B, w, h, bits, chroma):
+    """Frame sizes that spread the metric over many workgroups (the last one to finish
+    decides): 1080p 10-bit with junk above bit 9, and a width whose rows are neither a
+    multiple of 16 codes nor 16-byte aligned."""
+    say(f"scene full size {w}x{h} {bits}-bit")
+    clip = synth.gen_clip(w, h, 3, bits=bits, chroma=chroma, seed=4, scene_starts=[2],
+                          garbage_high_bits=(bits == 10))
+    _scene_case(B, [clip.frame(t) for t in range(3)], bits, chroma)
