@@ -9,6 +9,7 @@
 // channels of one pixel.  Storage type (TIN / TOUT) and MFMA type (TC) are template
 // parameters: float end to end, or float16 / bfloat16 storage and MFMA with float
 // accumulation; the offset head reads 16-bit features and computes in float.
+#include <algorithm>
 #include <type_traits>
 
 #include "nv_internal.h"
@@ -312,10 +313,10 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
           for (int part = 0; part < AS; ++part)
             if (part < np) acc[pb][ob] = Mma<TC>::step(wa[ob * AS + part], xb[pb], acc[pb][ob]);
     };
-    fetch(0, wa0, xb0);
     if constexpr (std::is_same<TC, float>::value) {
       // float: four MFMAs per fragment pair leave the loads enough time to land, and
       // the unrolled form (the copies fold into register renaming) schedules best
+      fetch(0, wa0, xb0);
 #pragma unroll 3
       for (int it = 0; it < NIT; ++it) {
         if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
@@ -328,14 +329,38 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
         }
       }
     } else {
-#pragma unroll 1
-      for (int it = 0; it < NIT; it += 2) {
-        if (it + 1 < NIT) fetch(it + 1, wa1, xb1);
-        mma(wa0, xb0);
-        if (it + 1 < NIT) {
-          if (it + 2 < NIT) fetch(it + 2, wa0, xb0);
-          mma(wa1, xb1);
-        }
+      // 16-bit: one MFMA per fragment pair is too short to cover an L2 hit, so the
+      // steps are unrolled and the A fragments (global) are requested PW steps ahead,
+      // the B fragments (LDS) one step ahead.  The scheduling barrier after each step
+      // keeps the compiler from hoisting every load to the top (which would cost far
+      // more registers than the prefetch depth needs).
+      constexpr int PW = 2;
+      u32x4 wq[PW + 1][OBW * AS], xq[2][RW];
+      auto fetch_w = [&](int it, u32x4 (&wa)[OBW * AS]) {
+        const int tap = it / NCG, cg = it - tap * NCG;
+        const u32x4* wp = wbase + tap * wstride_tap + (size_t)cg * wobtot * 64;
+#pragma unroll
+        for (int ob = 0; ob < OBW; ++ob)
+#pragma unroll
+          for (int part = 0; part < AS; ++part)
+            if (part < np) wa[ob * AS + part] = wp[(ob * AS + part) * 64];
+      };
+      auto fetch_b = [&](int it, u32x4 (&xb)[RW]) {
+        const int tap = it / NCG, cg = it - tap * NCG;
+        const int dy = tap / 3, dx = tap - 3 * dy;
+#pragma unroll
+        for (int pb = 0; pb < RW; ++pb) xb[pb] = ldu4(tbase + ((pb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
+      };
+#pragma unroll
+      for (int k = 0; k < PW; ++k)
+        if (k < NIT) fetch_w(k, wq[k]);
+      fetch_b(0, xq[0]);
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        if (it + PW < NIT) fetch_w(it + PW, wq[(it + PW) % (PW + 1)]);
+        if (it + 1 < NIT) fetch_b(it + 1, xq[(it + 1) & 1]);
+        mma(wq[it % (PW + 1)], xq[it & 1]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
