@@ -208,6 +208,7 @@ struct Profiler {
 // them per context (see nv_autotune).
 struct Tuning {
   int pb_block = 2, pb_up = 2, pb_dcn = 2;
+  int off1 = 2, off2 = 2;   // offset-head tile codes (split head: three shapes)
 };
 
 struct BatchState;
@@ -693,10 +694,10 @@ nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, con
   if (mask & 2u) {
     const ConvImg i1 = conv_img(fa, fb, sel, nullptr, fa, nullptr, ws.o1, hp, wp);
     NV_TRY(timed(ctx, NV_K_OFF1, s, "off1",
-                 [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, 2, i1, C, 0, s); }));
+                 [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, i1, C, 0, s); }));
     const ConvImg i2 = conv_img(ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
     NV_TRY(timed(ctx, NV_K_OFF2, s, "off2", [&] {
-      return launch_conv(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, 2, i2, ctx->ldo, 18 * G, s);
+      return launch_conv(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, i2, ctx->ldo, 18 * G, s);
     }));
     DcnImg di;
     di.fa = fa;
@@ -1383,10 +1384,10 @@ nv_status batch_enqueue(nv_context* ctx, hipStream_t s) {
     NV_TRY(check_launch(launch_conv_batch(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, T->blk_b,
                                           T->cnt[BL_BLOCK], C, 0, s), "block.b batch"));
   }
-  NV_TRY(check_launch(launch_conv_batch(ctx->off1, CONV_OFF1, EPI_LRELU, ft, 2, T->off1, T->cnt[BL_OFF1], C, 0, s),
-                      "off1 batch"));
-  NV_TRY(check_launch(launch_conv_batch(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, 2, T->off2, T->cnt[BL_OFF2],
-                                        ctx->ldo, 18 * G, s), "off2 batch"));
+  NV_TRY(check_launch(launch_conv_batch(ctx->off1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, T->off1,
+                                        T->cnt[BL_OFF1], C, 0, s), "off1 batch"));
+  NV_TRY(check_launch(launch_conv_batch(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, T->off2,
+                                        T->cnt[BL_OFF2], ctx->ldo, 18 * G, s), "off2 batch"));
   NV_TRY(check_launch(launch_dcn_batch(ctx->dcn, ft, ctx->tune.pb_dcn, T->dcn, T->cnt[BL_DCN], ctx->ldo, G, s),
                       "dcn batch"));
   for (int o = 0; o < 2; ++o) {
@@ -1578,10 +1579,12 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     const float* rb = s->rgb[Gr.slot_b];
     T.off1[k] = conv_img(fa, fb, Gr.sel, nullptr, fa, nullptr, o1, hp, wp);
     T.off1[k].item_begin = it[BL_OFF1];
-    it[BL_OFF1] += conv_items(hp, wp, 2, ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot, ctx->off1.tc, 2));
+    it[BL_OFF1] += conv_items(hp, wp, tile_pb(ctx->tune.off1),
+                              ctx->off1.obtot / conv_ob(CONV_OFF1, EPI_LRELU, ctx->off1.obtot, ctx->off1.tc, ctx->tune.off1));
     T.off2[k] = conv_img(o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
     T.off2[k].item_begin = it[BL_OFF2];
-    it[BL_OFF2] += conv_items(hp, wp, 2, ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot, ctx->off2.tc, 2));
+    it[BL_OFF2] += conv_items(hp, wp, tile_pb(ctx->tune.off2),
+                              ctx->off2.obtot / conv_ob(CONV_OFF2, EPI_OFFSET, ctx->off2.obtot, ctx->off2.tc, ctx->tune.off2));
     DcnImg& d = T.dcn[k];
     d.fa = fa;
     d.fb = fb;
@@ -1707,15 +1710,17 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     if (FILE* f = fopen(cache, "r")) {
       char line[256];
       while (fgets(line, sizeof line, f)) {
-        int a = 0, b = 0, c = 0;
+        int a = 0, b = 0, c = 0, d = 2, e = 2;
         char k2[128];
-        if (sscanf(line, "%127[^|]| %d %d %d", k2, &a, &b, &c) == 4) {
+        if (sscanf(line, "%127[^|]| %d %d %d %d %d", k2, &a, &b, &c, &d, &e) >= 4) {
           std::string ks(k2);
           while (!ks.empty() && ks.back() == ' ') ks.pop_back();
-          if (ks == key && a > 0 && b > 0 && c > 0) {
+          if (ks == key && a > 0 && b > 0 && c > 0 && d > 0 && e > 0) {
             ctx->tune.pb_block = a;
             ctx->tune.pb_up = b;
             ctx->tune.pb_dcn = c;
+            ctx->tune.off1 = d;
+            ctx->tune.off2 = e;
             found = true;
           }
         }
@@ -1731,6 +1736,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     // inputs for the timing runs: zero offsets keep every DCN sample inside the frame
     HIP_TRY(hipMemsetAsync(ws.feat[0], 0, (size_t)hp * wp * C * dtype_bytes(ft), s));
     HIP_TRY(hipMemsetAsync(ws.offs, 0, (size_t)hp * wp * ctx->ldo * 4, s));
+    HIP_TRY(hipMemsetAsync(ws.o1, 0, (size_t)hp * wp * C * 4, s));
     char buf[256];
     // bulk conv tiles: rows per wave 1, 2, 4, and for 16-bit / FP8 also with two waves
     // along the output blocks
@@ -1744,12 +1750,23 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
               bulk_tile_lds(ctx->ut, C, tile_code(pb, 1, 1)) <= lds_limit())
             bulk_tiles.push_back(tile_code(pb, 1, 1));
     }
+    // split offset head: rows per wave 2 (all output blocks) or 4 (two blocks), or two
+    // waves along the output blocks
+    auto head_tiles = [&](const PackedConv& P) {
+      std::vector<int> t = {tile_code(2, 1)};
+      if (P.tc == DT_F16 && P.obtot % 2 == 0) {
+        t.push_back(tile_code(4, 1));
+        t.push_back(tile_code(2, 2));
+      }
+      return t;
+    };
     struct Cand {
       const char* name;
       int* slot;
       std::vector<int> pbs;
-    } cands[3] = {{"block", &ctx->tune.pb_block, bulk_tiles}, {"up", &ctx->tune.pb_up, bulk_tiles},
-                  {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}}};
+    } cands[5] = {{"block", &ctx->tune.pb_block, bulk_tiles}, {"up", &ctx->tune.pb_up, bulk_tiles},
+                  {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}},
+                  {"off1", &ctx->tune.off1, head_tiles(ctx->off1)}, {"off2", &ctx->tune.off2, head_tiles(ctx->off2)}};
     for (auto& cd : cands) {
       float best = 1e30f;
       int best_pb = *cd.slot;
@@ -1768,6 +1785,14 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
         } else if (cd.slot == &ctx->tune.pb_up) {
           const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.u, hp, wp);
           st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, pb, im, 4 * C, 0, s); });
+        } else if (cd.slot == &ctx->tune.off1) {
+          const ConvImg im = conv_img(ws.feat[0], ws.feat[0], nullptr, nullptr, nullptr, nullptr, ws.o1, hp, wp);
+          st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, pb, im, C, 0, s); });
+        } else if (cd.slot == &ctx->tune.off2) {
+          const ConvImg im = conv_img(ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, ws.offs, hp, wp);
+          st = time_launch(s, 3, &ms, [&] {
+            return launch_conv(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, pb, im, ctx->ldo, 18 * ctx->G, s);
+          });
         } else {
           DcnImg di;
           di.fa = ws.feat[0];
@@ -1794,7 +1819,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     }
     if (cache) {
       if (FILE* f = fopen(cache, "a")) {
-        fprintf(f, "%s | %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn);
+        fprintf(f, "%s | %d %d %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn,
+                ctx->tune.off1, ctx->tune.off2);
         fclose(f);
       }
     }
@@ -1802,9 +1828,10 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     rep = "from cache: ";
     rep += key;
   }
-  char tail[128];
-  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d; LDS limit %d]", tile_name(ctx->tune.pb_block).c_str(),
-           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn, lds_limit());
+  char tail[160];
+  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d, off1 %s, off2 %s; LDS limit %d]",
+           tile_name(ctx->tune.pb_block).c_str(), tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn,
+           tile_name(ctx->tune.off1).c_str(), tile_name(ctx->tune.off2).c_str(), lds_limit());
   rep += tail;
   if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
     HIP_TRY(hipDeviceSynchronize());

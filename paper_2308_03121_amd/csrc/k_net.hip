@@ -1190,27 +1190,46 @@ hipError_t conv_bulk(const ConvCall& c, int epi, int tile) {
 }
 
 // Offset head: first conv reads the two feature maps (TIN) and computes in float, on
-// float MFMA or (split) on float16 MFMA with two-part weights.
+// float MFMA or (split) on float16 MFMA with two-part weights.  The split form has
+// three tile shapes (see head_ob): rows per wave 2 with all of a workgroup's output
+// blocks per wave, rows per wave 4 with two output blocks, and two waves along the
+// output blocks.
 template <typename TIN, int CCH>
-hipError_t conv_off1(const ConvCall& c, bool split) {
+hipError_t conv_off1(const ConvCall& c, bool split, int tile) {
+  const int pb = tile_pb(tile), wo = tile_wo(tile);
   if (split) {
     if constexpr (std::is_same<TIN, float>::value) return hipErrorInvalidValue;
     else {
+      if (wo == 2 && pb == 2) {
+        if (c.L.obtot % 4 == 0) return run_conv<TIN, f16, float, CCH, 2, 4, 2, EPI_LRELU, SPLIT_W, 2>(c);
+        if (c.L.obtot % 2 == 0) return run_conv<TIN, f16, float, CCH, 2, 2, 2, EPI_LRELU, SPLIT_W, 2>(c);
+        return hipErrorInvalidValue;
+      }
+      if (wo == 1 && pb == 4) return run_conv<TIN, f16, float, CCH, 2, 2, 4, EPI_LRELU, SPLIT_W>(c);
+      if (wo != 1 || pb != 2) return hipErrorInvalidValue;
       if (c.L.obtot % 4 == 0) return run_conv<TIN, f16, float, CCH, 2, 4, 2, EPI_LRELU, SPLIT_W>(c);
       return run_conv<TIN, f16, float, CCH, 2, 2, 2, EPI_LRELU, SPLIT_W>(c);
     }
   }
+  if (wo != 1 || pb != 2) return hipErrorInvalidValue;
   if (c.L.obtot % 4 == 0) return run_conv<TIN, float, float, CCH, 2, 4, 2, EPI_LRELU>(c);
   return run_conv<TIN, float, float, CCH, 2, 2, 2, EPI_LRELU>(c);
 }
 
 template <int CCH>
-hipError_t conv_off2(const ConvCall& c, bool split) {
+hipError_t conv_off2(const ConvCall& c, bool split, int tile) {
+  const int pb = tile_pb(tile), wo = tile_wo(tile);
   if (split) {
+    if (wo == 2 && pb == 2 && c.L.obtot % 2 == 0)
+      return run_conv<float, f16, float, CCH, 2, 2, 2, EPI_OFFSET, SPLIT_WX, 2>(c);
+    if (wo == 1 && pb == 4 && c.L.obtot % 2 == 0)
+      return run_conv<float, f16, float, CCH, 2, 2, 4, EPI_OFFSET, SPLIT_WX>(c);
+    if (wo != 1 || pb != 2) return hipErrorInvalidValue;
     if (c.L.obtot % 7 == 0) return run_conv<float, f16, float, CCH, 2, 7, 2, EPI_OFFSET, SPLIT_WX>(c);
     if (c.L.obtot % 4 == 0) return run_conv<float, f16, float, CCH, 2, 4, 2, EPI_OFFSET, SPLIT_WX>(c);
     return run_conv<float, f16, float, CCH, 2, 1, 2, EPI_OFFSET, SPLIT_WX>(c);
   }
+  if (wo != 1 || pb != 2) return hipErrorInvalidValue;
   if (c.L.obtot % 7 == 0) return run_conv<float, float, float, CCH, 1, 7, 2, EPI_OFFSET>(c);
   if (c.L.obtot % 4 == 0) return run_conv<float, float, float, CCH, 1, 4, 2, EPI_OFFSET>(c);
   return run_conv<float, float, float, CCH, 1, 1, 2, EPI_OFFSET>(c);
@@ -1219,8 +1238,8 @@ hipError_t conv_off2(const ConvCall& c, bool split) {
 template <typename T>
 hipError_t conv_any(const ConvCall& c, int epi, int role, int cch, int pb, bool split) {
   if (role == CONV_OFF1) {
-    if (cch == 64) return conv_off1<T, 64>(c, split);
-    if (cch == 32) return conv_off1<T, 32>(c, split);
+    if (cch == 64) return conv_off1<T, 64>(c, split, pb);
+    if (cch == 32) return conv_off1<T, 32>(c, split, pb);
     return hipErrorInvalidValue;
   }
   if (cch == 64) return conv_bulk<T, 64>(c, epi, pb);
@@ -1235,8 +1254,8 @@ hipError_t conv_dispatch(const PackedConv& P, int role, int epi, int tin, int pb
   if (role == CONV_OFF2) {
     if (tin != DT_F32 || (P.tc != DT_F32 && !split)) return hipErrorInvalidValue;
     const int cch = split ? P.cin / 2 : P.cin;   // split: packed over [hi | lo] chunks
-    if (cch == 64) return conv_off2<64>(c, split);
-    if (cch == 32) return conv_off2<32>(c, split);
+    if (cch == 64) return conv_off2<64>(c, split, pb);
+    if (cch == 32) return conv_off2<32>(c, split, pb);
     return hipErrorInvalidValue;
   }
   if (P.tc == DT_F8) {
@@ -1244,7 +1263,7 @@ hipError_t conv_dispatch(const PackedConv& P, int role, int epi, int tin, int pb
     return conv_bulk<f8, 64>(c, epi, pb);
   }
   const int cch = role == CONV_OFF1 ? P.cin / 2 : P.cin;
-  if (role == CONV_OFF1 && ((P.tc != DT_F32 && !split) || pb != 2)) return hipErrorInvalidValue;
+  if (role == CONV_OFF1 && P.tc != DT_F32 && !split) return hipErrorInvalidValue;
   if (role != CONV_OFF1 && P.tc != tin) return hipErrorInvalidValue;
   switch (tin) {
     case DT_F32: return conv_any<float>(c, epi, role, cch, pb, split);
@@ -1377,8 +1396,16 @@ hipError_t hr_dispatch(const PackedConv& P, int tu, const HrImg* im, const HrImg
 }  // namespace
 
 int conv_ob(int role, int epi, int obtot, int tc, int tile) {
-  if (role == CONV_OFF2) return obtot % 7 == 0 ? 7 : (obtot % 4 == 0 ? 4 : 1);
-  if (role == CONV_OFF1) return obtot % 4 == 0 ? 4 : 2;
+  const bool split = tc == DT_F16;
+  const int pb = tile_pb(tile), wo = tile_wo(tile);
+  if (role == CONV_OFF2) {
+    if (split && (wo == 2 || pb == 4)) return 2;
+    return obtot % 7 == 0 ? 7 : (obtot % 4 == 0 ? 4 : 1);
+  }
+  if (role == CONV_OFF1) {
+    if (split && pb == 4) return 2;
+    return obtot % 4 == 0 ? 4 : 2;
+  }
   if (tile_lw(tile)) return 4;
   if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : 8;
   return obtot % 4 == 0 ? 4 : 2;
