@@ -25,6 +25,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# HBM bytes per launch of the FP32 residual-block conv (the two launch kinds of a block
+# averaged, as the kernel timing is), from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+# scaled by a plain device copy's readings (x2.00 and x1.00); the command lines and the
+# per-kernel table are in profiles/c2_fp32_hbm_traffic.md.  Valid for the kernel source
+# the counters were taken on; retake them after changing it.
+FP32_CONV_BLOCK_TRAFFIC = {
+    "first conv (LReLU)": {"fetch_kib": 69530, "write_kib": 130560},
+    "second conv (+ skip)": {"fetch_kib": 135344, "write_kib": 130560},
+    "fetch_scale": 2.00, "write_scale": 1.00,
+}
+
+
+def conv_block_traffic():
+    t = FP32_CONV_BLOCK_TRAFFIC
+    kinds = [v for v in t.values() if isinstance(v, dict)]
+    per = [1024 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) for k in kinds]
+    return sum(per) / len(per)
+
+
 PEAKS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp8-fusion": 5000.0}   # dense TFLOP/s
 HBM_PEAK_GBS = 8000.0
 
@@ -100,6 +119,13 @@ def device_copy_gbs(torch, mib=1024, reps=10):
     s = e0.elapsed_time(e1) / 1000.0 / reps
     del a, b
     return round(2 * mib * (1 << 20) / s / 1e9, 1)
+
+
+def conv_block_bytes(hp, wp, C, elem=4):
+    """Algorithmic HBM bytes of a residual-block conv launch, the two kinds averaged: the
+    first reads its input and writes its output, the second also reads the skip."""
+    m = hp * wp * C * elem
+    return (2 * m + 3 * m) // 2
 
 
 def group_flops_per_px(C, R, G):
@@ -438,7 +464,11 @@ def main():
                    "cuts_detected": [t for t, c in enumerate(cuts) if c]},
         "roofline": {"bound": "mfma", "kernel": f"{dom} ({'3x3 conv 64->64' if dom == 'conv_block' else dom})",
                      "achieved": achieved, "peak": PEAKS[args.precision], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAKS[args.precision], 4), "traffic": None,
+                     "frac": round(achieved / PEAKS[args.precision], 4),
+                     "traffic": (round(conv_block_traffic()) if args.precision == "fp32" and dom == "conv_block"
+                                 else None),
+                     "traffic_algorithmic": (conv_block_bytes(hp, wp, cfg.channels) if dom == "conv_block"
+                                             else None),
                      "flop_per_launch": dom_work, "avg_launch_us": kernels[dom]["avg_us"]},
         "path": {"tflop_per_step": round(path_flop / 1e12, 2),
                  "tflops": round(path_flop / (ms / 1000.0) / 1e12, 2),
