@@ -281,7 +281,9 @@ nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* stream, cha
 /* Kinds of launches the library times when profiling is on. */
 enum {
   NV_K_UNPACK = 0, NV_K_SCENE = 1, NV_K_CONV_IN = 2, NV_K_CONV_BLOCK = 3, NV_K_OFF1 = 4,
-  NV_K_OFF2 = 5, NV_K_DCN = 6, NV_K_UP = 7, NV_K_HR = 8, NV_K_PACK = 9, NV_K_COUNT = 10
+  NV_K_OFF2 = 5, NV_K_DCN = 6, NV_K_UP = 7, NV_K_HR = 8, NV_K_PACK = 9,
+  NV_K_RESBLOCK = 10,   /* both convs of a residual block in one launch (16-bit maps, C = 64) */
+  NV_K_COUNT = 11
 };
 
 /* on != 0: from now on every launch the context makes (including those of its streams)

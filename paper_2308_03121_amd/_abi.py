@@ -79,7 +79,7 @@ _SIGS = {
     "nv_calibrate": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), c_int32, c_void_p]),
     "nv_fp8_scales": (c_int32, [c_void_p, PF, c_int32, c_int32, c_void_p]),
 }
-NV_K_COUNT = 10
+NV_K_COUNT = 11
 
 _lib = None
 

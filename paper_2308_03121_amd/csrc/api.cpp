@@ -209,6 +209,7 @@ struct Profiler {
 struct Tuning {
   int pb_block = 2, pb_up = 2, pb_dcn = 2;
   int off1 = 2, off2 = 2;   // offset-head tile codes (split head: three shapes)
+  int fused = 0;            // residual blocks as one launch where supported (1) or as two
 };
 
 struct BatchState;
@@ -660,14 +661,34 @@ nv_status calib_layer(nv_context* ctx, int l, std::initializer_list<const void*>
                       "qscale");
 }
 
+// Whether the residual blocks run as one launch each: 16-bit maps with 64 channels and
+// the tuner's choice; FP8 blocks and calibration passes use the separate convs.
+static bool resblocks_fused(const nv_context* ctx) {
+  return ctx->tune.fused && !ctx->calibrating && !ctx->blocks.empty() &&
+         resblock_supported(ctx->blocks[0], ctx->blocks[1], ctx->ft);
+}
+
 nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
   NV_TRY(ensure_workspace(ctx, hp, wp));
   const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
   NV_TRY(timed(ctx, NV_K_CONV_IN, s, "conv_in",
                [&] { return launch_conv_in(ctx->conv_in, ft, rgb, feat, hp, wp, s); }));
+  const size_t n = (size_t)hp * wp * C;
+  if (resblocks_fused(ctx)) {
+    // ping-pong between feat and the workspace map; an odd block count ends with a copy
+    void* a = feat;
+    void* b = ctx->ws.t0;
+    for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
+      const ConvImg im = conv_img(a, nullptr, nullptr, nullptr, nullptr, nullptr, b, hp, wp);
+      NV_TRY(timed(ctx, NV_K_RESBLOCK, s, "resblock",
+                   [&] { return launch_resblock(ctx->blocks[2 * r], ctx->blocks[2 * r + 1], ft, im, s); }));
+      std::swap(a, b);
+    }
+    if (a != feat) HIP_TRY(hipMemcpyAsync(feat, a, n * dtype_bytes(ft), hipMemcpyDeviceToDevice, s));
+    return NV_OK;
+  }
   const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->ws.t0, hp, wp);
   const ConvImg ib = conv_img(ctx->ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
-  const size_t n = (size_t)hp * wp * C;
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
     if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r, {feat}, n, s));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.a", [&] {
@@ -1710,9 +1731,9 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     if (FILE* f = fopen(cache, "r")) {
       char line[256];
       while (fgets(line, sizeof line, f)) {
-        int a = 0, b = 0, c = 0, d = 2, e = 2;
+        int a = 0, b = 0, c = 0, d = 2, e = 2, fz = 0;
         char k2[128];
-        if (sscanf(line, "%127[^|]| %d %d %d %d %d", k2, &a, &b, &c, &d, &e) >= 4) {
+        if (sscanf(line, "%127[^|]| %d %d %d %d %d %d", k2, &a, &b, &c, &d, &e, &fz) >= 4) {
           std::string ks(k2);
           while (!ks.empty() && ks.back() == ' ') ks.pop_back();
           if (ks == key && a > 0 && b > 0 && c > 0 && d > 0 && e > 0) {
@@ -1721,6 +1742,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
             ctx->tune.pb_dcn = c;
             ctx->tune.off1 = d;
             ctx->tune.off2 = e;
+            ctx->tune.fused = fz != 0;
             found = true;
           }
         }
@@ -1817,10 +1839,27 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
       snprintf(buf, sizeof buf, " -> %s; ", tile_name(best_pb).c_str());
       rep += buf;
     }
+    // residual block: one fused launch against the two convs with the chosen tile
+    if (!ctx->blocks.empty() && resblock_supported(ctx->blocks[0], ctx->blocks[1], ft)) {
+      float t_fused = 0.0f, t_pair = 0.0f;
+      const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
+      NV_TRY(time_launch(s, 3, &t_fused, [&] { return launch_resblock(ctx->blocks[0], ctx->blocks[1], ft, im, s); }));
+      const ConvImg ia = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
+      const ConvImg ib = conv_img(ws.t0, nullptr, nullptr, nullptr, nullptr, ws.feat[0], ws.u, hp, wp);
+      NV_TRY(time_launch(s, 3, &t_pair, [&] {
+        const hipError_t e = launch_conv(ctx->blocks[0], CONV_BULK, EPI_LRELU, ft, ctx->tune.pb_block, ia, C, 0, s);
+        if (e != hipSuccess) return e;
+        return launch_conv(ctx->blocks[1], CONV_BULK, EPI_RES, ft, ctx->tune.pb_block, ib, C, 0, s);
+      }));
+      ctx->tune.fused = t_fused < t_pair;
+      snprintf(buf, sizeof buf, "resblock: fused=%.1fus pair=%.1fus -> %s; ", 1000.0f * t_fused, 1000.0f * t_pair,
+               ctx->tune.fused ? "fused" : "pair");
+      rep += buf;
+    }
     if (cache) {
       if (FILE* f = fopen(cache, "a")) {
-        fprintf(f, "%s | %d %d %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn,
-                ctx->tune.off1, ctx->tune.off2);
+        fprintf(f, "%s | %d %d %d %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn,
+                ctx->tune.off1, ctx->tune.off2, ctx->tune.fused);
         fclose(f);
       }
     }
@@ -1829,9 +1868,10 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     rep += key;
   }
   char tail[160];
-  snprintf(tail, sizeof tail, " [block %s, up %s, dcn pb%d, off1 %s, off2 %s; LDS limit %d]",
-           tile_name(ctx->tune.pb_block).c_str(), tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn,
-           tile_name(ctx->tune.off1).c_str(), tile_name(ctx->tune.off2).c_str(), lds_limit());
+  snprintf(tail, sizeof tail, " [block %s%s, up %s, dcn pb%d, off1 %s, off2 %s; LDS limit %d]",
+           tile_name(ctx->tune.pb_block).c_str(), resblocks_fused(ctx) ? " (fused blocks)" : "",
+           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn, tile_name(ctx->tune.off1).c_str(),
+           tile_name(ctx->tune.off2).c_str(), lds_limit());
   rep += tail;
   if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
     HIP_TRY(hipDeviceSynchronize());
@@ -1844,8 +1884,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
 
 // ----------------------------------------------------------- kernel timing ----
 
-static const char* const kKindNames[NV_K_COUNT] = {"unpack", "scene", "conv_in", "conv_block", "off1",
-                                                   "off2",   "dcn",   "up",      "hr",         "pack"};
+static const char* const kKindNames[NV_K_COUNT] = {"unpack", "scene", "conv_in", "conv_block", "off1", "off2",
+                                                   "dcn",    "up",    "hr",      "pack",       "resblock"};
 
 extern "C" const char* nv_profile_kind_name(int32_t kind) {
   return kind >= 0 && kind < NV_K_COUNT ? kKindNames[kind] : "";

@@ -401,6 +401,153 @@ __global__ __launch_bounds__(256) void k_conv3x3_batch(ConvLayer L, const ConvIm
   }
 }
 
+// ---- residual block as one kernel (16-bit maps, C = 64) ----
+// A workgroup of eight waves produces a 16 x 16 tile of y = x + conv_b(LReLU(conv_a(x))).
+// It stages x over the tile and a 2-pixel halo (20 x 20), computes the first conv over
+// the tile and a 1-pixel halo (18 x 18 = 324 pixels, taken in 21 groups of 16 in
+// row-major order, so the B operand's 16 pixels need not share a row) and keeps it in
+// registers until every wave is done with the staged x, then writes it, LReLU-ed and
+// rounded to the storage type, over the same LDS (zero outside the image: the second
+// conv's zero padding), and runs the second conv over the tile; the skip is read from
+// x in global memory.  Each output accumulates in the same order and rounds at the
+// same points as the two separate launches, so the results are bit-identical to them.
+// HBM traffic drops from ~5 map transfers per block to 2, for 21/16 of the first conv's
+// MFMA work.
+constexpr int kRbT = 16, kRbI = kRbT + 2, kRbX = kRbT + 4;
+constexpr int kRbNI = kRbI * kRbI, kRbGA = (kRbNI + 15) / 16;
+
+template <typename TC>
+__global__ __launch_bounds__(512, 4) void k_resblock(ConvLayer La, ConvLayer Lb, ConvImg im) {
+  constexpr int C = 64, LDP = C + 16 / (int)sizeof(TC);
+  constexpr int KG = 32, QE = 8, NCG = 2, NIT = 9 * NCG, OB = 4, PW = 1;
+  constexpr int NGA = (kRbGA + 7) / 8;            // first-conv pixel groups per wave, at most
+  static_assert(kRbX * kRbX >= kRbNI, "the intermediate fits where x was staged");
+  __shared__ __attribute__((aligned(16))) TC lds[kRbX * kRbX * LDP];
+
+  const int tiles_x = (im.W + kRbT - 1) / kRbT;
+  const int ntile = tiles_x * ((im.H + kRbT - 1) / kRbT);
+  const int t = xcd_tile(blockIdx.x, ntile);
+  const int ty0 = (t / tiles_x) * kRbT, tx0 = (t % tiles_x) * kRbT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+  const TC* x = static_cast<const TC*>(im.src0);
+  TC* y = static_cast<TC*>(im.dst);
+
+  // stage x over the tile and its 2-pixel halo (zero outside the image)
+  {
+    constexpr int V = C / 8, NV = kRbX * kRbX * V, SB = 4;
+    for (int i0 = 0; i0 < NV; i0 += SB * 512) {
+      u32x4 rb[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 512 + (int)threadIdx.x;
+        rb[u] = u32x4{0u, 0u, 0u, 0u};
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          const int ly = pix / kRbX, lx = pix - ly * kRbX;
+          const int gy = ty0 + ly - 2, gx = tx0 + lx - 2;
+          if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) rb[u] = ldu4(x + ((size_t)gy * im.W + gx) * C + 8 * v);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 512 + (int)threadIdx.x;
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          stu4(&lds[pix * LDP + 8 * v], rb[u]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // one conv over up to NGA pixel groups per wave: A and B fragments one step ahead,
+  // every step unrolled with a scheduling barrier (registers are kept to 128 so that two
+  // workgroups share a CU)
+  auto conv = [&](const ConvLayer& L, const int (&pbase)[NGA], int ng, int row_stride, f32x4 (&acc)[NGA][OB]) {
+    const u32x4* wbase = L.wfrag + lane;
+    auto fetch_w = [&](int it, u32x4 (&wa)[OB]) {
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[((size_t)it * L.obtot + ob) * 64];
+    };
+    auto fetch_b = [&](int it, u32x4 (&xb)[NGA]) {
+      const int tap = it / NCG, cg = it - tap * NCG;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      const int off = (dy * row_stride + dx) * LDP + KG * cg;
+#pragma unroll
+      for (int k = 0; k < NGA; ++k) xb[k] = ldu4(&lds[pbase[k] + off]);
+    };
+#pragma unroll
+    for (int k = 0; k < NGA; ++k)
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) acc[k][ob] = zero4();
+    u32x4 wq[PW + 1][OB], xq[2][NGA];
+#pragma unroll
+    for (int k = 0; k < PW; ++k) fetch_w(k, wq[k]);
+    fetch_b(0, xq[0]);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      if (it + PW < NIT) fetch_w(it + PW, wq[(it + PW) % (PW + 1)]);
+      if (it + 1 < NIT) fetch_b(it + 1, xq[(it + 1) & 1]);
+#pragma unroll
+      for (int k = 0; k < NGA; ++k)
+        if (k < ng)
+#pragma unroll
+          for (int ob = 0; ob < OB; ++ob) acc[k][ob] = Mma<TC>::step(wq[it % (PW + 1)][ob], xq[it & 1][k], acc[k][ob]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  // first conv: groups wave, wave + 8, wave + 16 of the 324 intermediate pixels
+  const int nga = (kRbGA - wave + 7) / 8;
+  int pa[NGA];
+#pragma unroll
+  for (int k = 0; k < NGA; ++k) {
+    const int i = min(16 * (wave + 8 * k) + j, kRbNI - 1);
+    const int iy = i / kRbI, ix = i - iy * kRbI;
+    pa[k] = (iy * kRbX + ix) * LDP + QE * q;
+  }
+  f32x4 acc[NGA][OB];
+  conv(La, pa, nga, kRbX, acc);
+  __syncthreads();   // every wave is done reading x from LDS
+#pragma unroll
+  for (int k = 0; k < NGA; ++k) {
+    const int i = 16 * (wave + 8 * k) + j;
+    if (k >= nga || i >= kRbNI) continue;
+    const int iy = i / kRbI, ix = i - iy * kRbI;
+    const int gy = ty0 - 1 + iy, gx = tx0 - 1 + ix;
+    const bool inside = gy >= 0 && gy < im.H && gx >= 0 && gx < im.W;
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      const int row = ob * 16 + 4 * q;
+      f32x4 v = acc[k][ob];
+      v += ld4(La.bias + row);
+      store4f<TC>(&lds[i * LDP + row], inside ? lrelu4(v) : zero4());
+    }
+  }
+  __syncthreads();
+
+  // second conv: output rows 2 wave, 2 wave + 1 of the tile
+  int pbb[NGA];
+#pragma unroll
+  for (int k = 0; k < NGA; ++k) pbb[k] = ((2 * wave + min(k, 1)) * kRbI + j) * LDP + QE * q;
+  conv(Lb, pbb, 2, kRbI, acc);
+#pragma unroll
+  for (int pb = 0; pb < 2; ++pb) {
+    const int gy = ty0 + 2 * wave + pb, gx = tx0 + j;
+    if (gy >= im.H || gx >= im.W) continue;
+    const size_t at = ((size_t)gy * im.W + gx) * C;
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      const int row = ob * 16 + 4 * q;
+      f32x4 v = acc[pb][ob];
+      v += ld4(Lb.bias + row);
+      v += load4f<TC>(x + at + row);
+      store4f<TC>(y + at + row, v);
+    }
+  }
+}
+
 // ---- bulk conv with LDS-resident weights (16-bit and FP8 MFMA types) ----
 // Switched off: its first launch on the device stopped in the HIP runtime ("cannot find
 // symbol" for the kernel, 99.6 KB of static LDS, below the device's 160 KB) and no cause
@@ -1455,6 +1602,20 @@ hipError_t launch_conv(const PackedConv& P, int role, int epi, int tin, int pb, 
   const ConvLayer L = make_layer(P, ldy, sig_lo);
   const ConvCall c{L, &im, nullptr, nullptr, s};
   return conv_dispatch(P, role, epi, tin, pb, c);
+}
+
+bool resblock_supported(const PackedConv& A, const PackedConv& Bc, int tin) {
+  return (tin == DT_F16 || tin == DT_BF16) && A.tc == tin && Bc.tc == tin && A.cin == 64 && A.cout == 64 &&
+         Bc.cin == 64 && Bc.cout == 64 && A.obtot == 4 && Bc.obtot == 4;
+}
+
+hipError_t launch_resblock(const PackedConv& A, const PackedConv& Bc, int tin, const ConvImg& im, hipStream_t s) {
+  if (!resblock_supported(A, Bc, tin) || im.src0 == im.dst) return hipErrorInvalidValue;
+  const ConvLayer La = make_layer(A, 64, 0), Lb = make_layer(Bc, 64, 0);
+  const int ntile = ((im.W + kRbT - 1) / kRbT) * ((im.H + kRbT - 1) / kRbT);
+  if (tin == DT_F16) hipLaunchKernelGGL(k_resblock<f16>, dim3(ntile), dim3(512), 0, s, La, Lb, im);
+  else hipLaunchKernelGGL(k_resblock<bf16>, dim3(ntile), dim3(512), 0, s, La, Lb, im);
+  return hipGetLastError();
 }
 
 hipError_t launch_conv_batch(const PackedConv& P, int role, int epi, int tin, int pb,

@@ -193,6 +193,12 @@ bool lds_weight_tiles();   // whether the LDS-resident-weight tiles are enabled
 // Output blocks per workgroup chosen by the conv dispatch for a role / epilogue / MFMA
 // type / tile code.
 int conv_ob(int role, int epi, int obtot, int tc, int tile);
+
+// One residual block, y = x + conv_b(LReLU(conv_a(x))), as one launch (16-bit maps,
+// C = 64); im.src0 = x, im.dst = y (a different buffer), im.H / im.W.  Bit-identical to
+// the two separate bulk-conv launches.
+bool resblock_supported(const PackedConv& A, const PackedConv& Bc, int tin);
+hipError_t launch_resblock(const PackedConv& A, const PackedConv& Bc, int tin, const ConvImg& im, hipStream_t s);
 inline int conv_items(int H, int W, int pb, int nobg) {
   return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
 }
