@@ -332,6 +332,25 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
   out->tc = tc;
   HIP_TRY(hipMalloc(&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
+  // 16-bit types: also the 32x32x16 MFMA A fragments, 16 bytes per lane:
+  //   frag32[((tap * NKG16 + kg) * obtot32 + ob) * 64 + lane]
+  //     = W[o = rowmap(32*ob + lane%32)][c = 16*kg + 8*(lane/32) + e][tap], e < 8
+  if (tc != DT_F32 && cout % 32 == 0 && cin % 16 == 0) {
+    const int ob32 = cout / 32, nkg16 = cin / 16;
+    std::vector<uint8_t> f32x((size_t)9 * nkg16 * ob32 * 64 * 16, 0);
+    for (int tap = 0; tap < 9; ++tap)
+      for (int kg = 0; kg < nkg16; ++kg)
+        for (int ob = 0; ob < ob32; ++ob)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int o = rowmap(32 * ob + lane % 32);
+            const int c0 = 16 * kg + 8 * (lane / 32);
+            put_fragment(&f32x[((((size_t)tap * nkg16 + kg) * ob32 + ob) * 64 + lane) * 16], tc, c0,
+                         [&](int c) { return w[((size_t)o * cin + c) * 9 + tap]; });
+          }
+    HIP_TRY(hipMalloc(&out->frag32, f32x.size()));
+    ctx->allocs.push_back(out->frag32);
+    HIP_TRY(hipMemcpy(out->frag32, f32x.data(), f32x.size(), hipMemcpyHostToDevice));
+  }
   HIP_TRY(dev_alloc(&out->bias, bias.size()));
   ctx->allocs.push_back(out->bias);
   HIP_TRY(hipMemcpy(out->frag, frag.data(), frag.size(), hipMemcpyHostToDevice));
@@ -1692,6 +1711,7 @@ namespace {
 std::string tile_name(int code) {
   char b[32];
   if (tile_lw(code)) snprintf(b, sizeof b, "pb%dlw", tile_pb(code));
+  else if (tile_m32(code)) snprintf(b, sizeof b, "pb%dm32", tile_pb(code));
   else if (tile_wo(code) == 1) snprintf(b, sizeof b, "pb%d", tile_pb(code));
   else snprintf(b, sizeof b, "pb%dw%d", tile_pb(code), tile_wo(code));
   return b;
@@ -1782,11 +1802,19 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
       }
       return t;
     };
+    // 32x32x16 MFMA form for 16-bit convs with 64 input channels
+    std::vector<int> block_tiles = bulk_tiles, up_tiles = bulk_tiles;
+    if (C == 64) {
+      for (int pb : {2, 4}) {
+        if (!ctx->blocks.empty() && ctx->blocks[0].frag32) block_tiles.push_back(tile_code(pb, 1, 0, 1));
+        if (ctx->up.frag32) up_tiles.push_back(tile_code(pb, 1, 0, 1));
+      }
+    }
     struct Cand {
       const char* name;
       int* slot;
       std::vector<int> pbs;
-    } cands[5] = {{"block", &ctx->tune.pb_block, bulk_tiles}, {"up", &ctx->tune.pb_up, bulk_tiles},
+    } cands[5] = {{"block", &ctx->tune.pb_block, block_tiles}, {"up", &ctx->tune.pb_up, up_tiles},
                   {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}},
                   {"off1", &ctx->tune.off1, head_tiles(ctx->off1)}, {"off2", &ctx->tune.off2, head_tiles(ctx->off2)}};
     for (auto& cd : cands) {

@@ -369,6 +369,154 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
   }
 }
 
+// 32x32x16 MFMA form of a bulk conv (16-bit maps, 64 input channels).  One MFMA takes
+// 32 output channels x 32 pixels x 16 reduction indices: twice the work of a 16x16x32
+// MFMA for the same 2 KB of operands, which halves the LDS and L1 bytes per flop.  The
+// workgroup tile is 4 PB rows x 16 pixels as in conv_tile; wave w takes rows
+// [w PB, (w+1) PB) as PB / 2 blocks of 32 pixels (two rows of 16: lane l's column is
+// pixel l % 32 of the block, its quarter of K is channels 8 (l / 32) .. + 7 of the
+// 16-channel group).  A fragments (L.wfrag = the 32-row packing, L.obtot counted in
+// 32-row blocks) are requested two steps ahead, B fragments one step ahead.  Result
+// register v of lane l is output channel 8 (v / 4) + 4 (l / 32) + v % 4 of its block.
+template <typename TC, int OB32, int PB, int EPI>
+__device__ __forceinline__ void conv_tile32(const ConvLayer& L, const ConvImg& im, int ty0, int tx0, int ob0,
+                                            TC* tile) {
+  static_assert(!std::is_same<TC, float>::value && !std::is_same<TC, f8>::value, "16-bit MFMA types");
+  static_assert(PB == 2 || PB == 4, "whole 32-pixel blocks per wave");
+  constexpr int CCH = 64, KG = 16, NCG = CCH / KG, NIT = 9 * NCG, RB = PB / 2, PW = 2;
+  constexpr int LDP = ConvSmem<TC, CCH, PB>::LDP;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 31, h = lane >> 5;
+  const int pr = p >> 4, pc = p & 15;
+
+  const TC* src = static_cast<const TC*>(im.src0);
+  if (im.sel != nullptr && *im.sel != 0u && im.alt0 != nullptr) src = static_cast<const TC*>(im.alt0);
+  {
+    constexpr int V = CCH / 8, NV = (4 * PB + 2) * (kTW + 2) * V, SB = 8;
+    for (int i0 = 0; i0 < NV; i0 += SB * 256) {
+      u32x4 rb[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 256 + (int)threadIdx.x;
+        rb[u] = u32x4{0u, 0u, 0u, 0u};
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          const int ly = pix / (kTW + 2), lx = pix - ly * (kTW + 2);
+          const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+          if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) rb[u] = ldu4(src + ((size_t)gy * im.W + gx) * CCH + 8 * v);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int idx = i0 + u * 256 + (int)threadIdx.x;
+        if (idx < NV) {
+          const int pix = idx / V, v = idx - pix * V;
+          stu4(&tile[pix * LDP + 8 * v], rb[u]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  f32x16 acc[RB][OB32];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int ob = 0; ob < OB32; ++ob)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[rb][ob][v] = 0.0f;
+  const u32x4* wbase = L.wfrag + (size_t)ob0 * 64 + lane;
+  const TC* tbase = &tile[((wave * PB + pr) * (kTW + 2) + pc) * LDP + 8 * h];
+  auto fetch_w = [&](int it, u32x4 (&wa)[OB32]) {
+#pragma unroll
+    for (int ob = 0; ob < OB32; ++ob) wa[ob] = wbase[((size_t)it * L.obtot + ob) * 64];
+  };
+  auto fetch_b = [&](int it, u32x4 (&xb)[RB]) {
+    const int tap = it / NCG, cg = it - tap * NCG;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) xb[rb] = ldu4(tbase + ((2 * rb + dy) * (kTW + 2) + dx) * LDP + KG * cg);
+  };
+  u32x4 wq[PW + 1][OB32], xq[2][RB];
+#pragma unroll
+  for (int k = 0; k < PW; ++k) fetch_w(k, wq[k]);
+  fetch_b(0, xq[0]);
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    if (it + PW < NIT) fetch_w(it + PW, wq[(it + PW) % (PW + 1)]);
+    if (it + 1 < NIT) fetch_b(it + 1, xq[(it + 1) & 1]);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int ob = 0; ob < OB32; ++ob) {
+        if constexpr (std::is_same<TC, f16>::value)
+          acc[rb][ob] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, wq[it % (PW + 1)][ob]),
+                                                               __builtin_bit_cast(f16x8, xq[it & 1][rb]),
+                                                               acc[rb][ob], 0, 0, 0);
+        else
+          acc[rb][ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, wq[it % (PW + 1)][ob]),
+                                                                __builtin_bit_cast(bf16x8, xq[it & 1][rb]),
+                                                                acc[rb][ob], 0, 0, 0);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // epilogue: the same per-channel arithmetic as conv_store, four channels at a time
+  TC* dst = static_cast<TC*>(im.dst);
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int gy = ty0 + wave * PB + 2 * rb + pr, gx = tx0 + pc;
+    if (gy >= im.H || gx >= im.W) continue;
+#pragma unroll
+    for (int ob = 0; ob < OB32; ++ob)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int row = (ob0 + ob) * 32 + 8 * m + 4 * h;     // A row = packed output row
+        f32x4 v = f32x4{acc[rb][ob][4 * m], acc[rb][ob][4 * m + 1], acc[rb][ob][4 * m + 2], acc[rb][ob][4 * m + 3]};
+        v += ld4(L.bias + row);
+        if (EPI == EPI_LRELU) {
+          store4f<TC>(dst + ((size_t)gy * im.W + gx) * L.ldy + row, lrelu4(v));
+        } else if (EPI == EPI_RES) {
+          const size_t at = ((size_t)gy * im.W + gx) * L.ldy + row;
+          v += load4f<TC>(static_cast<const TC*>(im.res) + at);
+          store4f<TC>(dst + at, v);
+        } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g/4) + t at sub-pixel g%4
+          const int g = row >> 4, sp = g & 3, c = 16 * (g >> 2) + (row & 15);
+          const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
+          store4f<TC>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
+        }
+      }
+  }
+}
+
+template <typename TC, int OB32, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv32(ConvLayer L, ConvImg im) {
+  __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, 64, PB>::N];
+  const int tiles_x = (im.W + kTW - 1) / kTW;
+  const int nobg = L.obtot / OB32;
+  const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
+  const int b = xcd_tile(blockIdx.x, ntile * nobg);
+  const int t = b / nobg, obg = b - t * nobg;
+  conv_tile32<TC, OB32, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, obg * OB32, tile);
+}
+
+template <typename TC, int OB32, int PB, int EPI>
+__global__ __launch_bounds__(256) void k_conv32_batch(ConvLayer L, const ConvImg* __restrict__ jobs,
+                                                      const int* __restrict__ count) {
+  __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, 64, PB>::N];
+  const int njobs = count[0], total = count[1];
+  const int nobg = L.obtot / OB32;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const ConvImg im = jobs[find_job(jobs, njobs, item)];
+    const int local = item - im.item_begin;
+    const int t = local / nobg, obg = local - t * nobg;
+    const int tiles_x = (im.W + kTW - 1) / kTW;
+    conv_tile32<TC, OB32, PB, EPI>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, obg * OB32, tile);
+    __syncthreads();
+  }
+}
+
 template <typename TIN, typename TC, typename TOUT, int CCH, int NCHUNK, int OB, int PB, int EPI, int SPLIT, int WO>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvLayer L, ConvImg im) {
   __shared__ __attribute__((aligned(16))) TC tile[ConvSmem<TC, CCH, PB>::N];
@@ -1318,6 +1466,31 @@ int bulk_lds_bytes(int tile) {
 // Residual-block convs and the pixel-shuffle conv: storage and MFMA in T; tile is a
 // tile code (rows per wave, waves along the output blocks, LDS-resident weights).
 // A tile whose LDS exceeds the device's per-workgroup limit is refused, not launched.
+template <typename TC, int OB32, int PB, int EPI>
+hipError_t run_conv32(const ConvCall& c) {
+  if (c.L.obtot % OB32 != 0) return hipErrorInvalidValue;
+  if (c.im) {
+    const int ntile = ((c.im->W + kTW - 1) / kTW) * ((c.im->H + 4 * PB - 1) / (4 * PB));
+    hipLaunchKernelGGL((k_conv32<TC, OB32, PB, EPI>), dim3(ntile * (c.L.obtot / OB32)), dim3(256), 0, c.s, c.L,
+                       *c.im);
+  } else {
+    hipLaunchKernelGGL((k_conv32_batch<TC, OB32, PB, EPI>), dim3(kBatchGrid), dim3(256), 0, c.s, c.L, c.jobs,
+                       c.count);
+  }
+  return hipGetLastError();
+}
+
+// 32x32 form: c.L carries the 32-row fragments with obtot in 32-row blocks.
+template <typename TC, int PB>
+hipError_t conv32_pb(const ConvCall& c, int epi) {
+  switch (epi) {
+    case EPI_LRELU: return run_conv32<TC, 2, PB, EPI_LRELU>(c);
+    case EPI_RES: return run_conv32<TC, 2, PB, EPI_RES>(c);
+    case EPI_SHUFFLE: return run_conv32<TC, PB == 2 ? 4 : 2, PB, EPI_SHUFFLE>(c);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int CCH>
 hipError_t conv_bulk(const ConvCall& c, int epi, int tile) {
   const int pb = tile_pb(tile), wo = tile_wo(tile);
@@ -1327,6 +1500,14 @@ hipError_t conv_bulk(const ConvCall& c, int epi, int tile) {
     if constexpr (!std::is_same<T, float>::value && CCH == 64) {
       if (pb == 2) return conv_lw<T, 2>(c, epi);
       if (pb == 4) return conv_lw<T, 4>(c, epi);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (tile_m32(tile)) {
+    if constexpr (!std::is_same<T, float>::value && !std::is_same<T, f8>::value && CCH == 64) {
+      if (wo != 1) return hipErrorInvalidValue;
+      if (pb == 2) return conv32_pb<T, 2>(c, epi);
+      if (pb == 4) return conv32_pb<T, 4>(c, epi);
     }
     return hipErrorInvalidValue;
   }
@@ -1408,6 +1589,18 @@ hipError_t conv_dispatch(const PackedConv& P, int role, int epi, int tin, int pb
   if (P.tc == DT_F8) {
     if (role != CONV_BULK || tin != DT_F16 || P.cin != 64 || !P.oscale || !P.ainv) return hipErrorInvalidValue;
     return conv_bulk<f8, 64>(c, epi, pb);
+  }
+  if (role == CONV_BULK && tile_m32(pb)) {
+    if (!P.frag32 || P.tc != tin) return hipErrorInvalidValue;
+    ConvLayer L32 = c.L;
+    L32.wfrag = reinterpret_cast<const u32x4*>(P.frag32);
+    L32.obtot = P.cout / 32;
+    const ConvCall c32{L32, c.im, c.jobs, c.count, c.s};
+    switch (tin) {
+      case DT_F16: return conv_bulk<f16, 64>(c32, epi, pb);
+      case DT_BF16: return conv_bulk<bf16, 64>(c32, epi, pb);
+    }
+    return hipErrorInvalidValue;
   }
   const int cch = role == CONV_OFF1 ? P.cin / 2 : P.cin;
   if (role == CONV_OFF1 && P.tc != DT_F32 && !split) return hipErrorInvalidValue;
@@ -1554,6 +1747,7 @@ int conv_ob(int role, int epi, int obtot, int tc, int tile) {
     return obtot % 4 == 0 ? 4 : 2;
   }
   if (tile_lw(tile)) return 4;
+  if (tile_m32(tile)) return epi == EPI_SHUFFLE ? (pb == 2 ? 8 : 4) : 4;   // in 16-row blocks
   if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : 8;
   return obtot % 4 == 0 ? 4 : 2;
 }

@@ -114,6 +114,7 @@ inline int dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_F8 ? 1 : 2)
 // setup (captured graphs read the current values).
 struct PackedConv {
   void* frag = nullptr;    // device
+  void* frag32 = nullptr;  // device, 32-row fragments for the 32x32 MFMA form (16-bit bulk convs)
   float* bias = nullptr;   // device, obtot*16 floats
   float* oscale = nullptr; // device, obtot*16 floats (FP8 only)
   float* ainv = nullptr;   // device scalar (FP8 only)
@@ -179,10 +180,15 @@ struct HrImg {
 // 1/wo of the workgroup's output blocks), and lw: the persistent form that keeps a
 // 64-channel output group's weights in LDS (16-bit and FP8, pb 2 or 4, wo 1), packed
 // in one int.
-inline int tile_code(int pb, int wo, int lw = 0) { return pb | ((wo - 1) << 8) | (lw << 12); }
+inline int tile_code(int pb, int wo, int lw = 0, int m32 = 0) {
+  return pb | ((wo - 1) << 8) | (lw << 12) | (m32 << 13);
+}
 inline int tile_pb(int code) { return code & 0xFF; }
 inline int tile_wo(int code) { return 1 + ((code >> 8) & 0xF); }
 inline int tile_lw(int code) { return (code >> 12) & 1; }
+// m32: 32x32x16 MFMA form (16-bit bulk convs with 64 input channels): each wave takes
+// pb rows as pb / 2 blocks of 32 pixels (two rows of 16), pb = 2 or 4, wo = 1.
+inline int tile_m32(int code) { return (code >> 13) & 1; }
 
 // Static LDS of a bulk conv tile (MFMA type tc, cch input channels), and the current
 // device's per-workgroup LDS limit; tiles above the limit are refused by the dispatch.

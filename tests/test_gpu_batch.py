@@ -213,6 +213,26 @@ def test_fused_residual_blocks_bit_identical(B, prec, tmp_path, monkeypatch):
     ctx.close()
 
 
+def test_m32_tiles_batch_bit_identical(B, tmp_path, monkeypatch):
+    """With the 32x32x16 MFMA tiles (forced through the tuner's cache file) the batched
+    launches give the same bits as the per-stream launches."""
+    say("m32 tiles batch vs streams")
+    cfg = synth.NetConfig(64, 1, 8)
+    blob = synth.gen_weights(cfg, seed=10)
+    clips = _clips()
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"prec=1 C=64 R=1 size=64x48 | {2 | (1 << 13)} {4 | (1 << 13)} 1 2 2 0\n")
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision="fp16")
+    monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+    rep = ctx.autotune(48, 64)
+    monkeypatch.delenv("NNVISR_TUNE_CACHE")
+    assert "from cache" in rep and "m32" in rep, rep
+    ref = _per_stream(B, ctx, clips, dev)
+    _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
+    ctx.close()
+
+
 @pytest.mark.skip(reason="the LDS-resident-weight conv tile stopped in the HIP runtime on its first launch "
                          "(kernel symbol not found) and no cause has been found in the code yet; the tile is "
                          "switched off in the library and kept off the GPU until one is shown")

@@ -65,6 +65,44 @@ def test_network_16bit_against_oracle(B, prec, cfg, hp, wp):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("pb", [2, 4])
+def test_network_m32_tiles_against_oracle(B, prec, pb, tmp_path, monkeypatch):
+    """The 32x32x16 MFMA form of the residual-block and pixel-shuffle convs (forced
+    through the tuner's cache file) against the FP64 oracle, same bars as above."""
+    say(f"m32 tiles {prec} pb{pb}")
+    cfg = synth.NetConfig(64, 4, 8)
+    blob = synth.gen_weights(cfg, seed=1)
+    W = oracle_weights(cfg, blob)
+    code = {"fp16": 1, "bf16": 2}[prec]
+    m32 = pb | (1 << 13)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"prec={code} C=64 R=4 size=64x48 | {m32} {m32} 1 2 2 0\n")
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+    rep = ctx.autotune(48, 64)
+    monkeypatch.delenv("NNVISR_TUNE_CACHE")
+    assert "from cache" in rep and f"block pb{pb}m32" in rep and f"up pb{pb}m32" in rep, rep
+    hp, wp = 40, 72
+    rng = np.random.default_rng(hp + wp)
+    rgb_a = rng.uniform(0, 1, (3, hp, wp)).astype(np.float32)
+    rgb_b = np.clip(rgb_a + rng.normal(0, 0.05, rgb_a.shape), 0, 1).astype(np.float32)
+    ta, tb = torch.from_numpy(rgb_a).cuda(), torch.from_numpy(rgb_b).cuda()
+    fa, fb = ctx.extract(ta), ctx.extract(tb)
+    hr, _, _ = ctx.fuse(ta, tb, fa, fb, 7)
+    torch.cuda.synchronize()
+    ra, rb = rgb_a.astype(np.float64), rgb_b.astype(np.float64)
+    ofa, ofb = network.extract(ra, W, cfg.res_blocks), network.extract(rb, W, cfg.res_blocks)
+    full = network.fuse(ra, rb, ofa, ofb, W, cfg.offset_groups)
+    print(f"  feature max-abs {max_abs(nhwc_to_chw(fa), ofa):.2e}", flush=True)
+    for t, key in enumerate((0.0, 0.5, 1.0)):
+        got = hr[t].cpu().numpy()
+        err, p = max_abs(got, full[key]), pipeline.psnr_float(full[key], got)
+        print(f"  t={key}: HR max-abs {err:.2e}, PSNR {p:.1f} dB", flush=True)
+        assert err <= HR_TOL[prec] and p >= PSNR_MIN, (key, err, p)
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16", "fp8"])
 @pytest.mark.parametrize("head_fp32", [False, True], ids=["split-head", "fp32-head"])
 def test_offset_head_is_float_class(B, prec, head_fp32):
