@@ -102,6 +102,46 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
 // channels 32 (q % 2) .. +32.  The fifth step pairs tap 8 with a zero-weight tap (its
 // lanes read tap 8's samples again, which are finite).  The accumulator is rescaled
 // by s_w[row] x s_act in the epilogue.
+// Epilogue through LDS for a 16-bit tile holding all 64 output channels: each wave
+// writes bias-added, activated (or skip-added, in float as in conv_store) results into
+// the LDS tile in the storage type, then the workgroup copies whole pixels out.  The
+// arithmetic and rounding are conv_store's, so the results are bit-identical.
+template <typename TC, int OBW, int RW, int PB, int EPI>
+__device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[RW][OBW],
+                                                  int ty0, int tx0, int wr, int wo, TC* tile) {
+  constexpr int C = 64, OLDP = C + 16 / (int)sizeof(TC), TH = 4 * PB;
+  static_assert(TH * kTW * OLDP <= ConvSmem<TC, C, PB>::N, "the output tile fits in the input tile's LDS");
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, j = lane & 15;
+  __syncthreads();   // every wave is done reading the input tile
+#pragma unroll
+  for (int pb = 0; pb < RW; ++pb) {
+    const int r = wr * RW + pb, gy = ty0 + r, gx = tx0 + j;
+    const bool inside = gy < im.H && gx < im.W;
+#pragma unroll
+    for (int ob = 0; ob < OBW; ++ob) {
+      const int row = (wo * OBW + ob) * 16 + 4 * q;
+      f32x4 v = acc[pb][ob];
+      v += ld4(L.bias + row);
+      if (EPI == EPI_LRELU) {
+        v = lrelu4(v);
+      } else if (inside) {
+        v += load4f<TC>(static_cast<const TC*>(im.res) + ((size_t)gy * im.W + gx) * C + row);
+      }
+      store4f<TC>(&tile[(r * kTW + j) * OLDP + row], v);
+    }
+  }
+  __syncthreads();
+  TC* dst = static_cast<TC*>(im.dst);
+  constexpr int NCHK = TH * kTW * (C / 8);
+#pragma unroll
+  for (int idx = (int)threadIdx.x; idx < NCHK; idx += 256) {
+    const int px = idx >> 3, ck = idx & 7;
+    const int gy = ty0 + px / kTW, gx = tx0 + px % kTW;
+    if (gy < im.H && gx < im.W) stu4(dst + ((size_t)gy * im.W + gx) * C + 8 * ck, ldu4(&tile[px * OLDP + 8 * ck]));
+  }
+}
+
 template <int OB, int PB, int EPI, int WO>
 __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& im, int ty0, int tx0, int obase,
                                              f8* tile) {
@@ -365,6 +405,18 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
     }
   }
 
+  // 16-bit maps whose workgroup holds all 64 output channels of its pixels: the results
+  // go through the (now idle) LDS tile so that each wave stores whole 128-byte pixels,
+  // one contiguous kilobyte per instruction, instead of 32-byte pieces of sixteen
+  constexpr bool kStaged = !std::is_same<TC, float>::value && std::is_same<TIN, TC>::value &&
+                           std::is_same<TOUT, TC>::value && SPLIT == 0 && NCHUNK == 1 && CCH == 64 && OB == 4 &&
+                           (EPI == EPI_LRELU || EPI == EPI_RES);
+  if constexpr (kStaged) {
+    if (L.obtot == OB && L.ldy == 16 * OB) {
+      conv_store_staged<TC, OBW, RW, PB, EPI>(L, im, acc, ty0, tx0, wr, wo, tile);
+      return;
+    }
+  }
   conv_store<TOUT, OBW, RW, EPI>(L, im, acc, ty0 + wr * RW, tx0, obase + wo * OBW, SPLIT ? L.oscale : nullptr);
   }
 }
