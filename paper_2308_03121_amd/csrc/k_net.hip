@@ -80,10 +80,19 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
         v += load4f<TOUT>(static_cast<const TOUT*>(im.res) + at);
         store4f<TOUT>(dst + at, v);
       } else if (EPI == EPI_OFFSET) {
+        if (row + 4 <= L.cout && (L.sig_lo & 3) == 0) {
+          // whole group of four channels: offsets, or mask logits through the sigmoid
+          if (row >= L.sig_lo) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = row + r;
-          if (o < L.cout) dst[at + r] = (TOUT)(o >= L.sig_lo ? sigmoidf(v[r]) : v[r]);
+            for (int r = 0; r < 4; ++r) v[r] = sigmoidf(v[r]);
+          }
+          store4f<TOUT>(dst + at, v);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int o = row + r;
+            if (o < L.cout) dst[at + r] = (TOUT)(o >= L.sig_lo ? sigmoidf(v[r]) : v[r]);
+          }
         }
       } else {  // EPI_SHUFFLE: A row 16*ob + t is channel 16*(ob/4) + t at sub-pixel ob%4
         const int obg = obase + ob;
@@ -102,10 +111,11 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
 // channels 32 (q % 2) .. +32.  The fifth step pairs tap 8 with a zero-weight tap (its
 // lanes read tap 8's samples again, which are finite).  The accumulator is rescaled
 // by s_w[row] x s_act in the epilogue.
-// Epilogue through LDS for a 16-bit tile holding all 64 output channels: each wave
-// writes bias-added, activated (or skip-added, in float as in conv_store) results into
-// the LDS tile in the storage type, then the workgroup copies whole pixels out.  The
-// arithmetic and rounding are conv_store's, so the results are bit-identical.
+// Epilogue through LDS for a tile holding all 64 output channels: each wave writes
+// bias-added, activated (or skip-added, in float as in conv_store) results into the
+// LDS tile in the storage type, then the workgroup copies whole pixels out in 16-byte
+// pieces.  The arithmetic and rounding are conv_store's, so the results are
+// bit-identical.
 template <typename TC, int OBW, int RW, int PB, int EPI>
 __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[RW][OBW],
                                                   int ty0, int tx0, int wr, int wo, TC* tile) {
@@ -133,12 +143,13 @@ __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const Conv
   }
   __syncthreads();
   TC* dst = static_cast<TC*>(im.dst);
-  constexpr int NCHK = TH * kTW * (C / 8);
+  constexpr int E = 16 / (int)sizeof(TC), NPC = C / E;      // elements per piece, pieces per pixel
+  constexpr int NCHK = TH * kTW * NPC;
 #pragma unroll
   for (int idx = (int)threadIdx.x; idx < NCHK; idx += 256) {
-    const int px = idx >> 3, ck = idx & 7;
+    const int px = idx / NPC, ck = idx - px * NPC;
     const int gy = ty0 + px / kTW, gx = tx0 + px % kTW;
-    if (gy < im.H && gx < im.W) stu4(dst + ((size_t)gy * im.W + gx) * C + 8 * ck, ldu4(&tile[px * OLDP + 8 * ck]));
+    if (gy < im.H && gx < im.W) stu4(dst + ((size_t)gy * im.W + gx) * C + E * ck, ldu4(&tile[px * OLDP + E * ck]));
   }
 }
 
@@ -405,12 +416,11 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
     }
   }
 
-  // 16-bit maps whose workgroup holds all 64 output channels of its pixels: the results
-  // go through the (now idle) LDS tile so that each wave stores whole 128-byte pixels,
-  // one contiguous kilobyte per instruction, instead of 32-byte pieces of sixteen
-  constexpr bool kStaged = !std::is_same<TC, float>::value && std::is_same<TIN, TC>::value &&
-                           std::is_same<TOUT, TC>::value && SPLIT == 0 && NCHUNK == 1 && CCH == 64 && OB == 4 &&
-                           (EPI == EPI_LRELU || EPI == EPI_RES);
+  // a workgroup that holds all 64 output channels of its pixels: the results go through
+  // the (now idle) LDS tile so that each wave stores whole pixels, one contiguous
+  // kilobyte per instruction, instead of 32- or 64-byte pieces of sixteen pixels
+  constexpr bool kStaged = std::is_same<TIN, TC>::value && std::is_same<TOUT, TC>::value && SPLIT == 0 &&
+                           NCHUNK == 1 && CCH == 64 && OB == 4 && (EPI == EPI_LRELU || EPI == EPI_RES);
   if constexpr (kStaged) {
     if (L.obtot == OB && L.ldy == 16 * OB) {
       conv_store_staged<TC, OBW, RW, PB, EPI>(L, im, acc, ty0, tx0, wr, wo, tile);
