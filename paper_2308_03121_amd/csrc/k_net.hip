@@ -1045,48 +1045,142 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
   auto piece = [](int c, int v4) { return ROT ? ((v4 + (c >> 1)) & 3) : v4; };
   const TC* sbase = ROT ? &S[((wave * PB) * kTW + j) * LDS_P] : &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
 
+  // gather: item = (pixel, chunk in phase, tap), tap fastest; S[p][(gi*9 + tap)*CW + c].
+  // A thread takes U items per round.  Each item always reads its four corners
+  // (coordinates clamped into the map); a corner outside the map, or a pixel outside
+  // the image, gets weight 0.  The rounds are software-pipelined: round r + 1's offsets
+  // are loaded while round r's corner loads are in flight, and the next phase's first
+  // offsets while the current phase's MFMAs run, so the two dependent global loads of
+  // an item (offsets, then corners) do not both wait in every round.
+  constexpr int NITEM = NPX * GP * 9;
+  constexpr int U = 1;
+  constexpr int NR = (NITEM + U * 256 - 1) / (U * 256);
+  constexpr int NV8 = CW / 8;
+  static_assert(CW % 8 == 0 || CW % 4 == 0, "chunks of 4 or 8 channels");
+  struct ItemPos {
+    int tap, gi, p, u, g, gy, gx;
+    bool inside;
+  };
+  auto item_pos = [&](int item) {
+    ItemPos ip;
+    ip.tap = item % 9;
+    const int rest = item / 9;
+    ip.gi = rest % GP;
+    ip.p = rest / GP;
+    ip.gy = ty0 + ip.p / kTW;
+    ip.gx = tx0 + (ip.p % kTW);
+    ip.inside = ip.gy < im.H && ip.gx < im.W;
+    return ip;
+  };
+  auto load_offs = [&](int ph, int r, float (&od)[U][3]) {
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      const int item = r * U * 256 + uu * 256 + (int)threadIdx.x;
+      od[uu][0] = od[uu][1] = od[uu][2] = 0.0f;
+      if (item >= NITEM) continue;
+      const ItemPos ip = item_pos(item);
+      const int u = ph * GP + ip.gi, g = u / NCH;
+      const float* orow = im.offs + ((size_t)min(ip.gy, im.H - 1) * im.W + min(ip.gx, im.W - 1)) * L.ldo;
+      od[uu][0] = orow[2 * (9 * g + ip.tap)];
+      od[uu][1] = orow[2 * (9 * g + ip.tap) + 1];
+      od[uu][2] = ip.inside ? orow[18 * G + 9 * g + ip.tap] : 0.0f;
+    }
+  };
+  float od_next[U][3];
+  load_offs(0, 0, od_next);
+
   for (int ph = 0; ph < NPHASE; ++ph) {
     if (ph) __syncthreads();
-    // gather: item = (pixel, chunk in phase, tap), tap fastest; S[p][(gi*9 + tap)*CW + c].
-    // A thread takes U items at a time: first the offsets of all U, then the corner
-    // vectors of all U, so several independent loads are in flight per thread.  Each
-    // item always reads its four corners (coordinates clamped into the map); a corner
-    // outside the map, or a pixel outside the image, gets weight 0.
-    constexpr int NITEM = NPX * GP * 9;
-    constexpr int U = 2;
-    for (int i0 = 0; i0 < NITEM; i0 += U * 256) {
-      const TF* cp[U][4];
-      float cw[U][4];
-      TC* sp[U];
+    if constexpr (CW % 8 == 0) {
+      float od[2][U][3];
 #pragma unroll
-      for (int uu = 0; uu < U; ++uu) {
-        const int item = i0 + uu * 256 + (int)threadIdx.x;
-        sp[uu] = nullptr;
-        if (item >= NITEM) continue;
-        const int tap = item % 9, rest = item / 9;
-        const int gi = rest % GP, p = rest / GP;
-        const int u = ph * GP + gi;                  // chunk index over the 2C channels
-        const int g = u / NCH;                       // its offset group
-        const int gy = ty0 + p / kTW, gx = tx0 + (p % kTW);
-        const bool inside = gy < im.H && gx < im.W;
-        const int gyc = min(gy, im.H - 1), gxc = min(gx, im.W - 1);
-        sp[uu] = &S[p * LDS_P + (gi * 9 + tap) * CW];
-        const int ky = tap / 3, kx = tap - 3 * ky;
-        const float* orow = im.offs + ((size_t)gyc * im.W + gxc) * L.ldo;
-        const float dyo = orow[2 * (9 * g + tap)];
-        const float dxo = orow[2 * (9 * g + tap) + 1];
-        float m = inside ? orow[18 * G + 9 * g + tap] : 0.0f;
+      for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) od[0][uu][k] = od_next[uu][k];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        Raw8<TF> raw[U][4][NV8];
+        float cw[U][4];
+        TC* sp[U];
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+          const int item = r * U * 256 + uu * 256 + (int)threadIdx.x;
+          sp[uu] = nullptr;
+          if (item >= NITEM) continue;
+          const ItemPos ip = item_pos(item);
+          const int u = ph * GP + ip.gi;
+          sp[uu] = &S[ip.p * LDS_P + (ip.gi * 9 + ip.tap) * CW];
+          const int ky = ip.tap / 3, kx = ip.tap - 3 * ky;
+          float m = od[r & 1][uu][2];
+          if (kF8) m *= qs;
+          // beyond one pixel outside the map every sample is zero; the clamp keeps the
+          // integer conversion defined for any offset value
+          const float py = fminf(fmaxf((float)(ip.gy + ky - 1) + od[r & 1][uu][0], -2.0f), hmax + 1.0f);
+          const float px = fminf(fmaxf((float)(ip.gx + kx - 1) + od[r & 1][uu][1], -2.0f), wmax + 1.0f);
+          const float y0f = floorf(py), x0f = floorf(px);
+          const float ly = py - y0f, lx = px - x0f;
+          const int y0 = (int)y0f, x0 = (int)x0f;
+          const int ci = u * CW;
+          const TF* src = ci < C ? fa : fb;
+          const int cl = ci < C ? ci : ci - C;
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+              const int yy = y0 + cy, xx = x0 + cx;
+              const bool ok = yy >= 0 && yy < im.H && xx >= 0 && xx < im.W;
+              const int yc = min(max(yy, 0), im.H - 1), xc = min(max(xx, 0), im.W - 1);
+              cw[uu][2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
+              const TF* cp = src + ((size_t)yc * im.W + xc) * C + cl;
+#pragma unroll
+              for (int v = 0; v < NV8; ++v) raw[uu][2 * cy + cx][v].load(cp + 8 * v);
+            }
+        }
+        if (r + 1 < NR) load_offs(ph, r + 1, od[(r + 1) & 1]);
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+          if (sp[uu] == nullptr) continue;
+#pragma unroll
+          for (int v = 0; v < NV8; ++v) {
+            f32x4 lo = zero4(), hi = zero4();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              f32x4 a, b;
+              raw[uu][k][v].to_f32(a, b);
+              lo += cw[uu][k] * a;
+              hi += cw[uu][k] * b;
+            }
+            if constexpr (ROT) {
+              const int c = (int)((sp[uu] - S) % LDS_P) / CW;   // chunk index within the pixel row
+              store4f<TC>(sp[uu] + 4 * piece(c, 2 * v), lo);
+              store4f<TC>(sp[uu] + 4 * piece(c, 2 * v + 1), hi);
+            } else {
+              store8f<TC>(sp[uu] + 8 * v, lo, hi);
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep each round's loads in their round
+      }
+    } else {
+      // 4-channel chunks (offset groups of fewer than 8 channels): one item at a time
+      for (int item = (int)threadIdx.x; item < NITEM; item += 256) {
+        const ItemPos ip = item_pos(item);
+        const int u = ph * GP + ip.gi, g = u / NCH;
+        TC* sp = &S[ip.p * LDS_P + (ip.gi * 9 + ip.tap) * CW];
+        const int ky = ip.tap / 3, kx = ip.tap - 3 * ky;
+        const float* orow = im.offs + ((size_t)min(ip.gy, im.H - 1) * im.W + min(ip.gx, im.W - 1)) * L.ldo;
+        float m = ip.inside ? orow[18 * G + 9 * g + ip.tap] : 0.0f;
         if (kF8) m *= qs;
-        // beyond one pixel outside the map every sample is zero; the clamp keeps the
-        // integer conversion defined for any offset value
-        const float py = fminf(fmaxf((float)(gy + ky - 1) + dyo, -2.0f), hmax + 1.0f);
-        const float px = fminf(fmaxf((float)(gx + kx - 1) + dxo, -2.0f), wmax + 1.0f);
+        const float py = fminf(fmaxf((float)(ip.gy + ky - 1) + orow[2 * (9 * g + ip.tap)], -2.0f), hmax + 1.0f);
+        const float px = fminf(fmaxf((float)(ip.gx + kx - 1) + orow[2 * (9 * g + ip.tap) + 1], -2.0f), wmax + 1.0f);
         const float y0f = floorf(py), x0f = floorf(px);
         const float ly = py - y0f, lx = px - x0f;
         const int y0 = (int)y0f, x0 = (int)x0f;
         const int ci = u * CW;
         const TF* src = ci < C ? fa : fb;
         const int cl = ci < C ? ci : ci - C;
+        float cw[4];
+        const TF* cp[4];
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
@@ -1094,44 +1188,20 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
             const int yy = y0 + cy, xx = x0 + cx;
             const bool ok = yy >= 0 && yy < im.H && xx >= 0 && xx < im.W;
             const int yc = min(max(yy, 0), im.H - 1), xc = min(max(xx, 0), im.W - 1);
-            cw[uu][2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
-            cp[uu][2 * cy + cx] = src + ((size_t)yc * im.W + xc) * C + cl;
+            cw[2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
+            cp[2 * cy + cx] = src + ((size_t)yc * im.W + xc) * C + cl;
           }
-      }
 #pragma unroll
-      for (int uu = 0; uu < U; ++uu) {
-        if (sp[uu] == nullptr) continue;
-        if constexpr (CW % 8 == 0) {
+        for (int v = 0; v < CW; v += 4) {
+          f32x4 acc4 = zero4();
 #pragma unroll
-          for (int v = 0; v < CW; v += 8) {
-            f32x4 lo = zero4(), hi = zero4();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              f32x4 a, b;
-              load8f<TF>(cp[uu][k] + v, a, b);
-              lo += cw[uu][k] * a;
-              hi += cw[uu][k] * b;
-            }
-            if constexpr (ROT) {
-              const int c = (int)((sp[uu] - S) % LDS_P) / CW;   // chunk index within the pixel row
-              store4f<TC>(sp[uu] + 4 * piece(c, v / 4), lo);
-              store4f<TC>(sp[uu] + 4 * piece(c, v / 4 + 1), hi);
-            } else {
-              store8f<TC>(sp[uu] + v, lo, hi);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < CW; v += 4) {
-            f32x4 acc4 = zero4();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc4 += cw[uu][k] * load4f<TF>(cp[uu][k] + v);
-            store4f<TC>(sp[uu] + v, acc4);
-          }
+          for (int k = 0; k < 4; ++k) acc4 += cw[k] * load4f<TF>(cp[k] + v);
+          store4f<TC>(sp + v, acc4);
         }
       }
     }
     __syncthreads();
+    if (ph + 1 < NPHASE) load_offs(ph + 1, 0, od_next);
 
     const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot) * 64 + lane;
     // nine steps over two register buffers (see conv_tile)
