@@ -300,8 +300,10 @@ void put_fragment(uint8_t* dst, int tc, int c0, G g) {
 //     = W[o = rowmap(16*ob + lane%16)][c = KG*kg + (KG/4)*(lane/16) + e][tap], e < KG/4
 // with KG = 16 channels per group for float and 32 for 16-bit types, and
 // bias[r] = b[rowmap(r)], zero for padded rows.  rowmap is the identity except for
-// the pixel-shuffle conv, whose A row 16*ob + t carries channel 16*(ob/4) + t of
-// sub-pixel ob%4, i.e. original output channel 4*(16*(ob/4) + t) + ob%4.
+// the pixel-shuffle conv (cout = 4 C): its A row 16*ob + t carries channel
+// 16*(ob % NB) + t of sub-pixel ob / NB (NB = C / 16 row blocks per sub-pixel), i.e.
+// original output channel 4*(16*(ob % NB) + t) + ob / NB, so that each group of NB
+// blocks is one sub-pixel's whole channel vector.
 nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, int cin,
                     bool shuffle, int tc, PackedConv* out) {
   const int KG = tc == DT_F32 ? 16 : 32;
@@ -311,8 +313,8 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
   std::vector<float> bias((size_t)obtot * 16, 0.0f);
   auto rowmap = [&](int r) -> int {
     if (!shuffle) return r;
-    const int ob = r / 16, t = r % 16;
-    return 4 * (16 * (ob / 4) + t) + (ob % 4);
+    const int ob = r / 16, t = r % 16, nb = cout / 64;
+    return 4 * (16 * (ob % nb) + t) + ob / nb;
   };
   for (int tap = 0; tap < 9; ++tap)
     for (int kg = 0; kg < nkg; ++kg)
@@ -431,8 +433,8 @@ nv_status pack_conv_f8(nv_context* ctx, const float* w, const float* b, int cout
   std::vector<float> bias((size_t)obtot * 16, 0.0f);
   auto rowmap = [&](int r) -> int {
     if (!shuffle) return r;
-    const int ob = r / 16, t = r % 16;
-    return 4 * (16 * (ob / 4) + t) + (ob % 4);
+    const int ob = r / 16, t = r % 16, nb = cout / 64;
+    return 4 * (16 * (ob % nb) + t) + ob / nb;
   };
   *wscale = f8_row_scales(w, cout, cin, obtot, rowmap);
   for (int st = 0; st < 5; ++st)

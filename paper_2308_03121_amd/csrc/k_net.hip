@@ -94,9 +94,9 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
             if (o < L.cout) dst[at + r] = (TOUT)(o >= L.sig_lo ? sigmoidf(v[r]) : v[r]);
           }
         }
-      } else {  // EPI_SHUFFLE: A row 16*ob + t is channel 16*(ob/4) + t at sub-pixel ob%4
-        const int obg = obase + ob;
-        const int sp = obg & 3, c = 16 * (obg >> 2) + 4 * q;
+      } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g % NB) + t at sub-pixel g / NB
+        const int obg = obase + ob, nb = L.ccout >> 4;
+        const int sp = obg / nb, c = 16 * (obg - sp * nb) + 4 * q;
         const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
         store4f<TOUT>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
       }
@@ -150,6 +150,51 @@ __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const Conv
     const int px = idx / NPC, ck = idx - px * NPC;
     const int gy = ty0 + px / kTW, gx = tx0 + px % kTW;
     if (gy < im.H && gx < im.W) stu4(dst + ((size_t)gy * im.W + gx) * C + E * ck, ldu4(&tile[px * OLDP + E * ck]));
+  }
+}
+
+// Pixel-shuffle epilogue through LDS: the workgroup's row blocks obase .. obase + 7
+// are sub-pixels sp0 = obase / 4 and sp0 + 1 with all 64 channels each (four blocks per
+// sub-pixel); each pass writes one sub-pixel's LReLU-ed results into the LDS tile and
+// copies whole high-resolution pixels out.  Same arithmetic as conv_store.
+template <typename TC, int OBW, int RW, int PB>
+__device__ __forceinline__ void conv_store_shuffle_staged(const ConvLayer& L, const ConvImg& im,
+                                                          const f32x4 (&acc)[RW][OBW], int ty0, int tx0, int wr,
+                                                          int wo, int obase, TC* tile) {
+  constexpr int C = 64, OLDP = C + 16 / (int)sizeof(TC), TH = 4 * PB;
+  static_assert(TH * kTW * OLDP <= ConvSmem<TC, C, PB>::N, "a sub-pixel's tile fits in the input tile's LDS");
+  constexpr int E = 16 / (int)sizeof(TC), NPC = C / E;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, j = lane & 15;
+  const int sp0 = obase >> 2;
+  TC* dst = static_cast<TC*>(im.dst);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    __syncthreads();   // the input tile, or the previous sub-pixel, is fully read
+#pragma unroll
+    for (int pb = 0; pb < RW; ++pb) {
+      const int r = wr * RW + pb;
+#pragma unroll
+      for (int ob = 0; ob < OBW; ++ob) {
+        const int g = obase + wo * OBW + ob;
+        if ((g >> 2) - sp0 != s) continue;
+        const int row = g * 16 + 4 * q;
+        f32x4 v = acc[pb][ob];
+        v += ld4(L.bias + row);
+        store4f<TC>(&tile[(r * kTW + j) * OLDP + 16 * (g & 3) + 4 * q], lrelu4(v));
+      }
+    }
+    __syncthreads();
+    const int sp = sp0 + s;
+#pragma unroll
+    for (int idx = (int)threadIdx.x; idx < TH * kTW * NPC; idx += 256) {
+      const int px = idx / NPC, ck = idx - px * NPC;
+      const int gy = ty0 + px / kTW, gx = tx0 + px % kTW;
+      if (gy < im.H && gx < im.W) {
+        const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
+        stu4(dst + ((size_t)Y * (2 * im.W) + X) * C + E * ck, ldu4(&tile[px * OLDP + E * ck]));
+      }
+    }
   }
 }
 
@@ -427,6 +472,16 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
       return;
     }
   }
+  // pixel shuffle with 64 high-resolution channels: a workgroup's eight row blocks are
+  // two whole sub-pixels, written one at a time through LDS as whole pixels
+  constexpr bool kStagedShuffle = std::is_same<TIN, TC>::value && std::is_same<TOUT, TC>::value && SPLIT == 0 &&
+                                  NCHUNK == 1 && CCH == 64 && OB == 8 && EPI == EPI_SHUFFLE;
+  if constexpr (kStagedShuffle) {
+    if (L.ccout == 64 && obase % 4 == 0) {
+      conv_store_shuffle_staged<TC, OBW, RW, PB>(L, im, acc, ty0, tx0, wr, wo, obase, tile);
+      return;
+    }
+  }
   conv_store<TOUT, OBW, RW, EPI>(L, im, acc, ty0 + wr * RW, tx0, obase + wo * OBW, SPLIT ? L.oscale : nullptr);
   }
 }
@@ -543,8 +598,8 @@ __device__ __forceinline__ void conv_tile32(const ConvLayer& L, const ConvImg& i
           const size_t at = ((size_t)gy * im.W + gx) * L.ldy + row;
           v += load4f<TC>(static_cast<const TC*>(im.res) + at);
           store4f<TC>(dst + at, v);
-        } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g/4) + t at sub-pixel g%4
-          const int g = row >> 4, sp = g & 3, c = 16 * (g >> 2) + (row & 15);
+        } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g % NB) + t at sub-pixel g / NB
+          const int g = row >> 4, nb = L.ccout >> 4, sp = g / nb, c = 16 * (g - sp * nb) + (row & 15);
           const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
           store4f<TC>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
         }
@@ -1234,6 +1289,32 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 
   TF* dst = static_cast<TF*>(im.dst);
   const int gx = tx0 + j;
+  if constexpr (std::is_same<TF, TC>::value) {
+    // through the idle sample buffer, so that each wave stores whole pixels (one
+    // contiguous kilobyte per instruction); same arithmetic as the direct form
+    constexpr int OLDP = C + 16 / (int)sizeof(TF);
+    static_assert(TH * kTW * OLDP <= DcnSmem<TC, CPG, PB>::N, "output tile fits the sample buffer");
+    __syncthreads();
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int r = wave * PB + pb;
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) {
+        const int row = ob * 16 + 4 * q;
+        const f32x4 v = acc[pb][ob] + ld4(L.bias + row);
+        store4f<TF>(&S[(r * kTW + j) * OLDP + row], lrelu4(v));
+      }
+    }
+    __syncthreads();
+    constexpr int E = 16 / (int)sizeof(TF), NPC = C / E;
+#pragma unroll
+    for (int idx = (int)threadIdx.x; idx < TH * kTW * NPC; idx += 256) {
+      const int px = idx / NPC, ck = idx - px * NPC;
+      const int oy = ty0 + px / kTW, ox = tx0 + px % kTW;
+      if (oy < im.H && ox < im.W) stu4(dst + ((size_t)oy * im.W + ox) * C + E * ck, ldu4(&S[px * OLDP + E * ck]));
+    }
+    return;
+  }
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
     const int gy = ty0 + wave * PB + pb;
