@@ -1453,18 +1453,30 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
     wa[cg][1] = L.wfrag[(cg * 2 + 1) * 64 + lane];
   }
   const u32x4 zero = {0u, 0u, 0u, 0u};
-  for (int pbk = wave; pbk < NPB; pbk += 4) {
-    const int p = pbk * 16 + j;
+  // a wave's pixel blocks are wave, wave + 4, ...: all of their loads are issued before
+  // the first MFMA, so the blocks do not each wait on a round trip of their own
+  constexpr int MAXB = (NPB + 3) / 4;
+  u32x4 xb[MAXB][NCG];
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    const int p = (wave + 4 * k) * 16 + j;
     const int ry = p / RW, rx = p - ry * RW;
     const int Y = ty0 + ry - 1, X = tx0 + rx - 1;
-    const bool ok = p < NP && Y >= 0 && Y < H2 && X >= 0 && X < W2;
+    const bool ok = wave + 4 * k < NPB && p < NP && Y >= 0 && Y < H2 && X >= 0 && X < W2;
     const TU* up = u + ((size_t)(ok ? Y : 0) * W2 + (ok ? X : 0)) * C + QE * q;
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) xb[k][cg] = ok ? ldu4(up + KG * cg) : zero;
+  }
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    const int pbk = wave + 4 * k;
+    if (pbk >= NPB) continue;
+    const int p = pbk * 16 + j;
     f32x4 acc0 = zero4(), acc1 = zero4();
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
-      const u32x4 xb = ok ? ldu4(up + KG * cg) : zero;
-      acc0 = Mma<TU>::step(wa[cg][0], xb, acc0);
-      acc1 = Mma<TU>::step(wa[cg][1], xb, acc1);
+      acc0 = Mma<TU>::step(wa[cg][0], xb[k][cg], acc0);
+      acc1 = Mma<TU>::step(wa[cg][1], xb[k][cg], acc1);
     }
     float* rp = &R[p * LDR];
 #pragma unroll
