@@ -164,7 +164,54 @@ def cpu_baseline(clip, blob, cfg, budget_s=20.0):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     best["cores"] = int(threads)
     best["kind"] = "oracle"
+    best["os_cpu_count"] = os.cpu_count()
+    best["cpu_model"] = cpu_model()
+    # the same sample on one thread
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pipeline.enhance_clip(frames, clip.bits, clip.chroma, W, cfg.res_blocks, cfg.offset_groups)
+        dt1 = time.perf_counter() - t0
+    best["single_thread"] = {"value": mpix / dt1, "unit": "output Mpix/s", "seconds": dt1, "cores": 1}
     return best
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def c1_group_bench(B, synth, torch, reps=50):
+    """One frame group of two 64x64 8-bit 4:2:0 frames through nv_enhance_group (plain
+    FP32, C=32, R=2, G=8): 3 output frames of 128x128; latency per group from the
+    median of `reps` timed calls (inputs resident, device events on the stream)."""
+    clip = synth.gen_group_c1()
+    cfg = synth.NET_C1
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, synth.gen_weights(cfg, seed=1))
+    fmt = B.fmt_struct(64, 64, 8, 420)
+    fa, fb = B.to_device_frame(*clip.frame(0)), B.to_device_frame(*clip.frame(1))
+    outs = [B.alloc_frame(128, 128, 8, 420) for _ in range(3)]
+    for _ in range(5):
+        ctx.enhance_group(fmt, fa, fb, outs=outs)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.enhance_group(fmt, fa, fb, outs=outs)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1000.0)
+    ctx.close()
+    us = float(np.median(times))
+    return {"workload": "one group of two 64x64 8-bit 4:2:0 frames, C=32 R=2 G=8, FP32",
+            "latency_us": round(us, 1), "output_mpix_per_s": round(3 * 128 * 128 / us, 2), "reps": reps}
 
 
 def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16", "fp8", "fp8-fusion"), steps=2):
@@ -501,6 +548,11 @@ def main():
     if others:
         rec["other_precisions"] = others
         print("# other precisions: " + json.dumps(others), file=sys.stderr, flush=True)
+    print("# C1: one 64x64 group", file=sys.stderr, flush=True)
+    try:
+        rec["c1_group"] = c1_group_bench(B, synth, torch)
+    except Exception as e:
+        rec["c1_group"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_c3:
         print("# precisions on the 48-frame 1920x1080 10-bit clip", file=sys.stderr, flush=True)
         try:
