@@ -273,7 +273,7 @@ __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& 
 #pragma unroll
       for (int ob = 0; ob < OBW; ++ob) acc[pb][ob] = Mma<f8>::step(wa[ob], xb[pb], acc[pb][ob]);
   };
-  // two register buffers, step i+1 loading while step i multiplies (see conv_tile)
+  // two register buffers, step i+1 loading while step i multiplies
   fetch(0, wa0, xb0);
 #pragma unroll 1
   for (int st = 0; st < NST; st += 2) {
@@ -376,10 +376,9 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
     }
     __syncthreads();
 
-    // (tap, channel group) steps, software-pipelined over two register buffers: the
-    // A fragments (global) and B fragments (LDS) of step i+1 load into one buffer
-    // while the MFMAs of step i read the other, so no fragment is ever copied between
-    // registers (a copy would wait for the loads it was meant to overlap).
+    // (tap, channel group) steps, software-pipelined: the fragments of later steps are
+    // loading while the MFMAs of step i run (float: one step ahead; 16-bit: A two steps
+    // and B one step ahead, see below).
     constexpr int NIT = 9 * NCG;
     const u32x4* wbase = L.wfrag + ((size_t)(ch * NCG) * wobtot + (obase + wo * OBW) * AS) * 64 + lane;
     const size_t wstride_tap = (size_t)NKG * wobtot * 64;
@@ -1259,7 +1258,7 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
     if (ph + 1 < NPHASE) load_offs(ph + 1, 0, od_next);
 
     const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot) * 64 + lane;
-    // nine steps over two register buffers (see conv_tile)
+    // nine steps over two register buffers, step i+1 loading while step i multiplies
     Frag wa0[OB], xb0[PB], wa1[OB], xb1[PB];
     auto fetch = [&](int st, Frag (&wa)[OB], Frag (&xb)[PB]) {
 #pragma unroll
