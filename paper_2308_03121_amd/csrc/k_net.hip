@@ -52,7 +52,11 @@ template <typename TC, int CCH, int PB>
 struct ConvSmem {
   static constexpr int TH = 4 * PB;
   static constexpr int LDP = CCH + 16 / (int)sizeof(TC);   // LDS pixel stride (16-byte pad)
-  static constexpr int N = (TH + 2) * (kTW + 2) * LDP;
+  // the input tile, or (FP8 tiles, whose storage type is float16) the staged 16-bit
+  // output tile if that is larger
+  static constexpr int NIN = (TH + 2) * (kTW + 2) * LDP;
+  static constexpr int NOUT = std::is_same<TC, f8>::value ? TH * kTW * (CCH + 8) * 2 : 0;
+  static constexpr int N = NIN > NOUT ? NIN : NOUT;
 };
 
 // Epilogue of a wave's part of a conv tile (rows y0 .. y0 + PB, output blocks obase ..
@@ -116,11 +120,13 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
 // LDS tile in the storage type, then the workgroup copies whole pixels out in 16-byte
 // pieces.  The arithmetic and rounding are conv_store's, so the results are
 // bit-identical.
-template <typename TC, int OBW, int RW, int PB, int EPI>
+template <typename TC, int OBW, int RW, int PB, int EPI, typename TL = TC>
 __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[RW][OBW],
-                                                  int ty0, int tx0, int wr, int wo, TC* tile) {
+                                                  int ty0, int tx0, int wr, int wo, TC* tile,
+                                                  const float* oscale = nullptr) {
   constexpr int C = 64, OLDP = C + 16 / (int)sizeof(TC), TH = 4 * PB;
-  static_assert(TH * kTW * OLDP <= ConvSmem<TC, C, PB>::N, "the output tile fits in the input tile's LDS");
+  static_assert(TH * kTW * OLDP * (int)sizeof(TC) <= ConvSmem<TL, C, PB>::N * (int)sizeof(TL),
+                "the output tile fits in the workgroup's LDS tile");
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, j = lane & 15;
   __syncthreads();   // every wave is done reading the input tile
@@ -131,7 +137,7 @@ __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const Conv
 #pragma unroll
     for (int ob = 0; ob < OBW; ++ob) {
       const int row = (wo * OBW + ob) * 16 + 4 * q;
-      f32x4 v = acc[pb][ob];
+      f32x4 v = oscale ? acc[pb][ob] * ld4(oscale + row) : acc[pb][ob];
       v += ld4(L.bias + row);
       if (EPI == EPI_LRELU) {
         v = lrelu4(v);
@@ -282,6 +288,13 @@ __device__ __forceinline__ void conv_tile_f8(const ConvLayer& L, const ConvImg& 
     if (st + 1 < NST) {
       if (st + 2 < NST) fetch(st + 2, wa0, xb0);
       mma(wa1, xb1);
+    }
+  }
+  if constexpr (OB == 4 && (EPI == EPI_LRELU || EPI == EPI_RES)) {
+    if (L.obtot == OB && L.ldy == 16 * OB) {   // all 64 channels: whole pixels through LDS
+      conv_store_staged<f16, OBW, RW, PB, EPI, f8>(L, im, acc, ty0, tx0, wr, wo, reinterpret_cast<f16*>(tile),
+                                                   L.oscale);
+      return;
     }
   }
   conv_store<f16, OBW, RW, EPI>(L, im, acc, ty0 + wr * RW, tx0, obase + wo * OBW, L.oscale);
