@@ -1368,10 +1368,10 @@ __global__ __launch_bounds__(256) void k_dcn_batch(DcnLayer L, const DcnImg* __r
 // blockIdx.y selects 16 output channels, so every weight read is uniform (scalar loads).
 template <typename TOUT>
 __device__ __forceinline__ void conv_in_px(const float* __restrict__ rgb, const float* __restrict__ w,
-                                           const float* __restrict__ b, TOUT* __restrict__ dst, int H,
-                                           int W, int C, int p, int o0) {
-  if (p >= H * W) return;
-  const int y = p / W, x = p - y * W;
+                                           const float* __restrict__ b, int H, int W, int p, int o0,
+                                           float (&out)[16]) {
+  const int pc = min(p, H * W - 1);
+  const int y = pc / W, x = pc - y * W;
   const size_t plane = (size_t)H * W;
   float in[27];
 #pragma unroll
@@ -1384,7 +1384,6 @@ __device__ __forceinline__ void conv_in_px(const float* __restrict__ rgb, const 
         in[c * 9 + ky * 3 + kx] =
             (yy >= 0 && yy < H && xx >= 0 && xx < W) ? rgb[c * plane + (size_t)yy * W + xx] : 0.0f;
       }
-  float out[16];
 #pragma unroll
   for (int o = 0; o < 16; ++o) {
     float s = b[o0 + o];
@@ -1393,34 +1392,53 @@ __device__ __forceinline__ void conv_in_px(const float* __restrict__ rgb, const 
     for (int k = 0; k < 27; ++k) s = fmaf(wo[k], in[k], s);
     out[o] = lrelu(s);
   }
-  TOUT* d = dst + (size_t)p * C + o0;
+}
+
+// One workgroup: 4096 / C consecutive pixels (in row-major order) x all C channels.
+// Thread t computes channel block t / PPW (16 channels) of pixel t % PPW, so the C/16
+// waves of a pixel run share its inputs in L1; the results go through LDS and leave as
+// one contiguous run of whole pixels.
+template <typename TOUT, int C>
+__device__ __forceinline__ void conv_in_block(const float* __restrict__ rgb, const float* __restrict__ w,
+                                              const float* __restrict__ b, TOUT* __restrict__ dst, int H,
+                                              int W, int blk, TOUT* lds) {
+  constexpr int PPW = 256 / (C / 16), OLDP = C + 16 / (int)sizeof(TOUT);
+  constexpr int E = 16 / (int)sizeof(TOUT), NPC = C / E;
+  // the channel block is the same across a wave (PPW is a multiple of 64): scalar weights
+  const int cb = __builtin_amdgcn_readfirstlane((int)threadIdx.x / PPW), pl = threadIdx.x - cb * PPW;
+  const int p0 = blk * PPW;
+  float out[16];
+  conv_in_px<TOUT>(rgb, w, b, H, W, p0 + pl, 16 * cb, out);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    store4f<TOUT>(d + 4 * v, f32x4{out[4 * v], out[4 * v + 1], out[4 * v + 2], out[4 * v + 3]});
+    store4f<TOUT>(&lds[pl * OLDP + 16 * cb + 4 * v], f32x4{out[4 * v], out[4 * v + 1], out[4 * v + 2], out[4 * v + 3]});
+  __syncthreads();
+  const int np = min(PPW, H * W - p0);
+#pragma unroll
+  for (int idx = (int)threadIdx.x; idx < PPW * NPC; idx += 256) {
+    const int px = idx / NPC, ck = idx - px * NPC;
+    if (px < np) stu4(dst + (size_t)(p0 + px) * C + E * ck, ldu4(&lds[px * OLDP + E * ck]));
+  }
 }
 
-template <typename TOUT>
-__global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb,
-                                                 const float* __restrict__ w,
-                                                 const float* __restrict__ b,
-                                                 TOUT* __restrict__ dst, int H, int W, int C) {
-  conv_in_px<TOUT>(rgb, w, b, dst, H, W, C, blockIdx.x * 256 + threadIdx.x, blockIdx.y * 16);
+template <typename TOUT, int C>
+__global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ rgb, const float* __restrict__ w,
+                                                 const float* __restrict__ b, TOUT* __restrict__ dst, int H, int W) {
+  __shared__ __attribute__((aligned(16))) TOUT lds[(256 / (C / 16)) * (C + 16 / sizeof(TOUT))];
+  conv_in_block<TOUT, C>(rgb, w, b, dst, H, W, blockIdx.x, lds);
 }
 
-// Persistent form: item = (256-pixel block, 16-channel block) of one image.
-template <typename TOUT>
-__global__ __launch_bounds__(256) void k_conv_in_batch(const float* __restrict__ w,
-                                                       const float* __restrict__ b, int C,
+// Persistent form: item = pixel run of one image.
+template <typename TOUT, int C>
+__global__ __launch_bounds__(256) void k_conv_in_batch(const float* __restrict__ w, const float* __restrict__ b,
                                                        const ConvInImg* __restrict__ jobs,
                                                        const int* __restrict__ count) {
+  __shared__ __attribute__((aligned(16))) TOUT lds[(256 / (C / 16)) * (C + 16 / sizeof(TOUT))];
   const int njobs = count[0], total = count[1];
-  const int ncb = C / 16;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const ConvInImg& im = jobs[find_job(jobs, njobs, item)];
-    const int local = item - im.item_begin;
-    const int pblk = local / ncb, cb = local - pblk * ncb;
-    conv_in_px<TOUT>(im.rgb, w, b, static_cast<TOUT*>(im.dst), im.H, im.W, C, pblk * 256 + threadIdx.x,
-                     cb * 16);
+    conv_in_block<TOUT, C>(im.rgb, w, b, static_cast<TOUT*>(im.dst), im.H, im.W, item - im.item_begin, lds);
+    __syncthreads();
   }
 }
 
@@ -1989,28 +2007,43 @@ int conv_ob(int role, int epi, int obtot, int tc, int tile) {
   return obtot % 4 == 0 ? 4 : 2;
 }
 
-hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
-                          hipStream_t s) {
-  const dim3 grid((H * W + 255) / 256, L.cout / 16);
+template <int C>
+hipError_t launch_conv_in_c(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W, hipStream_t s) {
+  const dim3 grid(conv_in_items(H, W, C));
   if (tout == DT_F32)
-    hipLaunchKernelGGL((k_conv_in<float>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<float*>(dst), H, W, L.cout);
+    hipLaunchKernelGGL((k_conv_in<float, C>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<float*>(dst), H, W);
   else if (tout == DT_F16)
-    hipLaunchKernelGGL((k_conv_in<f16>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<f16*>(dst), H, W, L.cout);
+    hipLaunchKernelGGL((k_conv_in<f16, C>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<f16*>(dst), H, W);
   else if (tout == DT_BF16)
-    hipLaunchKernelGGL((k_conv_in<bf16>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<bf16*>(dst), H, W, L.cout);
+    hipLaunchKernelGGL((k_conv_in<bf16, C>), grid, dim3(256), 0, s, rgb, L.w, L.b, static_cast<bf16*>(dst), H, W);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
-                                hipStream_t s) {
+hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
+                          hipStream_t s) {
+  if (L.cout == 64) return launch_conv_in_c<64>(L, tout, rgb, dst, H, W, s);
+  if (L.cout == 32) return launch_conv_in_c<32>(L, tout, rgb, dst, H, W, s);
+  return hipErrorInvalidValue;
+}
+
+template <int C>
+hipError_t launch_conv_in_batch_c(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
+                                  hipStream_t s) {
   const dim3 grid(kBatchGrid);
-  if (tout == DT_F32) hipLaunchKernelGGL((k_conv_in_batch<float>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
-  else if (tout == DT_F16) hipLaunchKernelGGL((k_conv_in_batch<f16>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
-  else if (tout == DT_BF16) hipLaunchKernelGGL((k_conv_in_batch<bf16>), grid, dim3(256), 0, s, L.w, L.b, L.cout, jobs, count);
+  if (tout == DT_F32) hipLaunchKernelGGL((k_conv_in_batch<float, C>), grid, dim3(256), 0, s, L.w, L.b, jobs, count);
+  else if (tout == DT_F16) hipLaunchKernelGGL((k_conv_in_batch<f16, C>), grid, dim3(256), 0, s, L.w, L.b, jobs, count);
+  else if (tout == DT_BF16) hipLaunchKernelGGL((k_conv_in_batch<bf16, C>), grid, dim3(256), 0, s, L.w, L.b, jobs, count);
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_conv_in_batch(const PlainConv& L, int tout, const ConvInImg* jobs, const int* count,
+                                hipStream_t s) {
+  if (L.cout == 64) return launch_conv_in_batch_c<64>(L, tout, jobs, count, s);
+  if (L.cout == 32) return launch_conv_in_batch_c<32>(L, tout, jobs, count, s);
+  return hipErrorInvalidValue;
 }
 
 int bulk_tile_lds(int tc, int cch, int tile) {

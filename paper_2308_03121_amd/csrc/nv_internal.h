@@ -209,7 +209,8 @@ inline int conv_items(int H, int W, int pb, int nobg) {
   return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
 }
 inline int hr_items(int H, int W) { return ((2 * W + 15) / 16) * ((2 * H + 15) / 16); }
-inline int conv_in_items(int H, int W, int C) { return ((H * W + 255) / 256) * (C / 16); }
+// input conv: one item per run of 4096 / C consecutive pixels (all C channels)
+inline int conv_in_items(int H, int W, int C) { return (H * W + 4096 / C - 1) / (4096 / C); }
 
 hipError_t launch_conv_in(const PlainConv& L, int tout, const float* rgb, void* dst, int H, int W,
                           hipStream_t s);
