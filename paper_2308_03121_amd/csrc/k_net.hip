@@ -120,10 +120,23 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
 // LDS tile in the storage type, then the workgroup copies whole pixels out in 16-byte
 // pieces.  The arithmetic and rounding are conv_store's, so the results are
 // bit-identical.
-template <typename TC, int OBW, int RW, int PB, int EPI, typename TL = TC>
+// Four 16-bit elements held raw in two dwords -> four floats.
+template <typename TC>
+__device__ __forceinline__ f32x4 raw4f(u32x2 r) {
+  if constexpr (std::is_same<TC, f16>::value) {
+    const f16x4 v = __builtin_bit_cast(f16x4, r);
+    return f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  } else {
+    const bf16x4 v = __builtin_bit_cast(bf16x4, r);
+    return f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  }
+}
+
+template <typename TC, int OBW, int RW, int PB, int EPI, typename TL = TC, bool PRE = false>
 __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const ConvImg& im, const f32x4 (&acc)[RW][OBW],
                                                   int ty0, int tx0, int wr, int wo, TC* tile,
-                                                  const float* oscale = nullptr) {
+                                                  const float* oscale = nullptr,
+                                                  const u32x2 (*resr)[OBW] = nullptr) {
   constexpr int C = 64, OLDP = C + 16 / (int)sizeof(TC), TH = 4 * PB;
   static_assert(TH * kTW * OLDP * (int)sizeof(TC) <= ConvSmem<TL, C, PB>::N * (int)sizeof(TL),
                 "the output tile fits in the workgroup's LDS tile");
@@ -141,6 +154,8 @@ __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const Conv
       v += ld4(L.bias + row);
       if (EPI == EPI_LRELU) {
         v = lrelu4(v);
+      } else if constexpr (PRE) {
+        v += raw4f<TC>(resr[pb][ob]);   // skip values loaded before the main loop
       } else if (inside) {
         v += load4f<TC>(static_cast<const TC*>(im.res) + ((size_t)gy * im.W + gx) * C + row);
       }
@@ -347,6 +362,30 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
 #pragma unroll
     for (int ob = 0; ob < OBW; ++ob) acc[pb][ob] = zero4();
 
+  constexpr bool kStaged = std::is_same<TIN, TC>::value && std::is_same<TOUT, TC>::value && SPLIT == 0 &&
+                           NCHUNK == 1 && CCH == 64 && OB == 4 && (EPI == EPI_LRELU || EPI == EPI_RES);
+  const bool staged_rt = L.obtot == OB && L.ldy == 16 * OB;
+  // 16-bit residual conv with the staged epilogue: the skip values of this lane's
+  // outputs are requested before the main loop, so their HBM latency is hidden behind
+  // it instead of following the last MFMA (same arithmetic; two registers per output
+  // fragment)
+  constexpr bool kPre = kStaged && EPI == EPI_RES && sizeof(TC) == 2;
+  u32x2 resr[RW][kPre ? OBW : 1];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int pb = 0; pb < RW; ++pb) {
+      const int gy = ty0 + wr * RW + pb, gx = tx0 + j;
+      const bool inside = staged_rt && gy < im.H && gx < im.W;
+#pragma unroll
+      for (int ob = 0; ob < OBW; ++ob) {
+        const int row = (wo * OBW + ob) * 16 + 4 * q;
+        resr[pb][ob] = inside ? *reinterpret_cast<const u32x2*>(static_cast<const TC*>(im.res) +
+                                                                 ((size_t)gy * im.W + gx) * 64 + row)
+                              : u32x2{0u, 0u};
+      }
+    }
+  }
+
   const TIN* src0 = static_cast<const TIN*>(im.src0);
   const TIN* src1 = static_cast<const TIN*>(im.src1);
   if (im.sel != nullptr && *im.sel != 0u) {
@@ -476,11 +515,12 @@ __device__ __forceinline__ void conv_tile(const ConvLayer& L, const ConvImg& im,
   // a workgroup that holds all 64 output channels of its pixels: the results go through
   // the (now idle) LDS tile so that each wave stores whole pixels, one contiguous
   // kilobyte per instruction, instead of 32- or 64-byte pieces of sixteen pixels
-  constexpr bool kStaged = std::is_same<TIN, TC>::value && std::is_same<TOUT, TC>::value && SPLIT == 0 &&
-                           NCHUNK == 1 && CCH == 64 && OB == 4 && (EPI == EPI_LRELU || EPI == EPI_RES);
   if constexpr (kStaged) {
-    if (L.obtot == OB && L.ldy == 16 * OB) {
-      conv_store_staged<TC, OBW, RW, PB, EPI>(L, im, acc, ty0, tx0, wr, wo, tile);
+    if (staged_rt) {
+      if constexpr (kPre)
+        conv_store_staged<TC, OBW, RW, PB, EPI, TC, true>(L, im, acc, ty0, tx0, wr, wo, tile, nullptr, resr);
+      else
+        conv_store_staged<TC, OBW, RW, PB, EPI>(L, im, acc, ty0, tx0, wr, wo, tile);
       return;
     }
   }
