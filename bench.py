@@ -34,6 +34,7 @@ FP32_CONV_BLOCK_TRAFFIC = {
     "first conv (LReLU)": {"fetch_kib": 69945, "write_kib": 130560},
     "second conv (+ skip)": {"fetch_kib": 135829, "write_kib": 130560},
     "fetch_scale": 2.00, "write_scale": 1.00,
+    "tile": "pb2",   # the tile the tuner chose for the counted launches
 }
 
 
@@ -516,7 +517,9 @@ def main():
         "roofline": {"bound": "mfma", "kernel": f"{dom} ({'3x3 conv 64->64' if dom == 'conv_block' else dom})",
                      "achieved": achieved, "peak": PEAKS[args.precision], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAKS[args.precision], 4),
-                     "traffic": (round(conv_block_traffic()) if args.precision == "fp32" and dom == "conv_block"
+                     "traffic": (round(conv_block_traffic())
+                                 if args.precision == "fp32" and dom == "conv_block"
+                                 and f"[block {FP32_CONV_BLOCK_TRAFFIC['tile']}," in tuning[args.precision]
                                  else None),
                      "traffic_algorithmic": (conv_block_bytes(hp, wp, cfg.channels) if dom == "conv_block"
                                              else None),

@@ -1782,11 +1782,13 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     HIP_TRY(hipMemsetAsync(ws.offs, 0, (size_t)hp * wp * ctx->ldo * 4, s));
     HIP_TRY(hipMemsetAsync(ws.o1, 0, (size_t)hp * wp * C * 4, s));
     char buf[256];
-    // bulk conv tiles: rows per wave 1, 2, 4, and for 16-bit / FP8 also with two waves
-    // along the output blocks
+    // bulk conv tiles: rows per wave 1, 2, 4, and with two waves along the output blocks
+    // rows per wave 1, 2 (16-bit / FP8 also 4: the float form would need twice the
+    // fragment registers)
     std::vector<int> bulk_tiles = {1, 2, 4};
+    for (int pb : {1, 2}) bulk_tiles.push_back(tile_code(pb, 2));
     if (ft != DT_F32) {
-      for (int pb : {1, 2, 4}) bulk_tiles.push_back(tile_code(pb, 2));
+      bulk_tiles.push_back(tile_code(4, 2));
       // LDS-resident weights, where the device allows the workgroup that much LDS
       if (C == 64 && lds_weight_tiles())
         for (int pb : {2, 4})

@@ -1698,9 +1698,8 @@ hipError_t conv_bulk_pbw(const ConvCall& c, int epi) {
 template <typename T, int CCH, int PB>
 hipError_t conv_bulk_pb(const ConvCall& c, int epi, int wo) {
   if (wo == 1) return conv_bulk_pbw<T, CCH, PB, 1>(c, epi);
-  // two waves along the output blocks: 16-bit and FP8 MFMA types
-  if constexpr (!std::is_same<T, float>::value)
-    if (wo == 2) return conv_bulk_pbw<T, CCH, PB, 2>(c, epi);
+  // two waves along the output blocks
+  if (wo == 2) return conv_bulk_pbw<T, CCH, PB, 2>(c, epi);
   return hipErrorInvalidValue;
 }
 

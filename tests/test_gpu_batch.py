@@ -276,3 +276,27 @@ def test_lds_weight_tiles_bit_identical(B, prec, tmp_path, monkeypatch):
     _same(_per_stream(B, ctx, clips, dev), ref)
     _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
     ctx.close()
+
+
+def test_fp32_two_wave_tiles_bit_identical(B, tmp_path, monkeypatch):
+    """FP32 bulk convs with two waves along the output blocks (forced through the tuner's
+    cache file) give the same bits as the default tiles, per stream and batched."""
+    say("fp32 two-wave tiles")
+    cfg = synth.NetConfig(64, 1, 8)
+    blob = synth.gen_weights(cfg, seed=12)
+    clips = _clips()
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    ctx0 = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision="fp32")
+    ref = _per_stream(B, ctx0, clips, dev)
+    ctx0.close()
+    w2 = 1 << 8                                      # two waves along the output blocks
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"prec=0 C=64 R=1 size=64x48 | {2 | w2} {1 | w2} 2 2 2 0\n")
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision="fp32")
+    monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+    rep = ctx.autotune(48, 64)
+    monkeypatch.delenv("NNVISR_TUNE_CACHE")
+    assert "from cache" in rep and "block pb2w2" in rep and "up pb1w2" in rep, rep
+    _same(_per_stream(B, ctx, clips, dev), ref)
+    _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
+    ctx.close()
