@@ -1,0 +1,59 @@
+"""Host-side bookkeeping of bench.py: the algorithmic work and bytes it divides by, the
+counter-derived traffic figure, and the one-GPU guard.  No GPU is touched."""
+import os
+import re
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _layers(C, R, G):
+    # (pixel factor, input channels, output channels) of every 3x3 conv of one stream
+    # group: one feature extraction, the offset head and the DCN for the middle frame,
+    # and the pixel-shuffle and HR convs of both output frames (HR at 4x the pixels)
+    lay = [(1, 3, C)] + [(1, C, C)] * (2 * R)
+    lay += [(1, 2 * C, C), (1, C, 27 * G), (1, 2 * C, C)]
+    lay += [(1, C, 4 * C), (4, C, 3)] * 2
+    return lay
+
+
+def test_group_flops_match_layer_count():
+    for C, R, G in [(64, 10, 8), (32, 2, 8), (64, 6, 8)]:
+        want = sum(2 * 9 * ci * co * f for f, ci, co in _layers(C, R, G))
+        assert bench.group_flops_per_px(C, R, G) == want
+    # the main workload: 120 groups of 960x544 padded pixels, 165.4 TFLOP per step
+    assert abs(bench.group_flops_per_px(64, 10, 8) * 960 * 544 * 120 / 1e12 - 165.4) < 0.05
+
+
+def test_block_conv_work_and_bytes():
+    flop, unit = bench.kernel_work("conv_block", 544, 960, 64, 8, 4)
+    assert unit == "flop" and flop == 2 * 9 * 64 * 64 * 544 * 960
+    # first conv: read x, write y; second: also read the skip -> 2.5 maps per launch
+    m = 544 * 960 * 64 * 4
+    assert bench.conv_block_bytes(544, 960, 64) == 5 * m // 2 == 334233600
+
+
+def test_counter_traffic_is_near_algorithmic():
+    t = bench.FP32_CONV_BLOCK_TRAFFIC
+    assert re.fullmatch(r"pb[124](w2)?", t["tile"])
+    traffic = bench.conv_block_traffic()
+    algo = bench.conv_block_bytes(544, 960, 64)
+    assert algo <= traffic <= 1.10 * algo
+
+
+def test_pixel_stage_bytes():
+    # pack of one 3840x2160 10-bit 4:2:0 frame: float R'G'B' in, 1.5 codes of 2 B out
+    assert bench.pixel_bytes("pack", 1920, 1080, 10, 420) == 4 * 1920 * 1080 * (12 + 3)
+    # unpack of one 1920x1080 10-bit 4:2:0 frame to the padded float planes
+    assert bench.pixel_bytes("unpack", 1920, 1080, 10, 420) == 1920 * 1080 * 3 + 12 * 1080 * 1920
+    assert bench.pixel_bytes("scene", 1920, 1080, 8, 444) == 2 * 1920 * 1080
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
