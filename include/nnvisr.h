@@ -17,7 +17,11 @@
  *  - Colour is ITU-R BT.709, limited range, non-linear R'G'B'; 4:2:0 chroma is
  *    left-sited (co-sited with even luma columns, between luma rows 2i and 2i+1).
  *  - A context is used by one host thread at a time; calls on one context that
- *    overlap in time are not supported.
+ *    overlap in time are not supported.  Successive calls may use different HIP
+ *    streams: device work that reuses the context's workspace, or one clip stream's
+ *    device state, is ordered behind the previous call that used it (the library
+ *    records an event after each such call and makes the next call's stream wait on it
+ *    when the stream differs), so results do not depend on the streams chosen.
  *  - No C++ exception crosses this interface.
  */
 #ifndef NNVISR_H
@@ -110,7 +114,9 @@ typedef struct nv_stream nv_stream;
 
 /* ---------------------------------------------------------------- context ---- */
 
-/* Create a context on HIP device `device`.  `weights` (HOST memory, float32,
+/* Create a context on HIP device `device` for one network (section 3.1, network
+ * integration: the network is supplied once and split into an extract stage run per
+ * frame and a fusion stage run per frame group).  `weights` (HOST memory, float32,
  * n_floats long) is the flat weight blob in this tensor order, each conv 3x3 OIHW
  * followed by its bias: conv_in (C,3), R x [block.a (C,C), block.b (C,C)],
  * off1 (C,2C), off2 (27G,C), dcn (C,2C), up (4C,C), hr (3,C).  The library copies
@@ -157,7 +163,8 @@ nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int32_t set, vo
 nv_status nv_unpack(const nv_format* fmt, const nv_planes* in, float* d_rgb, int32_t hp,
                     int32_t wp, void* stream);
 
-/* Requantise planar float32 R'G'B' to a frame of format `fmt`: clamp R'G'B' to [0,1],
+/* Requantise planar float32 R'G'B' to a frame of format `fmt` (section 3.1, pixel
+ * formats: the enhanced frames leave in the clip's Y'CbCr format): clamp R'G'B' to [0,1],
  * BT.709 forward matrix, 4:2:0 chroma by the (1/4,1/2,1/4) x (1/2,1/2) left-sited
  * filter with replicated edges, code = clamp(floor(v + 1/2), 0, 2^bits - 1).  d_rgb
  * is [3][rh][rw] (rh >= fmt->height, rw >= fmt->width, rw a multiple of 4, d_rgb
@@ -203,8 +210,10 @@ nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
 
 /* --------------------------------------------------------- end to end ---- */
 
-/* One frame group, two frames in, three frames out (t = 0, 1/2, 1), each of format
- * fmt at twice the width and height. */
+/* One frame group (section 3.1: a frame group in, enhanced frames out): two frames in,
+ * three frames out (t = 0, 1/2, 1), each of format fmt at twice the width and height
+ * (the space-time setting of section 3.2: scale 2 with Interpolation and Double frame).
+ * in[2] and out[3] are HOST arrays of device planes. */
 nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
                            const nv_planes out[3], void* stream);
 
@@ -228,7 +237,10 @@ nv_status nv_stream_reset(nv_stream* s);
  * (cuts[0..n-1], n <= frames pushed); synchronises `stream`. */
 nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n, void* stream);
 
-/* Device bytes a stream of this format keeps resident (for admission control). */
+/* Device bytes a stream of this format keeps resident (for admission control): the
+ * frame store of section 3.3 for n = 1 (the overlap frame's pixels and features, two
+ * ring slots) plus the scene state (previous luma plane, histogram, cut flags).  The
+ * context workspace and the batch workspace (nv_batch_footprint) are not included. */
 nv_status nv_stream_footprint(const nv_context* ctx, const nv_format* fmt, size_t* bytes);
 
 /* ------------------------------------------------------------ batching ---- */

@@ -155,9 +155,24 @@ FrameOut to_frame_out(const nv_format* f, const nv_planes* p) {
 
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
+// Every device allocation of the library goes through here.  Test hook: when the
+// environment variable NNVISR_FAULT_ALLOC_MIN_BYTES holds a positive number, requests
+// of at least that many bytes fail as out of memory (read at every call, so a test can
+// switch it on and off around one call).
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (const char* f = getenv("NNVISR_FAULT_ALLOC_MIN_BYTES")) {
+    const long long lim = atoll(f);
+    if (lim > 0 && bytes >= (size_t)lim) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
 template <class T>
 hipError_t dev_alloc(T** p, size_t count) {
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+  return dev_malloc(reinterpret_cast<void**>(p), count * sizeof(T) > 0 ? count * sizeof(T) : 16);
 }
 
 template <class T>
@@ -181,6 +196,17 @@ struct Workspace {
   float* rgb[2] = {nullptr, nullptr};  // group inputs [3][hp][wp]
   void* feat[2] = {nullptr, nullptr};  // group features [hp][wp][C]
   size_t bytes = 0;
+};
+
+// Orders device work that reuses one set of buffers (the context workspace, or one clip
+// stream's ring and scene state) across the HIP streams a caller uses: the event
+// recorded after the last call that touched the buffers, and the stream it ran on.  A
+// call on another HIP stream first makes that stream wait for the event; calls on the
+// same stream are ordered by the stream itself.
+struct Order {
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  bool any = false;
 };
 
 // Launch timing: a pair of HIP events around each launch while enabled.
@@ -237,6 +263,7 @@ struct nv_context {
   bool q_ready = false;
   bool calibrating = false;
   Workspace ws;
+  Order ws_ord;                     // last use of ws
   std::vector<void*> allocs;
 };
 
@@ -332,7 +359,7 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
   out->cout = cout;
   out->obtot = obtot;
   out->tc = tc;
-  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  HIP_TRY(dev_malloc((void**)&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   // 16-bit types: also the 32x32x16 MFMA A fragments, 16 bytes per lane:
   //   frag32[((tap * NKG16 + kg) * obtot32 + ob) * 64 + lane]
@@ -349,7 +376,7 @@ nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, i
             put_fragment(&f32x[((((size_t)tap * nkg16 + kg) * ob32 + ob) * 64 + lane) * 16], tc, c0,
                          [&](int c) { return w[((size_t)o * cin + c) * 9 + tap]; });
           }
-    HIP_TRY(hipMalloc(&out->frag32, f32x.size()));
+    HIP_TRY(dev_malloc((void**)&out->frag32, f32x.size()));
     ctx->allocs.push_back(out->frag32);
     HIP_TRY(hipMemcpy(out->frag32, f32x.data(), f32x.size(), hipMemcpyHostToDevice));
   }
@@ -397,7 +424,7 @@ nv_status pack_conv_split(nv_context* ctx, const float* w, const float* b, int c
   out->cout = cout;
   out->obtot = obtot;
   out->tc = DT_F16;
-  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  HIP_TRY(dev_malloc((void**)&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   HIP_TRY(dev_alloc(&out->bias, bias.size()));
   ctx->allocs.push_back(out->bias);
@@ -453,7 +480,7 @@ nv_status pack_conv_f8(nv_context* ctx, const float* w, const float* b, int cout
   out->cout = cout;
   out->obtot = obtot;
   out->tc = DT_F8;
-  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  HIP_TRY(dev_malloc((void**)&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   HIP_TRY(dev_alloc(&out->bias, bias.size()));
   ctx->allocs.push_back(out->bias);
@@ -503,7 +530,7 @@ nv_status pack_dcn(nv_context* ctx, const float* w, const float* b, int C, int G
   out->cout = C;
   out->obtot = obtot;
   out->tc = tc;
-  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  HIP_TRY(dev_malloc((void**)&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   HIP_TRY(dev_alloc(&out->bias, C));
   ctx->allocs.push_back(out->bias);
@@ -535,7 +562,7 @@ nv_status pack_hr(nv_context* ctx, const float* w, const float* b, int cin, int 
   out->cout = 3;
   out->obtot = 2;
   out->tc = tc;
-  HIP_TRY(hipMalloc(&out->frag, frag.size()));
+  HIP_TRY(dev_malloc((void**)&out->frag, frag.size()));
   ctx->allocs.push_back(out->frag);
   HIP_TRY(dev_alloc(&out->bias, bias.size()));
   ctx->allocs.push_back(out->bias);
@@ -602,7 +629,9 @@ void free_workspace(Workspace& ws) {
 }
 
 // Grows the workspace to (hp, wp).  Freeing memory that queued work may still read
-// requires the device to be idle first.
+// requires the device to be idle first.  The new buffers are allocated into a local
+// Workspace and installed only when every allocation succeeded, so a failed growth
+// leaves an empty workspace (the next call allocates again), never a partial one.
 nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   Workspace& ws = ctx->ws;
   if (ws.hp >= hp && ws.wp >= wp && ws.t0) return NV_OK;
@@ -613,20 +642,25 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   }
   const size_t px = (size_t)nh * nw, C = ctx->C, fb = dtype_bytes(ctx->ft);
   Workspace n;
+  hipError_t e = dev_malloc(&n.t0, px * C * fb);
+  if (e == hipSuccess) e = dev_alloc(&n.o1, px * C);
+  if (e == hipSuccess) e = dev_alloc(&n.offs, px * ctx->ldo);
+  if (e == hipSuccess) e = dev_malloc(&n.fmid, px * C * fb);
+  if (e == hipSuccess) e = dev_malloc(&n.u, 4 * px * C * fb);
+  if (e == hipSuccess) e = dev_alloc(&n.hr, 12 * px);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = dev_alloc(&n.rgb[i], 3 * px);
+    if (e == hipSuccess) e = dev_malloc(&n.feat[i], px * C * fb);
+  }
+  if (e != hipSuccess) {
+    free_workspace(n);
+    return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "workspace of %dx%d: %s", nw, nh,
+                hipGetErrorString(e));
+  }
   n.hp = nh;
   n.wp = nw;
-  HIP_TRY(hipMalloc(&n.t0, px * C * fb));
-  ws = n;  // from here on free_workspace() releases whatever was allocated
-  HIP_TRY(dev_alloc(&ws.o1, px * C));
-  HIP_TRY(dev_alloc(&ws.offs, px * ctx->ldo));
-  HIP_TRY(hipMalloc(&ws.fmid, px * C * fb));
-  HIP_TRY(hipMalloc(&ws.u, 4 * px * C * fb));
-  HIP_TRY(dev_alloc(&ws.hr, 12 * px));
-  for (int i = 0; i < 2; ++i) {
-    HIP_TRY(dev_alloc(&ws.rgb[i], 3 * px));
-    HIP_TRY(hipMalloc(&ws.feat[i], px * C * fb));
-  }
-  ws.bytes = px * (C * fb * 8 + 4 * C + 4 * (size_t)ctx->ldo + 48 + 24);
+  n.bytes = px * (C * fb * 8 + 4 * C + 4 * (size_t)ctx->ldo + 48 + 24);
+  ws = n;
   return NV_OK;
 }
 
@@ -656,6 +690,38 @@ nv_status timed(nv_context* ctx, int kind, hipStream_t s, const char* what, F&& 
     nv_status s_ = (expr);      \
     if (s_ != NV_OK) return s_; \
   } while (0)
+
+nv_status order_begin(Order& o, hipStream_t s) {
+  if (o.any && o.last != s) HIP_TRY(hipStreamWaitEvent(s, o.ev, 0));
+  return NV_OK;
+}
+
+nv_status order_end(Order& o, hipStream_t s) {
+  if (!o.ev) HIP_TRY(hipEventCreateWithFlags(&o.ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(o.ev, s));
+  o.last = s;
+  o.any = true;
+  return NV_OK;
+}
+
+void order_free(Order& o) {
+  if (o.ev) (void)hipEventDestroy(o.ev);
+  o = Order{};
+}
+
+// Runs body() on HIP stream s after the last users of the buffers behind `ords`, and
+// marks s as their last user afterwards (also when body fails part way, since some of
+// its work may be queued).
+template <class F>
+nv_status ordered(std::initializer_list<Order*> ords, hipStream_t s, F&& body) {
+  for (Order* o : ords) NV_TRY(order_begin(*o, s));
+  const nv_status st = body();
+  for (Order* o : ords) {
+    const nv_status se = order_end(*o, s);
+    if (st == NV_OK && se != NV_OK) return se;
+  }
+  return st;
+}
 
 ConvImg conv_img(const void* src0, const void* src1, const uint32_t* sel, const void* alt0,
                  const void* alt1, const void* res, void* dst, int H, int W) {
@@ -891,6 +957,7 @@ extern "C" nv_status nv_context_destroy(nv_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_workspace(ctx->ws);
+  order_free(ctx->ws_ord);
   batch_release(ctx->batch);
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
@@ -985,7 +1052,8 @@ extern "C" nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp,
   if (!ctx || !d_rgb || !d_feat) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_dims(hp, wp));
   NV_TRY(check_ready(ctx));
-  return extract_impl(ctx, d_rgb, hp, wp, d_feat, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return ordered({&ctx->ws_ord}, s, [&] { return extract_impl(ctx, d_rgb, hp, wp, d_feat, s); });
 }
 
 extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
@@ -998,8 +1066,11 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   NV_TRY(check_ready(ctx));
   for (int t = 0; t < 3; ++t)
     if ((out_mask & (1u << t)) && (!d_hr || !d_hr[t])) return fail(NV_E_INVALID, "d_hr[%d] is NULL", t);
-  return fuse_impl(ctx, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets,
-                   d_fmid, nullptr, nullptr, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return ordered({&ctx->ws_ord}, s, [&] {
+    return fuse_impl(ctx, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets, d_fmid,
+                     nullptr, nullptr, s);
+  });
 }
 
 extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
@@ -1016,14 +1087,16 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
   NV_TRY(ensure_workspace(ctx, hp, wp));
   hipStream_t s = (hipStream_t)stream;
   Workspace& ws = ctx->ws;
-  for (int i = 0; i < 2; ++i) {
-    const Frame f = to_frame(fmt, &in[i]);
-    NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
-    NV_TRY(extract_impl(ctx, ws.rgb[i], hp, wp, ws.feat[i], s));
-  }
-  const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
-  return fuse_impl(ctx, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr,
-                   nullptr, nullptr, &of, po, s);
+  return ordered({&ctx->ws_ord}, s, [&] {
+    for (int i = 0; i < 2; ++i) {
+      const Frame f = to_frame(fmt, &in[i]);
+      NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
+      NV_TRY(extract_impl(ctx, ws.rgb[i], hp, wp, ws.feat[i], s));
+    }
+    const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
+    return fuse_impl(ctx, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
+                     nullptr, &of, po, s);
+  });
 }
 
 // ------------------------------------------------------------------- FP8 ----
@@ -1039,18 +1112,21 @@ extern "C" nv_status nv_calibrate(nv_context* ctx, const nv_format* fmt, const n
   NV_TRY(ensure_workspace(ctx, hp, wp));
   hipStream_t s = (hipStream_t)stream;
   Workspace& ws = ctx->ws;
-  HIP_TRY(hipMemsetAsync(ctx->q_amax, 0, ctx->q_layers.size() * sizeof(uint32_t), s));
   ctx->calibrating = true;
-  nv_status st = NV_OK;
-  for (int i = 0; i < n_frames && st == NV_OK; ++i) {
-    const int cur = i & 1, prv = cur ^ 1;
-    const Frame f = to_frame(fmt, &frames[i]);
-    st = check_launch(launch_unpack(f, ws.rgb[cur], hp, wp, s), "unpack");
-    if (st == NV_OK) st = extract_impl(ctx, ws.rgb[cur], hp, wp, ws.feat[cur], s);
-    if (st == NV_OK && i > 0 && ctx->ut == DT_F8)
-      st = fuse_impl(ctx, ws.rgb[prv], ws.rgb[cur], ws.feat[prv], ws.feat[cur], hp, wp, nullptr, 7u, nullptr,
-                     nullptr, nullptr, nullptr, nullptr, s);
-  }
+  const nv_status st = ordered({&ctx->ws_ord}, s, [&] {
+    HIP_TRY(hipMemsetAsync(ctx->q_amax, 0, ctx->q_layers.size() * sizeof(uint32_t), s));
+    nv_status r = NV_OK;
+    for (int i = 0; i < n_frames && r == NV_OK; ++i) {
+      const int cur = i & 1, prv = cur ^ 1;
+      const Frame f = to_frame(fmt, &frames[i]);
+      r = check_launch(launch_unpack(f, ws.rgb[cur], hp, wp, s), "unpack");
+      if (r == NV_OK) r = extract_impl(ctx, ws.rgb[cur], hp, wp, ws.feat[cur], s);
+      if (r == NV_OK && i > 0 && ctx->ut == DT_F8)
+        r = fuse_impl(ctx, ws.rgb[prv], ws.rgb[cur], ws.feat[prv], ws.feat[cur], hp, wp, nullptr, 7u, nullptr,
+                      nullptr, nullptr, nullptr, nullptr, s);
+    }
+    return r;
+  });
   ctx->calibrating = false;
   if (st != NV_OK) return st;
   ctx->q_ready = true;
@@ -1117,6 +1193,7 @@ struct nv_stream {
   uint32_t* hd = nullptr;
   uint32_t* cuts = nullptr;      // [kCutRing]
   SceneAcc* acc = nullptr;       // scene accumulators, zero between frames
+  Order ord;                     // last call that touched this stream's device state
   size_t bytes = 0;
   int slot(int64_t frame) const { return (int)(frame % (int64_t)rgb.size()); }
 };
@@ -1140,6 +1217,7 @@ static void stream_free(nv_stream* s) {
   dev_free(s->hd);
   dev_free(s->cuts);
   dev_free(s->acc);
+  order_free(s->ord);
 }
 
 // Grows the slot ring to at least r slots, keeping the last pushed frame.
@@ -1152,7 +1230,7 @@ static nv_status stream_ring(nv_stream* s, int r) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < r && e == hipSuccess; ++i) {
     e = dev_alloc(&rgb[i], 3 * px);
-    if (e == hipSuccess) e = hipMalloc(&feat[i], fbytes);
+    if (e == hipSuccess) e = dev_malloc((void**)&feat[i], fbytes);
   }
   if (e == hipSuccess && s->t > 0 && old > 0) {
     HIP_TRY(hipDeviceSynchronize());
@@ -1197,7 +1275,7 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   s->wp = round_up(fmt->width, 8);
   s->luma_pitch = luma_pitch(fmt);
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&s->luma[i], (size_t)s->luma_pitch * fmt->height);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = dev_malloc((void**)&s->luma[i], (size_t)s->luma_pitch * fmt->height);
   if (e == hipSuccess) e = dev_alloc(&s->hist, 128);
   if (e == hipSuccess) e = dev_alloc(&s->sad, 1);
   if (e == hipSuccess) e = dev_alloc(&s->hd, 1);
@@ -1228,6 +1306,9 @@ static nv_status emit_group(nv_stream* s, int slot_a, int slot_b, const uint32_t
                    s->wp, cut_b, 3u, nullptr, nullptr, nullptr, &s->ofmt, po, hs);
 }
 
+static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t external_cut, const nv_planes out[2],
+                           int32_t* n_out, hipStream_t hs);
+
 extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_t external_cut,
                                     const nv_planes out[2], int32_t* n_out, void* stream) {
   if (!s || !n_out) return fail(NV_E_INVALID, "NULL argument");
@@ -1239,6 +1320,11 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
     for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
   }
   hipStream_t hs = (hipStream_t)stream;
+  return ordered({&s->ctx->ws_ord, &s->ord}, hs, [&] { return push_impl(s, frame, external_cut, out, n_out, hs); });
+}
+
+static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t external_cut, const nv_planes out[2],
+                           int32_t* n_out, hipStream_t hs) {
   const int cur = s->slot(s->t), prv = s->t > 0 ? s->slot(s->t - 1) : 0;
   const Frame f = to_frame(&s->fmt, frame);
   NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
@@ -1279,7 +1365,8 @@ extern "C" nv_status nv_stream_end(nv_stream* s, const nv_planes out[2], int32_t
   if (!out) return fail(NV_E_INVALID, "out is NULL");
   for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
   const int last = s->slot(s->t - 1);
-  NV_TRY(emit_group(s, last, last, nullptr, out, (hipStream_t)stream));
+  hipStream_t hs = (hipStream_t)stream;
+  NV_TRY(ordered({&s->ctx->ws_ord, &s->ord}, hs, [&] { return emit_group(s, last, last, nullptr, out, hs); }));
   *n_out = 2;
   return NV_OK;
 }
@@ -1288,6 +1375,7 @@ extern "C" nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n
   if (!s || (!host_cuts && n > 0)) return fail(NV_E_INVALID, "NULL argument");
   if (n < 0 || n > s->t || n > kCutRing) return fail(NV_E_INVALID, "n = %d but %lld frames pushed", n, (long long)s->t);
   if (n == 0) return NV_OK;
+  NV_TRY(order_begin(s->ord, (hipStream_t)stream));
   HIP_TRY(hipMemcpyAsync(host_cuts, s->cuts, (size_t)n * 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return NV_OK;
@@ -1373,7 +1461,7 @@ nv_status pool_reserve(Pool& p, size_t bytes, bool* grew) {
   free_raw(reinterpret_cast<void*&>(p.base));
   p.cap = 0;
   void* b = nullptr;
-  HIP_TRY(hipMalloc(&b, bytes));
+  HIP_TRY(dev_malloc((void**)&b, bytes));
   p.base = static_cast<char*>(b);
   p.cap = bytes;
   *grew = true;
@@ -1398,18 +1486,24 @@ static void batch_release(BatchState* b) {
 
 namespace {
 
+// Creates the batch state; it is attached to the context only when every piece of it
+// was created, so a failure leaves the context as it was.
 nv_status batch_init(nv_context* ctx) {
   if (ctx->batch) return NV_OK;
   BatchState* b = new (std::nothrow) BatchState;
   if (!b) return fail(NV_E_NOMEM, "host allocation failed");
-  ctx->batch = b;
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(BatchTables), hipHostMallocDefault));
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(BatchTables), hipHostMallocDefault);
+  if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&b->dev), sizeof(BatchTables));
+  if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&b->acc), sizeof(SceneAccum));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    batch_release(b);
+    return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "batch state: %s", hipGetErrorString(e));
+  }
   std::memset(b->host, 0, sizeof(BatchTables));
-  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&b->dev), sizeof(BatchTables)));
-  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&b->acc), sizeof(SceneAccum)));
-  HIP_TRY(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
-  HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  ctx->batch = b;
   return NV_OK;
 }
 
@@ -1671,6 +1765,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
 
   // ---- upload, then launch (graph replay or direct) ----
   if (B->any) HIP_TRY(hipStreamWaitEvent(hs, B->done, 0));
+  for (int i = 0; i < n; ++i) NV_TRY(order_begin(reqs[i].stream->ord, hs));
   HIP_TRY(hipMemcpyAsync(B->dev, B->host, sizeof(BatchTables), hipMemcpyHostToDevice, hs));
   HIP_TRY(hipEventRecord(B->uploaded, hs));
   B->any = true;
@@ -1694,6 +1789,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     NV_TRY(batch_enqueue(ctx, hs));
   }
   HIP_TRY(hipEventRecord(B->done, hs));
+  for (int i = 0; i < n; ++i) NV_TRY(order_end(reqs[i].stream->ord, hs));
 
   // ---- stream states advance ----
   for (int i = 0; i < n; ++i) {
@@ -1775,6 +1871,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
   if (!found) {
     NV_TRY(ensure_workspace(ctx, hp, wp));
     hipStream_t s = (hipStream_t)stream;
+    NV_TRY(order_begin(ctx->ws_ord, s));
     Workspace& ws = ctx->ws;
     const int C = ctx->C, ft = ctx->ft;
     // inputs for the timing runs: zero offsets keep every DCN sample inside the frame
@@ -1888,6 +1985,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
                ctx->tune.fused ? "fused" : "pair");
       rep += buf;
     }
+    NV_TRY(order_end(ctx->ws_ord, s));
     if (cache) {
       if (FILE* f = fopen(cache, "a")) {
         fprintf(f, "%s | %d %d %d %d %d %d\n", key, ctx->tune.pb_block, ctx->tune.pb_up, ctx->tune.pb_dcn,

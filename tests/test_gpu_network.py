@@ -259,3 +259,49 @@ def test_full_size_c2_stream_cuts_and_outputs(B):
         assert np.max(np.abs(y_got.astype(np.int64) - y_ref.astype(np.int64))) <= 1
     st.close()
     ctx.close()
+
+
+def test_two_streams_alternate_hip_streams(B):
+    """Two clip streams of one context pushed alternately on two HIP streams (each
+    stream's pushes also switch HIP stream): the shared workspace and each stream's
+    state are ordered across HIP streams by the library, so every output equals the same
+    clip run alone, bit for bit, and matches the oracle."""
+    say("two clip streams on two HIP streams")
+    cfg = synth.NetConfig(32, 1, 8)
+    blob = synth.gen_weights(cfg, seed=7)
+    n, w, h = 5, 48, 32
+    clips = [synth.gen_clip(w, h, n, seed=21, scene_starts=[3]), synth.gen_clip(w, h, n, seed=22, scene_starts=[2])]
+    ctx = _ctx(B, cfg, blob)
+    fmt = B.fmt_struct(w, h, 8, 420)
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(n)] for c in clips]
+    alone = []
+    for k in range(2):
+        st = ctx.open_stream(fmt)
+        out = []
+        for t in range(n):
+            out += st.push(dev[k][t])
+        out += st.end()
+        torch.cuda.synchronize()
+        alone.append([B.frame_to_numpy(o, 8) for o in out])
+        st.close()
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sts = [ctx.open_stream(fmt) for _ in range(2)]
+    torch.cuda.synchronize()
+    mixed = [[], []]
+    for t in range(n):
+        for k in range(2):
+            mixed[k] += sts[k].push(dev[k][t], stream=hs[(t + k) % 2])
+    for k in range(2):
+        mixed[k] += sts[k].end(stream=hs[k])
+    torch.cuda.synchronize()
+    W = oracle_weights(cfg, blob)
+    for k in range(2):
+        assert len(mixed[k]) == 2 * n
+        got = [B.frame_to_numpy(o, 8) for o in mixed[k]]
+        for g, a in zip(got, alone[k]):
+            assert all(np.array_equal(x, y) for x, y in zip(g, a))
+        _cuts, ref = pipeline.enhance_clip([clips[k].frame(t) for t in range(n)], 8, 420, W, 1, 8)
+        for g, r in zip(got, ref):
+            _codes_close(g, r["codes"], 8)
+        sts[k].close()
+    ctx.close()

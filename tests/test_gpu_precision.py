@@ -205,3 +205,48 @@ def test_full_size_c3_windows(B, prec):
             print(f"  window ({y0},{x0}) t={t}: max-abs {err:.2e} PSNR {p:.1f} dB", flush=True)
             assert err <= tol and p >= PSNR_MIN
     ctx.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp8"])
+def test_full_size_c3_product_geometry(B, prec):
+    """The 1920x1080 10-bit frames padded as the product pads them (1080 rows, a
+    multiple of 8) and run with the tuner's tiles for that size, as the benchmark runs
+    them: tiles that are 16 rows high leave a partial tile at the bottom.  The bottom
+    window (frame edge, partial tile) and the centre are checked against the oracle."""
+    say(f"full-size C3 {prec} at 1080 rows, tuned tiles")
+    cfg = synth.NET_C2
+    blob = synth.gen_weights(cfg, seed=1)
+    W = oracle_weights(cfg, blob)
+    clip = synth.gen_clip(1920, 1080, 2, bits=10, chroma=420, seed=0, scene_starts=[])
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+    fmt = B.fmt_struct(1920, 1080, 10, 420)
+    dev = [B.to_device_frame(*clip.frame(t)) for t in range(2)]
+    if prec == "fp8":
+        ctx.calibrate(fmt, dev)
+    H, Wd = 1080, 1920
+    print("  " + ctx.autotune(H, Wd), flush=True)
+    ra_t = B.unpack(fmt, dev[0], H, Wd)
+    rb_t = B.unpack(fmt, dev[1], H, Wd)
+    fa, fb = ctx.extract(ra_t), ctx.extract(rb_t)
+    hr, _, _ = ctx.fuse(ra_t, rb_t, fa, fb, 3)
+    torch.cuda.synchronize()
+    hr_np = [hr[0].cpu().numpy(), hr[1].cpu().numpy()]
+    ra, rb = ra_t.cpu().numpy().astype(np.float64), rb_t.cpu().numpy().astype(np.float64)
+    tol = {"fp8": 6e-2}.get(prec, HR_TOL.get(prec))
+    for (y0, x0) in [(H - 112, Wd - 112), (H - 112, 904), (488, 904)]:
+        ca, cb = ra[:, y0:y0 + 112, x0:x0 + 112], rb[:, y0:y0 + 112, x0:x0 + 112]
+        res = network.fuse(ca, cb, network.extract(ca, W, cfg.res_blocks),
+                           network.extract(cb, W, cfg.res_blocks), W, cfg.offset_groups,
+                           times=(0.0, 0.5), keep=True)
+        ylo, yhi = (y0 if y0 == 0 else y0 + MARGIN), (y0 + 112 if y0 + 112 == H else y0 + 112 - MARGIN)
+        xlo, xhi = (x0 if x0 == 0 else x0 + MARGIN), (x0 + 112 if x0 + 112 == Wd else x0 + 112 - MARGIN)
+        inner = res["offsets"][:, ylo - y0:yhi - y0, xlo - x0:xhi - x0]
+        assert np.abs(inner).max() < MARGIN - 26
+        for i, t in enumerate((0.0, 0.5)):
+            ref = res[t][:, 2 * (ylo - y0):2 * (yhi - y0), 2 * (xlo - x0):2 * (xhi - x0)]
+            got = hr_np[i][:, 2 * ylo:2 * yhi, 2 * xlo:2 * xhi]
+            err, p = max_abs(got, ref), pipeline.psnr_float(ref, got)
+            print(f"  window ({y0},{x0}) t={t}: max-abs {err:.2e} PSNR {p:.1f} dB", flush=True)
+            assert err <= tol and p >= PSNR_MIN
+    ctx.close()

@@ -1,5 +1,6 @@
 """The oracle's end-to-end composition: shapes, stream order and group consistency."""
 import numpy as np
+import pytest
 
 import synth
 from oracle import network, pipeline, pixel, scene
@@ -63,3 +64,61 @@ def test_psnr_definitions():
     p = (np.zeros((2, 2), np.uint8),) * 3
     q = (np.ones((2, 2), np.uint8),) * 3
     assert abs(pipeline.psnr_codes(p, q, 8) - 20 * np.log10(255.0)) < 1e-9
+
+
+def _marker_blob(order):
+    """A blob in which every weight encodes its own position and every bias a distinct
+    negative marker: w[L][o][i][ky][kx] = 100000 L + 1000 o + 100 i + 10 ky + kx and
+    b[L][o] = -(100000 L + 1000 o + 1.5), all exact in float32 for the sizes used."""
+    parts = []
+    for L, (_name, cout, cin) in enumerate(order):
+        o, i, ky, kx = np.meshgrid(np.arange(cout), np.arange(cin), np.arange(3), np.arange(3), indexing="ij")
+        parts.append((100000 * L + 1000 * o + 100 * i + 10 * ky + kx).astype(np.float32).ravel())
+        parts.append(-(100000 * L + 1000 * np.arange(cout) + 1.5).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def test_weights_dict_order_and_oihw_reshape():
+    """Pins the blob reader every oracle network test builds its weights with.  The
+    expected tensor order is the one the C-ABI header documents for the weight blob
+    (conv_in, then block.a / block.b per residual block, off1, off2, dcn, up, hr), each
+    conv OIHW followed by its bias; it is written out here, not taken from the
+    generator, and every element is checked against its position marker, so a
+    bias/weight swap, a wrong layer order or a transposed reshape of a square layer
+    (block convs are C x C) fails."""
+    C, R, G = 4, 2, 2
+    order = [("conv_in", C, 3)]
+    for r in range(R):
+        order += [(f"block{r}.a", C, C), (f"block{r}.b", C, C)]
+    order += [("off1", C, 2 * C), ("off2", 27 * G, C), ("dcn", C, 2 * C), ("up", 4 * C, C), ("hr", 3, C)]
+    cfg = synth.NetConfig(C, R, G)
+    assert [(n, co, ci) for n, co, ci, _g in synth.weight_layout(cfg)] == order
+    blob = _marker_blob(order)
+    assert blob.size == sum(co * ci * 9 + co for _n, co, ci in order)
+    W = pipeline.weights_dict(blob, synth.weight_layout(cfg))
+    assert list(W) == [n for n, _co, _ci in order]
+    for L, (name, cout, cin) in enumerate(order):
+        w, b = W[name]
+        assert w.shape == (cout, cin, 3, 3) and b.shape == (cout,)
+        assert w.dtype == np.float64 and b.dtype == np.float64
+        for o in range(cout):
+            assert b[o] == -(100000 * L + 1000 * o + 1.5)
+            for i in range(cin):
+                for ky in range(3):
+                    for kx in range(3):
+                        assert w[o, i, ky, kx] == 100000 * L + 1000 * o + 100 * i + 10 * ky + kx
+    # the generator's own views into a real blob agree element for element
+    real = synth.gen_weights(cfg, seed=9)
+    Wr = pipeline.weights_dict(real, synth.weight_layout(cfg))
+    for name, (w, b) in synth.unpack_weights(cfg, real).items():
+        assert np.array_equal(Wr[name][0], w.astype(np.float64))
+        assert np.array_equal(Wr[name][1], b.astype(np.float64))
+
+
+def test_weights_dict_rejects_a_wrong_size():
+    cfg = synth.NetConfig(4, 1, 2)
+    blob = synth.gen_weights(cfg)
+    with pytest.raises(ValueError):
+        pipeline.weights_dict(blob[:-1], synth.weight_layout(cfg))
+    with pytest.raises(ValueError):
+        pipeline.weights_dict(np.concatenate([blob, [0.0]]), synth.weight_layout(cfg))
