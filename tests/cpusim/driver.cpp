@@ -1,0 +1,106 @@
+// Scenario driver of the CPU simulation build (tests/test_cpusim.py): runs the library's
+// C-ABI on host buffers that stand in for device memory and writes the results as raw
+// files for the test to compare with the FP64 oracle.
+//
+//   driver net DIR C R G PREC H W   reads DIR/weights.f32, DIR/rgb_a.f32, DIR/rgb_b.f32
+//                                   (planar float [3][H][W]); writes fa, fb (features),
+//                                   offs (float [H][W][ldo]), fmid, hr0, hr1, hr2
+//                                   (float [3][2H][2W]) as DIR/<name>.bin
+#include <hip/hip_runtime.h>
+#include <nnvisr.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+static std::vector<char> read_file(const std::string& p) {
+  std::vector<char> v;
+  FILE* f = fopen(p.c_str(), "rb");
+  if (!f) {
+    fprintf(stderr, "cannot read %s\n", p.c_str());
+    exit(2);
+  }
+  fseek(f, 0, SEEK_END);
+  v.resize(ftell(f));
+  fseek(f, 0, SEEK_SET);
+  if (!v.empty() && fread(v.data(), 1, v.size(), f) != v.size()) exit(2);
+  fclose(f);
+  return v;
+}
+
+static void write_file(const std::string& p, const void* d, size_t n) {
+  FILE* f = fopen(p.c_str(), "wb");
+  if (!f || fwrite(d, 1, n, f) != n) {
+    fprintf(stderr, "cannot write %s\n", p.c_str());
+    exit(2);
+  }
+  fclose(f);
+}
+
+#define CHECK(x)                                                                   \
+  do {                                                                             \
+    nv_status s_ = (x);                                                            \
+    if (s_ != NV_OK) {                                                             \
+      fprintf(stderr, "%s failed: %d %s\n", #x, (int)s_, nv_last_error());        \
+      exit(1);                                                                     \
+    }                                                                              \
+  } while (0)
+
+static void* dev(size_t bytes, const void* init = nullptr) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) exit(2);
+  if (init) memcpy(p, init, bytes);
+  return p;
+}
+
+static int run_net(int argc, char** argv) {
+  if (argc < 9) return 2;
+  const std::string dir = argv[2];
+  nv_net_config cfg;
+  cfg.channels = atoi(argv[3]);
+  cfg.res_blocks = atoi(argv[4]);
+  cfg.offset_groups = atoi(argv[5]);
+  cfg.scale = 2;
+  cfg.align = 8;
+  cfg.flags = NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE;
+  cfg.precision = atoi(argv[6]);
+  const int H = atoi(argv[7]), W = atoi(argv[8]);
+  const std::vector<char> wb = read_file(dir + "/weights.f32");
+  nv_context* ctx = nullptr;
+  CHECK(nv_context_create(0, &cfg, reinterpret_cast<const float*>(wb.data()), wb.size() / 4, &ctx));
+  const std::vector<char> ra = read_file(dir + "/rgb_a.f32"), rb = read_file(dir + "/rgb_b.f32");
+  const size_t px = (size_t)H * W, fe = (size_t)nv_feature_elem_bytes(ctx), C = cfg.channels;
+  const int ldo = 16 * ((27 * cfg.offset_groups + 15) / 16);
+  float* da = static_cast<float*>(dev(12 * px, ra.data()));
+  float* db = static_cast<float*>(dev(12 * px, rb.data()));
+  void* fa = dev(px * C * fe);
+  void* fb = dev(px * C * fe);
+  float* offs = static_cast<float*>(dev(px * ldo * 4));
+  void* fmid = dev(px * C * fe);
+  float* hr[3];
+  for (int t = 0; t < 3; ++t) hr[t] = static_cast<float*>(dev(48 * px));
+  fprintf(stderr, "net C=%d R=%d G=%d prec=%d %dx%d: extract\n", cfg.channels, cfg.res_blocks, cfg.offset_groups,
+          cfg.precision, W, H);
+  CHECK(nv_extract(ctx, da, H, W, fa, nullptr));
+  CHECK(nv_extract(ctx, db, H, W, fb, nullptr));
+  fprintf(stderr, "fuse\n");
+  CHECK(nv_fuse(ctx, da, db, fa, fb, H, W, nullptr, 7u, hr, offs, fmid, nullptr));
+  write_file(dir + "/fa.bin", fa, px * C * fe);
+  write_file(dir + "/fb.bin", fb, px * C * fe);
+  write_file(dir + "/offs.bin", offs, px * ldo * 4);
+  write_file(dir + "/fmid.bin", fmid, px * C * fe);
+  for (int t = 0; t < 3; ++t) write_file(dir + "/hr" + std::to_string(t) + ".bin", hr[t], 48 * px);
+  CHECK(nv_context_destroy(ctx));
+  for (void* p : {(void*)da, (void*)db, fa, fb, (void*)offs, fmid, (void*)hr[0], (void*)hr[1], (void*)hr[2]})
+    hipFree(p);
+  fprintf(stderr, "done\n");
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc >= 2 && strcmp(argv[1], "net") == 0) return run_net(argc, argv);
+  fprintf(stderr, "usage: driver net DIR C R G PREC H W\n");
+  return 2;
+}

@@ -1,0 +1,109 @@
+"""The library's kernels and host runtime executed on the CPU (tests/cpusim/).
+
+api.cpp, k_net.hip and k_pixel.hip are compiled as host C++ under AddressSanitizer
+against a simulated HIP device: every work-item runs as a
+fiber, __syncthreads() and the wave-wide operations (MFMA in each form the kernels use,
+lane shuffles, readfirstlane) are rendezvous points, __shared__ arrays are statics, and
+device memory is heap memory pre-filled with a non-zero pattern.  Any out-of-bounds
+global or LDS access is an ASan report; a barrier that a live work-item never reaches,
+or a wave operation not joined by every live lane, is reported as a hang (exit 3).
+The MFMA forms are emulated from their documented lane layouts in float64, so results
+are compared with the FP64 oracle at the GPU tests' float bar.
+
+The 64x64, C = 64, R = 2 network case is the one kept off the GPU after a run that went
+silent; here it runs through the same entry points (nv_extract, nv_fuse) with the
+context's default tiles.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import network
+from tests._helpers import oracle_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIM = os.path.join(ROOT, "tests", "cpusim")
+CSRC = os.path.join(ROOT, "paper_2308_03121_amd", "csrc")
+CXX = "/opt/rocm/llvm/bin/clang++"
+FLOAT_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    cxx = CXX if os.path.exists(CXX) else shutil.which("clang++")
+    if cxx is None:
+        pytest.skip("no clang++ with _Float16 and __bf16 support for the simulation build")
+    out = tmp_path_factory.mktemp("cpusim")
+    common = ["-std=c++17", "-g0", "-Wno-psabi", "-I" + SIM, "-I" + os.path.join(ROOT, "include")]
+    asan = ["-O1", "-fsanitize=address", "-fno-omit-frame-pointer"]
+    # the library's sources are instrumented; the simulator itself (scheduler, MFMA
+    # emulation) is optimised and uninstrumented
+    units = [(os.path.join(CSRC, "k_net.hip"), True, asan), (os.path.join(CSRC, "k_pixel.hip"), True, asan),
+             (os.path.join(CSRC, "api.cpp"), False, asan), (os.path.join(SIM, "sim.cpp"), False, ["-O2"]),
+             (os.path.join(SIM, "driver.cpp"), False, asan)]
+    procs, objs = [], []
+    for src, as_cxx, opt in units:
+        obj = str(out / (os.path.basename(src) + ".o"))
+        cmd = [cxx] + common + opt + (["-x", "c++"] if as_cxx else []) + ["-c", src, "-o", obj]
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    for p in procs:
+        log = p.communicate()[0]
+        assert p.returncode == 0, log[-4000:]
+    exe = str(out / "driver")
+    res = subprocess.run([cxx, "-fsanitize=address", "-o", exe] + objs, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-4000:]
+    return exe
+
+
+def _run(driver, args, timeout):
+    env = dict(os.environ)
+    env["ASAN_OPTIONS"] = "detect_leaks=0:detect_stack_use_after_return=0:abort_on_error=0"
+    res = subprocess.run([driver] + [str(a) for a in args], capture_output=True, text=True, env=env,
+                         timeout=timeout)
+    out = res.stdout + res.stderr
+    assert res.returncode != 3, "simulated hang:\n" + out[-4000:]
+    assert res.returncode == 0, out[-4000:]
+    assert "AddressSanitizer" not in out, out[-4000:]
+    return out
+
+
+def _chw(path, dt, h, w, c):
+    return np.fromfile(path, dtype=dt).reshape(h, w, c).astype(np.float64).transpose(2, 0, 1)
+
+
+@pytest.mark.parametrize("C,R,G,H,W", [(64, 2, 8, 64, 64)], ids=["C64R2-64x64"])
+def test_network_case_in_simulation(driver, tmp_path, C, R, G, H, W):
+    cfg = synth.NetConfig(C, R, G)
+    blob = synth.gen_weights(cfg, seed=1)
+    blob.astype(np.float32).tofile(tmp_path / "weights.f32")
+    rng = np.random.default_rng(H * W + C)
+    ra = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    rb = np.clip(ra + rng.normal(0, 0.05, ra.shape), 0, 1).astype(np.float32)
+    ra.tofile(tmp_path / "rgb_a.f32")
+    rb.tofile(tmp_path / "rgb_b.f32")
+    _run(driver, ["net", tmp_path, C, R, G, 0, H, W], timeout=900)
+
+    Wd = oracle_weights(cfg, blob)
+    ldo = 16 * ((27 * G + 15) // 16)
+    fa = _chw(tmp_path / "fa.bin", np.float32, H, W, C)
+    fb = _chw(tmp_path / "fb.bin", np.float32, H, W, C)
+    offs = _chw(tmp_path / "offs.bin", np.float32, H, W, ldo)
+    fmid = _chw(tmp_path / "fmid.bin", np.float32, H, W, C)
+    a64, b64 = ra.astype(np.float64), rb.astype(np.float64)
+    ofa, ofb = network.extract(a64, Wd, R), network.extract(b64, Wd, R)
+    assert np.abs(fa - ofa).max() <= FLOAT_TOL
+    assert np.abs(fb - ofb).max() <= FLOAT_TOL
+    o_off, o_mask = network.offset_head(fa, fb, Wd, G)
+    assert np.abs(offs[:18 * G] - o_off).max() <= FLOAT_TOL
+    assert np.abs(offs[18 * G:27 * G] - o_mask).max() <= FLOAT_TOL
+    o_fmid = network.align(fa, fb, offs[:18 * G], offs[18 * G:27 * G], Wd, G)
+    assert np.abs(fmid - o_fmid).max() <= FLOAT_TOL
+    full = network.fuse(a64, b64, ofa, ofb, Wd, G)
+    for t, key in enumerate((0.0, 0.5, 1.0)):
+        hr = np.fromfile(tmp_path / f"hr{t}.bin", dtype=np.float32).reshape(3, 2 * H, 2 * W)
+        assert np.abs(hr - full[key]).max() <= FLOAT_TOL, t
