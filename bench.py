@@ -259,7 +259,11 @@ def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16"
         cuts = [t for t, c in enumerate(st.cuts()) if c]
         res[prec] = {"value": round(mpix / (ms / 1000.0), 3), "unit": "Mpix/s", "ms_per_step": round(ms, 2),
                      "cuts": cuts,
-                     "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]}}
+                     "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]},
+                     "meets_50db_bar": prec != "fp8-fusion"}
+        if prec == "fp8-fusion":
+            res[prec]["note"] = ("below the 50 dB PSNR bar against the FP64 oracle (worst 1920x1080 window "
+                                 "about 46 dB, test_gpu_fp8 bar 44 dB): a speed figure only")
         if "pixel_stages" not in res:
             res["pixel_stages"] = pixel_rates(pr, 1, clip.width, clip.height, clip.bits, clip.chroma)
         print(f"# c3 {prec}: {res[prec]['value']} Mpix/s", file=sys.stderr, flush=True)
