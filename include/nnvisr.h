@@ -217,6 +217,25 @@ nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
 nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
                            const nv_planes out[3], void* stream);
 
+/* Allocation-free form of nv_enhance_group, for callers that cannot allocate device
+ * memory during the call (work recorded under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, validation and results (bit for bit)
+ * as nv_enhance_group, but the call allocates nothing: every temporary (R'G'B' of both
+ * inputs, their features, the offset head's hidden map, offsets and mask, aligned and
+ * high-resolution features, HR R'G'B') lives in a fixed device buffer of
+ * NV_STATIC_SCRATCH_BYTES per device, a static of the library that the HIP runtime
+ * allocates with the library's code object on each device that loads it and that stays
+ * allocated until the process ends; its address is looked up when a context is created
+ * on the device.  A group whose temporaries exceed the buffer (C = 64 in FP32 needs
+ * about 3.3 KB per padded pixel, so about 20 000 padded pixels, e.g. 160x128) returns
+ * NV_E_INVALID without enqueuing anything.  Every call on one device uses the same
+ * buffer, from every context on that device: calls that overlap in time on one device
+ * (on different HIP streams, from different contexts or threads) race and corrupt each
+ * other's results.  Calls are not timed by nv_profile_enable. */
+#define NV_STATIC_SCRATCH_BYTES (64u << 20)
+nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
+                                  const nv_planes out[3], void* stream);
+
 /* Clip-level streaming (section 3.2: one function from clip to enhanced clip).
  * push(t) unpacks frame t, runs the scene metric and the extract stage, and emits the
  * two outputs of group t-1 (frame t-1 at t = 0, then the interpolated frame), so

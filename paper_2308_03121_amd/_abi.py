@@ -16,6 +16,7 @@ NV_FP32, NV_FP16, NV_BF16, NV_FP8_E4M3 = range(4)
 NV_FLAG_INTERP, NV_FLAG_EXTRA, NV_FLAG_DOUBLE = 1, 2, 4
 NV_FLAG_HEAD_FP32 = 8
 NV_FLAG_FP8_FUSION = 16
+NV_STATIC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {0: "NV_OK", 1: "NV_E_INVALID", 2: "NV_E_UNSUPPORTED", 3: "NV_E_NOMEM",
                 4: "NV_E_DEVICE", 5: "NV_E_BUSY"}
 
@@ -61,6 +62,8 @@ _SIGS = {
                           c_void_p, c_uint32, POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
     "nv_enhance_group": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), POINTER(NvPlanes),
                                    c_void_p]),
+    "nv_enhance_group_static": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), POINTER(NvPlanes),
+                                          c_void_p]),
     "nv_stream_open": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvSceneParams), POINTER(c_void_p)]),
     "nv_stream_push": (c_int32, [c_void_p, POINTER(NvPlanes), c_int32, POINTER(NvPlanes),
                                  POINTER(c_int32), c_void_p]),

@@ -186,6 +186,17 @@ class Context:
         check(_abi.load().nv_enhance_group(self._h, byref(fmt), pin, pout, c_void_p(_stream(stream))))
         return outs
 
+    def enhance_group_static(self, fmt: NvFormat, frame_a, frame_b, outs=None, stream=None):
+        """enhance_group through the allocation-free entry point (nv_enhance_group_static):
+        the library's temporaries live in its static per-device scratch."""
+        if outs is None:
+            outs = [alloc_frame(2 * fmt.width, 2 * fmt.height, fmt.bits, fmt.chroma, frame_a[0].device)
+                    for _ in range(3)]
+        pin = (NvPlanes * 2)(planes_struct(*frame_a), planes_struct(*frame_b))
+        pout = (NvPlanes * 3)(*[planes_struct(*o) for o in outs])
+        check(_abi.load().nv_enhance_group_static(self._h, byref(fmt), pin, pout, c_void_p(_stream(stream))))
+        return outs
+
     def stream_footprint(self, fmt: NvFormat) -> int:
         n = c_size_t()
         check(_abi.load().nv_stream_footprint(self._h, byref(fmt), byref(n)))

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -154,6 +155,7 @@ FrameOut to_frame_out(const nv_format* f, const nv_planes* p) {
 }
 
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Every device allocation of the library goes through here.  Test hook: when the
 // environment variable NNVISR_FAULT_ALLOC_MIN_BYTES holds a positive number, requests
@@ -179,6 +181,41 @@ template <class T>
 void dev_free(T*& p) {
   if (p) (void)hipFree(p);
   p = nullptr;
+}
+
+}  // namespace
+
+// ------------------------------------------------------- static scratch ----
+
+// Device scratch of the allocation-free group entry point (nv_enhance_group_static):
+// one copy per device, allocated by the runtime with the code object and held until the
+// process ends.  In host code the array's name is not a device address; the address of
+// each device's copy comes from hipGetSymbolAddress at context creation (g_scratch_addr)
+// and only that is passed to kernels.
+static __device__ __align__(256) unsigned char g_static_scratch[NV_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Looks up the device address of the scratch array on `device`, the current device,
+// once per device.
+nv_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(NV_E_UNSUPPORTED, "device %d (at most %d)", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device]) return NV_OK;
+  void* p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(g_static_scratch)));
+  if (!p) return fail(NV_E_DEVICE, "no device address for the static scratch on device %d", device);
+  g_scratch_addr[device] = p;
+  return NV_OK;
+}
+
+void* scratch_addr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_addr[device] : nullptr;
 }
 
 }  // namespace
@@ -755,8 +792,8 @@ static bool resblocks_fused(const nv_context* ctx) {
          resblock_supported(ctx->blocks[0], ctx->blocks[1], ctx->ft);
 }
 
-nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
-  NV_TRY(ensure_workspace(ctx, hp, wp));
+// The extract stage of one frame in workspace ws (at least hp x wp).
+nv_status extract_impl(nv_context* ctx, Workspace& ws, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
   const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
   NV_TRY(timed(ctx, NV_K_CONV_IN, s, "conv_in",
                [&] { return launch_conv_in(ctx->conv_in, ft, rgb, feat, hp, wp, s); }));
@@ -764,7 +801,7 @@ nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* 
   if (resblocks_fused(ctx)) {
     // ping-pong between feat and the workspace map; an odd block count ends with a copy
     void* a = feat;
-    void* b = ctx->ws.t0;
+    void* b = ws.t0;
     for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
       const ConvImg im = conv_img(a, nullptr, nullptr, nullptr, nullptr, nullptr, b, hp, wp);
       NV_TRY(timed(ctx, NV_K_RESBLOCK, s, "resblock",
@@ -774,14 +811,14 @@ nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* 
     if (a != feat) HIP_TRY(hipMemcpyAsync(feat, a, n * dtype_bytes(ft), hipMemcpyDeviceToDevice, s));
     return NV_OK;
   }
-  const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ctx->ws.t0, hp, wp);
-  const ConvImg ib = conv_img(ctx->ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
+  const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
+  const ConvImg ib = conv_img(ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
     if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r, {feat}, n, s));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.a", [&] {
       return launch_conv(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, ia, C, 0, s);
     }));
-    if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r + 1, {ctx->ws.t0}, n, s));
+    if (ctx->calibrating) NV_TRY(calib_layer(ctx, 2 * r + 1, {ws.t0}, n, s));
     NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "block.b", [&] {
       return launch_conv(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, ib, C, 0, s);
     }));
@@ -789,13 +826,12 @@ nv_status extract_impl(nv_context* ctx, const float* rgb, int hp, int wp, void* 
   return NV_OK;
 }
 
-// After HR output t has been written to hr_out[t], pack it into pack_out[t] when given.
-nv_status fuse_impl(nv_context* ctx, const float* rgb_a, const float* rgb_b, const void* fa,
+// The fusion stage of group [a, b] in workspace ws (at least hp x wp).  After HR
+// output t has been written to hr_out[t], it is packed into pack_out[t] when given.
+nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const float* rgb_b, const void* fa,
                     const void* fb, int hp, int wp, const uint32_t* sel, uint32_t mask,
                     float* const hr_out[3], float* offs_out, void* fmid_out,
                     const nv_format* pack_fmt, const nv_planes* const pack_out[3], hipStream_t s) {
-  NV_TRY(ensure_workspace(ctx, hp, wp));
-  Workspace& ws = ctx->ws;
   const int C = ctx->C, G = ctx->G, ft = ctx->ft;
   float* offs = offs_out ? offs_out : ws.offs;
   void* fmid = fmid_out ? fmid_out : ws.fmid;
@@ -879,6 +915,7 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(NV_E_INVALID, "device %d of %d", device, ndev);
   HIP_TRY(hipSetDevice(device));
+  NV_TRY(scratch_setup(device));
   nv_context* ctx = new (std::nothrow) nv_context;
   if (!ctx) return fail(NV_E_NOMEM, "host allocation failed");
   ctx->device = device;
@@ -1053,7 +1090,8 @@ extern "C" nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp,
   NV_TRY(check_dims(hp, wp));
   NV_TRY(check_ready(ctx));
   hipStream_t s = (hipStream_t)stream;
-  return ordered({&ctx->ws_ord}, s, [&] { return extract_impl(ctx, d_rgb, hp, wp, d_feat, s); });
+  NV_TRY(ensure_workspace(ctx, hp, wp));
+  return ordered({&ctx->ws_ord}, s, [&] { return extract_impl(ctx, ctx->ws, d_rgb, hp, wp, d_feat, s); });
 }
 
 extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
@@ -1067,9 +1105,10 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   for (int t = 0; t < 3; ++t)
     if ((out_mask & (1u << t)) && (!d_hr || !d_hr[t])) return fail(NV_E_INVALID, "d_hr[%d] is NULL", t);
   hipStream_t s = (hipStream_t)stream;
+  NV_TRY(ensure_workspace(ctx, hp, wp));
   return ordered({&ctx->ws_ord}, s, [&] {
-    return fuse_impl(ctx, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets, d_fmid,
-                     nullptr, nullptr, s);
+    return fuse_impl(ctx, ctx->ws, d_rgb_a, d_rgb_b, d_feat_a, d_feat_b, hp, wp, d_sel, out_mask, d_hr, d_offsets,
+                     d_fmid, nullptr, nullptr, s);
   });
 }
 
@@ -1091,12 +1130,84 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
     for (int i = 0; i < 2; ++i) {
       const Frame f = to_frame(fmt, &in[i]);
       NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
-      NV_TRY(extract_impl(ctx, ws.rgb[i], hp, wp, ws.feat[i], s));
+      NV_TRY(extract_impl(ctx, ws, ws.rgb[i], hp, wp, ws.feat[i], s));
     }
     const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
-    return fuse_impl(ctx, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
+    return fuse_impl(ctx, ws, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
                      nullptr, &of, po, s);
   });
+}
+
+// ------------------------------------------------- allocation-free group ----
+
+namespace {
+
+// Bytes the group path needs at padded size hp x wp, and (base not null) the workspace
+// carved from base with every buffer 256-byte aligned.  Same buffers as ensure_workspace.
+size_t static_layout(const nv_context* ctx, int hp, int wp, char* base, Workspace* out) {
+  const size_t px = (size_t)hp * wp, C = ctx->C, fb = dtype_bytes(ctx->ft);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  Workspace w;
+  w.t0 = take(px * C * fb);
+  w.o1 = reinterpret_cast<float*>(take(px * C * 4));
+  w.offs = reinterpret_cast<float*>(take(px * ctx->ldo * 4));
+  w.fmid = take(px * C * fb);
+  w.u = take(4 * px * C * fb);
+  w.hr = reinterpret_cast<float*>(take(48 * px));
+  for (int i = 0; i < 2; ++i) {
+    w.rgb[i] = reinterpret_cast<float*>(take(12 * px));
+    w.feat[i] = take(px * C * fb);
+  }
+  w.hp = hp;
+  w.wp = wp;
+  w.bytes = off;
+  if (out) *out = w;
+  return off;
+}
+
+}  // namespace
+
+extern "C" nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
+                                             const nv_planes out[3], void* stream) {
+  if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
+  NV_TRY(check_ready(ctx));
+  NV_TRY(check_format(fmt, "input"));
+  NV_TRY(check_planes(fmt, &in[0], "input 0"));
+  NV_TRY(check_planes(fmt, &in[1], "input 1"));
+  const nv_format of = out_format(fmt);
+  NV_TRY(check_format(&of, "output"));
+  for (int i = 0; i < 3; ++i) NV_TRY(check_planes(&of, &out[i], "output"));
+  const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
+  const size_t need = static_layout(ctx, hp, wp, nullptr, nullptr);
+  if (need > (size_t)NV_STATIC_SCRATCH_BYTES)
+    return fail(NV_E_INVALID, "a %dx%d group needs %zu bytes of scratch; the static scratch holds %zu",
+                fmt->width, fmt->height, need, (size_t)NV_STATIC_SCRATCH_BYTES);
+  void* base = scratch_addr(ctx->device);
+  if (!base) return fail(NV_E_DEVICE, "static scratch of device %d was not set up", ctx->device);
+  Workspace ws;
+  static_layout(ctx, hp, wp, static_cast<char*>(base), &ws);
+  hipStream_t s = (hipStream_t)stream;
+  // launch timing would create events: this entry point runs untimed
+  const bool prof = ctx->prof.on;
+  ctx->prof.on = false;
+  nv_status st = NV_OK;
+  for (int i = 0; i < 2 && st == NV_OK; ++i) {
+    const Frame f = to_frame(fmt, &in[i]);
+    st = check_launch(launch_unpack(f, ws.rgb[i], hp, wp, s), "unpack");
+    if (st == NV_OK) st = extract_impl(ctx, ws, ws.rgb[i], hp, wp, ws.feat[i], s);
+  }
+  if (st == NV_OK) {
+    const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
+    st = fuse_impl(ctx, ws, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
+                   nullptr, &of, po, s);
+  }
+  ctx->prof.on = prof;
+  return st;
 }
 
 // ------------------------------------------------------------------- FP8 ----
@@ -1120,9 +1231,9 @@ extern "C" nv_status nv_calibrate(nv_context* ctx, const nv_format* fmt, const n
       const int cur = i & 1, prv = cur ^ 1;
       const Frame f = to_frame(fmt, &frames[i]);
       r = check_launch(launch_unpack(f, ws.rgb[cur], hp, wp, s), "unpack");
-      if (r == NV_OK) r = extract_impl(ctx, ws.rgb[cur], hp, wp, ws.feat[cur], s);
+      if (r == NV_OK) r = extract_impl(ctx, ws, ws.rgb[cur], hp, wp, ws.feat[cur], s);
       if (r == NV_OK && i > 0 && ctx->ut == DT_F8)
-        r = fuse_impl(ctx, ws.rgb[prv], ws.rgb[cur], ws.feat[prv], ws.feat[cur], hp, wp, nullptr, 7u, nullptr,
+        r = fuse_impl(ctx, ws, ws.rgb[prv], ws.rgb[cur], ws.feat[prv], ws.feat[cur], hp, wp, nullptr, 7u, nullptr,
                       nullptr, nullptr, nullptr, nullptr, s);
     }
     return r;
@@ -1302,7 +1413,8 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
 static nv_status emit_group(nv_stream* s, int slot_a, int slot_b, const uint32_t* cut_b,
                             const nv_planes out[2], hipStream_t hs) {
   const nv_planes* po[3] = {&out[0], &out[1], nullptr};
-  return fuse_impl(s->ctx, s->rgb[slot_a], s->rgb[slot_b], s->feat[slot_a], s->feat[slot_b], s->hp,
+  NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
+  return fuse_impl(s->ctx, s->ctx->ws, s->rgb[slot_a], s->rgb[slot_b], s->feat[slot_a], s->feat[slot_b], s->hp,
                    s->wp, cut_b, 3u, nullptr, nullptr, nullptr, &s->ofmt, po, hs);
 }
 
@@ -1346,7 +1458,8 @@ static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t externa
   J.rule = s->rule;
   J.external = external_cut;
   NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] { return launch_scene(J, false, hs); }));
-  NV_TRY(extract_impl(s->ctx, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
+  NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
+  NV_TRY(extract_impl(s->ctx, s->ctx->ws, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
   *n_out = 0;
   if (s->t > 0) {
     NV_TRY(emit_group(s, prv, cur, cut_t, out, hs));
@@ -1451,8 +1564,6 @@ struct BatchState {
 };
 
 namespace {
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 nv_status pool_reserve(Pool& p, size_t bytes, bool* grew) {
   *grew = false;

@@ -58,7 +58,7 @@ static void* dev(size_t bytes, const void* init = nullptr) {
 static int run_net(int argc, char** argv) {
   if (argc < 9) return 2;
   const std::string dir = argv[2];
-  nv_net_config cfg;
+  nv_net_config cfg{};
   cfg.channels = atoi(argv[3]);
   cfg.res_blocks = atoi(argv[4]);
   cfg.offset_groups = atoi(argv[5]);
@@ -99,8 +99,105 @@ static int run_net(int argc, char** argv) {
   return 0;
 }
 
+// One 8-bit 4:2:0 frame of pseudo-random codes (planes padded to a 64-byte pitch).
+struct HostFrame {
+  std::vector<uint8_t> p[3];
+  int64_t pitch[3];
+};
+static HostFrame make_frame(int w, int h, uint32_t seed) {
+  HostFrame f;
+  uint32_t x = seed * 2654435761u + 12345u;
+  for (int i = 0; i < 3; ++i) {
+    const int pw = i ? w / 2 : w, ph = i ? h / 2 : h;
+    f.pitch[i] = (pw + 63) / 64 * 64;
+    f.p[i].assign((size_t)f.pitch[i] * ph, 0);
+    for (int y = 0; y < ph; ++y)
+      for (int c = 0; c < pw; ++c) {
+        x = x * 1664525u + 1013904223u;
+        f.p[i][(size_t)y * f.pitch[i] + c] = (uint8_t)(16 + (x >> 24) % 220);
+      }
+  }
+  return f;
+}
+static nv_planes to_dev(const HostFrame& f) {
+  nv_planes p;
+  for (int i = 0; i < 3; ++i) {
+    p.data[i] = dev(f.p[i].size(), f.p[i].data());
+    p.pitch_bytes[i] = f.pitch[i];
+  }
+  return p;
+}
+static nv_planes out_planes(int w, int h) {
+  HostFrame z;
+  for (int i = 0; i < 3; ++i) {
+    const int pw = i ? w / 2 : w, ph = i ? h / 2 : h;
+    z.pitch[i] = (pw + 63) / 64 * 64;
+    z.p[i].assign((size_t)z.pitch[i] * ph, 0);
+  }
+  return to_dev(z);
+}
+
+// driver static C R G PREC: nv_enhance_group_static against nv_enhance_group on two
+// groups in a row (the second smaller), bit for bit, and a group too large for the
+// static scratch rejected with NV_E_INVALID.
+static int run_static(int argc, char** argv) {
+  if (argc < 6) return 2;
+  nv_net_config cfg{};
+  cfg.channels = atoi(argv[2]);
+  cfg.res_blocks = atoi(argv[3]);
+  cfg.offset_groups = atoi(argv[4]);
+  cfg.scale = 2;
+  cfg.align = 8;
+  cfg.flags = NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE;
+  cfg.precision = atoi(argv[5]);
+  std::vector<float> w(nv_weight_count(&cfg));
+  uint32_t x = 7;
+  for (float& v : w) {
+    x = x * 1664525u + 1013904223u;
+    v = ((int)(x >> 9) - (1 << 22)) / (float)(1 << 22) * 0.05f;
+  }
+  nv_context* ctx = nullptr;
+  CHECK(nv_context_create(0, &cfg, w.data(), w.size(), &ctx));
+  const int sizes[2][2] = {{40, 24}, {24, 16}};
+  for (int k = 0; k < 2; ++k) {
+    const int W = sizes[k][0], H = sizes[k][1];
+    nv_format fmt{W, H, 8, 420};
+    const nv_planes in[2] = {to_dev(make_frame(W, H, 1 + k)), to_dev(make_frame(W, H, 11 + k))};
+    nv_planes ref[3], got[3];
+    for (int t = 0; t < 3; ++t) {
+      ref[t] = out_planes(2 * W, 2 * H);
+      got[t] = out_planes(2 * W, 2 * H);
+    }
+    CHECK(nv_enhance_group(ctx, &fmt, in, ref, nullptr));
+    CHECK(nv_enhance_group_static(ctx, &fmt, in, got, nullptr));
+    for (int t = 0; t < 3; ++t)
+      for (int i = 0; i < 3; ++i) {
+        const size_t n = (size_t)ref[t].pitch_bytes[i] * (i ? H : 2 * H);
+        if (memcmp(ref[t].data[i], got[t].data[i], n) != 0) {
+          fprintf(stderr, "static: group %dx%d output %d plane %d differs\n", W, H, t, i);
+          return 1;
+        }
+      }
+    fprintf(stderr, "static: group %dx%d bit-identical\n", W, H);
+  }
+  nv_format big{4096, 4096, 8, 420};
+  const nv_planes bin[2] = {out_planes(4096, 4096), out_planes(4096, 4096)};
+  nv_planes bo[3];
+  for (int t = 0; t < 3; ++t) bo[t] = out_planes(8192, 8192);
+  const nv_status st = nv_enhance_group_static(ctx, &big, bin, bo, nullptr);
+  if (st != NV_E_INVALID) {
+    fprintf(stderr, "static: 4096x4096 group returned %d, expected NV_E_INVALID\n", (int)st);
+    return 1;
+  }
+  fprintf(stderr, "static: oversized group rejected: %s\n", nv_last_error());
+  CHECK(nv_context_destroy(ctx));
+  fprintf(stderr, "static ok\n");
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc >= 2 && strcmp(argv[1], "net") == 0) return run_net(argc, argv);
-  fprintf(stderr, "usage: driver net DIR C R G PREC H W\n");
+  if (argc >= 2 && strcmp(argv[1], "static") == 0) return run_static(argc, argv);
+  fprintf(stderr, "usage: driver net DIR C R G PREC H W | driver static C R G PREC\n");
   return 2;
 }

@@ -654,6 +654,11 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
   delete x;
   return hipSuccess;
 }
+// device-side statics are host statics in this build: the symbol's address is the array's
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) {
   for (auto& op : x->ops) op();
   return hipSuccess;

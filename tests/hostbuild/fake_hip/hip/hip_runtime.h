@@ -63,3 +63,7 @@ hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, void* a, void* b
 hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphExecDestroy(hipGraphExec_t x);
 hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s);
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
+#define HIP_SYMBOL(x) (reinterpret_cast<const void*>(&(x)))
+#define __align__(n) __attribute__((aligned(n)))
+#define __device__

@@ -107,3 +107,10 @@ def test_network_case_in_simulation(driver, tmp_path, C, R, G, H, W):
     for t, key in enumerate((0.0, 0.5, 1.0)):
         hr = np.fromfile(tmp_path / f"hr{t}.bin", dtype=np.float32).reshape(3, 2 * H, 2 * W)
         assert np.abs(hr - full[key]).max() <= FLOAT_TOL, t
+
+
+def test_static_group_entry_in_simulation(driver):
+    """nv_enhance_group_static is bit-identical to nv_enhance_group on two groups in a
+    row (the second smaller) and rejects a group too large for its static scratch."""
+    out = _run(driver, ["static", 32, 2, 8, 0], timeout=600)
+    assert "static ok" in out, out[-2000:]
