@@ -14,8 +14,10 @@
  *    is enqueued asynchronously on it; buffers must stay valid until it completes.
  *  - Arguments are validated on the host before anything is enqueued.  On any error
  *    nothing is enqueued, no state changes, and nv_last_error() describes why.
- *  - Colour is ITU-R BT.709, limited range, non-linear R'G'B'; 4:2:0 chroma is
- *    left-sited (co-sited with even luma columns, between luma rows 2i and 2i+1).
+ *  - Colour is non-linear R'G'B' and Y'CbCr of the frame format's colourspace (matrix,
+ *    range and 4:2:0 chroma siting, see nv_format); by default ITU-R BT.709, limited
+ *    range, left-sited chroma (co-sited with even luma columns, between luma rows 2i
+ *    and 2i+1).
  *  - A context is used by one host thread at a time; calls on one context that
  *    overlap in time are not supported.  Successive calls may use different HIP
  *    streams: device work that reuses the context's workspace, or one clip stream's
@@ -77,11 +79,31 @@ enum { NV_FLAG_HEAD_FP32 = 8 };
  * network's worst window). */
 enum { NV_FLAG_FP8_FUSION = 16 };
 
+/* Colourspace of a frame (section 3.1, colourspace paragraph: the same code values mean
+ * different colours under different colourspaces, so the matrix and range travel with
+ * the frame and a network is trained for one colourspace).
+ *  matrix      NV_MATRIX_BT709 (ITU-R BT.709), NV_MATRIX_BT601 (BT.601), NV_MATRIX_BT2020
+ *              (BT.2020 non-constant luminance): the luma weights Kr, Kb of
+ *              Y' = Kr R' + (1 - Kr - Kb) G' + Kb B', Cb' = (B' - Y') / (2 (1 - Kb)),
+ *              Cr' = (R' - Y') / (2 (1 - Kr)).
+ *  range       NV_RANGE_LIMITED: Y = (219 Y' + 16) 2^(b-8), C = (224 C' + 128) 2^(b-8);
+ *              NV_RANGE_FULL: Y = (2^b - 1) Y', C = (2^b - 1) C' + 2^(b-1).
+ *  chroma_loc  4:2:0 only.  NV_SITING_LEFT (MPEG-2): chroma sample (i, j) at luma column
+ *              2j, halfway between rows 2i and 2i+1; bilinear upsampling, (1/4, 1/2, 1/4) x
+ *              (1/2, 1/2) downsampling.  NV_SITING_CENTER (MPEG-1 / JPEG): at the centre of
+ *              its 2x2 luma block; bilinear upsampling, 2x2 box downsampling.
+ * Zero in all three is BT.709, limited range, left siting. */
+enum { NV_MATRIX_BT709 = 0, NV_MATRIX_BT601 = 1, NV_MATRIX_BT2020 = 2 };
+enum { NV_RANGE_LIMITED = 0, NV_RANGE_FULL = 1 };
+enum { NV_SITING_LEFT = 0, NV_SITING_CENTER = 1 };
+
 /* Frame format.  width/height are luma sizes (even for 4:2:0); bits is 8 (uint8
  * samples) or 10 (uint16 little-endian samples holding the code in the low 10 bits;
- * the upper 6 bits are ignored on input and written as zero); chroma is 420 or 444. */
+ * the upper 6 bits are ignored on input and written as zero); chroma is 420 or 444;
+ * matrix, range and chroma_loc as above. */
 typedef struct {
   int32_t width, height, bits, chroma;
+  int32_t matrix, range, chroma_loc;
 } nv_format;
 
 /* Planar Y, Cb, Cr.  pitch_bytes[i] is the distance between rows of plane i. */
@@ -93,11 +115,18 @@ typedef struct {
 /* Network shape.  channels C (32 or 64; 64 for NV_FP8_E4M3), res_blocks R (0..64),
  * offset_groups G (even, 2C divisible by G, 2C/G a multiple of 4), scale must be 2,
  * align must be 8, flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE, optionally
- * with NV_FLAG_HEAD_FP32 and (FP8 only) NV_FLAG_FP8_FUSION. */
+ * with NV_FLAG_HEAD_FP32 and (FP8 only) NV_FLAG_FP8_FUSION.  matrix and range name the
+ * colourspace the weights were trained for (section 3.1: networks are trained per
+ * colourspace and the one matching the clip is used): the enhancement calls of the
+ * context (group, clip stream, batch, calibration) refuse frames of another matrix or
+ * range with NV_E_UNSUPPORTED, so a caller holding one context per colourspace selects
+ * the network by the clip's format.  The pixel-format stages alone (nv_unpack, nv_pack,
+ * nv_scene_metric) take any colourspace. */
 typedef struct {
   int32_t channels, res_blocks, offset_groups, scale, align;
   uint32_t flags;
   int32_t precision;     /* nv_precision */
+  int32_t matrix, range; /* colourspace of the training data: NV_MATRIX_*, NV_RANGE_* */
 } nv_net_config;
 
 /* Scene-change rule: frame t starts a scene when
@@ -156,7 +185,8 @@ nv_status nv_fp8_scales(nv_context* ctx, float* amax, int32_t n, int32_t set, vo
 /* ------------------------------------------------- pixel-format stages ---- */
 
 /* Unpack one frame (section 3.1, pixel formats): decode codes, upsample 4:2:0 chroma
- * bilinearly, apply the BT.709 inverse matrix (no clamp), and write planar float32
+ * bilinearly for its siting, normalise by its range and apply its matrix's inverse (no
+ * clamp), and write planar float32
  * R'G'B' d_rgb[3][hp][wp] (plane stride hp*wp floats).  hp >= height and wp >= width, wp a
  * multiple of 4, d_rgb 16-byte aligned;
  * rows/columns beyond the frame replicate the last row/column (alignment padding). */
@@ -165,7 +195,7 @@ nv_status nv_unpack(const nv_format* fmt, const nv_planes* in, float* d_rgb, int
 
 /* Requantise planar float32 R'G'B' to a frame of format `fmt` (section 3.1, pixel
  * formats: the enhanced frames leave in the clip's Y'CbCr format): clamp R'G'B' to [0,1],
- * BT.709 forward matrix, 4:2:0 chroma by the (1/4,1/2,1/4) x (1/2,1/2) left-sited
+ * the format's forward matrix and range, 4:2:0 chroma by its siting's downsampling
  * filter with replicated edges, code = clamp(floor(v + 1/2), 0, 2^bits - 1).  d_rgb
  * is [3][rh][rw] (rh >= fmt->height, rw >= fmt->width, rw a multiple of 4, d_rgb
  * 16-byte aligned); only the top-left fmt->height x fmt->width region is read (crop). */

@@ -4,6 +4,8 @@ Per frame: unpack + pad, scene metric, extract.  Per group [a, b] (section 3.3
 grouping with n = 1 and the Interpolation, Extra-frame and Double-frame flags
 of section 3.1): fusion into HR frames at t = 0 and t = 1/2 (t = 1 too for a
 lone group), crop to twice the input size, requantise to the input's format.
+``colour`` (a dict of ``pixel`` keyword arguments: matrix, full, centre) is the
+clip's colourspace, used by both pixel-format stages; None is the default reading.
 """
 from __future__ import annotations
 
@@ -27,31 +29,31 @@ def weights_dict(blob, layout):
     return out
 
 
-def frame_rgb(Y, U, V, bits, chroma, align=8):
-    return pixel.pad(pixel.unpack(Y, U, V, bits, chroma), align)
+def frame_rgb(Y, U, V, bits, chroma, align=8, colour=None):
+    return pixel.pad(pixel.unpack(Y, U, V, bits, chroma, **(colour or {})), align)
 
 
 def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
-                  times=(0.0, 0.5, 1.0), align=8, keep=False):
+                  times=(0.0, 0.5, 1.0), align=8, keep=False, colour=None):
     """One frame group.  fb_planes=None means the duplicated group [a, a].
 
     Returns {"codes": {t: (Y, Cb, Cr)}, "hr": {t: cropped float HR RGB}} plus the
     intermediates when keep=True.
     """
     h, w = fa_planes[0].shape
-    rgb_a = frame_rgb(*fa_planes, bits, chroma, align)
+    rgb_a = frame_rgb(*fa_planes, bits, chroma, align, colour)
     fa = network.extract(rgb_a, W, res_blocks)
     if fb_planes is None:
         rgb_b, fb = rgb_a, fa
     else:
-        rgb_b = frame_rgb(*fb_planes, bits, chroma, align)
+        rgb_b = frame_rgb(*fb_planes, bits, chroma, align, colour)
         fb = network.extract(rgb_b, W, res_blocks)
     res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=times, keep=keep)
     out = {"codes": {}, "hr": {}}
     for t in times:
         hr = res[t][:, :2 * h, :2 * w]
         out["hr"][t] = hr
-        out["codes"][t] = pixel.pack(hr, bits, chroma)
+        out["codes"][t] = pixel.pack(hr, bits, chroma, **(colour or {}))
     if keep:
         out.update(rgb_a=rgb_a, rgb_b=rgb_b, fa=fa, fb=fb, offsets=res["offsets"],
                    mask=res["mask"], fmid=res["fmid"])
@@ -59,7 +61,7 @@ def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
 
 
 def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.SceneParams(),
-                 external=None, align=8):
+                 external=None, align=8, colour=None):
     """A whole clip in stream order.  frames: list of (Y, U, V).
 
     Returns (cuts, outputs) where outputs is the list of 2N emitted frames, each
@@ -71,7 +73,7 @@ def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.Scene
 
     def feat(i):
         if i not in feat_cache:
-            rgb_cache[i] = frame_rgb(*frames[i], bits, chroma, align)
+            rgb_cache[i] = frame_rgb(*frames[i], bits, chroma, align, colour)
             feat_cache[i] = network.extract(rgb_cache[i], W, res_blocks)
         return rgb_cache[i], feat_cache[i]
 
@@ -83,7 +85,7 @@ def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.Scene
         for t in (0.0, 0.5):
             hr = res[t][:, :2 * h, :2 * w]
             outputs.append({"group": (a, b), "t": t, "hr": hr,
-                            "codes": pixel.pack(hr, bits, chroma)})
+                            "codes": pixel.pack(hr, bits, chroma, **(colour or {}))})
         for old in [k for k in feat_cache if k < a]:
             del feat_cache[old], rgb_cache[old]
     return cuts, outputs

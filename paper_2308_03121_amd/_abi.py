@@ -17,12 +17,17 @@ NV_FLAG_INTERP, NV_FLAG_EXTRA, NV_FLAG_DOUBLE = 1, 2, 4
 NV_FLAG_HEAD_FP32 = 8
 NV_FLAG_FP8_FUSION = 16
 NV_STATIC_SCRATCH_BYTES = 64 << 20
+NV_MATRIX_BT709, NV_MATRIX_BT601, NV_MATRIX_BT2020 = 0, 1, 2
+NV_RANGE_LIMITED, NV_RANGE_FULL = 0, 1
+NV_SITING_LEFT, NV_SITING_CENTER = 0, 1
+MATRIX_CODES = {709: NV_MATRIX_BT709, 601: NV_MATRIX_BT601, 2020: NV_MATRIX_BT2020}
 STATUS_NAMES = {0: "NV_OK", 1: "NV_E_INVALID", 2: "NV_E_UNSUPPORTED", 3: "NV_E_NOMEM",
                 4: "NV_E_DEVICE", 5: "NV_E_BUSY"}
 
 
 class NvFormat(ctypes.Structure):
-    _fields_ = [("width", c_int32), ("height", c_int32), ("bits", c_int32), ("chroma", c_int32)]
+    _fields_ = [("width", c_int32), ("height", c_int32), ("bits", c_int32), ("chroma", c_int32),
+                ("matrix", c_int32), ("range", c_int32), ("chroma_loc", c_int32)]
 
 
 class NvPlanes(ctypes.Structure):
@@ -31,7 +36,8 @@ class NvPlanes(ctypes.Structure):
 
 class NvNetConfig(ctypes.Structure):
     _fields_ = [("channels", c_int32), ("res_blocks", c_int32), ("offset_groups", c_int32),
-                ("scale", c_int32), ("align", c_int32), ("flags", c_uint32), ("precision", c_int32)]
+                ("scale", c_int32), ("align", c_int32), ("flags", c_uint32), ("precision", c_int32),
+                ("matrix", c_int32), ("range", c_int32)]
 
 
 class NvSceneParams(ctypes.Structure):

@@ -24,8 +24,12 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else c_void_p(t.data_ptr())
 
 
-def fmt_struct(width: int, height: int, bits: int, chroma: int) -> NvFormat:
-    return NvFormat(width, height, bits, chroma)
+def fmt_struct(width: int, height: int, bits: int, chroma: int, matrix: int = 709, full: bool = False,
+               centre: bool = False) -> NvFormat:
+    """Frame format; matrix 709 / 601 / 2020, full range, centre chroma siting (4:2:0)."""
+    return NvFormat(width, height, bits, chroma, _abi.MATRIX_CODES[matrix],
+                    _abi.NV_RANGE_FULL if full else _abi.NV_RANGE_LIMITED,
+                    _abi.NV_SITING_CENTER if centre else _abi.NV_SITING_LEFT)
 
 
 def chroma_shape(width, height, chroma):
@@ -117,7 +121,7 @@ class Context:
 
     def __init__(self, channels: int, res_blocks: int, offset_groups: int, weights: np.ndarray,
                  precision: str = "fp32", device: int = 0, head_fp32: bool = False,
-                 fp8_fusion: bool = False):
+                 fp8_fusion: bool = False, matrix: int = 709, full: bool = False):
         lib = _abi.load()
         flags = _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | _abi.NV_FLAG_DOUBLE
         if head_fp32:
@@ -125,7 +129,10 @@ class Context:
         if fp8_fusion:
             flags |= _abi.NV_FLAG_FP8_FUSION
         self.fp8_fusion = fp8_fusion
-        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, flags, PRECISIONS[precision])
+        # matrix / full: the colourspace the weights were trained for
+        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, flags, PRECISIONS[precision],
+                               _abi.MATRIX_CODES[matrix], _abi.NV_RANGE_FULL if full else _abi.NV_RANGE_LIMITED)
+        self.colourspace = (matrix, bool(full))
         w = np.ascontiguousarray(weights, dtype=np.float32)
         self._h = c_void_p()
         check(lib.nv_context_create(device, byref(self.cfg),
@@ -142,7 +149,7 @@ class Context:
 
     @staticmethod
     def weight_count(channels, res_blocks, offset_groups) -> int:
-        cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, 7, 0)
+        cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, 7, 0, 0, 0)
         return int(_abi.load().nv_weight_count(byref(cfg)))
 
     def close(self):

@@ -32,20 +32,42 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _filtered(text: str):
+    # the host pass does not know the packed-fp32 feature and says so; that is harmless
+    return [ln for ln in text.strip().splitlines() if "packed-fp32-ops" not in ln]
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source into libnnvisr.so (always rebuilds).  Returns the path."""
+    """Compile every source into libnnvisr.so (always rebuilds): the translation units
+    are compiled in parallel into objects under _build/, then linked.  Returns the path."""
+    obj_dir = os.path.join(ROOT, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(obj_dir, src + ".o")
+        cmd = [hipcc()] + compile_flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    objs, failed = [], []
+    for cmd, obj, p in procs:
+        lines = _filtered(p.communicate()[0])
+        if p.returncode != 0:
+            failed.append("hipcc failed: " + " ".join(cmd) + "\n" + "\n".join(lines))
+        elif verbose and lines:
+            print("\n".join(lines), flush=True)
+        objs.append(obj)
+    if failed:
+        raise RuntimeError("\n".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    out = (res.stdout + res.stderr).strip()
-    # the host pass does not know the packed-fp32 feature and says so; that is harmless
-    lines = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
+    lines = _filtered(res.stdout + res.stderr)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(lines))
-    if verbose and lines:
-        print("\n".join(lines), flush=True)
+        raise RuntimeError("link failed:\n" + "\n".join(lines))
     os.replace(tmp, LIB)
     return LIB
 

@@ -93,6 +93,10 @@ nv_status check_config(const nv_net_config* c) {
     return fail(NV_E_INVALID, "precision %d is not an nv_precision", c->precision);
   if (c->precision == NV_FP8_E4M3 && c->channels != 64)
     return fail(NV_E_UNSUPPORTED, "FP8 precision is implemented for 64 channels");
+  if (c->matrix != NV_MATRIX_BT709 && c->matrix != NV_MATRIX_BT601 && c->matrix != NV_MATRIX_BT2020)
+    return fail(NV_E_INVALID, "matrix %d is not an NV_MATRIX_* value", c->matrix);
+  if (c->range != NV_RANGE_LIMITED && c->range != NV_RANGE_FULL)
+    return fail(NV_E_INVALID, "range %d is not an NV_RANGE_* value", c->range);
   return NV_OK;
 }
 
@@ -110,8 +114,16 @@ nv_status check_format(const nv_format* f, const char* what) {
     return fail(NV_E_INVALID, "%s: size %dx%d out of range", what, f->width, f->height);
   if (f->chroma == 420 && ((f->width | f->height) & 1))
     return fail(NV_E_INVALID, "%s: 4:2:0 needs even width and height", what);
+  if (f->matrix != NV_MATRIX_BT709 && f->matrix != NV_MATRIX_BT601 && f->matrix != NV_MATRIX_BT2020)
+    return fail(NV_E_INVALID, "%s: matrix %d is not an NV_MATRIX_* value", what, f->matrix);
+  if (f->range != NV_RANGE_LIMITED && f->range != NV_RANGE_FULL)
+    return fail(NV_E_INVALID, "%s: range %d is not an NV_RANGE_* value", what, f->range);
+  if (f->chroma_loc != NV_SITING_LEFT && f->chroma_loc != NV_SITING_CENTER)
+    return fail(NV_E_INVALID, "%s: chroma_loc %d is not an NV_SITING_* value", what, f->chroma_loc);
   return NV_OK;
 }
+
+int matrix_number(int m) { return m == NV_MATRIX_BT601 ? 601 : (m == NV_MATRIX_BT2020 ? 2020 : 709); }
 
 nv_status check_planes(const nv_format* f, const nv_planes* p, const char* what) {
   if (!p) return fail(NV_E_INVALID, "%s planes are NULL", what);
@@ -138,6 +150,9 @@ Frame to_frame(const nv_format* f, const nv_planes* p) {
   r.h = f->height;
   r.bits = f->bits;
   r.chroma = f->chroma;
+  r.matrix = matrix_number(f->matrix);
+  r.full = f->range == NV_RANGE_FULL;
+  r.centre = f->chroma == 420 && f->chroma_loc == NV_SITING_CENTER;
   return r;
 }
 
@@ -151,6 +166,9 @@ FrameOut to_frame_out(const nv_format* f, const nv_planes* p) {
   r.h = f->height;
   r.bits = f->bits;
   r.chroma = f->chroma;
+  r.matrix = matrix_number(f->matrix);
+  r.full = f->range == NV_RANGE_FULL;
+  r.centre = f->chroma == 420 && f->chroma_loc == NV_SITING_CENTER;
   return r;
 }
 
@@ -1078,6 +1096,16 @@ static nv_status check_ready(const nv_context* ctx) {
   return NV_OK;
 }
 
+// The network of a context was trained for one colourspace; frames of another matrix or
+// range are refused (the caller selects the context whose network matches the clip).
+static nv_status check_colourspace(const nv_context* ctx, const nv_format* f) {
+  if (f->matrix != ctx->cfg.matrix || f->range != ctx->cfg.range)
+    return fail(NV_E_UNSUPPORTED, "the network was trained for BT.%d %s range, the frames are BT.%d %s range",
+                matrix_number(ctx->cfg.matrix), ctx->cfg.range == NV_RANGE_FULL ? "full" : "limited",
+                matrix_number(f->matrix), f->range == NV_RANGE_FULL ? "full" : "limited");
+  return NV_OK;
+}
+
 static nv_status check_dims(int hp, int wp) {
   if (hp <= 0 || wp <= 0 || hp % 8 || wp % 8 || hp > kMaxDim || wp > kMaxDim)
     return fail(NV_E_INVALID, "padded size %dx%d must be positive multiples of 8", wp, hp);
@@ -1117,6 +1145,7 @@ extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, con
   if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_ready(ctx));
   NV_TRY(check_format(fmt, "input"));
+  NV_TRY(check_colourspace(ctx, fmt));
   NV_TRY(check_planes(fmt, &in[0], "input 0"));
   NV_TRY(check_planes(fmt, &in[1], "input 1"));
   const nv_format of = out_format(fmt);
@@ -1177,6 +1206,7 @@ extern "C" nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* f
   if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_ready(ctx));
   NV_TRY(check_format(fmt, "input"));
+  NV_TRY(check_colourspace(ctx, fmt));
   NV_TRY(check_planes(fmt, &in[0], "input 0"));
   NV_TRY(check_planes(fmt, &in[1], "input 1"));
   const nv_format of = out_format(fmt);
@@ -1218,6 +1248,7 @@ extern "C" nv_status nv_calibrate(nv_context* ctx, const nv_format* fmt, const n
   if (ctx->bt != DT_F8) return fail(NV_E_INVALID, "only FP8 contexts are calibrated");
   if (n_frames < 2) return fail(NV_E_INVALID, "calibration needs at least 2 frames (got %d)", n_frames);
   NV_TRY(check_format(fmt, "input"));
+  NV_TRY(check_colourspace(ctx, fmt));
   for (int i = 0; i < n_frames; ++i) NV_TRY(check_planes(fmt, &frames[i], "calibration frame"));
   const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
   NV_TRY(ensure_workspace(ctx, hp, wp));
@@ -1375,6 +1406,7 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   if (!ctx || !out) return fail(NV_E_INVALID, "NULL argument");
   *out = nullptr;
   NV_TRY(check_format(fmt, "stream"));
+  NV_TRY(check_colourspace(ctx, fmt));
   NV_TRY(check_scene_params(params));
   nv_stream* s = new (std::nothrow) nv_stream;
   if (!s) return fail(NV_E_NOMEM, "host allocation failed");
@@ -1755,7 +1787,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     const Frame fr = to_frame(&s->fmt, F.in);
     UnpackJob& u = T.unpack[k];
     u.f = fr;
-    u.m = make_inv(fr.bits);
+    u.m = make_inv(fr.bits, fr.matrix, fr.full);
     u.rgb = s->rgb[sl];
     u.hp = hp;
     u.wp = wp;
@@ -1857,7 +1889,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
       h.item_begin = it[BL_HR];
       PackJob& pk = T.pack[o][k];
       pk.f = to_frame_out(&s->ofmt, &Gr.out[o]);
-      pk.m = make_fwd(s->ofmt.bits);
+      pk.m = make_fwd(pk.f.bits, pk.f.matrix, pk.f.full);
       pk.rgb = hr;
       pk.rh = 2 * hp;
       pk.rw = 2 * wp;

@@ -12,32 +12,71 @@
 
 namespace nv {
 
-Inv make_inv(int bits) {
-  const double s = double(1 << (bits - 8));
+namespace {
+
+// Luma weights (Kr, Kb) of ITU-R BT.601, BT.709 and BT.2020 (non-constant luminance).
+void luma_weights(int matrix, double& kr, double& kb) {
+  if (matrix == 601) {
+    kr = 0.299;
+    kb = 0.114;
+  } else if (matrix == 2020) {
+    kr = 0.2627;
+    kb = 0.0593;
+  } else {
+    kr = kKr;
+    kb = kKb;
+  }
+}
+
+// Code scale and offset of luma and chroma: limited range 219 / 16 and 224 / 128 times
+// 2^(b-8); full range 2^b - 1 / 0 and 2^b - 1 / 2^(b-1).
+void code_range(int bits, int full, double& ys, double& yo, double& cs, double& co) {
+  if (full) {
+    ys = cs = double((1 << bits) - 1);
+    yo = 0.0;
+    co = double(1 << (bits - 1));
+  } else {
+    const double s = double(1 << (bits - 8));
+    ys = 219.0 * s;
+    yo = 16.0 * s;
+    cs = 224.0 * s;
+    co = 128.0 * s;
+  }
+}
+
+}  // namespace
+
+Inv make_inv(int bits, int matrix, int full) {
+  double kr, kb, ys, yo, cs, co;
+  luma_weights(matrix, kr, kb);
+  code_range(bits, full, ys, yo, cs, co);
+  const double kg = 1.0 - kr - kb;
   Inv m;
-  m.ys = float(1.0 / (219.0 * s));
-  m.yo = float(16.0 * s);
-  m.cs = float(1.0 / (224.0 * s));
-  m.co = float(128.0 * s);
-  m.rcr = float(2.0 * (1.0 - kKr));
-  m.bcb = float(2.0 * (1.0 - kKb));
-  m.gcb = float(2.0 * kKb * (1.0 - kKb) / kKg);
-  m.gcr = float(2.0 * kKr * (1.0 - kKr) / kKg);
+  m.ys = float(1.0 / ys);
+  m.yo = float(yo);
+  m.cs = float(1.0 / cs);
+  m.co = float(co);
+  m.rcr = float(2.0 * (1.0 - kr));
+  m.bcb = float(2.0 * (1.0 - kb));
+  m.gcb = float(2.0 * kb * (1.0 - kb) / kg);
+  m.gcr = float(2.0 * kr * (1.0 - kr) / kg);
   return m;
 }
 
-Fwd make_fwd(int bits) {
-  const double s = double(1 << (bits - 8));
+Fwd make_fwd(int bits, int matrix, int full) {
+  double kr, kb, ys, yo, cs, co;
+  luma_weights(matrix, kr, kb);
+  code_range(bits, full, ys, yo, cs, co);
   Fwd m;
-  m.kr = float(kKr);
-  m.kg = float(kKg);
-  m.kb = float(kKb);
-  m.cbs = float(1.0 / (2.0 * (1.0 - kKb)));
-  m.crs = float(1.0 / (2.0 * (1.0 - kKr)));
-  m.ys = float(219.0 * s);
-  m.yo = float(16.0 * s);
-  m.cs = float(224.0 * s);
-  m.co = float(128.0 * s);
+  m.kr = float(kr);
+  m.kg = float(1.0 - kr - kb);
+  m.kb = float(kb);
+  m.cbs = float(1.0 / (2.0 * (1.0 - kb)));
+  m.crs = float(1.0 / (2.0 * (1.0 - kr)));
+  m.ys = float(ys);
+  m.yo = float(yo);
+  m.cs = float(cs);
+  m.co = float(co);
   m.maxc = float((1 << bits) - 1);
   return m;
 }
@@ -137,9 +176,13 @@ __device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
 }
 
 // ---- unpack: four consecutive padded pixels of one row of each plane per thread ----
-// (Y'CbCr -> R'G'B': Y' = (Y - 16s) / 219s, C' = (C - 128s) / 224s,
-//  R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr')
-template <int BITS, bool C420>
+// (Y'CbCr -> R'G'B': Y' = (Y - yo) / ys, C' = (C - co) / cs with the range's scale and
+//  offset, R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr')
+// 4:2:0 chroma is first blended between its two nearest chroma rows (3/4, 1/4), then
+// along the row: left siting (CTR false) takes chroma column j at luma column 2j and the
+// mean of columns j, j+1 at 2j+1; centre siting takes 3/4 of column j and 1/4 of column
+// j-1 (at 2j) or j+1 (at 2j+1).  Edge columns and rows are replicated.
+template <int BITS, bool C420, bool CTR>
 __device__ __forceinline__ void unpack_px4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp,
                                            int wp, int y, int x0) {
   const int sy = min(y, f.h - 1);
@@ -160,7 +203,15 @@ __device__ __forceinline__ void unpack_px4(const Frame& f, const Inv& m, float* 
                         0.25f * Code<BITS>::get(f.p[1], f.pitch[1], ci2, cj);
       const float cr0 = 0.75f * Code<BITS>::get(f.p[2], f.pitch[2], ci, cj) +
                         0.25f * Code<BITS>::get(f.p[2], f.pitch[2], ci2, cj);
-      if (sx & 1) {
+      if (CTR) {
+        const int cn = (sx & 1) ? min(cj + 1, wc - 1) : max(cj - 1, 0);
+        const float cbn = 0.75f * Code<BITS>::get(f.p[1], f.pitch[1], ci, cn) +
+                          0.25f * Code<BITS>::get(f.p[1], f.pitch[1], ci2, cn);
+        const float crn = 0.75f * Code<BITS>::get(f.p[2], f.pitch[2], ci, cn) +
+                          0.25f * Code<BITS>::get(f.p[2], f.pitch[2], ci2, cn);
+        cb = 0.75f * cb0 + 0.25f * cbn;
+        cr = 0.75f * cr0 + 0.25f * crn;
+      } else if (sx & 1) {
         const int cj1 = min(cj + 1, wc - 1);
         const float cb1 = 0.75f * Code<BITS>::get(f.p[1], f.pitch[1], ci, cj1) +
                           0.25f * Code<BITS>::get(f.p[1], f.pitch[1], ci2, cj1);
@@ -212,7 +263,7 @@ __device__ __forceinline__ void code_pair(const void* base, int64_t pitch, int y
 // the frame read each plane row with vector loads (luma 4 codes; 4:2:0 chroma the 2 + 1
 // codes the bilinear filter needs from rows ci and ci2); runs that reach into the
 // padding use the per-pixel form.
-template <int BITS, bool C420>
+template <int BITS, bool C420, bool CTR = false>
 __device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __restrict__ rgb, int hp, int wp,
                                         int gid) {
   const int groups_per_row = wp >> 2;   // wp is a multiple of 4
@@ -220,7 +271,7 @@ __device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __r
   const int y = gid / groups_per_row;
   const int x0 = (gid - y * groups_per_row) << 2;
   if (x0 + 4 > f.w) {
-    unpack_px4<BITS, C420>(f, m, rgb, hp, wp, y, x0);
+    unpack_px4<BITS, C420, CTR>(f, m, rgb, hp, wp, y, x0);
     return;
   }
   const int sy = min(y, f.h - 1);
@@ -230,19 +281,30 @@ __device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __r
     const int hc = f.h >> 1, wc = f.w >> 1;
     const int ci = sy >> 1;
     const int ci2 = (sy & 1) ? min(ci + 1, hc - 1) : max(ci - 1, 0);
-    const int c0 = x0 >> 1, c2 = min(c0 + 2, wc - 1);
+    const int c0 = x0 >> 1, c2 = min(c0 + 2, wc - 1), cl = max(c0 - 1, 0);
 #pragma unroll
     for (int pl = 1; pl <= 2; ++pl) {
-      float top[2], bot[2], vb[3];
+      // vb[i]: chroma column c0 + i - 1 (cl, c0, c0 + 1, c2) blended between rows ci, ci2
+      float top[2], bot[2], vb[4];
       code_pair<BITS>(f.p[pl], f.pitch[pl], ci, c0, top);
       code_pair<BITS>(f.p[pl], f.pitch[pl], ci2, c0, bot);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) vb[i] = 0.75f * top[i] + 0.25f * bot[i];
-      vb[2] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, c2) +
+      for (int i = 0; i < 2; ++i) vb[1 + i] = 0.75f * top[i] + 0.25f * bot[i];
+      vb[3] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, c2) +
               0.25f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci2, c2);
       float* c = pl == 1 ? cb : cr;
+      if (CTR) {
+        vb[0] = 0.75f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci, cl) +
+                0.25f * Code<BITS>::get(f.p[pl], f.pitch[pl], ci2, cl);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) c[k] = (k & 1) ? 0.5f * (vb[k >> 1] + vb[(k >> 1) + 1]) : vb[k >> 1];
+        for (int k = 0; k < 4; ++k) {
+          const int j = 1 + (k >> 1);                  // this pixel's chroma column
+          c[k] = 0.75f * vb[j] + 0.25f * vb[(k & 1) ? j + 1 : j - 1];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = (k & 1) ? 0.5f * (vb[1 + (k >> 1)] + vb[2 + (k >> 1)]) : vb[1 + (k >> 1)];
+      }
     }
   } else {
     code_run<BITS, 4>(f.p[1], f.pitch[1], sy, x0, f.w, cb);
@@ -267,18 +329,20 @@ __device__ __forceinline__ void unpack4(const Frame& f, const Inv& m, float* __r
 
 __device__ __forceinline__ void unpack_any(const Frame& f, const Inv& m, float* rgb, int hp, int wp, int gid) {
   if (f.bits == 8) {
-    if (f.chroma == 420) unpack4<8, true>(f, m, rgb, hp, wp, gid);
-    else unpack4<8, false>(f, m, rgb, hp, wp, gid);
+    if (f.chroma != 420) unpack4<8, false>(f, m, rgb, hp, wp, gid);
+    else if (f.centre) unpack4<8, true, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<8, true>(f, m, rgb, hp, wp, gid);
   } else {
-    if (f.chroma == 420) unpack4<10, true>(f, m, rgb, hp, wp, gid);
-    else unpack4<10, false>(f, m, rgb, hp, wp, gid);
+    if (f.chroma != 420) unpack4<10, false>(f, m, rgb, hp, wp, gid);
+    else if (f.centre) unpack4<10, true, true>(f, m, rgb, hp, wp, gid);
+    else unpack4<10, true>(f, m, rgb, hp, wp, gid);
   }
 }
 
-template <int BITS, bool C420>
+template <int BITS, bool C420, bool CTR>
 __global__ __launch_bounds__(256) void k_unpack(Frame f, Inv m, float* __restrict__ rgb, int hp,
                                                 int wp) {
-  unpack4<BITS, C420>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
+  unpack4<BITS, C420, CTR>(f, m, rgb, hp, wp, blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_unpack_batch(const UnpackJob* __restrict__ jobs,
@@ -297,9 +361,10 @@ __device__ __forceinline__ int quant(float v, float maxc) {
   return (int)fminf(fmaxf(floorf(v + 0.5f), 0.0f), maxc);
 }
 
-// 4:2:0: one thread per chroma sample, i.e. one 2x2 luma block and the chroma filter
-// (1/4, 1/2, 1/4) over columns 2j-1..2j+1 times (1/2, 1/2) over rows 2i, 2i+1.
-template <int BITS>
+// 4:2:0: one thread per chroma sample, i.e. one 2x2 luma block and the chroma filter:
+// left siting (1/4, 1/2, 1/4) over columns 2j-1..2j+1 times (1/2, 1/2) over rows 2i,
+// 2i+1; centre siting (CTR) the mean of the 2x2 block.
+template <int BITS, bool CTR>
 __device__ __forceinline__ void pack420_px(const FrameOut& f, const Fwd& m,
                                            const float* __restrict__ rgb, int rh, int rw, int gid) {
   const int wc = f.w >> 1, hc = f.h >> 1;
@@ -312,13 +377,13 @@ __device__ __forceinline__ void pack420_px(const FrameOut& f, const Fwd& m,
     const int yy = 2 * i + dy;
     const float* row = rgb + (size_t)yy * rw;
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
+    for (int dx = CTR ? 0 : -1; dx <= 1; ++dx) {
       const int xx = max(2 * j + dx, 0);
       const float R = clamp01(row[xx]);
       const float G = clamp01(row[xx + plane]);
       const float B = clamp01(row[xx + 2 * plane]);
       const float Yn = fmaf(m.kb, B, fmaf(m.kg, G, m.kr * R));
-      const float wgt = dx == 0 ? 0.25f : 0.125f;
+      const float wgt = CTR || dx == 0 ? 0.25f : 0.125f;
       cbs = fmaf(wgt, (B - Yn) * m.cbs, cbs);
       crs = fmaf(wgt, (R - Yn) * m.crs, crs);
       if (dx >= 0) Code<BITS>::put(f.p[0], f.pitch[0], yy, xx, quant(fmaf(Yn, m.ys, m.yo), m.maxc));
@@ -345,7 +410,7 @@ __device__ __forceinline__ void pack444_px(const FrameOut& f, const Fwd& m,
 // Four chroma samples of chroma row i per thread (a 2 x 8 luma block): each R'G'B' row
 // is read as two float4 vectors plus the left neighbour, the codes are written as
 // vector runs.  Blocks that reach past the frame width use the per-sample form.
-template <int BITS>
+template <int BITS, bool CTR = false>
 __device__ __forceinline__ void pack420_x4(const FrameOut& f, const Fwd& m, const float* __restrict__ rgb,
                                            int rh, int rw, int gid) {
   const int wc = f.w >> 1, hc = f.h >> 1;
@@ -353,7 +418,7 @@ __device__ __forceinline__ void pack420_x4(const FrameOut& f, const Fwd& m, cons
   if (gid >= gpr * hc) return;
   const int i = gid / gpr, j0 = (gid - i * gpr) << 2;
   if (j0 + 4 > wc) {
-    for (int j = j0; j < wc; ++j) pack420_px<BITS>(f, m, rgb, rh, rw, i * wc + j);
+    for (int j = j0; j < wc; ++j) pack420_px<BITS, CTR>(f, m, rgb, rh, rw, i * wc + j);
     return;
   }
   const size_t plane = (size_t)rh * rw;
@@ -390,9 +455,9 @@ __device__ __forceinline__ void pack420_x4(const FrameOut& f, const Fwd& m, cons
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
+      for (int dx = CTR ? 0 : -1; dx <= 1; ++dx) {
         const int c = 1 + 2 * jj + dx;
-        const float wgt = dx == 0 ? 0.25f : 0.125f;
+        const float wgt = CTR || dx == 0 ? 0.25f : 0.125f;
         cbs[jj] = fmaf(wgt, (B[c] - Yn[c]) * m.cbs, cbs[jj]);
         crs[jj] = fmaf(wgt, (R[c] - Yn[c]) * m.crs, crs[jj]);
       }
@@ -445,18 +510,23 @@ __device__ __forceinline__ void pack444_x8(const FrameOut& f, const Fwd& m, cons
 __device__ __forceinline__ void pack_any(const FrameOut& f, const Fwd& m, const float* rgb, int rh,
                                          int rw, int gid) {
   if (f.chroma == 420) {
-    if (f.bits == 8) pack420_x4<8>(f, m, rgb, rh, rw, gid);
-    else pack420_x4<10>(f, m, rgb, rh, rw, gid);
+    if (f.bits == 8) {
+      if (f.centre) pack420_x4<8, true>(f, m, rgb, rh, rw, gid);
+      else pack420_x4<8>(f, m, rgb, rh, rw, gid);
+    } else {
+      if (f.centre) pack420_x4<10, true>(f, m, rgb, rh, rw, gid);
+      else pack420_x4<10>(f, m, rgb, rh, rw, gid);
+    }
   } else {
     if (f.bits == 8) pack444_x8<8>(f, m, rgb, rh, rw, gid);
     else pack444_x8<10>(f, m, rgb, rh, rw, gid);
   }
 }
 
-template <int BITS>
+template <int BITS, bool CTR>
 __global__ __launch_bounds__(256) void k_pack420(FrameOut f, Fwd m, const float* __restrict__ rgb,
                                                  int rh, int rw) {
-  pack420_x4<BITS>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
+  pack420_x4<BITS, CTR>(f, m, rgb, rh, rw, blockIdx.x * 256 + threadIdx.x);
 }
 
 template <int BITS>
@@ -700,23 +770,34 @@ __global__ __launch_bounds__(64) void k_scene_final_batch(const SceneJob* __rest
 }  // namespace
 
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s) {
-  const Inv m = make_inv(f.bits);
+  const Inv m = make_inv(f.bits, f.matrix, f.full);
   const int n = (wp >> 2) * hp;
   const dim3 grid((n + 255) / 256), blk(256);
-  if (f.bits == 8 && f.chroma == 420) hipLaunchKernelGGL((k_unpack<8, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
-  else if (f.bits == 8) hipLaunchKernelGGL((k_unpack<8, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
-  else if (f.chroma == 420) hipLaunchKernelGGL((k_unpack<10, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
-  else hipLaunchKernelGGL((k_unpack<10, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  const bool c420 = f.chroma == 420, ctr = c420 && f.centre;
+  if (f.bits == 8) {
+    if (ctr) hipLaunchKernelGGL((k_unpack<8, true, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
+    else if (c420) hipLaunchKernelGGL((k_unpack<8, true, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+    else hipLaunchKernelGGL((k_unpack<8, false, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  } else {
+    if (ctr) hipLaunchKernelGGL((k_unpack<10, true, true>), grid, blk, 0, s, f, m, rgb, hp, wp);
+    else if (c420) hipLaunchKernelGGL((k_unpack<10, true, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+    else hipLaunchKernelGGL((k_unpack<10, false, false>), grid, blk, 0, s, f, m, rgb, hp, wp);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const FrameOut& f, const float* rgb, int rh, int rw, hipStream_t s) {
-  const Fwd m = make_fwd(f.bits);
+  const Fwd m = make_fwd(f.bits, f.matrix, f.full);
   if (f.chroma == 420) {
     const int n = (((f.w >> 1) + 3) >> 2) * (f.h >> 1);
     const dim3 grid((n + 255) / 256), blk(256);
-    if (f.bits == 8) hipLaunchKernelGGL((k_pack420<8>), grid, blk, 0, s, f, m, rgb, rh, rw);
-    else hipLaunchKernelGGL((k_pack420<10>), grid, blk, 0, s, f, m, rgb, rh, rw);
+    if (f.bits == 8) {
+      if (f.centre) hipLaunchKernelGGL((k_pack420<8, true>), grid, blk, 0, s, f, m, rgb, rh, rw);
+      else hipLaunchKernelGGL((k_pack420<8, false>), grid, blk, 0, s, f, m, rgb, rh, rw);
+    } else {
+      if (f.centre) hipLaunchKernelGGL((k_pack420<10, true>), grid, blk, 0, s, f, m, rgb, rh, rw);
+      else hipLaunchKernelGGL((k_pack420<10, false>), grid, blk, 0, s, f, m, rgb, rh, rw);
+    }
   } else {
     const int n = ((f.w + 7) >> 3) * f.h;
     const dim3 grid((n + 255) / 256), blk(256);

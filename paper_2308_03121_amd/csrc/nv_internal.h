@@ -6,33 +6,38 @@
 
 namespace nv {
 
-// One Y'CbCr frame as the kernels see it.
+// One Y'CbCr frame as the kernels see it.  matrix: 709, 601 or 2020; full: full-range
+// codes; centre: 4:2:0 chroma sited at the centre of its 2x2 luma block (else co-sited
+// with the even luma column).
 struct Frame {
   const void* p[3];
   int64_t pitch[3];   // bytes
   int w, h, bits, chroma;
+  int matrix = 709, full = 0, centre = 0;
 };
 
 struct FrameOut {
   void* p[3];
   int64_t pitch[3];
   int w, h, bits, chroma;
+  int matrix = 709, full = 0, centre = 0;
 };
 
 struct SceneRule {
   int mad_thresh_8bit, hist_num, hist_den, enable;
 };
 
-// Limited-range BT.709 constants of the inverse (unpack) and forward (pack) matrices for
-// one bit depth; every derived coefficient is formed in double and rounded once.
+// Constants of the inverse (unpack) and forward (pack) matrices of one colourspace
+// (matrix 709 / 601 / 2020, limited or full range) and bit depth; every derived
+// coefficient is formed in double and rounded once.
 struct Inv {
   float ys, yo, cs, co, rcr, bcb, gcb, gcr;
 };
 struct Fwd {
   float kr, kg, kb, cbs, crs, ys, yo, cs, co, maxc;
 };
-Inv make_inv(int bits);
-Fwd make_fwd(int bits);
+Inv make_inv(int bits, int matrix = 709, int full = 0);
+Fwd make_fwd(int bits, int matrix = 709, int full = 0);
 
 // ---- pixel-format stages (k_pixel.hip) ----
 hipError_t launch_unpack(const Frame& f, float* rgb, int hp, int wp, hipStream_t s);

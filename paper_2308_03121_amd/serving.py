@@ -10,6 +10,11 @@ GPU joins the very next batch (iteration-level batching, not a queue of whole cl
 Per group the latency runs from the arrival of the frame that closes the group to the
 completion of the batch that emitted it.
 
+The executor holds one network context per colourspace and serves each stream with the
+network trained for the stream's colourspace (matrix and range), as the paper's
+framework loads the network for the clip's colourspace (section 3.1); a stream whose
+colourspace has no network is rejected at admission.
+
 The scheduler is host logic; the executor (`GpuExecutor`) is the only part that
 touches the device, so the scheduling rules can be exercised with another executor.
 """
@@ -33,6 +38,9 @@ class StreamSpec:
     chroma: int
     arrivals: list            # seconds after the start of the run, one per frame
     scene_starts: list = field(default_factory=list)
+    matrix: int = 709         # colourspace: BT.601 / 709 / 2020 matrix, full range, centre siting
+    full: bool = False
+    centre: bool = False
 
     @property
     def n_frames(self) -> int:
@@ -235,44 +243,86 @@ def torch_float32():
     return torch.float32
 
 
+def colourspace_of(obj):
+    """(matrix, full range) of a stream spec or of a network context."""
+    if hasattr(obj, "colourspace"):
+        return tuple(obj.colourspace)
+    return (int(obj.matrix), bool(obj.full))
+
+
+def select_context(ctxs, spec):
+    """The context whose network was trained for the stream's colourspace, or None.
+    ctxs: one context, or a mapping (matrix, full) -> context."""
+    key = colourspace_of(spec)
+    if isinstance(ctxs, dict):
+        return ctxs.get(key)
+    return ctxs if colourspace_of(ctxs) == key else None
+
+
+# Footprint of a stream no network can serve: larger than any budget, so the server
+# rejects it at admission.
+UNSERVABLE = 1 << 62
+
+
 class GpuExecutor:
-    """Executor over the library: one context, one HIP stream, frames from a device bank.
-    Streams that leave go to a pool per format and are reset for the next stream of that
-    format, so serving never frees or allocates stream memory (a free would synchronise
-    the device and stall the batches in flight)."""
+    """Executor over the library: one context per colourspace (a context or a mapping
+    (matrix, full) -> context), one HIP stream, frames from a device bank.  Each batch
+    step runs one nv_enhance_batch call per context with requests.  Streams that leave
+    go to a pool per format and are reset for the next stream of that format, so
+    serving never frees or allocates stream memory (a free would synchronise the device
+    and stall the batches in flight)."""
 
     def __init__(self, ctx, frame_source, batch_share_per_px: int = 0, max_chain: int = 4):
         import torch
         self.torch = torch
-        self.ctx = ctx
+        self.ctxs = ctx
         self.src = frame_source          # (spec, t) -> device frame tuple
         self.share = batch_share_per_px  # workspace bytes per admitted pixel
         self.max_chain = max_chain       # a chain of k frames keeps k + 1 frames resident
         self._pool = {}
+        self._ctx_of = {}                # id(stream handle) -> its context
 
     def now(self):
         return time.perf_counter()
 
-    def footprint(self, spec):
+    @staticmethod
+    def _fmt(spec):
         from . import binding as B
-        f = B.fmt_struct(spec.width, spec.height, spec.bits, spec.chroma)
+        return B.fmt_struct(spec.width, spec.height, spec.bits, spec.chroma, matrix=spec.matrix, full=spec.full,
+                            centre=spec.centre)
+
+    def footprint(self, spec):
+        ctx = select_context(self.ctxs, spec)
+        if ctx is None:
+            return UNSERVABLE
         hp, wp = (spec.height + 7) // 8 * 8, (spec.width + 7) // 8 * 8
-        slot = hp * wp * (12 + self.ctx.channels * (4 if self.ctx.feat_dtype == torch_float32() else 2))
-        return self.ctx.stream_footprint(f) + (self.max_chain - 1) * slot + self.share * hp * wp
+        slot = hp * wp * (12 + ctx.channels * (4 if ctx.feat_dtype == torch_float32() else 2))
+        return ctx.stream_footprint(self._fmt(spec)) + (self.max_chain - 1) * slot + self.share * hp * wp
 
     def open(self, spec):
-        from . import binding as B
-        key = (spec.width, spec.height, spec.bits, spec.chroma)
+        ctx = select_context(self.ctxs, spec)
+        key = (spec.width, spec.height, spec.bits, spec.chroma, spec.matrix, spec.full, spec.centre)
         if self._pool.get(key):
             st = self._pool[key].pop()
             st.reset()
-            return st
-        return self.ctx.open_stream(B.fmt_struct(*key))
+        else:
+            st = ctx.open_stream(self._fmt(spec))
+            st.pool_key = key
+        self._ctx_of[id(st)] = ctx
+        return st
 
     def submit(self, reqs):
         torch = self.torch
-        batch = [(st, [self.src(spec, t) for t in idx], None, end) for st, spec, idx, end in reqs]
-        outs = self.ctx.enhance_batch(batch)
+        # one batch call per context, outputs returned in request order
+        by_ctx = {}
+        for k, (st, spec, idx, end) in enumerate(reqs):
+            ctx = self._ctx_of[id(st)]
+            by_ctx.setdefault(id(ctx), (ctx, []))[1].append(k)
+        outs = [None] * len(reqs)
+        for ctx, ks in by_ctx.values():
+            batch = [(reqs[k][0], [self.src(reqs[k][1], t) for t in reqs[k][2]], None, reqs[k][3]) for k in ks]
+            for k, o in zip(ks, ctx.enhance_batch(batch)):
+                outs[k] = o
         ev = torch.cuda.Event()
         ev.record()
         return {"event": ev, "outs": outs}
@@ -294,8 +344,7 @@ class GpuExecutor:
         ticket["outs"] = None
 
     def close(self, st):
-        f = st.fmt
-        self._pool.setdefault((f.width, f.height, f.bits, f.chroma), []).append(st)
+        self._pool.setdefault(st.pool_key, []).append(st)
 
     def shutdown(self):
         for lst in self._pool.values():

@@ -195,9 +195,56 @@ static int run_static(int argc, char** argv) {
   return 0;
 }
 
+// driver unpack|pack DIR W H BITS CHROMA MATRIX RANGE SITING: the pixel-format stages of
+// one frame.  Planes are DIR/{y,u,v}.bin, tightly packed (1 or 2 bytes per sample); R'G'B'
+// is DIR/rgb.f32, planar float [3][hp][wp] (unpack: hp, wp the sizes rounded up to 8;
+// pack: hp = H, wp = W rounded up to 4).
+static int run_pixel(int argc, char** argv, bool unpack) {
+  if (argc < 10) return 2;
+  const std::string dir = argv[2];
+  nv_format fmt{atoi(argv[3]), atoi(argv[4]), atoi(argv[5]), atoi(argv[6]), atoi(argv[7]), atoi(argv[8]),
+                atoi(argv[9])};
+  const int W = fmt.width, H = fmt.height, bps = fmt.bits == 8 ? 1 : 2;
+  const int cw = fmt.chroma == 420 ? W / 2 : W, ch = fmt.chroma == 420 ? H / 2 : H;
+  nv_planes pl;
+  const char* names[3] = {"y", "u", "v"};
+  for (int i = 0; i < 3; ++i) {
+    const int pw = i ? cw : W, ph = i ? ch : H;
+    pl.pitch_bytes[i] = (int64_t)pw * bps;
+    if (unpack) {
+      const std::vector<char> d = read_file(dir + "/" + names[i] + ".bin");
+      pl.data[i] = dev(d.size(), d.data());
+    } else {
+      pl.data[i] = dev((size_t)pw * ph * bps);
+    }
+  }
+  if (unpack) {
+    const int hp = (H + 7) / 8 * 8, wp = (W + 7) / 8 * 8;
+    float* rgb = static_cast<float*>(dev((size_t)12 * hp * wp));
+    CHECK(nv_unpack(&fmt, &pl, rgb, hp, wp, nullptr));
+    write_file(dir + "/rgb.f32", rgb, (size_t)12 * hp * wp);
+    hipFree(rgb);
+  } else {
+    const int rw = (W + 3) / 4 * 4;
+    const std::vector<char> d = read_file(dir + "/rgb.f32");
+    if (d.size() != (size_t)12 * H * rw) return 2;
+    float* rgb = static_cast<float*>(dev(d.size(), d.data()));
+    CHECK(nv_pack(&fmt, rgb, H, rw, &pl, nullptr));
+    for (int i = 0; i < 3; ++i) {
+      const int pw = i ? cw : W, ph = i ? ch : H;
+      write_file(dir + "/" + names[i] + ".bin", pl.data[i], (size_t)pw * ph * bps);
+    }
+    hipFree(rgb);
+  }
+  for (int i = 0; i < 3; ++i) hipFree(pl.data[i]);
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc >= 2 && strcmp(argv[1], "unpack") == 0) return run_pixel(argc, argv, true);
+  if (argc >= 2 && strcmp(argv[1], "pack") == 0) return run_pixel(argc, argv, false);
   if (argc >= 2 && strcmp(argv[1], "net") == 0) return run_net(argc, argv);
   if (argc >= 2 && strcmp(argv[1], "static") == 0) return run_static(argc, argv);
-  fprintf(stderr, "usage: driver net DIR C R G PREC H W | driver static C R G PREC\n");
+  fprintf(stderr, "usage: driver net DIR C R G PREC H W | static C R G PREC | unpack|pack DIR W H BITS CHROMA MATRIX RANGE SITING\n");
   return 2;
 }

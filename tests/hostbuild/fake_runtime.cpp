@@ -225,8 +225,8 @@ namespace nv {
 
 static size_t px(int h, int w) { return (size_t)h * (size_t)w; }
 
-Inv make_inv(int) { return Inv{}; }
-Fwd make_fwd(int) { return Fwd{}; }
+Inv make_inv(int, int, int) { return Inv{}; }
+Fwd make_fwd(int, int, int) { return Fwd{}; }
 
 static void need_frame(const Frame& f, const char* what) {
   const int bps = f.bits == 8 ? 1 : 2;

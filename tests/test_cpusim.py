@@ -114,3 +114,34 @@ def test_static_group_entry_in_simulation(driver):
     row (the second smaller) and rejects a group too large for its static scratch."""
     out = _run(driver, ["static", 32, 2, 8, 0], timeout=600)
     assert "static ok" in out, out[-2000:]
+
+
+@pytest.mark.parametrize("w,h,bits,chroma", [(40, 24, 8, 420), (38, 22, 10, 420), (30, 18, 10, 444)])
+def test_pixel_stage_colourspaces_in_simulation(driver, tmp_path, w, h, bits, chroma):
+    """nv_unpack and nv_pack in every matrix, range and (4:2:0) siting against the oracle:
+    unpack within 1e-6, pack codes within one code (rounding ties)."""
+    from oracle import pixel
+    rng = np.random.default_rng(w * h + bits)
+    dt = np.uint8 if bits == 8 else np.uint16
+    cw, chh = (w // 2, h // 2) if chroma == 420 else (w, h)
+    mats = {709: 0, 601: 1, 2020: 2}
+    for matrix in (601, 709, 2020):
+        for full in (False, True):
+            for centre in ((False, True) if chroma == 420 else (False,)):
+                planes = [rng.integers(0, 1 << bits, s).astype(dt) for s in ((h, w), (chh, cw), (chh, cw))]
+                for name, a in zip("yuv", planes):
+                    a.tofile(tmp_path / f"{name}.bin")
+                args = [w, h, bits, chroma, mats[matrix], int(full), int(centre)]
+                _run(driver, ["unpack", tmp_path] + args, timeout=120)
+                hp, wp = (h + 7) // 8 * 8, (w + 7) // 8 * 8
+                got = np.fromfile(tmp_path / "rgb.f32", dtype=np.float32).reshape(3, hp, wp)
+                ref = pixel.pad(pixel.unpack(*planes, bits, chroma, matrix, full, centre), 8)
+                assert np.abs(got - ref).max() <= 1e-6, (matrix, full, centre)
+                rw = (w + 3) // 4 * 4
+                x = rng.uniform(-0.1, 1.1, (3, h, rw)).astype(np.float32)
+                x.tofile(tmp_path / "rgb.f32")
+                _run(driver, ["pack", tmp_path] + args, timeout=120)
+                want = pixel.pack(x[:, :, :w].astype(np.float64), bits, chroma, matrix, full, centre)
+                for name, r in zip("yuv", want):
+                    g = np.fromfile(tmp_path / f"{name}.bin", dtype=dt).reshape(r.shape)
+                    assert np.abs(g.astype(np.int64) - r.astype(np.int64)).max() <= 1, (name, matrix, full, centre)

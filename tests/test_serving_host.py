@@ -117,3 +117,33 @@ def test_poisson_workload_shape():
         assert all(10 <= g <= 60 for g in gaps)
     rate = sum(s.n_frames for s in specs) / sum(s.arrivals[-1] - s.arrivals[0] for s in specs) * 16
     assert 20 < rate < 80
+
+
+def test_network_selected_by_stream_colourspace():
+    """Each stream is served by the network trained for its colourspace (matrix, range);
+    a stream whose colourspace has no network cannot be admitted under any budget."""
+    from paper_2308_03121_amd.serving import UNSERVABLE, select_context
+
+    class Ctx:
+        def __init__(self, matrix, full):
+            self.colourspace = (matrix, full)
+
+    c709, c601f = Ctx(709, False), Ctx(601, True)
+    ctxs = {c709.colourspace: c709, c601f.colourspace: c601f}
+    mk = lambda m, f, c=False: StreamSpec(0, 64, 32, 8, 420, [0.0], matrix=m, full=f, centre=c)  # noqa: E731
+    assert select_context(ctxs, mk(709, False)) is c709
+    assert select_context(ctxs, mk(601, True, True)) is c601f     # siting does not select a network
+    assert select_context(ctxs, mk(2020, False)) is None
+    assert select_context(c709, mk(709, False)) is c709 and select_context(c709, mk(601, False)) is None
+
+    class Exec(FakeExecutor):
+        def footprint(self, spec):
+            return UNSERVABLE if select_context(ctxs, spec) is None else super().footprint(spec)
+
+    ex = Exec()
+    specs = [StreamSpec(0, 64, 32, 8, 420, [0.0, 0.01], matrix=709), StreamSpec(1, 64, 32, 8, 420, [0.0], matrix=2020),
+             StreamSpec(2, 64, 32, 8, 420, [0.0, 0.02], matrix=601, full=True)]
+    srv = Server(ex, hbm_budget=1 << 40)
+    rep = srv.run(specs)
+    assert rep["rejected"] == 1 and rep["admitted"] == 2
+    assert rep["groups"] == 4
