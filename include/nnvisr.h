@@ -286,6 +286,49 @@ nv_status nv_stream_reset(nv_stream* s);
  * (cuts[0..n-1], n <= frames pushed); synchronises `stream`. */
 nv_status nv_stream_cuts(nv_stream* s, uint32_t* host_cuts, int32_t n, void* stream);
 
+/* ------------------------------------------- general n, batches of b groups ---- */
+
+/* A clip grouped for a network that consumes n frames per run, with the Extra frame
+ * (n + 1 inputs) and Double frame (2n outputs) flags of section 3.1, run in batches of b
+ * groups over the frame store of section 3.3 (Fig. 1).  The network's fusion is pairwise,
+ * so a group's outputs are, for each frame it consumes, the frame itself (t = 0) and the
+ * frame between it and the group's next input (t = 1/2); over a clip every input frame
+ * gives these two outputs once, in input order, exactly as with nv_stream_push.
+ *
+ * Grouping (section 3.3): groups never cross a scene cut; the input after a scene's last
+ * frame is that frame again; a last group short of frames recycles the previous group's
+ * last frames; a scene shorter than n frames repeats its last frame.  A frame's outputs
+ * come from the first group that consumes it.
+ *
+ * Frame store (Fig. 1): n b + b positions of R'G'B' and features.  For the block of b
+ * groups starting at frame f0, frame f0 + i n (i = 0..b) sits at position b - 1 + i and
+ * frame f0 + i n + k (k = 1..n-1) at 2b + (k - 1) b + i, so each network input of the b
+ * groups is b consecutive positions and no frame is stored twice; after a full block the
+ * last frame is copied into the chain start (position b - 1, the figure's "6 to 5") and
+ * the next block starts from it.
+ *
+ * push() runs the scene metric, reads the frame's cut flag back to the host (the grouping
+ * depends on where scenes end, so push synchronises `stream`), then finishes the previous
+ * scene's groups if the frame starts a new scene, and stores and extracts the frame; when
+ * a block of b groups is complete its groups run.  end() runs the last scene's remaining
+ * groups.  out (HOST array of out_cap device planes of the output format) receives the
+ * emitted frames in order, *n_out of them; 2 n b entries always suffice.  n >= 1, b >= 1,
+ * n b + b <= 64.  The clip keeps its frame store on the device until nv_clip_close.
+ *
+ * nv_clip_trace copies what the clip ran, for inspection: per batch, the kind (0 a full
+ * block, 1 the remaining groups of a scene), the number of groups g, g x (n + 1) input
+ * frame numbers, and the frame number held at each of the n b + b store positions when
+ * the batch ran (-1 empty).  *len receives the total length; at most cap values are
+ * written to buf (HOST). */
+typedef struct nv_clip nv_clip;
+nv_status nv_clip_open(nv_context* ctx, const nv_format* fmt, const nv_scene_params* params, int32_t n,
+                       int32_t b, nv_clip** out);
+nv_status nv_clip_push(nv_clip* clip, const nv_planes* frame, int32_t external_cut, const nv_planes* out,
+                       int32_t out_cap, int32_t* n_out, void* stream);
+nv_status nv_clip_end(nv_clip* clip, const nv_planes* out, int32_t out_cap, int32_t* n_out, void* stream);
+nv_status nv_clip_trace(const nv_clip* clip, int32_t* buf, int32_t cap, int32_t* len);
+nv_status nv_clip_close(nv_clip* clip);
+
 /* Device bytes a stream of this format keeps resident (for admission control): the
  * frame store of section 3.3 for n = 1 (the overlap frame's pixels and features, two
  * ring slots) plus the scene state (previous luma plane, histogram, cut flags).  The

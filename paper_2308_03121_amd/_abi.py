@@ -70,6 +70,13 @@ _SIGS = {
                                    c_void_p]),
     "nv_enhance_group_static": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), POINTER(NvPlanes),
                                           c_void_p]),
+    "nv_clip_open": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvSceneParams), c_int32, c_int32,
+                               POINTER(c_void_p)]),
+    "nv_clip_push": (c_int32, [c_void_p, POINTER(NvPlanes), c_int32, POINTER(NvPlanes), c_int32, POINTER(c_int32),
+                               c_void_p]),
+    "nv_clip_end": (c_int32, [c_void_p, POINTER(NvPlanes), c_int32, POINTER(c_int32), c_void_p]),
+    "nv_clip_trace": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32)]),
+    "nv_clip_close": (c_int32, [c_void_p]),
     "nv_stream_open": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvSceneParams), POINTER(c_void_p)]),
     "nv_stream_push": (c_int32, [c_void_p, POINTER(NvPlanes), c_int32, POINTER(NvPlanes),
                                  POINTER(c_int32), c_void_p]),

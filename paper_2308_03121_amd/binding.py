@@ -332,3 +332,61 @@ class Stream:
             self.close()
         except Exception:
             pass
+
+
+class Clip:
+    """A clip grouped for a network consuming n frames per run, in batches of b groups over
+    the Fig. 1 frame store (nv_clip_*).  push() returns the output frames emitted by it."""
+
+    def __init__(self, ctx: Context, fmt: NvFormat, n: int, b: int, params: NvSceneParams | None = None):
+        self.ctx, self.fmt, self.n, self.b = ctx, fmt, n, b
+        self._h = c_void_p()
+        check(_abi.load().nv_clip_open(ctx._h, byref(fmt), byref(params) if params is not None else None, n, b,
+                                       byref(self._h)))
+
+    def _room(self):
+        cap = 2 * self.n * self.b
+        outs = [alloc_frame(2 * self.fmt.width, 2 * self.fmt.height, self.fmt.bits, self.fmt.chroma,
+                            self.ctx.device) for _ in range(cap)]
+        return outs, (NvPlanes * cap)(*[planes_struct(*o) for o in outs]), cap
+
+    def push(self, frame, external_cut: int = -1, stream=None):
+        outs, pout, cap = self._room()
+        n = c_int32()
+        check(_abi.load().nv_clip_push(self._h, byref(planes_struct(*frame)), external_cut, pout, cap, byref(n),
+                                       c_void_p(_stream(stream))))
+        return outs[:n.value]
+
+    def end(self, stream=None):
+        outs, pout, cap = self._room()
+        n = c_int32()
+        check(_abi.load().nv_clip_end(self._h, pout, cap, byref(n), c_void_p(_stream(stream))))
+        return outs[:n.value]
+
+    def trace(self):
+        """[(kind, [group inputs], [frame at each store position])] per batch run so far."""
+        lib = _abi.load()
+        ln = c_int32()
+        check(lib.nv_clip_trace(self._h, None, 0, byref(ln)))
+        buf = (c_int32 * max(ln.value, 1))()
+        check(lib.nv_clip_trace(self._h, buf, ln.value, byref(ln)))
+        vals, out, i, P = list(buf)[:ln.value], [], 0, self.n * self.b + self.b
+        while i < len(vals):
+            kind, g = vals[i], vals[i + 1]
+            i += 2
+            groups = [vals[i + j * (self.n + 1):i + (j + 1) * (self.n + 1)] for j in range(g)]
+            i += g * (self.n + 1)
+            out.append((kind, groups, vals[i:i + P]))
+            i += P
+        return out
+
+    def close(self):
+        if self._h:
+            _abi.load().nv_clip_close(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

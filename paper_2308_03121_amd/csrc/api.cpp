@@ -50,6 +50,7 @@ namespace {
 
 constexpr int kMaxDim = 16384;
 constexpr int kCutRing = 1 << 16;   // device cut flags kept per stream (ring)
+constexpr int kClipMaxPositions = 64;   // frame-store positions of a general-n clip (n b + b)
 
 struct LayerSpec {
   const char* name;
@@ -1467,11 +1468,9 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
   return ordered({&s->ctx->ws_ord, &s->ord}, hs, [&] { return push_impl(s, frame, external_cut, out, n_out, hs); });
 }
 
-static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t external_cut, const nv_planes out[2],
-                           int32_t* n_out, hipStream_t hs) {
-  const int cur = s->slot(s->t), prv = s->t > 0 ? s->slot(s->t - 1) : 0;
-  const Frame f = to_frame(&s->fmt, frame);
-  NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
+// The scene metric of frame s->t against the previous frame: writes its cut flag at
+// *cut_out (device) and keeps its luma plane and histogram for the next frame.
+static nv_status scene_step(nv_stream* s, const Frame& f, int32_t external_cut, hipStream_t hs, uint32_t** cut_out) {
   uint32_t* cut_t = s->cuts + (s->t % kCutRing);
   SceneJob J{};
   J.cur = f;
@@ -1490,6 +1489,31 @@ static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t externa
   J.rule = s->rule;
   J.external = external_cut;
   NV_TRY(timed(s->ctx, NV_K_SCENE, hs, "scene", [&] { return launch_scene(J, false, hs); }));
+  *cut_out = cut_t;
+  return NV_OK;
+}
+
+// After a frame: the scene state's "previous frame" becomes this one.
+static void scene_advance(nv_stream* s) {
+  s->t += 1;
+  s->luma_last ^= 1;
+  s->hist_last ^= 1;
+}
+
+// Unpack and extract one frame into ring slot `slot`.
+static nv_status frame_in(nv_stream* s, const Frame& f, int slot, hipStream_t hs) {
+  NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[slot], s->hp, s->wp, hs); }));
+  NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
+  return extract_impl(s->ctx, s->ctx->ws, s->rgb[slot], s->hp, s->wp, s->feat[slot], hs);
+}
+
+static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t external_cut, const nv_planes out[2],
+                           int32_t* n_out, hipStream_t hs) {
+  const int cur = s->slot(s->t), prv = s->t > 0 ? s->slot(s->t - 1) : 0;
+  const Frame f = to_frame(&s->fmt, frame);
+  NV_TRY(timed(s->ctx, NV_K_UNPACK, hs, "unpack", [&] { return launch_unpack(f, s->rgb[cur], s->hp, s->wp, hs); }));
+  uint32_t* cut_t = nullptr;
+  NV_TRY(scene_step(s, f, external_cut, hs, &cut_t));
   NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
   NV_TRY(extract_impl(s->ctx, s->ctx->ws, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
   *n_out = 0;
@@ -1497,9 +1521,7 @@ static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t externa
     NV_TRY(emit_group(s, prv, cur, cut_t, out, hs));
     *n_out = 2;
   }
-  s->t += 1;
-  s->luma_last ^= 1;
-  s->hist_last ^= 1;
+  scene_advance(s);
   return NV_OK;
 }
 
@@ -1537,6 +1559,209 @@ extern "C" nv_status nv_stream_close(nv_stream* s) {
   (void)hipDeviceSynchronize();
   stream_free(s);
   delete s;
+  return NV_OK;
+}
+
+// ------------------------------------------ general n, batches of b groups ----
+//
+// A clip grouped as the paper's framework groups it for a network that consumes n frames
+// per run with the Extra frame (n + 1 inputs) and Double frame (2n outputs) flags
+// (section 3.1, network integration), run in batches of b groups over the frame store of
+// section 3.3 (Fig. 1).  The network here fuses neighbouring frames pairwise, so a
+// group's 2n outputs are, for each consumed frame f, HR(f) and the frame between f and
+// the group's next input.
+//
+// Frame store (Fig. 1): P = n b + b positions.  For the block of b groups that starts
+// at frame f0 (frames f0 .. f0 + n b), frame f0 + i n (i = 0 .. b: every group's first
+// input and the last group's extra input) sits at position b - 1 + i, and frame
+// f0 + i n + k (k = 1 .. n - 1) at b - 1 + b + 1 + (k - 1) b + i.  Network input k of
+// the b groups is then b consecutive positions, the views of input 0 and of the extra
+// input overlap by b - 1 positions, and b n + 1 frames are stored, none twice.  After a
+// batch the last frame (f0 + n b) is copied into the chain start (position b - 1) and
+// the next block starts there; the first b - 1 positions stay empty.
+//
+// Grouping (section 3.3): groups never cross a scene cut; the input after a scene's
+// last frame is that frame again; a last group short of frames recycles the previous
+// group's last frames; a scene shorter than n frames repeats its last frame.  A frame's
+// two outputs are emitted once, by the first group that consumes it (a recycled
+// group's earlier frames are not computed again).
+
+struct nv_clip {
+  nv_stream* st = nullptr;         // scene state; its ring slots are the store positions
+  int n = 1, b = 1, P = 0;
+  int64_t t = 0;                   // frames pushed
+  int64_t scene0 = 0;              // first frame of the current scene
+  int64_t f0 = 0;                  // first frame of the current store block
+  int64_t next_emit = 0;           // frames before this one have been emitted
+  std::vector<int64_t> at;         // frame held at each store position, -1 when none
+  std::vector<int32_t> trace;      // see nv_clip_trace
+};
+
+namespace {
+
+int clip_pos(const nv_clip* c, int64_t f) {
+  const int64_t off = f - c->f0;
+  const int base = c->b - 1;
+  if (off % c->n == 0) return base + (int)(off / c->n);
+  return base + c->b + 1 + (int)((off % c->n) - 1) * c->b + (int)(off / c->n);
+}
+
+// The groups of a scene of L frames (scene-relative frame numbers): n + 1 inputs each,
+// the first n of them consumed.
+std::vector<std::vector<int64_t>> scene_groups(int64_t L, int n) {
+  std::vector<int64_t> frames;
+  for (int64_t i = 0; i < L; ++i) frames.push_back(i);
+  while ((int64_t)frames.size() < n) frames.push_back(L - 1);   // short scene: repeat the last frame
+  const int64_t len = (int64_t)frames.size();
+  std::vector<std::vector<int64_t>> gs;
+  for (int64_t pos = 0; pos < len; pos += n) {
+    const int64_t p = pos + n > len ? len - n : pos;             // short last group: recycle
+    std::vector<int64_t> in(frames.begin() + p, frames.begin() + p + n);
+    in.push_back(p + n < len ? frames[p + n] : L - 1);          // extra input
+    gs.push_back(in);
+  }
+  return gs;
+}
+
+// Runs groups (absolute frame numbers, n + 1 inputs each) whose frames are in the store:
+// for each consumed frame not yet emitted, its pair with the next input, two outputs.
+// Appends the batch to the trace (kind, group count, inputs, store map).
+nv_status clip_run(nv_clip* c, int kind, const std::vector<std::vector<int64_t>>& groups, const nv_planes* out,
+                   int32_t cap, int32_t* n_out, hipStream_t hs) {
+  c->trace.push_back(kind);
+  c->trace.push_back((int32_t)groups.size());
+  for (const auto& g : groups)
+    for (int64_t f : g) c->trace.push_back((int32_t)f);
+  for (int64_t f : c->at) c->trace.push_back((int32_t)f);
+  for (const auto& g : groups)
+    for (int k = 0; k < c->n; ++k) {
+      const int64_t f = g[k];
+      if (f < c->next_emit) continue;
+      if (*n_out + 2 > cap) return fail(NV_E_INVALID, "out has room for %d frames; more are due", cap);
+      const int pa = clip_pos(c, f), pb = clip_pos(c, g[k + 1]);
+      if (pa < 0 || pa >= c->P || pb < 0 || pb >= c->P || c->at[pa] != f || c->at[pb] != g[k + 1])
+        return fail(NV_E_DEVICE, "frame store does not hold frames %lld and %lld", (long long)f,
+                    (long long)g[k + 1]);
+      NV_TRY(emit_group(c->st, pa, pb, nullptr, out + *n_out, hs));
+      *n_out += 2;
+      c->next_emit = f + 1;
+    }
+  return NV_OK;
+}
+
+// The groups of the current scene [scene0, end) that the regular batches have not run.
+nv_status clip_flush(nv_clip* c, int64_t end, const nv_planes* out, int32_t cap, int32_t* n_out, hipStream_t hs) {
+  if (end <= c->scene0) return NV_OK;
+  const auto gs = scene_groups(end - c->scene0, c->n);
+  const size_t done = (size_t)((c->f0 - c->scene0) / c->n);
+  std::vector<std::vector<int64_t>> rest;
+  for (size_t i = done; i < gs.size(); ++i) {
+    std::vector<int64_t> g = gs[i];
+    for (int64_t& f : g) f += c->scene0;
+    rest.push_back(g);
+  }
+  return clip_run(c, 1, rest, out, cap, n_out, hs);
+}
+
+}  // namespace
+
+extern "C" nv_status nv_clip_open(nv_context* ctx, const nv_format* fmt, const nv_scene_params* params, int32_t n,
+                                  int32_t b, nv_clip** out) {
+  if (!ctx || !out) return fail(NV_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (n < 1 || b < 1 || n * b + b > kClipMaxPositions)
+    return fail(NV_E_INVALID, "n = %d, b = %d: need n, b >= 1 and n b + b <= %d", n, b, kClipMaxPositions);
+  nv_clip* c = new (std::nothrow) nv_clip;
+  if (!c) return fail(NV_E_NOMEM, "host allocation failed");
+  nv_status st = nv_stream_open(ctx, fmt, params, &c->st);
+  c->n = n;
+  c->b = b;
+  c->P = n * b + b;
+  if (st == NV_OK) st = stream_ring(c->st, c->P);
+  if (st != NV_OK) {
+    if (c->st) nv_stream_close(c->st);
+    delete c;
+    return st;
+  }
+  c->at.assign(c->P, -1);
+  *out = c;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_clip_push(nv_clip* c, const nv_planes* frame, int32_t external_cut, const nv_planes* out,
+                                  int32_t out_cap, int32_t* n_out, void* stream) {
+  if (!c || !n_out) return fail(NV_E_INVALID, "NULL argument");
+  *n_out = 0;
+  nv_stream* s = c->st;
+  NV_TRY(check_ready(s->ctx));
+  NV_TRY(check_planes(&s->fmt, frame, "frame"));
+  if (external_cut < -1 || external_cut > 1) return fail(NV_E_INVALID, "external_cut must be -1, 0 or 1");
+  if (out_cap < 0 || (out_cap > 0 && !out)) return fail(NV_E_INVALID, "out is NULL");
+  for (int i = 0; i < out_cap; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
+  if (c->t >= kCutRing) return fail(NV_E_UNSUPPORTED, "a clip holds at most %d frames", kCutRing);
+  hipStream_t hs = (hipStream_t)stream;
+  return ordered({&s->ctx->ws_ord, &s->ord}, hs, [&]() -> nv_status {
+    const Frame f = to_frame(&s->fmt, frame);
+    uint32_t* cut_d = nullptr;
+    NV_TRY(scene_step(s, f, external_cut, hs, &cut_d));
+    // the grouping depends on where scenes end: the cut flag comes back to the host
+    uint32_t cut = 1;
+    HIP_TRY(hipMemcpyAsync(&cut, cut_d, sizeof cut, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    const int64_t t = c->t;
+    if (t > 0 && cut) {
+      NV_TRY(clip_flush(c, t, out, out_cap, n_out, hs));
+      c->scene0 = c->f0 = t;
+      std::fill(c->at.begin(), c->at.end(), -1);
+    }
+    const int p = clip_pos(c, t);
+    NV_TRY(frame_in(s, f, p, hs));
+    c->at[p] = t;
+    scene_advance(s);
+    c->t = t + 1;
+    if (t - c->f0 == (int64_t)c->n * c->b) {
+      // a full block: b groups, then the last frame moves to the chain start ("6 to 5")
+      std::vector<std::vector<int64_t>> gs;
+      for (int g = 0; g < c->b; ++g) {
+        std::vector<int64_t> in;
+        for (int k = 0; k <= c->n; ++k) in.push_back(c->f0 + (int64_t)g * c->n + k);
+        gs.push_back(in);
+      }
+      NV_TRY(clip_run(c, 0, gs, out, out_cap, n_out, hs));
+      const int base = c->b - 1;
+      const size_t px = (size_t)s->hp * s->wp;
+      HIP_TRY(hipMemcpyAsync(s->rgb[base], s->rgb[p], 12 * px, hipMemcpyDeviceToDevice, hs));
+      HIP_TRY(hipMemcpyAsync(s->feat[base], s->feat[p], px * s->ctx->C * dtype_bytes(s->ctx->ft),
+                             hipMemcpyDeviceToDevice, hs));
+      std::fill(c->at.begin(), c->at.end(), -1);
+      c->at[base] = t;
+      c->f0 = t;
+    }
+    return NV_OK;
+  });
+}
+
+extern "C" nv_status nv_clip_end(nv_clip* c, const nv_planes* out, int32_t out_cap, int32_t* n_out, void* stream) {
+  if (!c || !n_out) return fail(NV_E_INVALID, "NULL argument");
+  *n_out = 0;
+  nv_stream* s = c->st;
+  if (out_cap < 0 || (out_cap > 0 && !out)) return fail(NV_E_INVALID, "out is NULL");
+  for (int i = 0; i < out_cap; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
+  hipStream_t hs = (hipStream_t)stream;
+  return ordered({&s->ctx->ws_ord, &s->ord}, hs, [&] { return clip_flush(c, c->t, out, out_cap, n_out, hs); });
+}
+
+extern "C" nv_status nv_clip_trace(const nv_clip* c, int32_t* buf, int32_t cap, int32_t* len) {
+  if (!c || !len || (cap > 0 && !buf)) return fail(NV_E_INVALID, "NULL argument");
+  *len = (int32_t)c->trace.size();
+  for (int32_t i = 0; i < cap && i < *len; ++i) buf[i] = c->trace[i];
+  return NV_OK;
+}
+
+extern "C" nv_status nv_clip_close(nv_clip* c) {
+  if (!c) return NV_OK;
+  nv_stream_close(c->st);
+  delete c;
   return NV_OK;
 }
 

@@ -240,7 +240,96 @@ static int run_pixel(int argc, char** argv, bool unpack) {
   return 0;
 }
 
+// driver clip C R G N B W H FRAMES S1 S2 ...: a clip of FRAMES pseudo-random 8-bit 4:2:0
+// frames whose scenes start at the listed frames (external cut flags, metric off) through
+// nv_clip_* with n = N, b = B and through nv_stream_*; the outputs must be bit-identical.
+// Prints "trace:" and the clip's trace values, then "clip ok".
+static int run_clip(int argc, char** argv) {
+  if (argc < 9) return 2;
+  nv_net_config cfg{};
+  cfg.channels = atoi(argv[2]);
+  cfg.res_blocks = atoi(argv[3]);
+  cfg.offset_groups = atoi(argv[4]);
+  cfg.scale = 2;
+  cfg.align = 8;
+  cfg.flags = NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE;
+  const int n = atoi(argv[5]), b = atoi(argv[6]), W = atoi(argv[7]), H = atoi(argv[8]), T = atoi(argv[9]);
+  std::vector<int> starts;
+  for (int i = 10; i < argc; ++i) starts.push_back(atoi(argv[i]));
+  std::vector<float> w(nv_weight_count(&cfg));
+  uint32_t x = 11;
+  for (float& v : w) {
+    x = x * 1664525u + 1013904223u;
+    v = ((int)(x >> 9) - (1 << 22)) / (float)(1 << 22) * 0.05f;
+  }
+  nv_context* ctx = nullptr;
+  CHECK(nv_context_create(0, &cfg, w.data(), w.size(), &ctx));
+  nv_format fmt{W, H, 8, 420};
+  nv_scene_params sp{24, 1, 4, 0};
+  std::vector<nv_planes> frames;
+  for (int t = 0; t < T; ++t) frames.push_back(to_dev(make_frame(W, H, 100 + t)));
+  auto ext = [&](int t) {
+    for (int s0 : starts)
+      if (s0 == t) return 1;
+    return 0;
+  };
+  nv_clip* clip = nullptr;
+  CHECK(nv_clip_open(ctx, &fmt, &sp, n, b, &clip));
+  const int cap = 2 * n * b;
+  std::vector<nv_planes> got;
+  std::vector<nv_planes> room(cap);
+  auto fresh = [&]() {
+    for (int i = 0; i < cap; ++i) room[i] = out_planes(2 * W, 2 * H);
+  };
+  for (int t = 0; t < T; ++t) {
+    fresh();
+    int32_t k = 0;
+    CHECK(nv_clip_push(clip, &frames[t], ext(t), room.data(), cap, &k, nullptr));
+    for (int i = 0; i < k; ++i) got.push_back(room[i]);
+  }
+  fresh();
+  int32_t k = 0;
+  CHECK(nv_clip_end(clip, room.data(), cap, &k, nullptr));
+  for (int i = 0; i < k; ++i) got.push_back(room[i]);
+  // the same frames through a clip stream (n = 1, no frame store)
+  nv_stream* st = nullptr;
+  CHECK(nv_stream_open(ctx, &fmt, &sp, &st));
+  std::vector<nv_planes> ref;
+  for (int t = 0; t <= T; ++t) {
+    nv_planes o[2] = {out_planes(2 * W, 2 * H), out_planes(2 * W, 2 * H)};
+    int32_t m = 0;
+    if (t < T) CHECK(nv_stream_push(st, &frames[t], ext(t), o, &m, nullptr));
+    else CHECK(nv_stream_end(st, o, &m, nullptr));
+    for (int i = 0; i < m; ++i) ref.push_back(o[i]);
+  }
+  if (got.size() != ref.size() || (int)got.size() != 2 * T) {
+    fprintf(stderr, "clip: %zu outputs, stream %zu, expected %d\n", got.size(), ref.size(), 2 * T);
+    return 1;
+  }
+  for (size_t i = 0; i < got.size(); ++i)
+    for (int pl = 0; pl < 3; ++pl) {
+      const size_t bytes = (size_t)got[i].pitch_bytes[pl] * (pl ? H : 2 * H);
+      if (memcmp(got[i].data[pl], ref[i].data[pl], bytes) != 0) {
+        fprintf(stderr, "clip: output %zu plane %d differs from the stream's\n", i, pl);
+        return 1;
+      }
+    }
+  int32_t len = 0;
+  CHECK(nv_clip_trace(clip, nullptr, 0, &len));
+  std::vector<int32_t> tr(len);
+  CHECK(nv_clip_trace(clip, tr.data(), len, &len));
+  printf("trace:");
+  for (int32_t v : tr) printf(" %d", v);
+  printf("\n");
+  CHECK(nv_clip_close(clip));
+  CHECK(nv_stream_close(st));
+  CHECK(nv_context_destroy(ctx));
+  printf("clip ok\n");
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc >= 2 && strcmp(argv[1], "clip") == 0) return run_clip(argc, argv);
   if (argc >= 2 && strcmp(argv[1], "unpack") == 0) return run_pixel(argc, argv, true);
   if (argc >= 2 && strcmp(argv[1], "pack") == 0) return run_pixel(argc, argv, false);
   if (argc >= 2 && strcmp(argv[1], "net") == 0) return run_net(argc, argv);

@@ -145,3 +145,28 @@ def test_pixel_stage_colourspaces_in_simulation(driver, tmp_path, w, h, bits, ch
                 for name, r in zip("yuv", want):
                     g = np.fromfile(tmp_path / f"{name}.bin", dtype=dt).reshape(r.shape)
                     assert np.abs(g.astype(np.int64) - r.astype(np.int64)).max() <= 1, (name, matrix, full, centre)
+
+
+def test_general_n_clip_in_simulation(driver):
+    """nv_clip_* with n = 3, b = 2 over scenes of 1, 2, 3 and 7 frames: outputs
+    bit-identical to nv_stream_push, groups equal to the oracle's grouping rules and the
+    full block's store equal to the Fig. 1 layout."""
+    from oracle import scene
+    n, b, lengths = 3, 2, [1, 2, 3, 7]
+    out = _run(driver, ["clip", 32, 1, 8, n, b, 32, 16, sum(lengths), 1, 3, 6], timeout=900)
+    assert "clip ok" in out
+    vals = [int(v) for v in out.split("trace:")[1].split("\n")[0].split()]
+    P, i, got = n * b + b, 0, []
+    while i < len(vals):
+        kind, g = vals[i], vals[i + 1]
+        i += 2
+        got.append((kind, [vals[i + j * (n + 1):i + (j + 1) * (n + 1)] for j in range(g)], vals[i + g * (n + 1):
+                                                                                               i + g * (n + 1) + P]))
+        i += g * (n + 1) + P
+    groups = [g["inputs"] for g in scene.groups_general(lengths, n, True)]
+    assert [g for _k, gs, _s in got for g in gs] == groups
+    assert [k for k, _g, _s in got] == [1, 1, 1, 0, 1]
+    fig = [-1] * P
+    for f, p in scene.frame_store_positions(n, b, 0).items():
+        fig[p] = f + 6
+    assert got[3][2] == fig
