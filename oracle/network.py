@@ -12,9 +12,13 @@ torchvision's offset/mask conventions as the operator it had to supply itself
             offsets = raw[:18G] (per group g, tap k: dy at 2(9g+k), dx at 2(9g+k)+1)
             mask    = sigmoid(raw[18G:])  (per group g, tap k at 9g+k)
   align   : Fmid = LReLU(DCN(cat(Fa, Fb), offsets, mask; 2C->C))   (aligned once, as in YOGO)
-  output t: U = LReLU(pixel_shuffle_2(conv(G_t; C->4C))),  HR_t = conv(U; C->3) + base_t
-            G_0 = Fa, G_1/2 = Fmid, G_1 = Fb;  base_0 = up2(rgb_a), base_1 = up2(rgb_b),
-            base_1/2 = (base_0 + base_1) / 2
+  output t: U = LReLU(pixel_shuffle_(sv,sh)(conv(G_t; C->sv sh C))),  HR_t = conv(U; C->3) + base_t
+            G_0 = Fa, G_1/2 = Fmid, G_1 = Fb;  base_0 = up(rgb_a), base_1 = up(rgb_b),
+            base_1/2 = (base_0 + base_1) / 2, up = bilinear x sv rows, x sh columns
+
+The scale (sv, sh) is the task's (section 3.2, end-user usage): (2, 2) space-time
+super-resolution, (1, 1) denoising or interpolation at the input size, (2, 1)
+deinterlacing (rows doubled).  A factor of 1 leaves that axis alone.
 
 All convs are 3x3, stride 1, zero padding 1, with bias; LReLU slope 0.1.
 Arrays are channel-first (C, H, W), float64.
@@ -51,11 +55,13 @@ def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     return out.reshape(cout, h, wd)
 
 
-def pixel_shuffle(x: np.ndarray, r: int = 2) -> np.ndarray:
-    """out[c, r*h + i, r*w + j] = in[r*r*c + r*i + j, h, w]."""
-    c4, h, w = x.shape
-    c = c4 // (r * r)
-    return x.reshape(c, r, r, h, w).transpose(0, 3, 1, 4, 2).reshape(c, h * r, w * r)
+def pixel_shuffle(x: np.ndarray, r: int = 2, rw: int | None = None) -> np.ndarray:
+    """out[c, r*h + i, rw*w + j] = in[r*rw*c + rw*i + j, h, w] (rows by r, columns by rw,
+    rw = r unless given)."""
+    rw = r if rw is None else rw
+    cr, h, w = x.shape
+    c = cr // (r * rw)
+    return x.reshape(c, r, rw, h, w).transpose(0, 3, 1, 4, 2).reshape(c, h * r, w * rw)
 
 
 def bilinear_zero(x: np.ndarray, py: np.ndarray, px: np.ndarray) -> np.ndarray:
@@ -108,7 +114,18 @@ def deform_conv3x3(x, offsets, mask, w, b, groups: int) -> np.ndarray:
     return out.reshape(cout, h, wd)
 
 
-def upsample2_bilinear(x: np.ndarray) -> np.ndarray:
+def upsample_bilinear(x: np.ndarray, sv: int = 2, sh: int = 2) -> np.ndarray:
+    """Bilinear resize by sv rows and sh columns (each 1 or 2): a factor of 1 keeps the
+    axis, a factor of 2 is upsample2_bilinear's rule along it."""
+    out = np.asarray(x, dtype=np.float64)
+    if sv == 2:
+        out = upsample2_bilinear(out, axes=(1,))
+    if sh == 2:
+        out = upsample2_bilinear(out, axes=(2,))
+    return out
+
+
+def upsample2_bilinear(x: np.ndarray, axes=(1, 2)) -> np.ndarray:
     """x2 bilinear resize with half-pixel centres and clamped edges: output row 2i
     takes 3/4 x_i + 1/4 x_{i-1}, row 2i+1 takes 3/4 x_i + 1/4 x_{i+1}; same for columns."""
     def along(a, axis):
@@ -121,7 +138,10 @@ def upsample2_bilinear(x: np.ndarray) -> np.ndarray:
         shp = list(a.shape)
         shp[axis] = 2 * n
         return out.reshape(shp)
-    return along(along(np.asarray(x, dtype=np.float64), 1), 2)
+    out = np.asarray(x, dtype=np.float64)
+    for ax in axes:
+        out = along(out, ax)
+    return out
 
 
 def _wb(W, name):
@@ -148,16 +168,16 @@ def align(fa, fb, offsets, mask, W: dict, groups: int) -> np.ndarray:
                                 *_wb(W, "dcn"), groups=groups))
 
 
-def reconstruct(feat: np.ndarray, base: np.ndarray, W: dict) -> np.ndarray:
-    u = lrelu(pixel_shuffle(conv3x3(feat, *_wb(W, "up"))))
+def reconstruct(feat: np.ndarray, base: np.ndarray, W: dict, scale=(2, 2)) -> np.ndarray:
+    u = lrelu(pixel_shuffle(conv3x3(feat, *_wb(W, "up")), scale[0], scale[1]))
     return conv3x3(u, *_wb(W, "hr")) + base
 
 
-def fuse(rgb_a, rgb_b, fa, fb, W: dict, groups: int, times=(0.0, 0.5, 1.0), keep=False):
-    """Fusion stage of one group [a, b]: HR RGB for each requested time t."""
+def fuse(rgb_a, rgb_b, fa, fb, W: dict, groups: int, times=(0.0, 0.5, 1.0), keep=False, scale=(2, 2)):
+    """Fusion stage of one group [a, b]: output RGB for each requested time t."""
     res = {}
-    base0 = upsample2_bilinear(rgb_a)
-    base1 = base0 if rgb_b is rgb_a else upsample2_bilinear(rgb_b)
+    base0 = upsample_bilinear(rgb_a, *scale)
+    base1 = base0 if rgb_b is rgb_a else upsample_bilinear(rgb_b, *scale)
     if 0.5 in times or keep:
         offs, mask = offset_head(fa, fb, W, groups)
         fmid = align(fa, fb, offs, mask, W, groups)
@@ -165,11 +185,11 @@ def fuse(rgb_a, rgb_b, fa, fb, W: dict, groups: int, times=(0.0, 0.5, 1.0), keep
             res["offsets"], res["mask"], res["fmid"] = offs, mask, fmid
     for t in times:
         if t == 0.0:
-            res[t] = reconstruct(fa, base0, W)
+            res[t] = reconstruct(fa, base0, W, scale)
         elif t == 1.0:
-            res[t] = reconstruct(fb, base1, W)
+            res[t] = reconstruct(fb, base1, W, scale)
         elif t == 0.5:
-            res[t] = reconstruct(fmid, 0.5 * (base0 + base1), W)
+            res[t] = reconstruct(fmid, 0.5 * (base0 + base1), W, scale)
         else:
             raise ValueError("times must be 0, 0.5 or 1")
     return res

@@ -6,6 +6,12 @@ of section 3.1): fusion into HR frames at t = 0 and t = 1/2 (t = 1 too for a
 lone group), crop to twice the input size, requantise to the input's format.
 ``colour`` (a dict of ``pixel`` keyword arguments: matrix, full, centre) is the
 clip's colourspace, used by both pixel-format stages; None is the default reading.
+
+The task (section 3.2, end-user usage; flags of section 3.1) is given by ``scale``
+(rows, columns) and the flags: ``interp`` (Interpolation with Extra frame: groups
+[a, b] as above) and ``double`` (Double frame: the group also emits frame a enhanced;
+without it frame a passes through unchanged, which needs scale (1, 1)).  Without
+``interp`` every frame is enhanced alone: one output per input frame.
 """
 from __future__ import annotations
 
@@ -61,14 +67,17 @@ def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
 
 
 def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.SceneParams(),
-                 external=None, align=8, colour=None):
+                 external=None, align=8, colour=None, scale=(2, 2), interp=True, double=True):
     """A whole clip in stream order.  frames: list of (Y, U, V).
 
-    Returns (cuts, outputs) where outputs is the list of 2N emitted frames, each
-    {"group": (a, b), "t": t, "codes": (Y, Cb, Cr), "hr": float RGB}.
+    Returns (cuts, outputs) where outputs is the list of emitted frames (2N with
+    interp, N without), each {"group": (a, b), "t": t, "codes": (Y, Cb, Cr), "hr": float
+    RGB or None for a frame passed through}.
     """
     cuts = scene.detect_cuts([f[0] for f in frames], bits, params, external)
     h, w = frames[0][0].shape
+    sv, sh = scale
+    pk = lambda x: pixel.pack(x, bits, chroma, **(colour or {}))   # noqa: E731
     rgb_cache, feat_cache = {}, {}
 
     def feat(i):
@@ -78,14 +87,26 @@ def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.Scene
         return rgb_cache[i], feat_cache[i]
 
     outputs = []
+    if not interp:
+        for t in range(len(frames)):
+            rgb, f = feat(t)
+            hr = network.reconstruct(f, network.upsample_bilinear(rgb, sv, sh), W, scale)[:, :sv * h, :sh * w]
+            outputs.append({"group": (t, t), "t": 0.0, "hr": hr, "codes": pk(hr)})
+            for old in [k for k in feat_cache if k < t]:
+                del feat_cache[old], rgb_cache[old]
+        return cuts, outputs
+    if not double and scale != (1, 1):
+        raise ValueError("input frames pass through only at scale (1, 1)")
     for a, b in scene.groups_n1(cuts):
         rgb_a, fa = feat(a)
         rgb_b, fb = feat(b)
-        res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=(0.0, 0.5))
+        res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=(0.0, 0.5), scale=scale)
         for t in (0.0, 0.5):
-            hr = res[t][:, :2 * h, :2 * w]
-            outputs.append({"group": (a, b), "t": t, "hr": hr,
-                            "codes": pixel.pack(hr, bits, chroma, **(colour or {}))})
+            if t == 0.0 and not double:
+                outputs.append({"group": (a, b), "t": t, "hr": None, "codes": tuple(np.asarray(p) for p in frames[a])})
+                continue
+            hr = res[t][:, :sv * h, :sh * w]
+            outputs.append({"group": (a, b), "t": t, "hr": hr, "codes": pk(hr)})
         for old in [k for k in feat_cache if k < a]:
             del feat_cache[old], rgb_cache[old]
     return cuts, outputs

@@ -9,11 +9,16 @@ its bias.
 Tensor order:
   conv_in  (C, 3)            extract, first layer
   block r  a (C, C), b (C, C)  extract, residual blocks r = 0..R-1
-  off1     (C, 2C)           offset head, first conv
-  off2     (27G, C)          offset head, second conv (18G offsets, 9G mask logits)
-  dcn      (C, 2C)           modulated deformable alignment
-  up       (4C, C)           conv before the x2 pixel shuffle
-  hr       (3, C)            high-resolution RGB residual
+  off1     (C, 2C)           offset head, first conv        (interpolating networks only)
+  off2     (27G, C)          offset head, second conv (18G offsets, 9G mask logits)  (")
+  dcn      (C, 2C)           modulated deformable alignment  (")
+  up       (sv sh C, C)      conv before the (sv, sh) pixel shuffle (4C for x2 both ways)
+  hr       (3, C)            output RGB residual
+
+The task (section 3.2, end-user usage) sets the scale (sv rows, sh columns) and the
+flags: an interpolating network (Interpolation + Extra frame) fuses frame pairs and, with
+Double frame, also emits its input frames enhanced; without Interpolation it enhances
+each frame alone (no offset head, no alignment).
 """
 from __future__ import annotations
 
@@ -29,12 +34,23 @@ class NetConfig:
     channels: int = 64
     res_blocks: int = 10
     offset_groups: int = 8
-    scale: int = 2
+    scale: int = 2            # horizontal scale factor
     align: int = 8
+    scale_v: int = 0          # vertical scale factor, 0 = the same as scale
+    interp: bool = True       # Interpolation + Extra frame
+    double: bool = True       # Double frame
 
     def __post_init__(self):
         if (2 * self.channels) % self.offset_groups:
             raise ValueError("2*channels must be divisible by offset_groups")
+
+    @property
+    def sv(self) -> int:
+        return self.scale_v or self.scale
+
+    @property
+    def sh(self) -> int:
+        return self.scale
 
 
 NET_C1 = NetConfig(32, 2, 8)
@@ -49,8 +65,9 @@ def weight_layout(cfg: NetConfig):
     for r in range(cfg.res_blocks):
         layers.append((f"block{r}.a", C, C, 1.0))
         layers.append((f"block{r}.b", C, C, 0.1))
-    layers += [("off1", C, 2 * C, 1.0), ("off2", 27 * G, C, 1.0),
-               ("dcn", C, 2 * C, 1.0), ("up", 4 * C, C, 1.0), ("hr", 3, C, 0.1)]
+    if cfg.interp:
+        layers += [("off1", C, 2 * C, 1.0), ("off2", 27 * G, C, 1.0), ("dcn", C, 2 * C, 1.0)]
+    layers += [("up", cfg.sv * cfg.sh * C, C, 1.0), ("hr", 3, C, 0.1)]
     return layers
 
 

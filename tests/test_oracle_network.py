@@ -264,3 +264,28 @@ def test_weights_blob_layout():
     assert np.std(W["up"][0]) == pytest.approx(he / np.sqrt(32 * 9), rel=0.05)
     assert np.std(W["block0.b"][0]) == pytest.approx(0.1 * he / np.sqrt(32 * 9), rel=0.1)
     assert blob.dtype == np.float32
+
+
+@pytest.mark.parametrize("r,rw", [(1, 1), (2, 1), (1, 2), (2, 2)])
+def test_pixel_shuffle_rectangular_is_the_index_map(r, rw):
+    """Brute force over every index: out[c, r*h + i, rw*w + j] = in[r*rw*c + rw*i + j, h, w]."""
+    c, h, w = 3, 2, 4
+    x = np.arange(c * r * rw * h * w, dtype=np.float64).reshape(c * r * rw, h, w)
+    out = network.pixel_shuffle(x, r, rw)
+    assert out.shape == (c, r * h, rw * w)
+    for cc in range(c):
+        for hh in range(h):
+            for ww in range(w):
+                for i in range(r):
+                    for j in range(rw):
+                        assert out[cc, r * hh + i, rw * ww + j] == x[r * rw * cc + rw * i + j, hh, ww]
+
+
+@pytest.mark.parametrize("sv,sh", [(1, 1), (2, 1), (1, 2), (2, 2)])
+def test_upsample_bilinear_per_axis_equals_torch(sv, sh):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((3, 5, 7))
+    ref = torch.nn.functional.interpolate(torch.from_numpy(x)[None], scale_factor=(sv, sh), mode="bilinear",
+                                          align_corners=False)[0].numpy()
+    assert np.allclose(network.upsample_bilinear(x, sv, sh), ref, atol=1e-12)

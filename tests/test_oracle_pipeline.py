@@ -122,3 +122,31 @@ def test_weights_dict_rejects_a_wrong_size():
         pipeline.weights_dict(blob[:-1], synth.weight_layout(cfg))
     with pytest.raises(ValueError):
         pipeline.weights_dict(np.concatenate([blob, [0.0]]), synth.weight_layout(cfg))
+
+
+def test_task_modes_output_counts_and_pass_through():
+    """Section 3.2 tasks: without Interpolation one output per input frame that depends
+    on that frame alone; Interpolation without Double frame passes the input frames
+    through unchanged between the interpolated ones (scale 1)."""
+    import synth
+    from oracle import pipeline
+    clip = synth.gen_clip(24, 16, 4, seed=2, scene_starts=[2])
+    frames = [clip.frame(t) for t in range(4)]
+    for cfg in (synth.NetConfig(32, 1, 8, scale=1, interp=False), synth.NetConfig(32, 1, 8, scale=2, interp=False),
+                synth.NetConfig(32, 1, 8, scale=1, scale_v=2, interp=False)):
+        W = pipeline.weights_dict(synth.gen_weights(cfg, seed=3), synth.weight_layout(cfg))
+        _c, out = pipeline.enhance_clip(frames, 8, 420, W, 1, 8, scale=(cfg.sv, cfg.sh), interp=False)
+        assert len(out) == 4 and out[0]["codes"][0].shape == (16 * cfg.sv, 24 * cfg.sh)
+        alt = list(frames)
+        alt[1] = tuple(np.ascontiguousarray(p[::-1]) for p in frames[1])
+        _c, out2 = pipeline.enhance_clip(alt, 8, 420, W, 1, 8, scale=(cfg.sv, cfg.sh), interp=False)
+        for t in (0, 2, 3):
+            assert all(np.array_equal(a, b) for a, b in zip(out[t]["codes"], out2[t]["codes"]))
+    cfg = synth.NetConfig(32, 1, 8, scale=1, double=False)
+    W = pipeline.weights_dict(synth.gen_weights(cfg, seed=3), synth.weight_layout(cfg))
+    _c, out = pipeline.enhance_clip(frames, 8, 420, W, 1, 8, scale=(1, 1), double=False)
+    assert len(out) == 8
+    for t in range(4):
+        assert out[2 * t]["hr"] is None
+        assert all(np.array_equal(a, b) for a, b in zip(out[2 * t]["codes"], frames[t]))
+        assert out[2 * t + 1]["codes"][0].shape == (16, 24)
