@@ -58,8 +58,12 @@ typedef enum { NV_FP32 = 0, NV_FP16 = 1, NV_BF16 = 2, NV_FP8_E4M3 = 3 } nv_preci
 
 /* Network flags of the paper's network-integration section (section 3.1):
  * Interpolation doubles the frame rate, Extra frame means the network takes n+1
- * frames, Double frame means it emits 2n frames.  The implemented network is
- * n = 1 with all three set. */
+ * frames, Double frame means it emits 2n frames (without it, and with Interpolation,
+ * the input frames are output unchanged and the network's outputs are the frames
+ * between them).  Supported: Interpolation|Extra frame|Double frame (groups [a, b], two
+ * outputs per input frame), Interpolation|Extra frame (scale 1 only: input frame a passes
+ * through, then the frame between a and b), and none (each frame enhanced alone, one
+ * output per input frame). */
 enum { NV_FLAG_INTERP = 1, NV_FLAG_EXTRA = 2, NV_FLAG_DOUBLE = 4 };
 
 /* Offset head arithmetic (a library option, not one of the paper's flags).  The head
@@ -112,10 +116,19 @@ typedef struct {
   int64_t pitch_bytes[3];
 } nv_planes;
 
-/* Network shape.  channels C (32 or 64; 64 for NV_FP8_E4M3), res_blocks R (0..64),
- * offset_groups G (even, 2C divisible by G, 2C/G a multiple of 4), scale must be 2,
- * align must be 8, flags must be NV_FLAG_INTERP|NV_FLAG_EXTRA|NV_FLAG_DOUBLE, optionally
- * with NV_FLAG_HEAD_FP32 and (FP8 only) NV_FLAG_FP8_FUSION.  matrix and range name the
+/* Network shape and task.  channels C (32 or 64; 64 for NV_FP8_E4M3), res_blocks R
+ * (0..64), offset_groups G (even, 2C divisible by G, 2C/G a multiple of 4), align must
+ * be 8.  The task (section 3.2, end-user usage) is set by the scale factors and the
+ * flags: scale is the horizontal factor and scale_v the vertical one (1 or 2 each;
+ * scale_v 0 = scale), flags as above, optionally with NV_FLAG_HEAD_FP32 and (FP8 only)
+ * NV_FLAG_FP8_FUSION.  The tasks of that section: scale 1 with no flags denoises; scale
+ * 2 with no flags is super-resolution; scale 1, scale_v 2 with no flags deinterlaces;
+ * scale 1 with Interpolation|Extra frame interpolates with the input frames passed
+ * through; scale 1 with all three interpolates and denoises; scale 2 with all three is
+ * space-time super-resolution (the only task for NV_FP8_E4M3, nv_enhance_batch and the
+ * batched paths).  Output frames are the input format at scale x width, scale_v x height.
+ * The weight blob omits off1, off2 and dcn for networks without Interpolation, and its
+ * up conv has scale x scale_v x C outputs (a plain conv when both are 1).  matrix and range name the
  * colourspace the weights were trained for (section 3.1: networks are trained per
  * colourspace and the one matching the clip is used): the enhancement calls of the
  * context (group, clip stream, batch, calibration) refuse frames of another matrix or
@@ -127,6 +140,7 @@ typedef struct {
   uint32_t flags;
   int32_t precision;     /* nv_precision */
   int32_t matrix, range; /* colourspace of the training data: NV_MATRIX_*, NV_RANGE_* */
+  int32_t scale_v;       /* vertical scale factor, 0 = the same as scale */
 } nv_net_config;
 
 /* Scene-change rule: frame t starts a scene when
@@ -148,8 +162,9 @@ typedef struct nv_stream nv_stream;
  * frame and a fusion stage run per frame group).  `weights` (HOST memory, float32,
  * n_floats long) is the flat weight blob in this tensor order, each conv 3x3 OIHW
  * followed by its bias: conv_in (C,3), R x [block.a (C,C), block.b (C,C)],
- * off1 (C,2C), off2 (27G,C), dcn (C,2C), up (4C,C), hr (3,C).  The library copies
- * and repacks it; the caller may free it on return. */
+ * off1 (C,2C), off2 (27G,C), dcn (C,2C), up (4C,C), hr (3,C) for the default task (see
+ * nv_net_config for the others).  The library copies and repacks it; the caller may free
+ * it on return. */
 nv_status nv_context_create(int32_t device, const nv_net_config* cfg, const float* weights,
                             size_t n_floats, nv_context** out);
 nv_status nv_context_destroy(nv_context* ctx);
@@ -241,8 +256,10 @@ nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float* d_rgb_b,
 /* --------------------------------------------------------- end to end ---- */
 
 /* One frame group (section 3.1: a frame group in, enhanced frames out): two frames in,
- * three frames out (t = 0, 1/2, 1), each of format fmt at twice the width and height
- * (the space-time setting of section 3.2: scale 2 with Interpolation and Double frame).
+ * three frames out (t = 0, 1/2, 1) of the output format (the input format scaled by the
+ * task's factors; twice the width and height for the space-time task of section 3.2).
+ * Without Double frame the t = 0 and t = 1 outputs are the inputs passed through.
+ * NV_E_UNSUPPORTED for networks without Interpolation (no groups: use a clip stream).
  * in[2] and out[3] are HOST arrays of device planes. */
 nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
                            const nv_planes out[3], void* stream);
@@ -268,8 +285,11 @@ nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* fmt, const n
 
 /* Clip-level streaming (section 3.2: one function from clip to enhanced clip).
  * push(t) unpacks frame t, runs the scene metric and the extract stage, and emits the
- * two outputs of group t-1 (frame t-1 at t = 0, then the interpolated frame), so
- * *n_out is 0 for t = 0 and 2 afterwards.  end() emits the last group's two outputs.
+ * two outputs of group t-1 (frame t-1 at t = 0, enhanced or passed through without
+ * Double frame, then the interpolated frame), so *n_out is 0 for t = 0 and 2
+ * afterwards; end() emits the last group's two outputs.  For a network without
+ * Interpolation push(t) emits frame t enhanced (*n_out = 1, out needs one entry) and
+ * end() emits nothing.
  * The cut decision stays on the device: no host synchronisation per frame. */
 nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt, const nv_scene_params* params,
                          nv_stream** out);

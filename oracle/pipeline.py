@@ -40,7 +40,7 @@ def frame_rgb(Y, U, V, bits, chroma, align=8, colour=None):
 
 
 def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
-                  times=(0.0, 0.5, 1.0), align=8, keep=False, colour=None):
+                  times=(0.0, 0.5, 1.0), align=8, keep=False, colour=None, scale=(2, 2)):
     """One frame group.  fb_planes=None means the duplicated group [a, a].
 
     Returns {"codes": {t: (Y, Cb, Cr)}, "hr": {t: cropped float HR RGB}} plus the
@@ -54,10 +54,10 @@ def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
     else:
         rgb_b = frame_rgb(*fb_planes, bits, chroma, align, colour)
         fb = network.extract(rgb_b, W, res_blocks)
-    res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=times, keep=keep)
+    res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=times, keep=keep, scale=scale)
     out = {"codes": {}, "hr": {}}
     for t in times:
-        hr = res[t][:, :2 * h, :2 * w]
+        hr = res[t][:, :scale[0] * h, :scale[1] * w]
         out["hr"][t] = hr
         out["codes"][t] = pixel.pack(hr, bits, chroma, **(colour or {}))
     if keep:

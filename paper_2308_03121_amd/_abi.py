@@ -37,7 +37,7 @@ class NvPlanes(ctypes.Structure):
 class NvNetConfig(ctypes.Structure):
     _fields_ = [("channels", c_int32), ("res_blocks", c_int32), ("offset_groups", c_int32),
                 ("scale", c_int32), ("align", c_int32), ("flags", c_uint32), ("precision", c_int32),
-                ("matrix", c_int32), ("range", c_int32)]
+                ("matrix", c_int32), ("range", c_int32), ("scale_v", c_int32)]
 
 
 class NvSceneParams(ctypes.Structure):

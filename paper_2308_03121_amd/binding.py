@@ -121,17 +121,22 @@ class Context:
 
     def __init__(self, channels: int, res_blocks: int, offset_groups: int, weights: np.ndarray,
                  precision: str = "fp32", device: int = 0, head_fp32: bool = False,
-                 fp8_fusion: bool = False, matrix: int = 709, full: bool = False):
+                 fp8_fusion: bool = False, matrix: int = 709, full: bool = False, scale: int = 2,
+                 scale_v: int = 0, interp: bool = True, double: bool = True):
         lib = _abi.load()
-        flags = _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | _abi.NV_FLAG_DOUBLE
+        # the task: scale factors (columns, rows; 0 = the same) and the network flags
+        flags = (_abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA if interp else 0) | (_abi.NV_FLAG_DOUBLE if double else 0)
         if head_fp32:
             flags |= _abi.NV_FLAG_HEAD_FP32
         if fp8_fusion:
             flags |= _abi.NV_FLAG_FP8_FUSION
         self.fp8_fusion = fp8_fusion
         # matrix / full: the colourspace the weights were trained for
-        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, 2, 8, flags, PRECISIONS[precision],
-                               _abi.MATRIX_CODES[matrix], _abi.NV_RANGE_FULL if full else _abi.NV_RANGE_LIMITED)
+        self.cfg = NvNetConfig(channels, res_blocks, offset_groups, scale, 8, flags, PRECISIONS[precision],
+                               _abi.MATRIX_CODES[matrix], _abi.NV_RANGE_FULL if full else _abi.NV_RANGE_LIMITED,
+                               scale_v)
+        self.scale_h, self.scale_v = scale, scale_v or scale
+        self.interp, self.double = interp, double
         self.colourspace = (matrix, bool(full))
         w = np.ascontiguousarray(weights, dtype=np.float32)
         self._h = c_void_p()
@@ -186,7 +191,8 @@ class Context:
     def enhance_group(self, fmt: NvFormat, frame_a, frame_b, outs=None, stream=None):
         """Two device frames in, three output frames (t = 0, 1/2, 1) at twice the size."""
         if outs is None:
-            outs = [alloc_frame(2 * fmt.width, 2 * fmt.height, fmt.bits, fmt.chroma, frame_a[0].device)
+            outs = [alloc_frame(self.scale_h * fmt.width, self.scale_v * fmt.height, fmt.bits, fmt.chroma,
+                                frame_a[0].device)
                     for _ in range(3)]
         pin = (NvPlanes * 2)(planes_struct(*frame_a), planes_struct(*frame_b))
         pout = (NvPlanes * 3)(*[planes_struct(*o) for o in outs])
@@ -197,7 +203,8 @@ class Context:
         """enhance_group through the allocation-free entry point (nv_enhance_group_static):
         the library's temporaries live in its static per-device scratch."""
         if outs is None:
-            outs = [alloc_frame(2 * fmt.width, 2 * fmt.height, fmt.bits, fmt.chroma, frame_a[0].device)
+            outs = [alloc_frame(self.scale_h * fmt.width, self.scale_v * fmt.height, fmt.bits, fmt.chroma,
+                                frame_a[0].device)
                     for _ in range(3)]
         pin = (NvPlanes * 2)(planes_struct(*frame_a), planes_struct(*frame_b))
         pout = (NvPlanes * 3)(*[planes_struct(*o) for o in outs])
@@ -294,8 +301,8 @@ class Stream:
 
     def _outs(self, outs):
         if outs is None:
-            outs = [alloc_frame(2 * self.fmt.width, 2 * self.fmt.height, self.fmt.bits, self.fmt.chroma,
-                                self.ctx.device) for _ in range(2)]
+            outs = [alloc_frame(self.ctx.scale_h * self.fmt.width, self.ctx.scale_v * self.fmt.height, self.fmt.bits,
+                                self.fmt.chroma, self.ctx.device) for _ in range(2)]
         return outs, (NvPlanes * 2)(*[planes_struct(*o) for o in outs])
 
     def push(self, frame, external_cut: int = -1, outs=None, stream=None):

@@ -57,6 +57,16 @@ struct LayerSpec {
   int cout, cin;
 };
 
+// Task of a network (section 3.2): scale factors and the Interpolation (with Extra
+// frame) and Double frame flags.
+int scale_h(const nv_net_config& c) { return c.scale; }
+int scale_v(const nv_net_config& c) { return c.scale_v ? c.scale_v : c.scale; }
+bool interpolating(const nv_net_config& c) { return (c.flags & NV_FLAG_INTERP) != 0; }
+bool doubling(const nv_net_config& c) { return (c.flags & NV_FLAG_DOUBLE) != 0; }
+bool default_task(const nv_net_config& c) {
+  return scale_h(c) == 2 && scale_v(c) == 2 && interpolating(c) && doubling(c);
+}
+
 std::vector<LayerSpec> layer_specs(const nv_net_config& c) {
   const int C = c.channels, G = c.offset_groups;
   std::vector<LayerSpec> v;
@@ -65,10 +75,12 @@ std::vector<LayerSpec> layer_specs(const nv_net_config& c) {
     v.push_back({"block.a", C, C});
     v.push_back({"block.b", C, C});
   }
-  v.push_back({"off1", C, 2 * C});
-  v.push_back({"off2", 27 * G, C});
-  v.push_back({"dcn", C, 2 * C});
-  v.push_back({"up", 4 * C, C});
+  if (interpolating(c)) {
+    v.push_back({"off1", C, 2 * C});
+    v.push_back({"off2", 27 * G, C});
+    v.push_back({"dcn", C, 2 * C});
+  }
+  v.push_back({"up", scale_v(c) * scale_h(c) * C, C});
   v.push_back({"hr", 3, C});
   return v;
 }
@@ -84,16 +96,24 @@ nv_status check_config(const nv_net_config* c) {
   if (G <= 0 || G % 2 != 0 || (2 * c->channels) % G != 0 || ((2 * c->channels) / G) % 4 != 0)
     return fail(NV_E_INVALID,
                 "offset_groups must be even and split 2C into groups of a multiple of 4 channels");
-  if (c->scale != 2) return fail(NV_E_UNSUPPORTED, "only scale 2 is implemented");
+  if (c->scale != 1 && c->scale != 2) return fail(NV_E_UNSUPPORTED, "scale must be 1 or 2 (got %d)", c->scale);
+  if (c->scale_v != 0 && c->scale_v != 1 && c->scale_v != 2)
+    return fail(NV_E_UNSUPPORTED, "scale_v must be 0, 1 or 2 (got %d)", c->scale_v);
   if (c->align != 8) return fail(NV_E_UNSUPPORTED, "only align 8 is implemented");
-  if ((c->flags & ~(uint32_t)(NV_FLAG_HEAD_FP32 | NV_FLAG_FP8_FUSION)) != (NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE))
-    return fail(NV_E_UNSUPPORTED, "only Interpolation|Extra frame|Double frame (n = 1) is implemented");
+  const uint32_t task = c->flags & ~(uint32_t)(NV_FLAG_HEAD_FP32 | NV_FLAG_FP8_FUSION);
+  if (task != (NV_FLAG_INTERP | NV_FLAG_EXTRA | NV_FLAG_DOUBLE) && task != (NV_FLAG_INTERP | NV_FLAG_EXTRA) &&
+      task != 0)
+    return fail(NV_E_UNSUPPORTED, "flags must be Interpolation|Extra frame[|Double frame] or none");
+  if (task == (NV_FLAG_INTERP | NV_FLAG_EXTRA) && (c->scale != 1 || scale_v(*c) != 1))
+    return fail(NV_E_INVALID, "without Double frame the input frames pass through: scale must be 1");
   if ((c->flags & NV_FLAG_FP8_FUSION) && c->precision != NV_FP8_E4M3)
     return fail(NV_E_INVALID, "NV_FLAG_FP8_FUSION needs NV_FP8_E4M3 precision");
   if (c->precision < NV_FP32 || c->precision > NV_FP8_E4M3)
     return fail(NV_E_INVALID, "precision %d is not an nv_precision", c->precision);
   if (c->precision == NV_FP8_E4M3 && c->channels != 64)
     return fail(NV_E_UNSUPPORTED, "FP8 precision is implemented for 64 channels");
+  if (c->precision == NV_FP8_E4M3 && !default_task(*c))
+    return fail(NV_E_UNSUPPORTED, "FP8 precision is implemented for the x2 space-time task");
   if (c->matrix != NV_MATRIX_BT709 && c->matrix != NV_MATRIX_BT601 && c->matrix != NV_MATRIX_BT2020)
     return fail(NV_E_INVALID, "matrix %d is not an NV_MATRIX_* value", c->matrix);
   if (c->range != NV_RANGE_LIMITED && c->range != NV_RANGE_FULL)
@@ -304,6 +324,8 @@ struct nv_context {
   BatchState* batch = nullptr;
   nv_net_config cfg{};
   int C = 0, G = 0, ldo = 0;
+  int sv = 2, sh = 2;               // scale factors of the task (rows, columns)
+  bool interp = true, dbl = true;   // Interpolation (with Extra frame), Double frame
   int ft = DT_F32;                  // feature storage type
   int bt = DT_F32;                  // MFMA type of the residual-block convs
   int ut = DT_F32;                  // MFMA type of the DCN contraction and the pixel-shuffle conv
@@ -383,21 +405,21 @@ void put_fragment(uint8_t* dst, int tc, int c0, G g) {
 //     = W[o = rowmap(16*ob + lane%16)][c = KG*kg + (KG/4)*(lane/16) + e][tap], e < KG/4
 // with KG = 16 channels per group for float and 32 for 16-bit types, and
 // bias[r] = b[rowmap(r)], zero for padded rows.  rowmap is the identity except for
-// the pixel-shuffle conv (cout = 4 C): its A row 16*ob + t carries channel
-// 16*(ob % NB) + t of sub-pixel ob / NB (NB = C / 16 row blocks per sub-pixel), i.e.
-// original output channel 4*(16*(ob % NB) + t) + ob / NB, so that each group of NB
-// blocks is one sub-pixel's whole channel vector.
+// the pixel-shuffle conv (cout = r2 C for r2 = sv sh sub-pixels; r2 = 1: no reordering):
+// its A row 16*ob + t carries channel 16*(ob % NB) + t of sub-pixel ob / NB (NB = C / 16
+// row blocks per sub-pixel), i.e. original output channel r2*(16*(ob % NB) + t) + ob / NB,
+// so that each group of NB blocks is one sub-pixel's whole channel vector.
 nv_status pack_conv(nv_context* ctx, const float* w, const float* b, int cout, int cin,
-                    bool shuffle, int tc, PackedConv* out) {
+                    int r2, int tc, PackedConv* out) {
   const int KG = tc == DT_F32 ? 16 : 32;
   const int obtot = (cout + 15) / 16;
   const int nkg = cin / KG;
   std::vector<uint8_t> frag((size_t)9 * nkg * obtot * 64 * 16, 0);
   std::vector<float> bias((size_t)obtot * 16, 0.0f);
   auto rowmap = [&](int r) -> int {
-    if (!shuffle) return r;
-    const int ob = r / 16, t = r % 16, nb = cout / 64;
-    return 4 * (16 * (ob % nb) + t) + ob / nb;
+    if (r2 <= 1) return r;
+    const int ob = r / 16, t = r % 16, nb = cout / (16 * r2);
+    return r2 * (16 * (ob % nb) + t) + ob / nb;
   };
   for (int tap = 0; tap < 9; ++tap)
     for (int kg = 0; kg < nkg; ++kg)
@@ -509,15 +531,15 @@ std::vector<float> f8_row_scales(const float* w, int cout, int cin, int obtot, c
 //   frag[(st * obtot + ob) * 64 + lane][e] = e4m3(W[o][c][tap] / s_w[r])
 // with r = 16*ob + lane%16, o = rowmap(r), q = lane/16, tap = 2*st + q/2, c = 32*(q%2) + e,
 // and zero where tap = 9.  wscale receives s_w per A row.
-nv_status pack_conv_f8(nv_context* ctx, const float* w, const float* b, int cout, int cin, bool shuffle,
+nv_status pack_conv_f8(nv_context* ctx, const float* w, const float* b, int cout, int cin, int r2,
                        PackedConv* out, std::vector<float>* wscale) {
   const int obtot = (cout + 15) / 16;
   std::vector<uint8_t> frag((size_t)5 * obtot * 64 * 32, 0);
   std::vector<float> bias((size_t)obtot * 16, 0.0f);
   auto rowmap = [&](int r) -> int {
-    if (!shuffle) return r;
-    const int ob = r / 16, t = r % 16, nb = cout / 64;
-    return 4 * (16 * (ob % nb) + t) + ob / nb;
+    if (r2 <= 1) return r;
+    const int ob = r / 16, t = r % 16, nb = cout / (16 * r2);
+    return r2 * (16 * (ob % nb) + t) + ob / nb;
   };
   *wscale = f8_row_scales(w, cout, cin, obtot, rowmap);
   for (int st = 0; st < 5; ++st)
@@ -702,8 +724,9 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   if (e == hipSuccess) e = dev_alloc(&n.o1, px * C);
   if (e == hipSuccess) e = dev_alloc(&n.offs, px * ctx->ldo);
   if (e == hipSuccess) e = dev_malloc(&n.fmid, px * C * fb);
-  if (e == hipSuccess) e = dev_malloc(&n.u, 4 * px * C * fb);
-  if (e == hipSuccess) e = dev_alloc(&n.hr, 12 * px);
+  const size_t r2 = (size_t)ctx->sv * ctx->sh;
+  if (e == hipSuccess) e = dev_malloc(&n.u, r2 * px * C * fb);
+  if (e == hipSuccess) e = dev_alloc(&n.hr, 3 * r2 * px);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
     e = dev_alloc(&n.rgb[i], 3 * px);
     if (e == hipSuccess) e = dev_malloc(&n.feat[i], px * C * fb);
@@ -715,7 +738,7 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   }
   n.hp = nh;
   n.wp = nw;
-  n.bytes = px * (C * fb * 8 + 4 * C + 4 * (size_t)ctx->ldo + 48 + 24);
+  n.bytes = px * (C * fb * (4 + r2) + 4 * C + 4 * (size_t)ctx->ldo + 12 * r2 + 24);
   ws = n;
   return NV_OK;
 }
@@ -884,8 +907,10 @@ nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const fl
     const ConvImg iu = conv_img(g, nullptr, sel, alt, nullptr, nullptr, ws.u, hp, wp);
     if (ctx->calibrating && ctx->ut == DT_F8)
       NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks + 1, {g}, (size_t)hp * wp * C, s));
+    // scale 1 in both directions: the conv before the (absent) shuffle is a plain conv
+    const int r2 = ctx->sv * ctx->sh;
     NV_TRY(timed(ctx, NV_K_UP, s, "up", [&] {
-      return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, iu, 4 * C, 0, s);
+      return launch_conv(ctx->up, CONV_BULK, r2 > 1 ? EPI_SHUFFLE : EPI_LRELU, ft, ctx->tune.pb_up, iu, r2 * C, 0, s);
     }));
     float* hr = hr_out && hr_out[t] ? hr_out[t] : ws.hr;
     HrImg hi;
@@ -898,20 +923,36 @@ nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const fl
     hi.W = wp;
     hi.tsel = tsel;
     hi.item_begin = 0;
+    hi.sv = ctx->sv;
+    hi.sh = ctx->sh;
     NV_TRY(timed(ctx, NV_K_HR, s, "hr", [&] { return launch_hr(ctx->hr, ft, hi, s); }));
     if (pack_fmt && pack_out && pack_out[t]) {
       const FrameOut fo = to_frame_out(pack_fmt, pack_out[t]);
-      NV_TRY(timed(ctx, NV_K_PACK, s, "pack", [&] { return launch_pack(fo, hr, 2 * hp, 2 * wp, s); }));
+      NV_TRY(timed(ctx, NV_K_PACK, s, "pack",
+                   [&] { return launch_pack(fo, hr, ctx->sv * hp, ctx->sh * wp, s); }));
     }
   }
   return NV_OK;
 }
 
-nv_format out_format(const nv_format* f) {
+// Output frames are the input format scaled by the task's factors.
+nv_format out_format(const nv_context* ctx, const nv_format* f) {
   nv_format o = *f;
-  o.width *= 2;
-  o.height *= 2;
+  o.width *= ctx->sh;
+  o.height *= ctx->sv;
   return o;
+}
+
+// Copies a frame's planes (codes unchanged): the pass-through of input frames.
+nv_status copy_planes(const nv_format* f, const nv_planes* src, const nv_planes* dst, hipStream_t s) {
+  const int bps = f->bits == 8 ? 1 : 2;
+  for (int i = 0; i < 3; ++i) {
+    const int w = (i == 0 || f->chroma == 444) ? f->width : f->width / 2;
+    const int h = (i == 0 || f->chroma == 444) ? f->height : f->height / 2;
+    HIP_TRY(hipMemcpy2DAsync(dst->data[i], dst->pitch_bytes[i], src->data[i], src->pitch_bytes[i], (size_t)w * bps, h,
+                             hipMemcpyDeviceToDevice, s));
+  }
+  return NV_OK;
 }
 
 }  // namespace
@@ -942,6 +983,10 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   ctx->C = cfg->channels;
   ctx->G = cfg->offset_groups;
   ctx->ldo = 16 * ((27 * ctx->G + 15) / 16);
+  ctx->sv = scale_v(*cfg);
+  ctx->sh = scale_h(*cfg);
+  ctx->interp = interpolating(*cfg);
+  ctx->dbl = doubling(*cfg);
   ctx->ft = cfg->precision == NV_FP16 || cfg->precision == NV_FP8_E4M3
                 ? DT_F16
                 : (cfg->precision == NV_BF16 ? DT_BF16 : DT_F32);
@@ -979,11 +1024,15 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
         st = pack_conv_split(ctx, w, b, L.cout, L.cin, nm == "off2" ? 2 : 1, &pc);
       } else if (tc == DT_F8) {
         std::vector<float> ws;
-        st = pack_conv_f8(ctx, w, b, L.cout, L.cin, nm == "up", &pc, &ws);
+        st = pack_conv_f8(ctx, w, b, L.cout, L.cin, nm == "up" ? ctx->sv * ctx->sh : 1, &pc, &ws);
         if (nm == "up") up_ws = ws;
         else wscales.push_back(ws);
       } else {
-        st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up", tc, &pc);
+        st = pack_conv(ctx, w, b, L.cout, L.cin, nm == "up" ? ctx->sv * ctx->sh : 1, tc, &pc);
+      }
+      if (nm == "up") {
+        pc.sv = ctx->sv;
+        pc.sh = ctx->sh;
       }
       if (nm == "block.a" || nm == "block.b") ctx->blocks.push_back(pc);
       else if (nm == "off1") ctx->off1 = pc;
@@ -1130,6 +1179,7 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   if (!ctx || !d_rgb_a || !d_rgb_b || !d_feat_a || !d_feat_b) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_dims(hp, wp));
   if (out_mask == 0 || out_mask > 7) return fail(NV_E_INVALID, "out_mask must be in 1..7");
+  if ((out_mask & 2u) && !ctx->interp) return fail(NV_E_INVALID, "t = 1/2 needs an interpolating network");
   NV_TRY(check_ready(ctx));
   for (int t = 0; t < 3; ++t)
     if ((out_mask & (1u << t)) && (!d_hr || !d_hr[t])) return fail(NV_E_INVALID, "d_hr[%d] is NULL", t);
@@ -1141,31 +1191,47 @@ extern "C" nv_status nv_fuse(nv_context* ctx, const float* d_rgb_a, const float*
   });
 }
 
+// One group [a, b] in workspace ws: three outputs, t = 0, 1/2, 1.  Without Double frame
+// the t = 0 and t = 1 outputs are the input frames passed through unchanged.
+static nv_status group_impl(nv_context* ctx, Workspace& ws, const nv_format* fmt, const nv_format* of,
+                            const nv_planes in[2], const nv_planes out[3], hipStream_t s) {
+  const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
+  for (int i = 0; i < 2; ++i) {
+    const Frame f = to_frame(fmt, &in[i]);
+    NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
+    NV_TRY(extract_impl(ctx, ws, ws.rgb[i], hp, wp, ws.feat[i], s));
+  }
+  const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
+  if (!ctx->dbl) {
+    NV_TRY(copy_planes(fmt, &in[0], &out[0], s));
+    NV_TRY(copy_planes(fmt, &in[1], &out[2], s));
+  }
+  return fuse_impl(ctx, ws, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, ctx->dbl ? 7u : 2u, nullptr,
+                   nullptr, nullptr, of, po, s);
+}
+
+static nv_status check_group_task(const nv_context* ctx) {
+  if (!ctx->interp)
+    return fail(NV_E_UNSUPPORTED, "a network without Interpolation has no frame groups: use a clip stream");
+  return NV_OK;
+}
+
 extern "C" nv_status nv_enhance_group(nv_context* ctx, const nv_format* fmt, const nv_planes in[2],
                                       const nv_planes out[3], void* stream) {
   if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_ready(ctx));
+  NV_TRY(check_group_task(ctx));
   NV_TRY(check_format(fmt, "input"));
   NV_TRY(check_colourspace(ctx, fmt));
   NV_TRY(check_planes(fmt, &in[0], "input 0"));
   NV_TRY(check_planes(fmt, &in[1], "input 1"));
-  const nv_format of = out_format(fmt);
+  const nv_format of = out_format(ctx, fmt);
   NV_TRY(check_format(&of, "output"));
   for (int i = 0; i < 3; ++i) NV_TRY(check_planes(&of, &out[i], "output"));
   const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
   NV_TRY(ensure_workspace(ctx, hp, wp));
   hipStream_t s = (hipStream_t)stream;
-  Workspace& ws = ctx->ws;
-  return ordered({&ctx->ws_ord}, s, [&] {
-    for (int i = 0; i < 2; ++i) {
-      const Frame f = to_frame(fmt, &in[i]);
-      NV_TRY(timed(ctx, NV_K_UNPACK, s, "unpack", [&] { return launch_unpack(f, ws.rgb[i], hp, wp, s); }));
-      NV_TRY(extract_impl(ctx, ws, ws.rgb[i], hp, wp, ws.feat[i], s));
-    }
-    const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
-    return fuse_impl(ctx, ws, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
-                     nullptr, &of, po, s);
-  });
+  return ordered({&ctx->ws_ord}, s, [&] { return group_impl(ctx, ctx->ws, fmt, &of, in, out, s); });
 }
 
 // ------------------------------------------------- allocation-free group ----
@@ -1187,8 +1253,9 @@ size_t static_layout(const nv_context* ctx, int hp, int wp, char* base, Workspac
   w.o1 = reinterpret_cast<float*>(take(px * C * 4));
   w.offs = reinterpret_cast<float*>(take(px * ctx->ldo * 4));
   w.fmid = take(px * C * fb);
-  w.u = take(4 * px * C * fb);
-  w.hr = reinterpret_cast<float*>(take(48 * px));
+  const size_t r2 = (size_t)ctx->sv * ctx->sh;
+  w.u = take(r2 * px * C * fb);
+  w.hr = reinterpret_cast<float*>(take(12 * r2 * px));
   for (int i = 0; i < 2; ++i) {
     w.rgb[i] = reinterpret_cast<float*>(take(12 * px));
     w.feat[i] = take(px * C * fb);
@@ -1206,11 +1273,12 @@ extern "C" nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* f
                                              const nv_planes out[3], void* stream) {
   if (!ctx || !in || !out) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_ready(ctx));
+  NV_TRY(check_group_task(ctx));
   NV_TRY(check_format(fmt, "input"));
   NV_TRY(check_colourspace(ctx, fmt));
   NV_TRY(check_planes(fmt, &in[0], "input 0"));
   NV_TRY(check_planes(fmt, &in[1], "input 1"));
-  const nv_format of = out_format(fmt);
+  const nv_format of = out_format(ctx, fmt);
   NV_TRY(check_format(&of, "output"));
   for (int i = 0; i < 3; ++i) NV_TRY(check_planes(&of, &out[i], "output"));
   const int hp = round_up(fmt->height, 8), wp = round_up(fmt->width, 8);
@@ -1226,17 +1294,7 @@ extern "C" nv_status nv_enhance_group_static(nv_context* ctx, const nv_format* f
   // launch timing would create events: this entry point runs untimed
   const bool prof = ctx->prof.on;
   ctx->prof.on = false;
-  nv_status st = NV_OK;
-  for (int i = 0; i < 2 && st == NV_OK; ++i) {
-    const Frame f = to_frame(fmt, &in[i]);
-    st = check_launch(launch_unpack(f, ws.rgb[i], hp, wp, s), "unpack");
-    if (st == NV_OK) st = extract_impl(ctx, ws, ws.rgb[i], hp, wp, ws.feat[i], s);
-  }
-  if (st == NV_OK) {
-    const nv_planes* po[3] = {&out[0], &out[1], &out[2]};
-    st = fuse_impl(ctx, ws, ws.rgb[0], ws.rgb[1], ws.feat[0], ws.feat[1], hp, wp, nullptr, 7u, nullptr, nullptr,
-                   nullptr, &of, po, s);
-  }
+  const nv_status st = group_impl(ctx, ws, fmt, &of, in, out, s);
   ctx->prof.on = prof;
   return st;
 }
@@ -1336,10 +1394,32 @@ struct nv_stream {
   uint32_t* hd = nullptr;
   uint32_t* cuts = nullptr;      // [kCutRing]
   SceneAcc* acc = nullptr;       // scene accumulators, zero between frames
+  void* raw[2] = {nullptr, nullptr};   // pass-through task: the last two input frames' planes
+  nv_planes raw_planes[2]{};
   Order ord;                     // last call that touched this stream's device state
   size_t bytes = 0;
   int slot(int64_t frame) const { return (int)(frame % (int64_t)rgb.size()); }
 };
+
+// Bytes of one frame's planes stored tightly (the pass-through copies).
+static size_t raw_frame_bytes(const nv_format* f) {
+  const size_t bps = f->bits == 8 ? 1 : 2, luma = (size_t)f->width * f->height;
+  return bps * (luma + 2 * (f->chroma == 420 ? luma / 4 : luma));
+}
+
+static nv_planes raw_view(const nv_format* f, void* base) {
+  nv_planes p;
+  const int bps = f->bits == 8 ? 1 : 2;
+  const int cw = f->chroma == 420 ? f->width / 2 : f->width, ch = f->chroma == 420 ? f->height / 2 : f->height;
+  char* b = static_cast<char*>(base);
+  p.data[0] = b;
+  p.pitch_bytes[0] = (int64_t)f->width * bps;
+  p.data[1] = b + (size_t)f->width * f->height * bps;
+  p.pitch_bytes[1] = (int64_t)cw * bps;
+  p.data[2] = static_cast<char*>(p.data[1]) + (size_t)cw * ch * bps;
+  p.pitch_bytes[2] = (int64_t)cw * bps;
+  return p;
+}
 
 static size_t slot_bytes(const nv_context* ctx, int hp, int wp) {
   return (size_t)hp * wp * (12 + (size_t)ctx->C * dtype_bytes(ctx->ft));
@@ -1347,8 +1427,9 @@ static size_t slot_bytes(const nv_context* ctx, int hp, int wp) {
 
 static size_t stream_bytes(const nv_context* ctx, const nv_format* f) {
   const int hp = round_up(f->height, 8), wp = round_up(f->width, 8);
+  const size_t raw = ctx->interp && !ctx->dbl ? 2 * raw_frame_bytes(f) : 0;
   return 2 * slot_bytes(ctx, hp, wp) + 2 * (size_t)luma_pitch(f) * f->height + 2 * 64 * 4 + 8 + 4 +
-         (size_t)kCutRing * 4 + sizeof(SceneAcc);
+         (size_t)kCutRing * 4 + sizeof(SceneAcc) + raw;
 }
 
 static void stream_free(nv_stream* s) {
@@ -1360,6 +1441,7 @@ static void stream_free(nv_stream* s) {
   dev_free(s->hd);
   dev_free(s->cuts);
   dev_free(s->acc);
+  for (int i = 0; i < 2; ++i) free_raw(s->raw[i]);
   order_free(s->ord);
 }
 
@@ -1413,7 +1495,7 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   if (!s) return fail(NV_E_NOMEM, "host allocation failed");
   s->ctx = ctx;
   s->fmt = *fmt;
-  s->ofmt = out_format(fmt);
+  s->ofmt = out_format(ctx, fmt);
   s->rule = to_rule(params);
   s->hp = round_up(fmt->height, 8);
   s->wp = round_up(fmt->width, 8);
@@ -1426,6 +1508,11 @@ extern "C" nv_status nv_stream_open(nv_context* ctx, const nv_format* fmt,
   if (e == hipSuccess) e = dev_alloc(&s->cuts, kCutRing);
   if (e == hipSuccess) e = dev_alloc(&s->acc, 1);
   if (e == hipSuccess) e = hipMemset(s->acc, 0, sizeof(SceneAcc));
+  if (ctx->interp && !ctx->dbl)
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = dev_malloc(&s->raw[i], raw_frame_bytes(fmt));
+      if (e == hipSuccess) s->raw_planes[i] = raw_view(fmt, s->raw[i]);
+    }
   nv_status st = NV_OK;
   if (e != hipSuccess)
     st = fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "stream allocation: %s", hipGetErrorString(e));
@@ -1447,6 +1534,12 @@ static nv_status emit_group(nv_stream* s, int slot_a, int slot_b, const uint32_t
                             const nv_planes out[2], hipStream_t hs) {
   const nv_planes* po[3] = {&out[0], &out[1], nullptr};
   NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
+  if (!s->ctx->dbl) {
+    // without Double frame the group's first frame passes through unchanged
+    NV_TRY(copy_planes(&s->fmt, &s->raw_planes[slot_a & 1], &out[0], hs));
+    return fuse_impl(s->ctx, s->ctx->ws, s->rgb[slot_a], s->rgb[slot_b], s->feat[slot_a], s->feat[slot_b], s->hp,
+                     s->wp, cut_b, 2u, nullptr, nullptr, nullptr, &s->ofmt, po, hs);
+  }
   return fuse_impl(s->ctx, s->ctx->ws, s->rgb[slot_a], s->rgb[slot_b], s->feat[slot_a], s->feat[slot_b], s->hp,
                    s->wp, cut_b, 3u, nullptr, nullptr, nullptr, &s->ofmt, po, hs);
 }
@@ -1460,7 +1553,10 @@ extern "C" nv_status nv_stream_push(nv_stream* s, const nv_planes* frame, int32_
   NV_TRY(check_ready(s->ctx));
   NV_TRY(check_planes(&s->fmt, frame, "frame"));
   if (external_cut < -1 || external_cut > 1) return fail(NV_E_INVALID, "external_cut must be -1, 0 or 1");
-  if (s->t > 0) {
+  if (!s->ctx->interp) {
+    if (!out) return fail(NV_E_INVALID, "out is NULL");
+    NV_TRY(check_planes(&s->ofmt, &out[0], "output"));
+  } else if (s->t > 0) {
     if (!out) return fail(NV_E_INVALID, "out is NULL");
     for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
   }
@@ -1517,6 +1613,16 @@ static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t externa
   NV_TRY(ensure_workspace(s->ctx, s->hp, s->wp));
   NV_TRY(extract_impl(s->ctx, s->ctx->ws, s->rgb[cur], s->hp, s->wp, s->feat[cur], hs));
   *n_out = 0;
+  if (!s->ctx->interp) {
+    // each frame enhanced alone: one output per input frame, at once
+    const nv_planes* po[3] = {&out[0], nullptr, nullptr};
+    NV_TRY(fuse_impl(s->ctx, s->ctx->ws, s->rgb[cur], s->rgb[cur], s->feat[cur], s->feat[cur], s->hp, s->wp, nullptr,
+                     1u, nullptr, nullptr, nullptr, &s->ofmt, po, hs));
+    *n_out = 1;
+    scene_advance(s);
+    return NV_OK;
+  }
+  if (!s->ctx->dbl) NV_TRY(copy_planes(&s->fmt, frame, &s->raw_planes[cur & 1], hs));
   if (s->t > 0) {
     NV_TRY(emit_group(s, prv, cur, cut_t, out, hs));
     *n_out = 2;
@@ -1528,7 +1634,7 @@ static nv_status push_impl(nv_stream* s, const nv_planes* frame, int32_t externa
 extern "C" nv_status nv_stream_end(nv_stream* s, const nv_planes out[2], int32_t* n_out, void* stream) {
   if (!s || !n_out) return fail(NV_E_INVALID, "NULL argument");
   *n_out = 0;
-  if (s->t == 0) return NV_OK;
+  if (s->t == 0 || !s->ctx->interp) return NV_OK;
   if (!out) return fail(NV_E_INVALID, "out is NULL");
   for (int i = 0; i < 2; ++i) NV_TRY(check_planes(&s->ofmt, &out[i], "output"));
   const int last = s->slot(s->t - 1);
@@ -1671,6 +1777,8 @@ extern "C" nv_status nv_clip_open(nv_context* ctx, const nv_format* fmt, const n
   *out = nullptr;
   if (n < 1 || b < 1 || n * b + b > kClipMaxPositions)
     return fail(NV_E_INVALID, "n = %d, b = %d: need n, b >= 1 and n b + b <= %d", n, b, kClipMaxPositions);
+  if (!ctx->interp || !ctx->dbl)
+    return fail(NV_E_UNSUPPORTED, "general-n clips run interpolating networks with Double frame");
   nv_clip* c = new (std::nothrow) nv_clip;
   if (!c) return fail(NV_E_NOMEM, "host allocation failed");
   nv_status st = nv_stream_open(ctx, fmt, params, &c->st);
@@ -1938,6 +2046,8 @@ extern "C" nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes) {
 extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs, int32_t n, void* stream) {
   if (!ctx || (!reqs && n > 0) || n < 0) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(check_ready(ctx));
+  if (!default_task(ctx->cfg))
+    return fail(NV_E_UNSUPPORTED, "batches run the x2 space-time task; other tasks use clip streams");
   hipStream_t hs = (hipStream_t)stream;
   // ---- validation (nothing is enqueued or changed before it passes) ----
   int nframes = 0, ngroups = 0;
@@ -2112,6 +2222,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
       h.W = wp;
       h.tsel = o == 0 ? 0 : 2;
       h.item_begin = it[BL_HR];
+      h.sv = h.sh = 2;
       PackJob& pk = T.pack[o][k];
       pk.f = to_frame_out(&s->ofmt, &Gr.out[o]);
       pk.m = make_fwd(pk.f.bits, pk.f.matrix, pk.f.full);
@@ -2211,6 +2322,10 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
   char key[128];
   snprintf(key, sizeof key, "prec=%d C=%d R=%d size=%dx%d", ctx->cfg.precision, ctx->C, ctx->cfg.res_blocks,
            wp, hp);
+  if (!default_task(ctx->cfg)) {   // the task changes the pixel-shuffle conv and drops the alignment
+    const size_t n = strlen(key);
+    snprintf(key + n, sizeof key - n, " task=%dx%d/%d%d", ctx->sv, ctx->sh, (int)ctx->interp, (int)ctx->dbl);
+  }
   std::string rep;
   bool found = false;
   if (cache) {
@@ -2273,6 +2388,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     };
     // 32x32x16 MFMA form for 16-bit convs with 64 input channels
     std::vector<int> block_tiles = bulk_tiles, up_tiles = bulk_tiles;
+    const int r2 = ctx->sv * ctx->sh, up_epi = r2 > 1 ? EPI_SHUFFLE : EPI_LRELU;
     if (C == 64) {
       for (int pb : {2, 4}) {
         if (!ctx->blocks.empty() && ctx->blocks[0].frag32) block_tiles.push_back(tile_code(pb, 1, 0, 1));
@@ -2287,6 +2403,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
                   {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}},
                   {"off1", &ctx->tune.off1, head_tiles(ctx->off1)}, {"off2", &ctx->tune.off2, head_tiles(ctx->off2)}};
     for (auto& cd : cands) {
+      // networks that do not interpolate have no offset head and no alignment
+      if (!ctx->interp && cd.slot != &ctx->tune.pb_block && cd.slot != &ctx->tune.pb_up) continue;
       float best = 1e30f;
       int best_pb = *cd.slot;
       rep += cd.name;
@@ -2298,12 +2416,12 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
           const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
           st = time_launch(s, 3, &ms, [&] {
             return launch_conv(ctx->blocks.empty() ? ctx->up : ctx->blocks[0], CONV_BULK,
-                               ctx->blocks.empty() ? EPI_SHUFFLE : EPI_LRELU, ft, pb, im,
-                               ctx->blocks.empty() ? 4 * C : C, 0, s);
+                               ctx->blocks.empty() ? up_epi : EPI_LRELU, ft, pb, im,
+                               ctx->blocks.empty() ? r2 * C : C, 0, s);
           });
         } else if (cd.slot == &ctx->tune.pb_up) {
           const ConvImg im = conv_img(ws.feat[0], nullptr, nullptr, nullptr, nullptr, nullptr, ws.u, hp, wp);
-          st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, pb, im, 4 * C, 0, s); });
+          st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->up, CONV_BULK, up_epi, ft, pb, im, r2 * C, 0, s); });
         } else if (cd.slot == &ctx->tune.off1) {
           const ConvImg im = conv_img(ws.feat[0], ws.feat[0], nullptr, nullptr, nullptr, nullptr, ws.o1, hp, wp);
           st = time_launch(s, 3, &ms, [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, pb, im, C, 0, s); });

@@ -34,6 +34,7 @@ struct ConvLayer {
   int sig_lo;   // EPI_OFFSET: sigmoid on channels >= sig_lo
   int obtot;    // total 16-channel output blocks of the layer
   int ccout;    // EPI_SHUFFLE: channels of the high-resolution map
+  int sv, sh;   // EPI_SHUFFLE: sub-pixel rows and columns (sub-pixel s -> row s / sh, column s % sh)
 };
 
 // Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
@@ -101,8 +102,8 @@ __device__ __forceinline__ void conv_store(const ConvLayer& L, const ConvImg& im
       } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g % NB) + t at sub-pixel g / NB
         const int obg = obase + ob, nb = L.ccout >> 4;
         const int sp = obg / nb, c = 16 * (obg - sp * nb) + 4 * q;
-        const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
-        store4f<TOUT>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
+        const int Y = L.sv * gy + sp / L.sh, X = L.sh * gx + sp % L.sh;
+        store4f<TOUT>(dst + ((size_t)Y * (L.sh * im.W) + X) * L.ccout + c, lrelu4(v));
       }
     }
   }
@@ -177,7 +178,8 @@ __device__ __forceinline__ void conv_store_staged(const ConvLayer& L, const Conv
 // Pixel-shuffle epilogue through LDS: the workgroup's row blocks obase .. obase + 7
 // are sub-pixels sp0 = obase / 4 and sp0 + 1 with all 64 channels each (four blocks per
 // sub-pixel); each pass writes one sub-pixel's LReLU-ed results into the LDS tile and
-// copies whole high-resolution pixels out.  Same arithmetic as conv_store.
+// copies whole high-resolution pixels out (sub-pixel s at row s / sh, column s % sh of
+// the sv x sh block).  Same arithmetic as conv_store.
 template <typename TC, int OBW, int RW, int PB>
 __device__ __forceinline__ void conv_store_shuffle_staged(const ConvLayer& L, const ConvImg& im,
                                                           const f32x4 (&acc)[RW][OBW], int ty0, int tx0, int wr,
@@ -212,8 +214,8 @@ __device__ __forceinline__ void conv_store_shuffle_staged(const ConvLayer& L, co
       const int px = idx / NPC, ck = idx - px * NPC;
       const int gy = ty0 + px / kTW, gx = tx0 + px % kTW;
       if (gy < im.H && gx < im.W) {
-        const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
-        stu4(dst + ((size_t)Y * (2 * im.W) + X) * C + E * ck, ldu4(&tile[px * OLDP + E * ck]));
+        const int Y = L.sv * gy + sp / L.sh, X = L.sh * gx + sp % L.sh;
+        stu4(dst + ((size_t)Y * (L.sh * im.W) + X) * C + E * ck, ldu4(&tile[px * OLDP + E * ck]));
       }
     }
   }
@@ -652,8 +654,8 @@ __device__ __forceinline__ void conv_tile32(const ConvLayer& L, const ConvImg& i
           store4f<TC>(dst + at, v);
         } else {  // EPI_SHUFFLE: A row 16*g + t is channel 16*(g % NB) + t at sub-pixel g / NB
           const int g = row >> 4, nb = L.ccout >> 4, sp = g / nb, c = 16 * (g - sp * nb) + (row & 15);
-          const int Y = 2 * gy + (sp >> 1), X = 2 * gx + (sp & 1);
-          store4f<TC>(dst + ((size_t)Y * (2 * im.W) + X) * L.ccout + c, lrelu4(v));
+          const int Y = L.sv * gy + sp / L.sh, X = L.sh * gx + sp % L.sh;
+          store4f<TC>(dst + ((size_t)Y * (L.sh * im.W) + X) * L.ccout + c, lrelu4(v));
         }
       }
   }
@@ -1489,14 +1491,21 @@ __global__ __launch_bounds__(256) void k_conv_in_batch(const float* __restrict__
 // output pixel then sums the nine responses of its shifted neighbours:
 //   out[o][p] = b[o] + sum_tap R[3*tap + o][p + delta_tap] + base[o][p].
 // Pixels outside the map have U = 0, hence R = 0: the conv's zero padding.
-// tsel: 0 -> base of frame a, 1 -> frame b, 2 -> the mean of both.
-__device__ __forceinline__ float up2_sample(const float* pl, int H, int W, int Y, int X) {
-  const int i = Y >> 1, jx = X >> 1;
+// tsel: 0 -> base of frame a, 1 -> frame b, 2 -> the mean of both.  The base is the
+// bilinear resize by sv rows and sh columns (a factor of 1 keeps the axis; a factor of 2
+// takes 3/4 of the nearest and 1/4 of the next sample along it, rows first).
+__device__ __forceinline__ float up_sample(const float* pl, int H, int W, int Y, int X, int sv, int sh) {
+  const int i = sv == 2 ? Y >> 1 : Y, jx = sh == 2 ? X >> 1 : X;
   const int i2 = (Y & 1) ? min(i + 1, H - 1) : max(i - 1, 0);
   const int j2 = (X & 1) ? min(jx + 1, W - 1) : max(jx - 1, 0);
-  const float r0 = 0.75f * pl[(size_t)i * W + jx] + 0.25f * pl[(size_t)i2 * W + jx];
-  const float r1 = 0.75f * pl[(size_t)i * W + j2] + 0.25f * pl[(size_t)i2 * W + j2];
-  return 0.75f * r0 + 0.25f * r1;
+  if (sv == 2 && sh == 2) {
+    const float r0 = 0.75f * pl[(size_t)i * W + jx] + 0.25f * pl[(size_t)i2 * W + jx];
+    const float r1 = 0.75f * pl[(size_t)i * W + j2] + 0.25f * pl[(size_t)i2 * W + j2];
+    return 0.75f * r0 + 0.25f * r1;
+  }
+  if (sv == 2) return 0.75f * pl[(size_t)i * W + jx] + 0.25f * pl[(size_t)i2 * W + jx];
+  if (sh == 2) return 0.75f * pl[(size_t)i * W + jx] + 0.25f * pl[(size_t)i * W + j2];
+  return pl[(size_t)i * W + jx];
 }
 
 struct HrLayer {
@@ -1511,7 +1520,7 @@ template <typename TU, int C>
 __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int ty0, int tx0, float* R) {
   constexpr int T = kHrT, RW = kHrRW, NP = kHrNP, NPB = kHrNPB, LDR = kHrLDR;
   constexpr int KG = Mma<TU>::KG, QE = KG / 4, NCG = C / KG;
-  const int H2 = 2 * im.H, W2 = 2 * im.W;
+  const int H2 = im.sv * im.H, W2 = im.sh * im.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
   const TU* u = static_cast<const TU*>(im.u);
@@ -1573,9 +1582,11 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
   float base[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (im.tsel == 0) base[c] = up2_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X);
-    else if (im.tsel == 1) base[c] = up2_sample(rb + c * lpl, im.H, im.W, Y, X);
-    else base[c] = 0.5f * (up2_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X) + up2_sample(rb + c * lpl, im.H, im.W, Y, X));
+    if (im.tsel == 0) base[c] = up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
+    else if (im.tsel == 1) base[c] = up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
+    else
+      base[c] = 0.5f * (up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh) +
+                        up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh));
   }
   im.dst[(size_t)Y * W2 + X] = s0 + base[0];
   im.dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
@@ -1585,8 +1596,8 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
 template <typename TU, int C>
 __global__ __launch_bounds__(256) void k_hr(HrLayer L, HrImg im) {
   __shared__ float R[kHrNPB * 16 * kHrLDR];
-  const int tiles_x = (2 * im.W + kHrT - 1) / kHrT;
-  const int ntile = tiles_x * ((2 * im.H + kHrT - 1) / kHrT);
+  const int tiles_x = (im.sh * im.W + kHrT - 1) / kHrT;
+  const int ntile = tiles_x * ((im.sv * im.H + kHrT - 1) / kHrT);
   const int t = xcd_tile(blockIdx.x, ntile);
   hr_tile<TU, C>(L, im, (t / tiles_x) * kHrT, (t % tiles_x) * kHrT, R);
 }
@@ -1599,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_hr_batch(HrLayer L, const HrImg* __rest
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const HrImg im = jobs[find_job(jobs, njobs, item)];
     const int t = item - im.item_begin;
-    const int tiles_x = (2 * im.W + kHrT - 1) / kHrT;
+    const int tiles_x = (im.sh * im.W + kHrT - 1) / kHrT;
     hr_tile<TU, C>(L, im, (t / tiles_x) * kHrT, (t % tiles_x) * kHrT, R);
     __syncthreads();
   }
@@ -1688,9 +1699,14 @@ hipError_t conv_bulk_pbw(const ConvCall& c, int epi) {
       if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_RES, SPLIT_NONE, WO>(c);
       return run_conv<S, T, S, CCH, 1, 2, PB, EPI_RES, SPLIT_NONE, WO>(c);
     case EPI_SHUFFLE:
-      // FP8 fragments are twice as wide: half the output blocks per workgroup
+      // FP8 fragments are twice as wide: half the output blocks per workgroup; fewer
+      // sub-pixels (a factor of 2 along one axis only) give fewer output blocks
       if constexpr (std::is_same<T, f8>::value) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
-      else return run_conv<S, T, S, CCH, 1, 8, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
+      else {
+        if (c.L.obtot % 8 == 0) return run_conv<S, T, S, CCH, 1, 8, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
+        if (c.L.obtot % 4 == 0) return run_conv<S, T, S, CCH, 1, 4, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
+        return run_conv<S, T, S, CCH, 1, 2, PB, EPI_SHUFFLE, SPLIT_NONE, WO>(c);
+      }
   }
   return hipErrorInvalidValue;
 }
@@ -1917,7 +1933,9 @@ ConvLayer make_layer(const PackedConv& P, int ldy, int sig_lo) {
   L.cout = P.cout;
   L.sig_lo = sig_lo;
   L.obtot = P.obtot;
-  L.ccout = P.cout / 4;
+  L.sv = P.sv;
+  L.sh = P.sh;
+  L.ccout = P.cout / (P.sv * P.sh);
   return L;
 }
 
@@ -2007,7 +2025,7 @@ hipError_t dcn_dispatch(const PackedConv& P, int tf, int pb, int ldo, int groups
 
 template <typename TU, int C>
 void run_hr(const HrLayer& L, const HrImg* im, const HrImg* jobs, const int* count, hipStream_t s) {
-  if (im) hipLaunchKernelGGL((k_hr<TU, C>), dim3(hr_items(im->H, im->W)), dim3(256), 0, s, L, *im);
+  if (im) hipLaunchKernelGGL((k_hr<TU, C>), dim3(hr_items(im->H, im->W, im->sv, im->sh)), dim3(256), 0, s, L, *im);
   else hipLaunchKernelGGL((k_hr_batch<TU, C>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
 }
 
@@ -2042,7 +2060,7 @@ int conv_ob(int role, int epi, int obtot, int tc, int tile) {
   }
   if (tile_lw(tile)) return 4;
   if (tile_m32(tile)) return epi == EPI_SHUFFLE ? (pb == 2 ? 8 : 4) : 4;   // in 16-row blocks
-  if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : 8;
+  if (epi == EPI_SHUFFLE) return tc == DT_F8 ? 4 : (obtot % 8 == 0 ? 8 : (obtot % 4 == 0 ? 4 : 2));
   return obtot % 4 == 0 ? 4 : 2;
 }
 

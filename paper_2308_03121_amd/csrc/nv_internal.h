@@ -124,6 +124,7 @@ struct PackedConv {
   float* oscale = nullptr; // device, obtot*16 floats (FP8 only)
   float* ainv = nullptr;   // device scalar (FP8 only)
   int cin = 0, cout = 0, obtot = 0, tc = DT_F32;
+  int sv = 2, sh = 2;      // pixel-shuffle conv: sub-pixel rows and columns of its output
 };
 
 // The 3 -> C input conv runs on the vector ALUs with the plain OIHW layout.
@@ -170,6 +171,7 @@ struct DcnImg {
   int item_begin;
 };
 
+// The output conv of one image: U is [sv H][sh W][C], the output R'G'B' [3][sv H][sh W].
 struct HrImg {
   const void* u;
   const float* rgb_a;
@@ -178,6 +180,7 @@ struct HrImg {
   float* dst;
   int H, W, tsel;
   int item_begin;
+  int sv = 2, sh = 2;
 };
 
 // Tile shape of a bulk conv launch: rows per wave pb (1, 2, 4; a workgroup covers 4 pb
@@ -213,7 +216,7 @@ hipError_t launch_resblock(const PackedConv& A, const PackedConv& Bc, int tin, c
 inline int conv_items(int H, int W, int pb, int nobg) {
   return ((W + 15) / 16) * ((H + 4 * pb - 1) / (4 * pb)) * nobg;
 }
-inline int hr_items(int H, int W) { return ((2 * W + 15) / 16) * ((2 * H + 15) / 16); }
+inline int hr_items(int H, int W, int sv = 2, int sh = 2) { return ((sh * W + 15) / 16) * ((sv * H + 15) / 16); }
 // input conv: one item per run of 4096 / C consecutive pixels (all C channels)
 inline int conv_in_items(int H, int W, int C) { return (H * W + 4096 / C - 1) / (4096 / C); }
 

@@ -328,7 +328,67 @@ static int run_clip(int argc, char** argv) {
   return 0;
 }
 
+// driver task DIR C R G SCALE SCALE_V FLAGS W H T: a clip stream of T 8-bit 4:2:0 frames
+// (DIR/f<t>_{y,u,v}.bin, tight planes) with weights DIR/weights.f32 for a network of the
+// given scale factors and flags; writes the emitted frames as DIR/o<k>_{y,u,v}.bin and
+// prints "outputs <count>".
+static int run_task(int argc, char** argv) {
+  if (argc < 12) return 2;
+  const std::string dir = argv[2];
+  nv_net_config cfg{};
+  cfg.channels = atoi(argv[3]);
+  cfg.res_blocks = atoi(argv[4]);
+  cfg.offset_groups = atoi(argv[5]);
+  cfg.scale = atoi(argv[6]);
+  cfg.scale_v = atoi(argv[7]);
+  cfg.align = 8;
+  cfg.flags = (uint32_t)atoi(argv[8]);
+  const int W = atoi(argv[9]), H = atoi(argv[10]), T = atoi(argv[11]);
+  const std::vector<char> wb = read_file(dir + "/weights.f32");
+  nv_context* ctx = nullptr;
+  CHECK(nv_context_create(0, &cfg, reinterpret_cast<const float*>(wb.data()), wb.size() / 4, &ctx));
+  nv_format fmt{W, H, 8, 420};
+  nv_scene_params sp{24, 1, 4, 1};
+  nv_stream* st = nullptr;
+  CHECK(nv_stream_open(ctx, &fmt, &sp, &st));
+  const int sv = cfg.scale_v ? cfg.scale_v : cfg.scale, sh = cfg.scale;
+  const int OW = W * sh, OH = H * sv;
+  const char* names[3] = {"y", "u", "v"};
+  int k = 0;
+  auto save = [&](const nv_planes& o) {
+    for (int i = 0; i < 3; ++i) {
+      const int pw = i ? OW / 2 : OW, ph = i ? OH / 2 : OH;
+      std::vector<uint8_t> buf((size_t)pw * ph);
+      for (int y = 0; y < ph; ++y)
+        memcpy(&buf[(size_t)y * pw], static_cast<char*>(o.data[i]) + (size_t)y * o.pitch_bytes[i], pw);
+      write_file(dir + "/o" + std::to_string(k) + "_" + names[i] + ".bin", buf.data(), buf.size());
+    }
+    ++k;
+  };
+  for (int t = 0; t <= T; ++t) {
+    nv_planes o[2] = {out_planes(OW, OH), out_planes(OW, OH)};
+    int32_t m = 0;
+    if (t < T) {
+      nv_planes in;
+      for (int i = 0; i < 3; ++i) {
+        const std::vector<char> d = read_file(dir + "/f" + std::to_string(t) + "_" + names[i] + ".bin");
+        in.data[i] = dev(d.size(), d.data());
+        in.pitch_bytes[i] = i ? W / 2 : W;
+      }
+      CHECK(nv_stream_push(st, &in, -1, o, &m, nullptr));
+    } else {
+      CHECK(nv_stream_end(st, o, &m, nullptr));
+    }
+    for (int i = 0; i < m; ++i) save(o[i]);
+  }
+  printf("outputs %d\n", k);
+  CHECK(nv_stream_close(st));
+  CHECK(nv_context_destroy(ctx));
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc >= 2 && strcmp(argv[1], "task") == 0) return run_task(argc, argv);
   if (argc >= 2 && strcmp(argv[1], "clip") == 0) return run_clip(argc, argv);
   if (argc >= 2 && strcmp(argv[1], "unpack") == 0) return run_pixel(argc, argv, true);
   if (argc >= 2 && strcmp(argv[1], "pack") == 0) return run_pixel(argc, argv, false);

@@ -42,6 +42,8 @@ hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
 hipError_t hipHostFree(void* p);
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind k);
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind k, hipStream_t s);
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                             size_t height, hipMemcpyKind k, hipStream_t s);
 hipError_t hipMemset(void* p, int v, size_t bytes);
 hipError_t hipMemsetAsync(void* p, int v, size_t bytes, hipStream_t s);
 hipError_t hipDeviceSynchronize(void);

@@ -144,6 +144,15 @@ hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind k) 
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind k, hipStream_t) {
   return hipMemcpy(dst, src, bytes, k);
 }
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                             size_t height, hipMemcpyKind k, hipStream_t) {
+  if (height == 0) return hipSuccess;
+  if (k == hipMemcpyDeviceToDevice || k == hipMemcpyHostToDevice) need(dst, (height - 1) * dpitch + width, "memcpy2d dst");
+  if (k == hipMemcpyDeviceToDevice || k == hipMemcpyDeviceToHost) need(src, (height - 1) * spitch + width, "memcpy2d src");
+  for (size_t r = 0; r < height; ++r)
+    std::memmove(static_cast<char*>(dst) + r * dpitch, static_cast<const char*>(src) + r * spitch, width);
+  return hipSuccess;
+}
 hipError_t hipMemset(void* p, int v, size_t bytes) {
   need(p, bytes, "memset");
   if (fake::in_alloc(p, bytes)) std::memset(p, v, bytes);

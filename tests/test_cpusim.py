@@ -170,3 +170,31 @@ def test_general_n_clip_in_simulation(driver):
     for f, p in scene.frame_store_positions(n, b, 0).items():
         fig[p] = f + 6
     assert got[3][2] == fig
+
+
+@pytest.mark.parametrize("scale,scale_v,flags", [(1, 0, 0), (2, 0, 0), (1, 2, 0), (1, 0, 3), (1, 0, 7), (2, 0, 7)],
+                         ids=["denoise", "sr", "deinterlace", "interp-pass", "interp-denoise", "space-time"])
+def test_task_modes_in_simulation(driver, tmp_path, scale, scale_v, flags):
+    """A clip stream in each task of the end-user section against the oracle: every
+    output frame within one code (pass-through frames identical to the inputs)."""
+    from oracle import pipeline
+    interp, double = bool(flags & 1), bool(flags & 4)
+    cfg = synth.NetConfig(32, 1, 8, scale=scale, scale_v=scale_v, interp=interp, double=double)
+    blob = synth.gen_weights(cfg, seed=5)
+    blob.astype(np.float32).tofile(tmp_path / "weights.f32")
+    T, W, H = 4, 32, 16
+    clip = synth.gen_clip(W, H, T, seed=9, scene_starts=[2])
+    frames = [clip.frame(t) for t in range(T)]
+    for t, fr in enumerate(frames):
+        for name, a in zip("yuv", fr):
+            np.ascontiguousarray(a).tofile(tmp_path / f"f{t}_{name}.bin")
+    out = _run(driver, ["task", tmp_path, 32, 1, 8, scale, scale_v, flags, W, H, T], timeout=900)
+    n = int(out.split("outputs")[1].split()[0])
+    _c, ref = pipeline.enhance_clip(frames, 8, 420, oracle_weights(cfg, blob), 1, 8, scale=(cfg.sv, cfg.sh),
+                                    interp=interp, double=double)
+    assert n == len(ref)
+    for k, r in enumerate(ref):
+        got = [np.fromfile(tmp_path / f"o{k}_{name}.bin", dtype=np.uint8).reshape(p.shape)
+               for name, p in zip("yuv", r["codes"])]
+        d = max(int(np.abs(g.astype(np.int64) - p.astype(np.int64)).max()) for g, p in zip(got, r["codes"]))
+        assert d == 0 if r["hr"] is None else d <= 1, (k, d)
