@@ -16,6 +16,18 @@ torchvision's offset/mask conventions as the operator it had to supply itself
             G_0 = Fa, G_1/2 = Fmid, G_1 = Fb;  base_0 = up(rgb_a), base_1 = up(rgb_b),
             base_1/2 = (base_0 + base_1) / 2, up = bilinear x sv rows, x sh columns
 
+With a feature pyramid of L levels (the extract stage's output as section 3.1 defines
+it; L = 1 is the network above), level 1 is the trunk's output and each further level
+halves both dimensions:
+
+  pyramid : F^1 = extract(rgb);  F^l = LReLU(conv(avgpool2(F^(l-1)); C->C))  for l = 2..L
+  cascade : from l = L down to 1, with the level's own offset head and DCN weights,
+            offsets^l = head offsets^l + 2 up2(offsets^(l+1))   (coarse motion in fine pixels)
+            mask^l    = the head's mask^l
+            A^l       = LReLU(DCN(cat(Fa^l, Fb^l), offsets^l, mask^l)) + up2(A^(l+1))
+            Fmid = A^1
+  (the terms with l + 1 are absent at l = L; up2 is the x2 bilinear resize below)
+
 The scale (sv, sh) is the task's (section 3.2, end-user usage): (2, 2) space-time
 super-resolution, (1, 1) denoising or interpolation at the input size, (2, 1)
 deinterlacing (rows doubled).  A factor of 1 leaves that axis alone.
@@ -144,6 +156,16 @@ def upsample2_bilinear(x: np.ndarray, axes=(1, 2)) -> np.ndarray:
     return out
 
 
+def avgpool2(x: np.ndarray) -> np.ndarray:
+    """Mean of each 2x2 block: out[c, i, j] = (x[c, 2i, 2j] + x[c, 2i, 2j+1] + x[c, 2i+1, 2j]
+    + x[c, 2i+1, 2j+1]) / 4 (even dimensions)."""
+    x = np.asarray(x, dtype=np.float64)
+    c, h, w = x.shape
+    if h % 2 or w % 2:
+        raise ValueError("avgpool2 needs even dimensions")
+    return x.reshape(c, h // 2, 2, w // 2, 2).mean(axis=(2, 4))
+
+
 def _wb(W, name):
     w, b = W[name]
     return np.asarray(w, dtype=np.float64), np.asarray(b, dtype=np.float64)
@@ -157,15 +179,47 @@ def extract(rgb: np.ndarray, W: dict, res_blocks: int) -> np.ndarray:
     return x
 
 
-def offset_head(fa: np.ndarray, fb: np.ndarray, W: dict, groups: int):
-    o = lrelu(conv3x3(np.concatenate([fa, fb]), *_wb(W, "off1")))
-    raw = conv3x3(o, *_wb(W, "off2"))
+def level_suffix(level: int) -> str:
+    """Weight-name suffix of a pyramid level's fusion layers ("" for level 1)."""
+    return "" if level == 1 else f".l{level}"
+
+
+def pyramid(f1: np.ndarray, W: dict, levels: int) -> list:
+    """[F^1, ..., F^L] from the trunk's output F^1."""
+    out = [np.asarray(f1, dtype=np.float64)]
+    for lv in range(2, levels + 1):
+        out.append(lrelu(conv3x3(avgpool2(out[-1]), *_wb(W, f"down{lv}"))))
+    return out
+
+
+def offset_head(fa: np.ndarray, fb: np.ndarray, W: dict, groups: int, level: int = 1):
+    sfx = level_suffix(level)
+    o = lrelu(conv3x3(np.concatenate([fa, fb]), *_wb(W, "off1" + sfx)))
+    raw = conv3x3(o, *_wb(W, "off2" + sfx))
     return raw[:18 * groups], sigmoid(raw[18 * groups:27 * groups])
 
 
-def align(fa, fb, offsets, mask, W: dict, groups: int) -> np.ndarray:
+def align(fa, fb, offsets, mask, W: dict, groups: int, level: int = 1) -> np.ndarray:
     return lrelu(deform_conv3x3(np.concatenate([fa, fb]), offsets, mask,
-                                *_wb(W, "dcn"), groups=groups))
+                                *_wb(W, "dcn" + level_suffix(level)), groups=groups))
+
+
+def align_pyramid(pa: list, pb: list, W: dict, groups: int):
+    """Cascaded alignment over two pyramids, coarsest level first.  Returns (Fmid, per-level
+    list of (offsets, mask, A) from level 1 up)."""
+    levels = len(pa)
+    offs_c = feat_c = None
+    per = []
+    for lv in range(levels, 0, -1):
+        offs, mask = offset_head(pa[lv - 1], pb[lv - 1], W, groups, lv)
+        if offs_c is not None:
+            offs = offs + 2.0 * upsample2_bilinear(offs_c)
+        a = align(pa[lv - 1], pb[lv - 1], offs, mask, W, groups, lv)
+        if feat_c is not None:
+            a = a + upsample2_bilinear(feat_c)
+        per.append((offs, mask, a))
+        offs_c, feat_c = offs, a
+    return feat_c, per[::-1]
 
 
 def reconstruct(feat: np.ndarray, base: np.ndarray, W: dict, scale=(2, 2)) -> np.ndarray:
@@ -174,13 +228,25 @@ def reconstruct(feat: np.ndarray, base: np.ndarray, W: dict, scale=(2, 2)) -> np
 
 
 def fuse(rgb_a, rgb_b, fa, fb, W: dict, groups: int, times=(0.0, 0.5, 1.0), keep=False, scale=(2, 2)):
-    """Fusion stage of one group [a, b]: output RGB for each requested time t."""
+    """Fusion stage of one group [a, b]: output RGB for each requested time t.  fa / fb are
+    the frames' features, or their pyramids (lists, level 1 first)."""
     res = {}
     base0 = upsample_bilinear(rgb_a, *scale)
     base1 = base0 if rgb_b is rgb_a else upsample_bilinear(rgb_b, *scale)
+    if isinstance(fa, list):
+        pa, pb = fa, fb
+        fa, fb = pa[0], pb[0]
+    else:
+        pa = pb = None
     if 0.5 in times or keep:
-        offs, mask = offset_head(fa, fb, W, groups)
-        fmid = align(fa, fb, offs, mask, W, groups)
+        if pa is None:
+            offs, mask = offset_head(fa, fb, W, groups)
+            fmid = align(fa, fb, offs, mask, W, groups)
+        else:
+            fmid, per = align_pyramid(pa, pb, W, groups)
+            offs, mask = per[0][0], per[0][1]
+            if keep:
+                res["levels"] = per
         if keep:
             res["offsets"], res["mask"], res["fmid"] = offs, mask, fmid
     for t in times:

@@ -11,7 +11,9 @@ The task (section 3.2, end-user usage; flags of section 3.1) is given by ``scale
 (rows, columns) and the flags: ``interp`` (Interpolation with Extra frame: groups
 [a, b] as above) and ``double`` (Double frame: the group also emits frame a enhanced;
 without it frame a passes through unchanged, which needs scale (1, 1)).  Without
-``interp`` every frame is enhanced alone: one output per input frame.
+``interp`` every frame is enhanced alone: one output per input frame.  ``levels`` is the
+number of feature-pyramid levels (section 3.1: the extract stage's output; cascaded
+alignment over them, see oracle.network); it needs ``interp``.
 """
 from __future__ import annotations
 
@@ -39,8 +41,13 @@ def frame_rgb(Y, U, V, bits, chroma, align=8, colour=None):
     return pixel.pad(pixel.unpack(Y, U, V, bits, chroma, **(colour or {})), align)
 
 
+def _features(rgb, W, res_blocks, levels):
+    f = network.extract(rgb, W, res_blocks)
+    return f if levels == 1 else network.pyramid(f, W, levels)
+
+
 def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
-                  times=(0.0, 0.5, 1.0), align=8, keep=False, colour=None, scale=(2, 2)):
+                  times=(0.0, 0.5, 1.0), align=8, keep=False, colour=None, scale=(2, 2), levels=1):
     """One frame group.  fb_planes=None means the duplicated group [a, a].
 
     Returns {"codes": {t: (Y, Cb, Cr)}, "hr": {t: cropped float HR RGB}} plus the
@@ -48,12 +55,12 @@ def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
     """
     h, w = fa_planes[0].shape
     rgb_a = frame_rgb(*fa_planes, bits, chroma, align, colour)
-    fa = network.extract(rgb_a, W, res_blocks)
+    fa = _features(rgb_a, W, res_blocks, levels)
     if fb_planes is None:
         rgb_b, fb = rgb_a, fa
     else:
         rgb_b = frame_rgb(*fb_planes, bits, chroma, align, colour)
-        fb = network.extract(rgb_b, W, res_blocks)
+        fb = _features(rgb_b, W, res_blocks, levels)
     res = network.fuse(rgb_a, rgb_b, fa, fb, W, groups, times=times, keep=keep, scale=scale)
     out = {"codes": {}, "hr": {}}
     for t in times:
@@ -62,12 +69,12 @@ def enhance_group(fa_planes, fb_planes, bits, chroma, W, res_blocks, groups,
         out["codes"][t] = pixel.pack(hr, bits, chroma, **(colour or {}))
     if keep:
         out.update(rgb_a=rgb_a, rgb_b=rgb_b, fa=fa, fb=fb, offsets=res["offsets"],
-                   mask=res["mask"], fmid=res["fmid"])
+                   mask=res["mask"], fmid=res["fmid"], levels=res.get("levels"))
     return out
 
 
 def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.SceneParams(),
-                 external=None, align=8, colour=None, scale=(2, 2), interp=True, double=True):
+                 external=None, align=8, colour=None, scale=(2, 2), interp=True, double=True, levels=1):
     """A whole clip in stream order.  frames: list of (Y, U, V).
 
     Returns (cuts, outputs) where outputs is the list of emitted frames (2N with
@@ -80,10 +87,13 @@ def enhance_clip(frames, bits, chroma, W, res_blocks, groups, params=scene.Scene
     pk = lambda x: pixel.pack(x, bits, chroma, **(colour or {}))   # noqa: E731
     rgb_cache, feat_cache = {}, {}
 
+    if levels > 1 and not interp:
+        raise ValueError("a feature pyramid needs an interpolating network")
+
     def feat(i):
         if i not in feat_cache:
             rgb_cache[i] = frame_rgb(*frames[i], bits, chroma, align, colour)
-            feat_cache[i] = network.extract(rgb_cache[i], W, res_blocks)
+            feat_cache[i] = _features(rgb_cache[i], W, res_blocks, levels)
         return rgb_cache[i], feat_cache[i]
 
     outputs = []

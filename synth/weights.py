@@ -9,9 +9,11 @@ its bias.
 Tensor order:
   conv_in  (C, 3)            extract, first layer
   block r  a (C, C), b (C, C)  extract, residual blocks r = 0..R-1
+  down l   (C, C)            extract, pyramid level l = 2..L (after a 2x2 mean pool)
   off1     (C, 2C)           offset head, first conv        (interpolating networks only)
   off2     (27G, C)          offset head, second conv (18G offsets, 9G mask logits)  (")
   dcn      (C, 2C)           modulated deformable alignment  (")
+  off1.l, off2.l, dcn.l      the same three for pyramid level l = 2..L, after level 1's
   up       (sv sh C, C)      conv before the (sv, sh) pixel shuffle (4C for x2 both ways)
   hr       (3, C)            output RGB residual
 
@@ -39,6 +41,7 @@ class NetConfig:
     scale_v: int = 0          # vertical scale factor, 0 = the same as scale
     interp: bool = True       # Interpolation + Extra frame
     double: bool = True       # Double frame
+    levels: int = 1           # feature pyramid levels (1 = the trunk's output only)
 
     def __post_init__(self):
         if (2 * self.channels) % self.offset_groups:
@@ -65,8 +68,12 @@ def weight_layout(cfg: NetConfig):
     for r in range(cfg.res_blocks):
         layers.append((f"block{r}.a", C, C, 1.0))
         layers.append((f"block{r}.b", C, C, 0.1))
+    for lv in range(2, cfg.levels + 1):
+        layers.append((f"down{lv}", C, C, 1.0))
     if cfg.interp:
-        layers += [("off1", C, 2 * C, 1.0), ("off2", 27 * G, C, 1.0), ("dcn", C, 2 * C, 1.0)]
+        for lv in range(1, cfg.levels + 1):
+            sfx = "" if lv == 1 else f".l{lv}"
+            layers += [("off1" + sfx, C, 2 * C, 1.0), ("off2" + sfx, 27 * G, C, 1.0), ("dcn" + sfx, C, 2 * C, 1.0)]
     layers += [("up", cfg.sv * cfg.sh * C, C, 1.0), ("hr", 3, C, 0.1)]
     return layers
 

@@ -289,3 +289,150 @@ def test_upsample_bilinear_per_axis_equals_torch(sv, sh):
     ref = torch.nn.functional.interpolate(torch.from_numpy(x)[None], scale_factor=(sv, sh), mode="bilinear",
                                           align_corners=False)[0].numpy()
     assert np.allclose(network.upsample_bilinear(x, sv, sh), ref, atol=1e-12)
+
+
+# ---- feature pyramid and cascaded alignment ----
+
+def _torch_dcn(x, offs, mask, wd, bd, G):
+    """Modulated DCN from scipy's bilinear sampler (zero outside the map), in float64."""
+    cin, h, w = x.shape
+    cg = cin // G
+    acc = np.repeat(np.asarray(bd, np.float64)[:, None, None], h, 1).repeat(w, 2)
+    ys, xs = np.meshgrid(np.arange(h, dtype=np.float64), np.arange(w, dtype=np.float64), indexing="ij")
+    for c in range(cin):
+        g = c // cg
+        for k in range(9):
+            ky, kx = divmod(k, 3)
+            s = map_coordinates(x[c], [ys + ky - 1 + offs[2 * (9 * g + k)], xs + kx - 1 + offs[2 * (9 * g + k) + 1]],
+                                order=1, mode="grid-constant", cval=0.0)
+            acc += np.asarray(wd[:, c, ky, kx], np.float64)[:, None, None] * (mask[9 * g + k] * s)
+    return acc
+
+
+def test_avgpool2_matches_torch_and_affine_closed_form():
+    x = _rng(30).standard_normal((5, 8, 12))
+    ref = F.avg_pool2d(torch.tensor(x)[None], 2)[0].numpy()
+    assert np.allclose(network.avgpool2(x), ref, rtol=0, atol=1e-14)
+    i, j = np.meshgrid(np.arange(8.0), np.arange(12.0), indexing="ij")
+    a = (3.0 + 0.5 * i - 0.25 * j)[None]
+    ii, jj = np.meshgrid(np.arange(4.0), np.arange(6.0), indexing="ij")
+    # the mean of an affine map over a 2x2 block is its value at the block's centre
+    assert np.allclose(network.avgpool2(a)[0], 3.0 + 0.5 * (2 * ii + 0.5) - 0.25 * (2 * jj + 0.5), atol=1e-14)
+    with pytest.raises(ValueError):
+        network.avgpool2(np.zeros((1, 3, 4)))
+
+
+def test_pyramid_levels_identity_down_conv_is_the_pool():
+    cfg = synth.NetConfig(8, 1, 2, levels=3)
+    W = pipeline.weights_dict(synth.gen_weights(cfg, seed=31), synth.weight_layout(cfg))
+    for lv in (2, 3):
+        w, b = W[f"down{lv}"]
+        w[...] = 0.0
+        b[...] = 0.0
+        for c in range(8):
+            w[c, c, 1, 1] = 1.0                   # centre tap only: the identity
+    f1 = _rng(32).uniform(0, 1, (8, 16, 24))      # non-negative: LReLU is the identity
+    p = network.pyramid(f1, W, 3)
+    assert len(p) == 3 and p[1].shape == (8, 8, 12) and p[2].shape == (8, 4, 6)
+    assert np.allclose(p[1], network.avgpool2(f1), atol=1e-14)
+    assert np.allclose(p[2], network.avgpool2(network.avgpool2(f1)), atol=1e-14)
+    assert len(network.pyramid(f1, W, 1)) == 1 and network.pyramid(f1, W, 1)[0] is not None
+
+
+def test_pyramid_one_level_is_the_plain_fusion():
+    cfg = synth.NetConfig(8, 1, 2)
+    W = pipeline.weights_dict(synth.gen_weights(cfg, seed=33), synth.weight_layout(cfg))
+    rng = _rng(34)
+    rgb_a, rgb_b = rng.uniform(0, 1, (3, 8, 16)), rng.uniform(0, 1, (3, 8, 16))
+    fa, fb = network.extract(rgb_a, W, 1), network.extract(rgb_b, W, 1)
+    plain = network.fuse(rgb_a, rgb_b, fa, fb, W, 2, keep=True)
+    pyr = network.fuse(rgb_a, rgb_b, [fa], [fb], W, 2, keep=True)
+    for k in (0.0, 0.5, 1.0, "offsets", "mask", "fmid"):
+        assert np.array_equal(plain[k], pyr[k])
+
+
+def test_two_level_cascade_matches_torch_composition():
+    """Pyramid and cascade rebuilt from torch ops (avg_pool2d, conv2d, interpolate) and
+    scipy's sampler for the DCN, in float64."""
+    C, G = 8, 2
+    cfg = synth.NetConfig(C, 1, G, levels=2)
+    W = pipeline.weights_dict(synth.gen_weights(cfg, seed=35), synth.weight_layout(cfg))
+    rng = _rng(36)
+    rgb_a, rgb_b = rng.uniform(0, 1, (3, 16, 24)), rng.uniform(0, 1, (3, 16, 24))
+    pa = network.pyramid(network.extract(rgb_a, W, 1), W, 2)
+    pb = network.pyramid(network.extract(rgb_b, W, 1), W, 2)
+    got = network.fuse(rgb_a, rgb_b, pa, pb, W, G, keep=True)
+
+    T = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))  # noqa: E731
+    conv = lambda x, n: F.conv2d(x, T(W[n][0]), T(W[n][1]), padding=1)  # noqa: E731
+    lr = lambda x: F.leaky_relu(x, 0.1)  # noqa: E731
+    up = lambda x: F.interpolate(x, scale_factor=2, mode="bilinear", align_corners=False)  # noqa: E731
+    ta = [T(pa[0])[None]]
+    tb = [T(pb[0])[None]]
+    ta.append(lr(conv(F.avg_pool2d(ta[0], 2), "down2")))
+    tb.append(lr(conv(F.avg_pool2d(tb[0], 2), "down2")))
+    assert np.allclose(ta[1][0].numpy(), pa[1], atol=1e-12)
+
+    def head(a, b, sfx):
+        raw = conv(lr(conv(torch.cat([a, b], 1), "off1" + sfx)), "off2" + sfx)
+        return raw[:, :18 * G], torch.sigmoid(raw[:, 18 * G:27 * G])
+
+    o2, m2 = head(ta[1], tb[1], ".l2")
+    a2 = lr(T(_torch_dcn(torch.cat([ta[1], tb[1]], 1)[0].numpy(), o2[0].numpy(), m2[0].numpy(), *W["dcn.l2"], G))[None])
+    o1, m1 = head(ta[0], tb[0], "")
+    o1 = o1 + 2.0 * up(o2)
+    a1 = lr(T(_torch_dcn(torch.cat([ta[0], tb[0]], 1)[0].numpy(), o1[0].numpy(), m1[0].numpy(), *W["dcn"], G))[None])
+    a1 = a1 + up(a2)
+    assert np.max(np.abs(got["offsets"] - o1[0].numpy())) <= 1e-10
+    assert np.max(np.abs(got["levels"][1][0] - o2[0].numpy())) <= 1e-10
+    assert np.max(np.abs(got["fmid"] - a1[0].numpy())) <= 1e-10
+
+
+def test_cascade_doubles_the_coarse_offsets():
+    """A constant integer offset d at level 2 (zero weights, bias d, unit masks) and no
+    offset of level 1's own give level 1 the offset 2d: its DCN equals the brute-force
+    conv of the maps shifted by 2d; level 1's DCN zeroed leaves Fmid = up2(A^2)."""
+    C, G = 4, 2
+    cfg = synth.NetConfig(C, 0, G, levels=2)
+    W = pipeline.weights_dict(synth.gen_weights(cfg, seed=37), synth.weight_layout(cfg))
+    d = (1.0, -1.0)
+    for sfx, bias in ((".l2", d), ("", (0.0, 0.0))):
+        w, b = W["off2" + sfx]
+        w[...] = 0.0
+        b[:18 * G:2] = bias[0]
+        b[1:18 * G:2] = bias[1]
+        b[18 * G:] = 40.0                          # sigmoid(40) is 1 in float64
+    rng = _rng(38)
+    fa = [rng.standard_normal((C, 8, 12)), None]
+    fb = [rng.standard_normal((C, 8, 12)), None]
+    fa[1] = network.pyramid(fa[0], W, 2)[1]
+    fb[1] = network.pyramid(fb[0], W, 2)[1]
+    _fm, per = network.align_pyramid(fa, fb, W, G)
+    offs1, mask1, a1 = per[0]
+    assert np.all(offs1[0::2] == 2 * d[0]) and np.all(offs1[1::2] == 2 * d[1]) and np.all(mask1 == 1.0)
+    x = np.concatenate([fa[0], fb[0]])
+    wd, bd = W["dcn"]
+    ref = np.zeros((C, 8, 12))
+    for o in range(C):
+        for yy in range(8):
+            for xx in range(12):
+                acc = bd[o]
+                for c in range(2 * C):
+                    for ky in range(3):
+                        for kx in range(3):
+                            sy, sx = yy + ky - 1 + 2, xx + kx - 1 - 2
+                            if 0 <= sy < 8 and 0 <= sx < 12:
+                                acc += wd[o, c, ky, kx] * x[c, sy, sx]
+                ref[o, yy, xx] = acc
+    assert np.allclose(a1, network.lrelu(ref) + network.upsample2_bilinear(per[1][2]), atol=1e-12)
+    wd[...] = 0.0
+    bd[...] = 0.0
+    fm, per = network.align_pyramid(fa, fb, W, G)
+    assert np.allclose(fm, network.upsample2_bilinear(per[1][2]), atol=1e-14)
+
+
+def test_pyramid_weight_layout_names_and_order():
+    cfg = synth.NetConfig(8, 1, 2, levels=3)
+    names = [n for n, *_ in synth.weight_layout(cfg)]
+    assert names == ["conv_in", "block0.a", "block0.b", "down2", "down3", "off1", "off2", "dcn",
+                     "off1.l2", "off2.l2", "dcn.l2", "off1.l3", "off2.l3", "dcn.l3", "up", "hr"]
