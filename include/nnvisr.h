@@ -134,13 +134,20 @@ typedef struct {
  * context (group, clip stream, batch, calibration) refuse frames of another matrix or
  * range with NV_E_UNSUPPORTED, so a caller holding one context per colourspace selects
  * the network by the clip's format.  The pixel-format stages alone (nv_unpack, nv_pack,
- * nv_scene_metric) take any colourspace. */
+ * nv_scene_metric) take any colourspace.  levels > 1 (interpolating networks in FP32,
+ * FP16 or BF16; not in nv_enhance_batch) makes the extract stage output a feature
+ * pyramid (section 3.1): level l >= 2 is conv + LReLU of the 2x2 mean pool of level
+ * l-1, and the alignment runs from the coarsest level down, each level adding twice
+ * the x2 resize of the coarser level's offsets to its own and the x2 resize of the
+ * coarser aligned features to its own; the blob then holds "down" (C x C) for levels
+ * 2..L after the residual blocks, and off1, off2, dcn for levels 2..L after level 1's. */
 typedef struct {
   int32_t channels, res_blocks, offset_groups, scale, align;
   uint32_t flags;
   int32_t precision;     /* nv_precision */
   int32_t matrix, range; /* colourspace of the training data: NV_MATRIX_*, NV_RANGE_* */
   int32_t scale_v;       /* vertical scale factor, 0 = the same as scale */
+  int32_t levels;        /* feature-pyramid levels, 0 or 1 = one, at most 4 */
 } nv_net_config;
 
 /* Scene-change rule: frame t starts a scene when
@@ -233,9 +240,14 @@ nv_status nv_scene_metric(const nv_format* fmt, const nv_planes* prev, const nv_
  * matching the precision) otherwise.  Features are NHWC [hp][wp][C]. */
 int32_t nv_feature_elem_bytes(const nv_context* ctx);
 
-/* Extract stage (section 3.1: per frame, a one-level feature pyramid) from planar
- * float32 R'G'B' d_rgb[3][hp][wp] (hp, wp multiples of 8) into NHWC features
- * d_feat[hp][wp][C] of the context's feature type. */
+/* Bytes of one frame's features at padded size hp x wp: every level of the context's
+ * feature pyramid, level 1 ([hp][wp][C]) first, then level l = 2..levels as
+ * [hp >> (l-1)][wp >> (l-1)][C], back to back.  0 on a NULL context. */
+size_t nv_feature_bytes(const nv_context* ctx, int32_t hp, int32_t wp);
+
+/* Extract stage (section 3.1: per frame, the feature pyramid) from planar float32
+ * R'G'B' d_rgb[3][hp][wp] (hp, wp multiples of 8) into the context's feature type at
+ * d_feat (nv_feature_bytes(ctx, hp, wp) bytes; level 1 is NHWC [hp][wp][C]). */
 nv_status nv_extract(nv_context* ctx, const float* d_rgb, int32_t hp, int32_t wp,
                      void* d_feat, void* stream);
 
@@ -407,7 +419,9 @@ enum {
   NV_K_UNPACK = 0, NV_K_SCENE = 1, NV_K_CONV_IN = 2, NV_K_CONV_BLOCK = 3, NV_K_OFF1 = 4,
   NV_K_OFF2 = 5, NV_K_DCN = 6, NV_K_UP = 7, NV_K_HR = 8, NV_K_PACK = 9,
   NV_K_RESBLOCK = 10,   /* both convs of a residual block in one launch (16-bit maps, C = 64) */
-  NV_K_COUNT = 11
+  NV_K_POOL = 11,       /* 2x2 mean pool starting a feature-pyramid level */
+  NV_K_CASCADE = 12,    /* x2 resize of a coarser pyramid level's offsets or aligned features */
+  NV_K_COUNT = 13
 };
 
 /* on != 0: from now on every launch the context makes (including those of its streams)

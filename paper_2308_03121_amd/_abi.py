@@ -37,7 +37,7 @@ class NvPlanes(ctypes.Structure):
 class NvNetConfig(ctypes.Structure):
     _fields_ = [("channels", c_int32), ("res_blocks", c_int32), ("offset_groups", c_int32),
                 ("scale", c_int32), ("align", c_int32), ("flags", c_uint32), ("precision", c_int32),
-                ("matrix", c_int32), ("range", c_int32), ("scale_v", c_int32)]
+                ("matrix", c_int32), ("range", c_int32), ("scale_v", c_int32), ("levels", c_int32)]
 
 
 class NvSceneParams(ctypes.Structure):
@@ -63,6 +63,7 @@ _SIGS = {
                                   POINTER(NvSceneParams), c_int32, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p]),
     "nv_feature_elem_bytes": (c_int32, [c_void_p]),
+    "nv_feature_bytes": (c_size_t, [c_void_p, c_int32, c_int32]),
     "nv_extract": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "nv_fuse": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                           c_void_p, c_uint32, POINTER(c_void_p), c_void_p, c_void_p, c_void_p]),
@@ -95,7 +96,7 @@ _SIGS = {
     "nv_calibrate": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), c_int32, c_void_p]),
     "nv_fp8_scales": (c_int32, [c_void_p, PF, c_int32, c_int32, c_void_p]),
 }
-NV_K_COUNT = 11
+NV_K_COUNT = 13
 
 _lib = None
 

@@ -122,10 +122,13 @@ class Context:
     def __init__(self, channels: int, res_blocks: int, offset_groups: int, weights: np.ndarray,
                  precision: str = "fp32", device: int = 0, head_fp32: bool = False,
                  fp8_fusion: bool = False, matrix: int = 709, full: bool = False, scale: int = 2,
-                 scale_v: int = 0, interp: bool = True, double: bool = True):
+                 scale_v: int = 0, interp: bool = True, double: bool = True, levels: int = 1):
         lib = _abi.load()
-        # the task: scale factors (columns, rows; 0 = the same) and the network flags
-        flags = (_abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA if interp else 0) | (_abi.NV_FLAG_DOUBLE if double else 0)
+        # the task: scale factors (columns, rows; 0 = the same) and the network flags (Double
+        # frame is a flag of interpolating networks only; a per-frame network has none)
+        flags = 0
+        if interp:
+            flags = _abi.NV_FLAG_INTERP | _abi.NV_FLAG_EXTRA | (_abi.NV_FLAG_DOUBLE if double else 0)
         if head_fp32:
             flags |= _abi.NV_FLAG_HEAD_FP32
         if fp8_fusion:
@@ -134,9 +137,10 @@ class Context:
         # matrix / full: the colourspace the weights were trained for
         self.cfg = NvNetConfig(channels, res_blocks, offset_groups, scale, 8, flags, PRECISIONS[precision],
                                _abi.MATRIX_CODES[matrix], _abi.NV_RANGE_FULL if full else _abi.NV_RANGE_LIMITED,
-                               scale_v)
+                               scale_v, levels)
+        self.levels = levels
         self.scale_h, self.scale_v = scale, scale_v or scale
-        self.interp, self.double = interp, double
+        self.interp, self.double = interp, interp and double
         self.colourspace = (matrix, bool(full))
         w = np.ascontiguousarray(weights, dtype=np.float32)
         self._h = c_void_p()
@@ -169,10 +173,27 @@ class Context:
             pass
 
     def extract(self, rgb: torch.Tensor, stream=None) -> torch.Tensor:
+        """Level 1 of the frame's features, [hp][wp][C]; with a pyramid the tensor's storage
+        holds every level (see pyramid_levels)."""
         _c, hp, wp = rgb.shape
-        feat = torch.empty((hp, wp, self.channels), dtype=self.feat_dtype, device=rgb.device)
-        check(_abi.load().nv_extract(self._h, _ptr(rgb), hp, wp, _ptr(feat), c_void_p(_stream(stream))))
-        return feat
+        lib = _abi.load()
+        n = int(lib.nv_feature_bytes(self._h, hp, wp)) // lib.nv_feature_elem_bytes(self._h)
+        store = torch.empty(n, dtype=self.feat_dtype, device=rgb.device)
+        check(lib.nv_extract(self._h, _ptr(rgb), hp, wp, _ptr(store), c_void_p(_stream(stream))))
+        return store[:hp * wp * self.channels].view(hp, wp, self.channels)
+
+    def pyramid_levels(self, feat: torch.Tensor) -> list:
+        """Views [level 1, level 2, ...] of the features extract() returned (NHWC each)."""
+        hp, wp, C = feat.shape
+        store = feat.untyped_storage()
+        flat = torch.empty(0, dtype=feat.dtype, device=feat.device).set_(store, feat.storage_offset(),
+                                                                        (store.nbytes() // feat.element_size(),))
+        out, off = [], 0
+        for lv in range(1, self.levels + 1):
+            h, w = hp >> (lv - 1), wp >> (lv - 1)
+            out.append(flat[off:off + h * w * C].view(h, w, C))
+            off += h * w * C
+        return out
 
     def fuse(self, rgb_a, rgb_b, feat_a, feat_b, out_mask=7, sel: torch.Tensor | None = None,
              want_offsets=False, want_fmid=False, stream=None):

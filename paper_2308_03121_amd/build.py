@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnnvisr.so")
-SOURCES = ["k_pixel.hip", "k_net.hip", "api.cpp"]
+SOURCES = ["k_pixel.hip", "k_net.hip", "k_dcn.hip", "k_pyr.hip", "api.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -11,6 +11,7 @@
 #include <functional>
 #include <initializer_list>
 #include <mutex>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,6 +56,7 @@ constexpr int kClipMaxPositions = 64;   // frame-store positions of a general-n 
 struct LayerSpec {
   const char* name;
   int cout, cin;
+  int level = 1;   // feature-pyramid level of a "down" conv or a fusion layer
 };
 
 // Task of a network (section 3.2): scale factors and the Interpolation (with Extra
@@ -66,6 +68,9 @@ bool doubling(const nv_net_config& c) { return (c.flags & NV_FLAG_DOUBLE) != 0; 
 bool default_task(const nv_net_config& c) {
   return scale_h(c) == 2 && scale_v(c) == 2 && interpolating(c) && doubling(c);
 }
+// Feature-pyramid levels (section 3.1: the extract stage's output); 0 reads as 1.
+int pyramid_levels(const nv_net_config& c) { return c.levels > 1 ? c.levels : 1; }
+constexpr int kMaxLevels = 4;   // level 4 is 1/8 of a padded frame (a multiple of 8)
 
 std::vector<LayerSpec> layer_specs(const nv_net_config& c) {
   const int C = c.channels, G = c.offset_groups;
@@ -75,10 +80,14 @@ std::vector<LayerSpec> layer_specs(const nv_net_config& c) {
     v.push_back({"block.a", C, C});
     v.push_back({"block.b", C, C});
   }
+  const int L = pyramid_levels(c);
+  for (int l = 2; l <= L; ++l) v.push_back({"down", C, C, l});
   if (interpolating(c)) {
-    v.push_back({"off1", C, 2 * C});
-    v.push_back({"off2", 27 * G, C});
-    v.push_back({"dcn", C, 2 * C});
+    for (int l = 1; l <= L; ++l) {
+      v.push_back({"off1", C, 2 * C, l});
+      v.push_back({"off2", 27 * G, C, l});
+      v.push_back({"dcn", C, 2 * C, l});
+    }
   }
   v.push_back({"up", scale_v(c) * scale_h(c) * C, C});
   v.push_back({"hr", 3, C});
@@ -118,6 +127,12 @@ nv_status check_config(const nv_net_config* c) {
     return fail(NV_E_INVALID, "matrix %d is not an NV_MATRIX_* value", c->matrix);
   if (c->range != NV_RANGE_LIMITED && c->range != NV_RANGE_FULL)
     return fail(NV_E_INVALID, "range %d is not an NV_RANGE_* value", c->range);
+  if (c->levels < 0 || c->levels > kMaxLevels)
+    return fail(NV_E_INVALID, "levels must be in [0, %d] (got %d)", kMaxLevels, c->levels);
+  if (pyramid_levels(*c) > 1 && !interpolating(*c))
+    return fail(NV_E_INVALID, "a feature pyramid needs an interpolating network (it feeds the alignment)");
+  if (pyramid_levels(*c) > 1 && c->precision == NV_FP8_E4M3)
+    return fail(NV_E_UNSUPPORTED, "FP8 precision is implemented for one pyramid level");
   return NV_OK;
 }
 
@@ -270,7 +285,9 @@ struct Workspace {
   void* u = nullptr;      // HR features         [2hp][2wp][C]    feature type
   float* hr = nullptr;    // HR RGB              [3][2hp][2wp]    float
   float* rgb[2] = {nullptr, nullptr};  // group inputs [3][hp][wp]
-  void* feat[2] = {nullptr, nullptr};  // group features [hp][wp][C]
+  void* feat[2] = {nullptr, nullptr};  // group features: every pyramid level, level 1 first
+  float* offs_lv = nullptr;  // pyramid levels 2..L: offsets + mask, level after level
+  void* fmid_lv = nullptr;   // pyramid levels 2..L: aligned features, level after level
   size_t bytes = 0;
 };
 
@@ -332,6 +349,14 @@ struct nv_context {
   PlainConv conv_in;
   std::vector<PackedConv> blocks;   // a, b per residual block
   PackedConv off1, off2, dcn, up, hr;
+  // feature pyramid: levels L, and for level l = 2..L (index l - 2) the conv after the
+  // 2x2 mean pool and the level's offset head and DCN
+  int levels = 1;
+  std::vector<PackedConv> down;
+  struct LevelFusion {
+    PackedConv off1, off2, dcn;
+  };
+  std::vector<LevelFusion> lvf;
   // FP8: quantised layers in calibration order (residual convs, dcn, up), each with
   // its per-row weight scales (device) and the running input max |x| (device, float
   // bits, one per layer); q_ready once scales were calibrated or set.
@@ -346,6 +371,33 @@ struct nv_context {
 };
 
 namespace {
+
+// Feature pyramid geometry: level l (1-based) of an hp x wp map is (hp >> (l-1)) x
+// (wp >> (l-1)) pixels (exact: padded sizes are multiples of 8 and L <= 4).  A frame's
+// features hold the levels one after another, level 1 first, each [h_l][w_l][C]; the
+// per-level offsets and aligned features of levels 2..L likewise, without level 1.
+size_t level_px_before(int hp, int wp, int l) {
+  size_t n = 0;
+  for (int k = 1; k < l; ++k) n += (size_t)(hp >> (k - 1)) * (wp >> (k - 1));
+  return n;
+}
+size_t feat_elems(const nv_context* ctx, int hp, int wp) {
+  return (size_t)ctx->C * level_px_before(hp, wp, ctx->levels + 1);
+}
+size_t feat_bytes(const nv_context* ctx, int hp, int wp) {
+  return feat_elems(ctx, hp, wp) * dtype_bytes(ctx->ft);
+}
+// Level l's map within a frame's feature buffer.
+template <class P>
+P* level_map(P* feat, const nv_context* ctx, int hp, int wp, int l) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(feat) +
+                              (size_t)ctx->C * level_px_before(hp, wp, l) * dtype_bytes(ctx->ft));
+}
+// Pixels of levels 2..L (the extra per-level buffers of the fusion stage).
+size_t upper_levels_px(const nv_context* ctx, int hp, int wp) {
+  return level_px_before(hp, wp, ctx->levels + 1) - (size_t)hp * wp;
+}
 
 // float -> bfloat16 bits, round to nearest even (no NaN inputs occur in weights)
 uint16_t to_bf16_bits(float f) {
@@ -696,6 +748,8 @@ void free_workspace(Workspace& ws) {
   dev_free(ws.o1);
   dev_free(ws.offs);
   free_raw(ws.fmid);
+  dev_free(ws.offs_lv);
+  free_raw(ws.fmid_lv);
   free_raw(ws.u);
   dev_free(ws.hr);
   for (int i = 0; i < 2; ++i) {
@@ -729,8 +783,11 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   if (e == hipSuccess) e = dev_alloc(&n.hr, 3 * r2 * px);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
     e = dev_alloc(&n.rgb[i], 3 * px);
-    if (e == hipSuccess) e = dev_malloc(&n.feat[i], px * C * fb);
+    if (e == hipSuccess) e = dev_malloc(&n.feat[i], feat_bytes(ctx, nh, nw));
   }
+  const size_t up = upper_levels_px(ctx, nh, nw);
+  if (e == hipSuccess && up) e = dev_alloc(&n.offs_lv, up * ctx->ldo);
+  if (e == hipSuccess && up) e = dev_malloc(&n.fmid_lv, up * C * fb);
   if (e != hipSuccess) {
     free_workspace(n);
     return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "workspace of %dx%d: %s", nw, nh,
@@ -738,7 +795,8 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   }
   n.hp = nh;
   n.wp = nw;
-  n.bytes = px * (C * fb * (4 + r2) + 4 * C + 4 * (size_t)ctx->ldo + 12 * r2 + 24);
+  n.bytes = px * (C * fb * (2 + r2) + 4 * C + 4 * (size_t)ctx->ldo + 12 * r2 + 24) +
+            2 * feat_bytes(ctx, nh, nw) + up * (4 * (size_t)ctx->ldo + C * fb);
   ws = n;
   return NV_OK;
 }
@@ -835,6 +893,23 @@ static bool resblocks_fused(const nv_context* ctx) {
 }
 
 // The extract stage of one frame in workspace ws (at least hp x wp).
+// Levels 2..L of a frame's feature pyramid from its level 1 (section 3.1, the extract
+// stage's output): per level the 2x2 mean pool of the level above (into the workspace
+// map t0) and the level's conv + LReLU.
+nv_status pyramid_impl(nv_context* ctx, Workspace& ws, void* feat, int hp, int wp, hipStream_t s) {
+  const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
+  for (int l = 2; l <= ctx->levels; ++l) {
+    const int h = hp >> (l - 1), w = wp >> (l - 1);
+    const void* above = level_map(static_cast<const void*>(feat), ctx, hp, wp, l - 1);
+    void* dst = level_map(feat, ctx, hp, wp, l);
+    NV_TRY(timed(ctx, NV_K_POOL, s, "pool", [&] { return launch_pool2(ft, above, ws.t0, h, w, C, s); }));
+    const ConvImg im = conv_img(ws.t0, nullptr, nullptr, nullptr, nullptr, nullptr, dst, h, w);
+    NV_TRY(timed(ctx, NV_K_CONV_BLOCK, s, "down",
+                 [&] { return launch_conv(ctx->down[l - 2], CONV_BULK, EPI_LRELU, ft, pb, im, C, 0, s); }));
+  }
+  return NV_OK;
+}
+
 nv_status extract_impl(nv_context* ctx, Workspace& ws, const float* rgb, int hp, int wp, void* feat, hipStream_t s) {
   const int C = ctx->C, ft = ctx->ft, pb = ctx->tune.pb_block;
   NV_TRY(timed(ctx, NV_K_CONV_IN, s, "conv_in",
@@ -851,7 +926,7 @@ nv_status extract_impl(nv_context* ctx, Workspace& ws, const float* rgb, int hp,
       std::swap(a, b);
     }
     if (a != feat) HIP_TRY(hipMemcpyAsync(feat, a, n * dtype_bytes(ft), hipMemcpyDeviceToDevice, s));
-    return NV_OK;
+    return pyramid_impl(ctx, ws, feat, hp, wp, s);
   }
   const ConvImg ia = conv_img(feat, nullptr, nullptr, nullptr, nullptr, nullptr, ws.t0, hp, wp);
   const ConvImg ib = conv_img(ws.t0, nullptr, nullptr, nullptr, nullptr, feat, feat, hp, wp);
@@ -865,7 +940,7 @@ nv_status extract_impl(nv_context* ctx, Workspace& ws, const float* rgb, int hp,
       return launch_conv(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, ib, C, 0, s);
     }));
   }
-  return NV_OK;
+  return pyramid_impl(ctx, ws, feat, hp, wp, s);
 }
 
 // The fusion stage of group [a, b] in workspace ws (at least hp x wp).  After HR
@@ -878,26 +953,50 @@ nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const fl
   float* offs = offs_out ? offs_out : ws.offs;
   void* fmid = fmid_out ? fmid_out : ws.fmid;
   if (mask & 2u) {
-    const ConvImg i1 = conv_img(fa, fb, sel, nullptr, fa, nullptr, ws.o1, hp, wp);
-    NV_TRY(timed(ctx, NV_K_OFF1, s, "off1",
-                 [&] { return launch_conv(ctx->off1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, i1, C, 0, s); }));
-    const ConvImg i2 = conv_img(ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs, hp, wp);
-    NV_TRY(timed(ctx, NV_K_OFF2, s, "off2", [&] {
-      return launch_conv(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, i2, ctx->ldo, 18 * G, s);
-    }));
-    DcnImg di;
-    di.fa = fa;
-    di.fb = fb;
-    di.sel = sel;
-    di.offs = offs;
-    di.dst = fmid;
-    di.H = hp;
-    di.W = wp;
-    di.item_begin = 0;
-    if (ctx->calibrating && ctx->ut == DT_F8)
-      NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks, {fa, fb}, (size_t)hp * wp * C, s));
-    NV_TRY(timed(ctx, NV_K_DCN, s, "dcn",
-                 [&] { return launch_dcn(ctx->dcn, ft, ctx->tune.pb_dcn, di, ctx->ldo, G, s); }));
+    // alignment, coarsest pyramid level first: level l's offsets add twice the x2
+    // resize of level l+1's, and its aligned features the x2 resize of level l+1's
+    const int L = ctx->levels;
+    const size_t px = (size_t)hp * wp, fbytes = dtype_bytes(ft);
+    auto offs_at = [&](int l) { return l == 1 ? offs : ws.offs_lv + (level_px_before(hp, wp, l) - px) * ctx->ldo; };
+    auto fmid_at = [&](int l) -> void* {
+      return l == 1 ? fmid : static_cast<char*>(ws.fmid_lv) + (level_px_before(hp, wp, l) - px) * C * fbytes;
+    };
+    for (int l = L; l >= 1; --l) {
+      const int h = hp >> (l - 1), w = wp >> (l - 1);
+      const void* fa_l = level_map(fa, ctx, hp, wp, l);
+      const void* fb_l = level_map(fb, ctx, hp, wp, l);
+      const PackedConv& O1 = l == 1 ? ctx->off1 : ctx->lvf[l - 2].off1;
+      const PackedConv& O2 = l == 1 ? ctx->off2 : ctx->lvf[l - 2].off2;
+      const PackedConv& DC = l == 1 ? ctx->dcn : ctx->lvf[l - 2].dcn;
+      float* offs_l = offs_at(l);
+      void* fmid_l = fmid_at(l);
+      const ConvImg i1 = conv_img(fa_l, fb_l, sel, nullptr, fa_l, nullptr, ws.o1, h, w);
+      NV_TRY(timed(ctx, NV_K_OFF1, s, "off1",
+                   [&] { return launch_conv(O1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, i1, C, 0, s); }));
+      const ConvImg i2 = conv_img(ws.o1, nullptr, nullptr, nullptr, nullptr, nullptr, offs_l, h, w);
+      NV_TRY(timed(ctx, NV_K_OFF2, s, "off2", [&] {
+        return launch_conv(O2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, i2, ctx->ldo, 18 * G, s);
+      }));
+      if (l < L)
+        NV_TRY(timed(ctx, NV_K_CASCADE, s, "cascade offsets", [&] {
+          return launch_up2_add(DT_F32, offs_l, ctx->ldo, offs_at(l + 1), ctx->ldo, h, w, 18 * G, 2.0f, s);
+        }));
+      DcnImg di;
+      di.fa = fa_l;
+      di.fb = fb_l;
+      di.sel = sel;
+      di.offs = offs_l;
+      di.dst = fmid_l;
+      di.H = h;
+      di.W = w;
+      di.item_begin = 0;
+      if (ctx->calibrating && ctx->ut == DT_F8)
+        NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks, {fa, fb}, (size_t)hp * wp * C, s));
+      NV_TRY(timed(ctx, NV_K_DCN, s, "dcn", [&] { return launch_dcn(DC, ft, ctx->tune.pb_dcn, di, ctx->ldo, G, s); }));
+      if (l < L)
+        NV_TRY(timed(ctx, NV_K_CASCADE, s, "cascade features",
+                     [&] { return launch_up2_add(ft, fmid_l, C, fmid_at(l + 1), C, h, w, C, 1.0f, s); }));
+    }
   }
   for (int t = 0; t < 3; ++t) {
     if (!(mask & (1u << t))) continue;
@@ -996,6 +1095,8 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   std::vector<std::vector<float>> wscales;      // FP8 row scales in calibration order
   std::vector<float> dcn_ws, up_ws;
   const auto specs = layer_specs(*cfg);
+  ctx->levels = pyramid_levels(*cfg);
+  ctx->lvf.resize(ctx->levels - 1);
   const float* p = weights;
   nv_status st = NV_OK;
   for (size_t i = 0; i < specs.size() && st == NV_OK; ++i) {
@@ -1012,7 +1113,9 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
     } else if (nm == "hr") {
       st = pack_hr(ctx, w, b, L.cin, ctx->ft, &ctx->hr);
     } else if (nm == "dcn") {
-      st = pack_dcn(ctx, w, b, L.cout, ctx->G, ctx->ut, &ctx->dcn, &dcn_ws);
+      std::vector<float> unused;   // row scales are kept for the FP8 (one-level) network only
+      st = L.level == 1 ? pack_dcn(ctx, w, b, L.cout, ctx->G, ctx->ut, &ctx->dcn, &dcn_ws)
+                        : pack_dcn(ctx, w, b, L.cout, ctx->G, ctx->ut, &ctx->lvf[L.level - 2].dcn, &unused);
     } else {
       // the offset head stays float-class in every precision: float MFMA in FP32 mode
       // (or on request), two-part float16 weights on float16 MFMA otherwise
@@ -1035,8 +1138,9 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
         pc.sh = ctx->sh;
       }
       if (nm == "block.a" || nm == "block.b") ctx->blocks.push_back(pc);
-      else if (nm == "off1") ctx->off1 = pc;
-      else if (nm == "off2") ctx->off2 = pc;
+      else if (nm == "down") ctx->down.push_back(pc);
+      else if (nm == "off1") (L.level == 1 ? ctx->off1 : ctx->lvf[L.level - 2].off1) = pc;
+      else if (nm == "off2") (L.level == 1 ? ctx->off2 : ctx->lvf[L.level - 2].off2) = pc;
       else if (nm == "up") ctx->up = pc;
     }
   }
@@ -1073,6 +1177,11 @@ extern "C" nv_status nv_context_destroy(nv_context* ctx) {
 extern "C" int32_t nv_feature_elem_bytes(const nv_context* ctx) {
   if (!ctx) return 0;
   return ctx->cfg.precision == NV_FP32 ? 4 : 2;
+}
+
+extern "C" size_t nv_feature_bytes(const nv_context* ctx, int32_t hp, int32_t wp) {
+  if (!ctx || hp <= 0 || wp <= 0) return 0;
+  return feat_bytes(ctx, hp, wp);
 }
 
 // ---------------------------------------------------------- pixel stages ----
@@ -1258,7 +1367,12 @@ size_t static_layout(const nv_context* ctx, int hp, int wp, char* base, Workspac
   w.hr = reinterpret_cast<float*>(take(12 * r2 * px));
   for (int i = 0; i < 2; ++i) {
     w.rgb[i] = reinterpret_cast<float*>(take(12 * px));
-    w.feat[i] = take(px * C * fb);
+    w.feat[i] = take(feat_bytes(ctx, hp, wp));
+  }
+  const size_t up = upper_levels_px(ctx, hp, wp);
+  if (up) {
+    w.offs_lv = reinterpret_cast<float*>(take(up * ctx->ldo * 4));
+    w.fmid_lv = take(up * C * fb);
   }
   w.hp = hp;
   w.wp = wp;
@@ -1422,7 +1536,7 @@ static nv_planes raw_view(const nv_format* f, void* base) {
 }
 
 static size_t slot_bytes(const nv_context* ctx, int hp, int wp) {
-  return (size_t)hp * wp * (12 + (size_t)ctx->C * dtype_bytes(ctx->ft));
+  return (size_t)hp * wp * 12 + feat_bytes(ctx, hp, wp);
 }
 
 static size_t stream_bytes(const nv_context* ctx, const nv_format* f) {
@@ -1449,7 +1563,7 @@ static void stream_free(nv_stream* s) {
 static nv_status stream_ring(nv_stream* s, int r) {
   const int old = (int)s->rgb.size();
   if (old >= r) return NV_OK;
-  const size_t px = (size_t)s->hp * s->wp, fbytes = px * s->ctx->C * dtype_bytes(s->ctx->ft);
+  const size_t px = (size_t)s->hp * s->wp, fbytes = feat_bytes(s->ctx, s->hp, s->wp);
   std::vector<float*> rgb(r, nullptr);
   std::vector<void*> feat(r, nullptr);
   hipError_t e = hipSuccess;
@@ -1839,8 +1953,8 @@ extern "C" nv_status nv_clip_push(nv_clip* c, const nv_planes* frame, int32_t ex
       const int base = c->b - 1;
       const size_t px = (size_t)s->hp * s->wp;
       HIP_TRY(hipMemcpyAsync(s->rgb[base], s->rgb[p], 12 * px, hipMemcpyDeviceToDevice, hs));
-      HIP_TRY(hipMemcpyAsync(s->feat[base], s->feat[p], px * s->ctx->C * dtype_bytes(s->ctx->ft),
-                             hipMemcpyDeviceToDevice, hs));
+      HIP_TRY(hipMemcpyAsync(s->feat[base], s->feat[p], feat_bytes(s->ctx, s->hp, s->wp), hipMemcpyDeviceToDevice,
+                             hs));
       std::fill(c->at.begin(), c->at.end(), -1);
       c->at[base] = t;
       c->f0 = t;
@@ -2048,6 +2162,8 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
   NV_TRY(check_ready(ctx));
   if (!default_task(ctx->cfg))
     return fail(NV_E_UNSUPPORTED, "batches run the x2 space-time task; other tasks use clip streams");
+  if (ctx->levels > 1)
+    return fail(NV_E_UNSUPPORTED, "batches run one-level networks; feature pyramids use clip streams");
   hipStream_t hs = (hipStream_t)stream;
   // ---- validation (nothing is enqueued or changed before it passes) ----
   int nframes = 0, ngroups = 0;
@@ -2112,7 +2228,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
   // ---- job tables ----
   if (B->any) HIP_TRY(hipEventSynchronize(B->uploaded));   // staging copy free again
   BatchTables& T = *B->host;
-  const int pbb = ctx->tune.pb_block, pbu = ctx->tune.pb_up, pbd = ctx->tune.pb_dcn;
+  const int pbb = ctx->tune.pb_block, pbu = ctx->tune.pb_up, pbd = ctx->tune.pb_dcn & (kDcnWindow - 1);
   int it[BL_COUNT] = {0};
   char* fp = B->frame_pool.base;
   for (size_t k = 0; k < frames.size(); ++k) {
@@ -2294,6 +2410,12 @@ std::string tile_name(int code) {
   return b;
 }
 
+std::string dcn_tile_name(int code) {
+  char b[32];
+  snprintf(b, sizeof b, "pb%d%s", code & (kDcnWindow - 1), (code & kDcnWindow) ? "win" : "");
+  return b;
+}
+
 template <class F>
 nv_status time_launch(hipStream_t s, int reps, float* ms, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
@@ -2400,7 +2522,11 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
       int* slot;
       std::vector<int> pbs;
     } cands[5] = {{"block", &ctx->tune.pb_block, block_tiles}, {"up", &ctx->tune.pb_up, up_tiles},
-                  {"dcn", &ctx->tune.pb_dcn, ctx->ut == DT_F8 ? std::vector<int>{1} : std::vector<int>{1, 2}},
+                  {"dcn", &ctx->tune.pb_dcn,
+                   ctx->ut == DT_F8 ? std::vector<int>{1}
+                   : dcn_window_supported(ft, ctx->dcn.tc, C, ctx->G)
+                       ? std::vector<int>{1, 2, 1 | kDcnWindow, 2 | kDcnWindow}
+                       : std::vector<int>{1, 2}},
                   {"off1", &ctx->tune.off1, head_tiles(ctx->off1)}, {"off2", &ctx->tune.off2, head_tiles(ctx->off2)}};
     for (auto& cd : cands) {
       // networks that do not interpolate have no offset head and no alignment
@@ -2443,7 +2569,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
           st = time_launch(s, 3, &ms, [&] { return launch_dcn(ctx->dcn, ft, pb, di, ctx->ldo, ctx->G, s); });
         }
         if (st != NV_OK) return st;
-        snprintf(buf, sizeof buf, " %s=%.1fus", tile_name(pb).c_str(), 1000.0f * ms);
+        snprintf(buf, sizeof buf, " %s=%.1fus",
+                 (cd.slot == &ctx->tune.pb_dcn ? dcn_tile_name(pb) : tile_name(pb)).c_str(), 1000.0f * ms);
         rep += buf;
         if (ms < best) {
           best = ms;
@@ -2484,9 +2611,9 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     rep += key;
   }
   char tail[160];
-  snprintf(tail, sizeof tail, " [block %s%s, up %s, dcn pb%d, off1 %s, off2 %s; LDS limit %d]",
+  snprintf(tail, sizeof tail, " [block %s%s, up %s, dcn %s, off1 %s, off2 %s; LDS limit %d]",
            tile_name(ctx->tune.pb_block).c_str(), resblocks_fused(ctx) ? " (fused blocks)" : "",
-           tile_name(ctx->tune.pb_up).c_str(), ctx->tune.pb_dcn, tile_name(ctx->tune.off1).c_str(),
+           tile_name(ctx->tune.pb_up).c_str(), dcn_tile_name(ctx->tune.pb_dcn).c_str(), tile_name(ctx->tune.off1).c_str(),
            tile_name(ctx->tune.off2).c_str(), lds_limit());
   rep += tail;
   if (ctx->batch && ctx->batch->exec) {   // the recorded graph holds the old tile shapes
@@ -2500,8 +2627,9 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
 
 // ----------------------------------------------------------- kernel timing ----
 
-static const char* const kKindNames[NV_K_COUNT] = {"unpack", "scene", "conv_in", "conv_block", "off1", "off2",
-                                                   "dcn",    "up",    "hr",      "pack",       "resblock"};
+static const char* const kKindNames[NV_K_COUNT] = {"unpack", "scene", "conv_in", "conv_block", "off1",
+                                                   "off2",   "dcn",   "up",      "hr",         "pack",
+                                                   "resblock", "pool", "cascade"};
 
 extern "C" const char* nv_profile_kind_name(int32_t kind) {
   return kind >= 0 && kind < NV_K_COUNT ? kKindNames[kind] : "";

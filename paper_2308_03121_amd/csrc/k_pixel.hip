@@ -163,18 +163,6 @@ __device__ __forceinline__ void code_store(void* base, int64_t pitch, int y, int
   }
 }
 
-// Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
-template <class J>
-__device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].item_begin <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // ---- unpack: four consecutive padded pixels of one row of each plane per thread ----
 // (Y'CbCr -> R'G'B': Y' = (Y - yo) / ys, C' = (C - co) / cs with the range's scale and
 //  offset, R = Y' + 2(1-Kr) Cr', B = Y' + 2(1-Kb) Cb', G = Y' - 2Kb(1-Kb)/Kg Cb' - 2Kr(1-Kr)/Kg Cr')

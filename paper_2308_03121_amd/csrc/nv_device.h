@@ -8,8 +8,12 @@ namespace nv {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr float kLreluSlope = 0.1f;
+
+// Width in pixels of the network kernels' output tiles (one MFMA column block).
+constexpr int kTW = 16;
 
 // BT.709 luma weights; every derived coefficient is formed in double and rounded once.
 constexpr double kKr = 0.2126;
@@ -39,6 +43,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   if ((nblk & 7) != 0) return bid;
   const int per = nblk >> 3;
   return (bid & 7) * per + (bid >> 3);
+}
+
+// Smallest j with jobs[j+1].item_begin > item (jobs sorted by item_begin, njobs >= 1).
+template <class J>
+__device__ __forceinline__ int find_job(const J* jobs, int njobs, int item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 }  // namespace nv

@@ -228,8 +228,24 @@ hipError_t launch_conv(const PackedConv& L, int role, int epi, int tin, int pb, 
                        int ldy, int sig_lo, hipStream_t s);
 hipError_t launch_dcn(const PackedConv& L, int tf, int pb, const DcnImg& im, int ldo, int groups,
                       hipStream_t s);
+// DCN tile code: rows per wave (1, 2), plus kDcnWindow for the form that reads a phase's
+// sampling corners from an LDS copy of their window (float and 16-bit maps with at least
+// 8 channels per offset group for 16-bit; bit-identical to the plain form).
+constexpr int kDcnWindow = 16;
+inline bool dcn_window_supported(int tf, int tc, int C, int groups) {
+  const int cpg = 2 * C / groups;
+  return tc == tf && tf != DT_F8 && (tf == DT_F32 ? cpg >= 4 : cpg >= 8);
+}
 // HR conv C->3 plus the bilinear x2 base of frame a (tsel 0), b (1) or their mean (2).
 hipError_t launch_hr(const PackedConv& L, int tu, const HrImg& im, hipStream_t s);
+
+// ---- feature pyramid (k_pyr.hip), NHWC maps of type t (float or 16-bit) ----
+// dst (H2 x W2 x C) = the 2x2 block means of src (2 H2 x 2 W2 x C).
+hipError_t launch_pool2(int t, const void* src, void* dst, int H2, int W2, int C, hipStream_t s);
+// dst[y][x][c] += scale * (x2 bilinear resize of src)[y][x][c] for c < nch; dst H x W
+// with channel stride ldd, src H/2 x W/2 with channel stride lds (H, W even).
+hipError_t launch_up2_add(int t, void* dst, int ldd, const void* src, int lds, int H, int W, int nch, float scale,
+                          hipStream_t s);
 
 // FP8 calibration: folds max |x| over n elements of x (float16 or float) into
 // *amax_bits (float bits, atomic max), and derives a layer's scales from it.

@@ -70,6 +70,11 @@ static int run_net(int argc, char** argv) {
   const std::vector<char> wb = read_file(dir + "/weights.f32");
   nv_context* ctx = nullptr;
   CHECK(nv_context_create(0, &cfg, reinterpret_cast<const float*>(wb.data()), wb.size() / 4, &ctx));
+  if (getenv("NNVISR_TUNE_CACHE")) {   // tiles forced through the tuner's cache file
+    char rep[512];
+    CHECK(nv_autotune(ctx, H, W, nullptr, rep, sizeof rep));
+    fprintf(stderr, "%s\n", rep);
+  }
   const std::vector<char> ra = read_file(dir + "/rgb_a.f32"), rb = read_file(dir + "/rgb_b.f32");
   const size_t px = (size_t)H * W, fe = (size_t)nv_feature_elem_bytes(ctx), C = cfg.channels;
   const int ldo = 16 * ((27 * cfg.offset_groups + 15) / 16);
@@ -344,6 +349,7 @@ static int run_task(int argc, char** argv) {
   cfg.align = 8;
   cfg.flags = (uint32_t)atoi(argv[8]);
   const int W = atoi(argv[9]), H = atoi(argv[10]), T = atoi(argv[11]);
+  cfg.levels = argc > 12 ? atoi(argv[12]) : 0;
   const std::vector<char> wb = read_file(dir + "/weights.f32");
   nv_context* ctx = nullptr;
   CHECK(nv_context_create(0, &cfg, reinterpret_cast<const float*>(wb.data()), wb.size() / 4, &ctx));

@@ -362,6 +362,23 @@ hipError_t launch_hr(const PackedConv& P, int tu, const HrImg& im, hipStream_t) 
   return hipSuccess;
 }
 
+hipError_t launch_pool2(int t, const void* src, void* dst, int H2, int W2, int C, hipStream_t) {
+  ++fake::g_launches;
+  const size_t n = px(H2, W2) * C * dtype_bytes(t);
+  need(src, 4 * n, "pool src");
+  need(dst, n, "pool dst");
+  return hipSuccess;
+}
+
+hipError_t launch_up2_add(int t, void* dst, int ldd, const void* src, int lds, int H, int W, int nch, float,
+                          hipStream_t) {
+  ++fake::g_launches;
+  if (nch > ldd || nch > lds) return hipErrorInvalidValue;
+  need(dst, px(H, W) * ldd * dtype_bytes(t), "cascade dst");
+  need(src, px(H / 2, W / 2) * lds * dtype_bytes(t), "cascade src");
+  return hipSuccess;
+}
+
 hipError_t launch_amax(int dt, const void* x, size_t n, uint32_t* amax, hipStream_t) {
   ++fake::g_launches;
   need(x, n * dtype_bytes(dt), "amax input");

@@ -1,6 +1,6 @@
 """The library's kernels and host runtime executed on the CPU (tests/cpusim/).
 
-api.cpp, k_net.hip and k_pixel.hip are compiled as host C++ under AddressSanitizer
+api.cpp, k_net.hip, k_dcn.hip, k_pyr.hip and k_pixel.hip are compiled as host C++ under AddressSanitizer
 against a simulated HIP device: every work-item runs as a
 fiber, __syncthreads() and the wave-wide operations (MFMA in each form the kernels use,
 lane shuffles, readfirstlane) are rendezvous points, __shared__ arrays are statics, and
@@ -42,7 +42,8 @@ def driver(tmp_path_factory):
     asan = ["-O1", "-fsanitize=address", "-fno-omit-frame-pointer"]
     # the library's sources are instrumented; the simulator itself (scheduler, MFMA
     # emulation) is optimised and uninstrumented
-    units = [(os.path.join(CSRC, "k_net.hip"), True, asan), (os.path.join(CSRC, "k_pixel.hip"), True, asan),
+    units = [(os.path.join(CSRC, "k_net.hip"), True, asan), (os.path.join(CSRC, "k_dcn.hip"), True, asan),
+             (os.path.join(CSRC, "k_pyr.hip"), True, asan), (os.path.join(CSRC, "k_pixel.hip"), True, asan),
              (os.path.join(CSRC, "api.cpp"), False, asan), (os.path.join(SIM, "sim.cpp"), False, ["-O2"]),
              (os.path.join(SIM, "driver.cpp"), False, asan)]
     procs, objs = [], []
@@ -107,6 +108,49 @@ def test_network_case_in_simulation(driver, tmp_path, C, R, G, H, W):
     for t, key in enumerate((0.0, 0.5, 1.0)):
         hr = np.fromfile(tmp_path / f"hr{t}.bin", dtype=np.float32).reshape(3, 2 * H, 2 * W)
         assert np.abs(hr - full[key]).max() <= FLOAT_TOL, t
+
+
+@pytest.mark.parametrize("prec,off_gain", [(1, 1.0), (1, 12.0), (0, 1.0), (2, 12.0)],
+                         ids=["fp16-window", "fp16-wide-offsets", "fp32-window", "bf16-wide-offsets"])
+def test_dcn_window_form_bit_identical_in_simulation(driver, tmp_path, prec, off_gain):
+    """The DCN form that reads a phase's sampling corners from an LDS copy of their
+    window (tile code 2 | 16, forced through the tuner's cache file) gives the same bits
+    as the plain form: with the generator's offsets (every phase fits its window) and
+    with the offset conv's weights scaled up (wide offsets: phases fall back to reading
+    the map), at a padded size with a ragged right tile."""
+    C, R, G, H, W = 64, 1, 8, 40, 56
+    cfg = synth.NetConfig(C, R, G)
+    blob = synth.gen_weights(cfg, seed=3)
+    w_off2, _b = synth.unpack_weights(cfg, blob)["off2"]
+    w_off2 *= off_gain
+    rng = np.random.default_rng(5)
+    ra = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    rb = np.clip(ra + rng.normal(0, 0.05, ra.shape), 0, 1).astype(np.float32)
+    outs = {}
+    for code in (2, 2 | 16):
+        d = tmp_path / f"t{code}"
+        d.mkdir()
+        blob.astype(np.float32).tofile(d / "weights.f32")
+        ra.tofile(d / "rgb_a.f32")
+        rb.tofile(d / "rgb_b.f32")
+        cache = d / "tune.txt"
+        cache.write_text(f"prec={prec} C={C} R={R} size={W}x{H} | 2 2 {code} 2 2 0\n")
+        env_cache = os.environ.get("NNVISR_TUNE_CACHE")
+        os.environ["NNVISR_TUNE_CACHE"] = str(cache)
+        try:
+            out = _run(driver, ["net", d, C, R, G, prec, H, W], timeout=900)
+        finally:
+            if env_cache is None:
+                del os.environ["NNVISR_TUNE_CACHE"]
+            else:
+                os.environ["NNVISR_TUNE_CACHE"] = env_cache
+        assert "from cache" in out, out[-2000:]
+        outs[code] = {k: (d / k).read_bytes() for k in ("offs.bin", "fmid.bin", "hr0.bin", "hr1.bin", "hr2.bin")}
+    ldo = 16 * ((27 * G + 15) // 16)
+    offs = np.frombuffer(outs[2]["offs.bin"], np.float32).reshape(H, W, ldo)[:, :, :18 * G]
+    print("max |offset|", float(np.abs(offs).max()))
+    for k in outs[2]:
+        assert outs[2][k] == outs[2 | 16][k], k
 
 
 def test_static_group_entry_in_simulation(driver):
@@ -198,3 +242,28 @@ def test_task_modes_in_simulation(driver, tmp_path, scale, scale_v, flags):
                for name, p in zip("yuv", r["codes"])]
         d = max(int(np.abs(g.astype(np.int64) - p.astype(np.int64)).max()) for g, p in zip(got, r["codes"]))
         assert d == 0 if r["hr"] is None else d <= 1, (k, d)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_feature_pyramid_stream_in_simulation(driver, tmp_path, levels):
+    """A clip stream of a network with a feature pyramid (space-time task) against the
+    oracle's cascaded alignment: every output frame within one code."""
+    from oracle import pipeline
+    cfg = synth.NetConfig(32, 1, 8, levels=levels)
+    blob = synth.gen_weights(cfg, seed=6)
+    blob.astype(np.float32).tofile(tmp_path / "weights.f32")
+    T, W, H = 3, 48, 32
+    clip = synth.gen_clip(W, H, T, seed=10, scene_starts=[])
+    frames = [clip.frame(t) for t in range(T)]
+    for t, fr in enumerate(frames):
+        for name, a in zip("yuv", fr):
+            np.ascontiguousarray(a).tofile(tmp_path / f"f{t}_{name}.bin")
+    out = _run(driver, ["task", tmp_path, 32, 1, 8, 2, 0, 7, W, H, T, levels], timeout=1200)
+    n = int(out.split("outputs")[1].split()[0])
+    _c, ref = pipeline.enhance_clip(frames, 8, 420, oracle_weights(cfg, blob), 1, 8, levels=levels)
+    assert n == len(ref) == 2 * T
+    for k, r in enumerate(ref):
+        got = [np.fromfile(tmp_path / f"o{k}_{name}.bin", dtype=np.uint8).reshape(p.shape)
+               for name, p in zip("yuv", r["codes"])]
+        d = max(int(np.abs(g.astype(np.int64) - p.astype(np.int64)).max()) for g, p in zip(got, r["codes"]))
+        assert d <= 1, (k, d)

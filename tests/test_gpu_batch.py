@@ -300,3 +300,37 @@ def test_fp32_two_wave_tiles_bit_identical(B, tmp_path, monkeypatch):
     _same(_per_stream(B, ctx, clips, dev), ref)
     _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,off_gain", [("fp16", 1.0), ("fp16", 12.0), ("bf16", 1.0), ("fp32", 1.0),
+                                           ("fp32", 12.0)])
+def test_dcn_window_tiles_bit_identical(B, prec, off_gain, tmp_path, monkeypatch):
+    """The DCN form that reads a phase's sampling corners from an LDS copy of their
+    window (forced through the tuner's cache file) gives the same bits as the plain
+    form, per stream and batched.  With the offset conv's weights scaled up, most phases
+    do not fit their window and read the maps directly."""
+    say(f"DCN window tiles {prec} offsets x{off_gain}")
+    cfg = synth.NetConfig(64, 1, 8)
+    blob = synth.gen_weights(cfg, seed=9)
+    synth.unpack_weights(cfg, blob)["off2"][0][...] *= off_gain
+    clips = _clips()
+    dev = [[B.to_device_frame(*c.frame(t)) for t in range(N_FRAMES)] for c in clips]
+    code = {"fp32": 0, "fp16": 1, "bf16": 2}[prec]
+
+    def forced(dcn):
+        cache = tmp_path / f"tune{dcn}.txt"
+        cache.write_text(f"prec={code} C=64 R=1 size=64x48 | 2 2 {dcn} 2 2 0\n")
+        ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
+        monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
+        rep = ctx.autotune(48, 64)
+        monkeypatch.delenv("NNVISR_TUNE_CACHE")
+        assert "from cache" in rep, rep
+        return ctx
+
+    ref_ctx = forced(2)
+    ref = _per_stream(B, ref_ctx, clips, dev)
+    ref_ctx.close()
+    ctx = forced(2 | 16)
+    _same(_per_stream(B, ctx, clips, dev), ref)
+    _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
+    ctx.close()
