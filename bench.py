@@ -104,6 +104,28 @@ def pixel_rates(prof, steps, w, h, bits, chroma):
     return out
 
 
+def batched_pixel_rates(prof, clips, frames_per_clip):
+    """GB/s of the batched pixel stages of one batch: every clip's frames unpacked and
+    scene-measured in one launch each, and one output frame per group packed per launch
+    (frames_per_clip - 1 groups per clip)."""
+    n_groups = frames_per_clip - 1
+    per_launch = {
+        "unpack": sum(frames_per_clip * pixel_bytes("unpack", *c) for c in clips),
+        "scene": sum(frames_per_clip * pixel_bytes("scene", *c) for c in clips),
+        "pack": sum(n_groups * pixel_bytes("pack", *c) for c in clips),
+    }
+    out = {}
+    for kind, nbytes in per_launch.items():
+        n, tot = prof.get(kind, (0, 0.0))
+        if not n:
+            continue
+        us = 1000.0 * tot / n
+        gbs = nbytes / (us * 1e3)
+        out[kind] = {"avg_us": round(us, 2), "bytes_per_launch": int(nbytes), "gbs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def device_copy_gbs(torch, mib=1024, reps=10):
     """Measured device-to-device copy rate (read + write bytes per second), the
     achievable HBM figure quoted beside the 8 TB/s specification."""
@@ -340,6 +362,16 @@ def batching_bench(B, synth, torch, reps=3):
         if prec == "fp16":
             res["fp16_tuning"] = tune
             res["batch_workspace_gb"] = round(ctx.batch_footprint() / 2 ** 30, 2)
+            # the batched pixel stages over every frame of the batch in one launch each,
+            # timed with the library's events (launched directly, not replayed)
+            ctx.batch_graph(False)
+            ctx.profile(True)
+            one_batch()
+            torch.cuda.synchronize()
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            ctx.batch_graph(True)
+            res["pixel_stages_batched"] = batched_pixel_rates(prof, clips, len(banks[clips[0]]))
         for st in streams:
             st.close()
         ctx.close()
@@ -378,7 +410,7 @@ def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=120, max_
     for label, sp in (("poisson", specs), ("saturation", [type(s)(s.sid, s.width, s.height, s.bits, s.chroma,
                                                                     [0.0] * s.n_frames, s.scene_starts)
                                                                for s in specs])):
-        ex = GpuExecutor(ctx, source, batch_share_per_px=0, max_chain=4)
+        ex = GpuExecutor(ctx, source, max_chain=4)   # admission counts the batch pools too
         srv = Server(ex, hbm_budget=int(budget_gb * 2 ** 30), max_chain=4, max_batch_px=int(max_batch_mpx * 1e6))
         rep = srv.run(sp)
         torch.cuda.synchronize()

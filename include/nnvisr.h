@@ -401,6 +401,13 @@ nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs, int32_t n,
 /* on != 0 (the default): record and replay the batch graph; 0: launch directly. */
 nv_status nv_batch_graph(nv_context* ctx, int32_t on);
 
+/* Device bytes the batch pools take per padded LR pixel (section 3.3: a batch holds its
+ * groups' temporaries and its frames' features): *per_group for each group of the batch
+ * (offset-head hidden map, offsets, aligned features, HR features, HR R'G'B') and
+ * *per_frame for each frame, before each buffer is rounded up to 256 bytes.  A server
+ * adds them to nv_stream_footprint when it admits streams to batched calls. */
+nv_status nv_batch_bytes_per_px(const nv_context* ctx, size_t* per_group, size_t* per_frame);
+
 /* Device bytes of batch workspace currently held by ctx. */
 nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes);
 
@@ -426,7 +433,8 @@ enum {
 
 /* on != 0: from now on every launch the context makes (including those of its streams)
  * is bracketed by HIP events recorded on the launch's stream; on == 0 stops recording.
- * Enabling clears previous records. */
+ * Enabling clears previous records.  Batched calls are timed when their graph replay
+ * is off (nv_batch_graph); a replayed graph is not. */
 nv_status nv_profile_enable(nv_context* ctx, int32_t on);
 
 /* Totals per kind since the last enable: launches[k] and device milliseconds ms[k]

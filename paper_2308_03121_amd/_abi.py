@@ -92,6 +92,7 @@ _SIGS = {
     "nv_enhance_batch": (c_int32, [c_void_p, POINTER(NvBatchReq), c_int32, c_void_p]),
     "nv_batch_graph": (c_int32, [c_void_p, c_int32]),
     "nv_batch_footprint": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nv_batch_bytes_per_px": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
     "nv_autotune": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, ctypes.c_char_p, c_size_t]),
     "nv_calibrate": (c_int32, [c_void_p, POINTER(NvFormat), POINTER(NvPlanes), c_int32, c_void_p]),
     "nv_fp8_scales": (c_int32, [c_void_p, PF, c_int32, c_int32, c_void_p]),

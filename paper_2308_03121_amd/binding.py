@@ -273,6 +273,12 @@ class Context:
     def batch_graph(self, on: bool):
         check(_abi.load().nv_batch_graph(self._h, 1 if on else 0))
 
+    def batch_bytes_per_px(self) -> tuple:
+        """(bytes per group, bytes per frame) per padded LR pixel of the batch pools."""
+        g, f = c_size_t(), c_size_t()
+        check(_abi.load().nv_batch_bytes_per_px(self._h, byref(g), byref(f)))
+        return int(g.value), int(f.value)
+
     def batch_footprint(self) -> int:
         n = c_size_t()
         check(_abi.load().nv_batch_footprint(self._h, byref(n)))

@@ -2097,30 +2097,44 @@ nv_status batch_init(nv_context* ctx) {
   return NV_OK;
 }
 
-// Every batched launch of one batch, in dependency order, on stream s.
-nv_status batch_enqueue(nv_context* ctx, hipStream_t s) {
+// Every batched launch of one batch, in dependency order, on stream s.  With timing
+// (profiling on, launched directly rather than recorded into the graph) each launch is
+// bracketed by the profiler's events.
+nv_status batch_enqueue(nv_context* ctx, hipStream_t s, bool timing) {
   BatchTables* T = ctx->batch->dev;
   const int C = ctx->C, G = ctx->G, ft = ctx->ft, pb = ctx->tune.pb_block;
-  NV_TRY(check_launch(launch_scene_batch(T->scene, T->cnt[BL_SCENE], s), "scene batch"));
-  NV_TRY(check_launch(launch_unpack_batch(T->unpack, T->cnt[BL_UNPACK], s), "unpack batch"));
-  NV_TRY(check_launch(launch_conv_in_batch(ctx->conv_in, ft, T->convin, T->cnt[BL_CONV_IN], s), "conv_in batch"));
+  nv_context* pc = timing ? ctx : nullptr;
+  NV_TRY(timed(pc, NV_K_SCENE, s, "scene batch", [&] { return launch_scene_batch(T->scene, T->cnt[BL_SCENE], s); }));
+  NV_TRY(timed(pc, NV_K_UNPACK, s, "unpack batch",
+               [&] { return launch_unpack_batch(T->unpack, T->cnt[BL_UNPACK], s); }));
+  NV_TRY(timed(pc, NV_K_CONV_IN, s, "conv_in batch",
+               [&] { return launch_conv_in_batch(ctx->conv_in, ft, T->convin, T->cnt[BL_CONV_IN], s); }));
   for (int r = 0; r < ctx->cfg.res_blocks; ++r) {
-    NV_TRY(check_launch(launch_conv_batch(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, T->blk_a,
-                                          T->cnt[BL_BLOCK], C, 0, s), "block.a batch"));
-    NV_TRY(check_launch(launch_conv_batch(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, T->blk_b,
-                                          T->cnt[BL_BLOCK], C, 0, s), "block.b batch"));
+    NV_TRY(timed(pc, NV_K_CONV_BLOCK, s, "block.a batch", [&] {
+      return launch_conv_batch(ctx->blocks[2 * r], CONV_BULK, EPI_LRELU, ft, pb, T->blk_a, T->cnt[BL_BLOCK], C, 0, s);
+    }));
+    NV_TRY(timed(pc, NV_K_CONV_BLOCK, s, "block.b batch", [&] {
+      return launch_conv_batch(ctx->blocks[2 * r + 1], CONV_BULK, EPI_RES, ft, pb, T->blk_b, T->cnt[BL_BLOCK], C, 0,
+                               s);
+    }));
   }
-  NV_TRY(check_launch(launch_conv_batch(ctx->off1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, T->off1,
-                                        T->cnt[BL_OFF1], C, 0, s), "off1 batch"));
-  NV_TRY(check_launch(launch_conv_batch(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, T->off2,
-                                        T->cnt[BL_OFF2], ctx->ldo, 18 * G, s), "off2 batch"));
-  NV_TRY(check_launch(launch_dcn_batch(ctx->dcn, ft, ctx->tune.pb_dcn, T->dcn, T->cnt[BL_DCN], ctx->ldo, G, s),
-                      "dcn batch"));
+  NV_TRY(timed(pc, NV_K_OFF1, s, "off1 batch", [&] {
+    return launch_conv_batch(ctx->off1, CONV_OFF1, EPI_LRELU, ft, ctx->tune.off1, T->off1, T->cnt[BL_OFF1], C, 0, s);
+  }));
+  NV_TRY(timed(pc, NV_K_OFF2, s, "off2 batch", [&] {
+    return launch_conv_batch(ctx->off2, CONV_OFF2, EPI_OFFSET, DT_F32, ctx->tune.off2, T->off2, T->cnt[BL_OFF2],
+                             ctx->ldo, 18 * G, s);
+  }));
+  NV_TRY(timed(pc, NV_K_DCN, s, "dcn batch", [&] {
+    return launch_dcn_batch(ctx->dcn, ft, ctx->tune.pb_dcn, T->dcn, T->cnt[BL_DCN], ctx->ldo, G, s);
+  }));
   for (int o = 0; o < 2; ++o) {
-    NV_TRY(check_launch(launch_conv_batch(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, T->up[o],
-                                          T->cnt[BL_UP], 4 * C, 0, s), "up batch"));
-    NV_TRY(check_launch(launch_hr_batch(ctx->hr, ft, T->hr[o], T->cnt[BL_HR], s), "hr batch"));
-    NV_TRY(check_launch(launch_pack_batch(T->pack[o], T->cnt[BL_PACK], s), "pack batch"));
+    NV_TRY(timed(pc, NV_K_UP, s, "up batch", [&] {
+      return launch_conv_batch(ctx->up, CONV_BULK, EPI_SHUFFLE, ft, ctx->tune.pb_up, T->up[o], T->cnt[BL_UP], 4 * C,
+                               0, s);
+    }));
+    NV_TRY(timed(pc, NV_K_HR, s, "hr batch", [&] { return launch_hr_batch(ctx->hr, ft, T->hr[o], T->cnt[BL_HR], s); }));
+    NV_TRY(timed(pc, NV_K_PACK, s, "pack batch", [&] { return launch_pack_batch(T->pack[o], T->cnt[BL_PACK], s); }));
   }
   return NV_OK;
 }
@@ -2146,6 +2160,16 @@ extern "C" nv_status nv_batch_graph(nv_context* ctx, int32_t on) {
   if (!ctx) return fail(NV_E_INVALID, "NULL argument");
   NV_TRY(batch_init(ctx));
   ctx->batch->graph_on = on != 0;
+  return NV_OK;
+}
+
+extern "C" nv_status nv_batch_bytes_per_px(const nv_context* ctx, size_t* per_group, size_t* per_frame) {
+  if (!ctx || !per_group || !per_frame) return fail(NV_E_INVALID, "NULL argument");
+  const size_t C = ctx->C, fb = dtype_bytes(ctx->ft);
+  // a group's offset-head hidden map, offsets, aligned features, HR features and HR
+  // R'G'B'; a frame's features (the batch pools, before 256-byte rounding per buffer)
+  *per_group = C * 4 + (size_t)ctx->ldo * 4 + C * fb + 4 * C * fb + 48;
+  *per_frame = C * fb;
   return NV_OK;
 }
 
@@ -2368,7 +2392,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     if (!B->exec) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
-      const nv_status st = batch_enqueue(ctx, B->cap);
+      const nv_status st = batch_enqueue(ctx, B->cap, false);
       const hipError_t ec = hipStreamEndCapture(B->cap, &g);
       if (st != NV_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -2381,7 +2405,7 @@ extern "C" nv_status nv_enhance_batch(nv_context* ctx, const nv_batch_req* reqs,
     }
     HIP_TRY(hipGraphLaunch(B->exec, hs));
   } else {
-    NV_TRY(batch_enqueue(ctx, hs));
+    NV_TRY(batch_enqueue(ctx, hs, true));
   }
   HIP_TRY(hipEventRecord(B->done, hs));
   for (int i = 0; i < n; ++i) NV_TRY(order_end(reqs[i].stream->ord, hs));

@@ -272,12 +272,14 @@ class GpuExecutor:
     serving never frees or allocates stream memory (a free would synchronise the device
     and stall the batches in flight)."""
 
-    def __init__(self, ctx, frame_source, batch_share_per_px: int = 0, max_chain: int = 4):
+    def __init__(self, ctx, frame_source, batch_share_per_px: int | None = None, max_chain: int = 4):
         import torch
         self.torch = torch
         self.ctxs = ctx
         self.src = frame_source          # (spec, t) -> device frame tuple
-        self.share = batch_share_per_px  # workspace bytes per admitted pixel
+        # batch-pool bytes per admitted pixel: by default what a full chain of the stream
+        # takes in a batch (max_chain groups and their frames, nv_batch_bytes_per_px)
+        self.share = batch_share_per_px
         self.max_chain = max_chain       # a chain of k frames keeps k + 1 frames resident
         self._pool = {}
         self._ctx_of = {}                # id(stream handle) -> its context
@@ -297,7 +299,11 @@ class GpuExecutor:
             return UNSERVABLE
         hp, wp = (spec.height + 7) // 8 * 8, (spec.width + 7) // 8 * 8
         slot = hp * wp * (12 + ctx.channels * (4 if ctx.feat_dtype == torch_float32() else 2))
-        return ctx.stream_footprint(self._fmt(spec)) + (self.max_chain - 1) * slot + self.share * hp * wp
+        share = self.share
+        if share is None:
+            per_group, per_frame = ctx.batch_bytes_per_px()
+            share = self.max_chain * per_group + (self.max_chain + 1) * per_frame
+        return ctx.stream_footprint(self._fmt(spec)) + (self.max_chain - 1) * slot + share * hp * wp
 
     def open(self, spec):
         ctx = select_context(self.ctxs, spec)

@@ -57,3 +57,14 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_batched_pixel_rates_count_every_frame_of_the_batch():
+    clips = [(640, 360, 8, 420), (1280, 720, 10, 444)]
+    prof = {"unpack": (1, 0.5), "scene": (1, 0.1), "pack": (2, 2.0)}
+    r = bench.batched_pixel_rates(prof, clips, 5)
+    want_unpack = 5 * (bench.pixel_bytes("unpack", *clips[0]) + bench.pixel_bytes("unpack", *clips[1]))
+    assert r["unpack"]["bytes_per_launch"] == want_unpack
+    assert r["unpack"]["avg_us"] == 500.0 and abs(r["unpack"]["gbs"] - want_unpack / 500e3) < 0.1
+    want_pack = 4 * (bench.pixel_bytes("pack", *clips[0]) + bench.pixel_bytes("pack", *clips[1]))
+    assert r["pack"]["bytes_per_launch"] == want_pack and r["pack"]["avg_us"] == 1000.0

@@ -100,6 +100,13 @@ def test_batch_bit_identical_to_streams(B, prec):
     _same(_batched(B, ctx, clips, dev, [[2, 4], [4, 2], [5, 1], [1, 5]]), ref)   # replayed graph
     ctx.batch_graph(False)
     _same(_batched(B, ctx, clips, dev, chains), ref)          # direct launches
+    ctx.profile(True)                                         # direct launches, timed
+    _same(_batched(B, ctx, clips, dev, [[6]] * 4), ref)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    n = prof["unpack"][0]                                     # one launch per stage and batch
+    assert n >= 1 and prof["scene"][0] == n and prof["pack"][0] == 2 * n and prof["dcn"][0] == n, prof
+    assert prof["conv_block"][0] == 2 * cfg.res_blocks * n and prof["unpack"][1] > 0, prof
     ctx.close()
 
 
