@@ -136,6 +136,7 @@ class Server:
     def run(self, specs, time_scale=1.0):
         """Run the workload in real time (arrival times scaled by time_scale)."""
         self._px = {s.sid: s.width * s.height for s in specs}
+        self._first = {s.sid: s.arrivals[0] for s in specs}
         pending = sorted(specs, key=lambda s: s.arrivals[0])
         t0 = self.ex.now()
         clock = lambda: (self.ex.now() - t0) / time_scale
@@ -232,6 +233,10 @@ class Server:
             "mean_groups_per_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
             "admitted": len(self.admissions),
             "rejected": self.rejected,
+            # time from a stream's first frame to its admission (waits for HBM budget)
+            "admission_waited": int(sum(1 for sid, t in self.admissions if t - self._first.get(sid, t) > 1e-3)),
+            "admission_wait_max_ms": float(max([1000 * (t - self._first.get(sid, t)) for sid, t in self.admissions]
+                                               or [0.0])),
         }
 
     def _spec_px(self, sid):

@@ -84,9 +84,15 @@ def test_admission_respects_budget():
     one = 80 * 48 * 10
     srv = Server(ex, hbm_budget=2 * one)
     specs = _specs(n=6)
-    srv.run(specs)
+    rep = srv.run(specs)
     assert ex.max_open <= 2
     assert srv.rejected == 0 and len(srv.admissions) == 6
+    # the streams beyond the first two waited for budget, and the report says so
+    assert rep["admission_waited"] >= 4 and rep["admission_wait_max_ms"] > 0.0
+    ex2 = FakeExecutor(bytes_per_px=10)
+    rep2 = Server(ex2, hbm_budget=10 ** 9).run(_specs(n=6))
+    # (the fake clock advances 1 ms per look, so even immediate admissions read a few ms)
+    assert rep2["admission_wait_max_ms"] < 10.0 < rep["admission_wait_max_ms"]
 
 
 def test_too_large_stream_is_rejected():
