@@ -73,6 +73,20 @@ def kernel_work(kind, hp, wp, C, G, bits_out_bytes):
     return None, None
 
 
+def mfma_share(pr, kind, hp, wp, C, G, prec):
+    """Achieved TFLOP/s of one kernel kind from a profile (launches, ms) and its share of
+    the precision's dense MFMA peak."""
+    n, tot = pr.get(kind, (0, 0.0))
+    flop, unit = kernel_work(kind, hp, wp, C, G, 0)
+    if not n or unit != "flop":
+        return None
+    us = 1000.0 * tot / n
+    tf = flop / (us * 1e-6) / 1e12
+    peak = PEAKS[prec.split("-")[0]]
+    return {"kernel": kind, "avg_launch_us": round(us, 2), "achieved": round(tf, 2), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(tf / peak, 4)}
+
+
 def pixel_bytes(kind, w, h, bits, chroma):
     """Algorithmic HBM bytes of one launch of a pixel-format / scene stage on a w x h
     input frame: unpack reads the codes and writes float R'G'B' at the padded size; the
@@ -217,6 +231,7 @@ def c1_group_bench(B, synth, torch, reps=50):
     clip = synth.gen_group_c1()
     cfg = synth.NET_C1
     ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, synth.gen_weights(cfg, seed=1))
+    tune = ctx.autotune(64, 64)     # tiles for this size: at 64x64 a launch fills few CUs
     fmt = B.fmt_struct(64, 64, 8, 420)
     fa, fb = B.to_device_frame(*clip.frame(0)), B.to_device_frame(*clip.frame(1))
     outs = [B.alloc_frame(128, 128, 8, 420) for _ in range(3)]
@@ -234,7 +249,8 @@ def c1_group_bench(B, synth, torch, reps=50):
     ctx.close()
     us = float(np.median(times))
     return {"workload": "one group of two 64x64 8-bit 4:2:0 frames, C=32 R=2 G=8, FP32",
-            "latency_us": round(us, 1), "output_mpix_per_s": round(3 * 128 * 128 / us, 2), "reps": reps}
+            "latency_us": round(us, 1), "output_mpix_per_s": round(3 * 128 * 128 / us, 2), "reps": reps,
+            "tuning": tune}
 
 
 def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16", "fp8", "fp8-fusion"), steps=2):
@@ -282,6 +298,7 @@ def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16"
         res[prec] = {"value": round(mpix / (ms / 1000.0), 3), "unit": "Mpix/s", "ms_per_step": round(ms, 2),
                      "cuts": cuts,
                      "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]},
+                     "conv_block_mfma": mfma_share(pr, "conv_block", hp, wp, cfg.channels, cfg.offset_groups, prec),
                      "meets_50db_bar": prec != "fp8-fusion"}
         if prec == "fp8-fusion":
             res[prec]["note"] = ("below the 50 dB PSNR bar against the FP64 oracle (worst 1920x1080 window "
@@ -587,7 +604,9 @@ def main():
         ms2 = (a1 - a0) / args.steps * 1000.0
         others[prec] = {"value": round(mpix / (ms2 / 1000.0), 3), "ms_per_step": round(ms2, 3),
                         "speedup_vs_" + args.precision: round(ms / ms2, 3),
-                        "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]}}
+                        "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]},
+                        "conv_block_mfma": mfma_share(pr, "conv_block", hp, wp, cfg.channels, cfg.offset_groups,
+                                                      prec)}
         st2.close()
         c2.close()
     rec["tuning"] = tuning

@@ -68,3 +68,12 @@ def test_batched_pixel_rates_count_every_frame_of_the_batch():
     assert r["unpack"]["avg_us"] == 500.0 and abs(r["unpack"]["gbs"] - want_unpack / 500e3) < 0.1
     want_pack = 4 * (bench.pixel_bytes("pack", *clips[0]) + bench.pixel_bytes("pack", *clips[1]))
     assert r["pack"]["bytes_per_launch"] == want_pack and r["pack"]["avg_us"] == 1000.0
+
+
+def test_mfma_share_of_a_profiled_kind():
+    flop = 2 * 9 * 64 * 64 * 544 * 960
+    r = bench.mfma_share({"conv_block": (10, 0.5)}, "conv_block", 544, 960, 64, 8, "fp16")
+    assert r["avg_launch_us"] == 50.0 and abs(r["achieved"] - flop / 50e-6 / 1e12) < 0.01
+    assert r["peak"] == 2500.0 and abs(r["frac"] - r["achieved"] / 2500.0) < 1e-4
+    assert bench.mfma_share({}, "conv_block", 544, 960, 64, 8, "fp8") is None
+    assert bench.mfma_share({"conv_block": (1, 1.0)}, "conv_block", 8, 8, 64, 8, "fp8-fusion")["peak"] == 5000.0

@@ -131,3 +131,39 @@ def test_pyramid_validation(B):
     assert e.value.status == _abi.NV_E_UNSUPPORTED
     st.close()
     ctx.close()
+
+
+def test_pyramid_general_n_clip(B):
+    """A general-n clip (n = 3, b = 2, section 3.3) of a two-level network: the same pairs
+    as a clip stream, bit for bit, and the oracle within the bar."""
+    say("pyramid clip n=3 b=2")
+    cfg = synth.NetConfig(32, 1, 8, levels=2)
+    blob = synth.gen_weights(cfg, seed=25)
+    T, w, h = 9, 48, 32
+    clip = synth.gen_clip(w, h, T, seed=26, scene_starts=[7])
+    frames = [clip.frame(t) for t in range(T)]
+    _c, ref = pipeline.enhance_clip(frames, 8, 420, oracle_weights(cfg, blob), cfg.res_blocks, cfg.offset_groups,
+                                    levels=2)
+    ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, levels=2)
+    fmt = B.fmt_struct(w, h, 8, 420)
+    dev = [B.to_device_frame(*f) for f in frames]
+    cl = B.Clip(ctx, fmt, 3, 2)
+    got = []
+    for f in dev:
+        got += cl.push(f)
+    got += cl.end()
+    st = ctx.open_stream(fmt)
+    alone = []
+    for f in dev:
+        alone += st.push(f)
+    alone += st.end()
+    torch.cuda.synchronize()
+    assert len(got) == len(alone) == len(ref) == 2 * T
+    for g, a, r in zip(got, alone, ref):
+        cg = B.frame_to_numpy(g, 8)
+        for pg, pa in zip(cg, B.frame_to_numpy(a, 8)):
+            assert np.array_equal(pg, pa)
+        _close(cg, r["codes"])
+    st.close()
+    cl.close()
+    ctx.close()
