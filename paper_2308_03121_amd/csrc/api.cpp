@@ -288,6 +288,8 @@ struct Workspace {
   void* feat[2] = {nullptr, nullptr};  // group features: every pyramid level, level 1 first
   float* offs_lv = nullptr;  // pyramid levels 2..L: offsets + mask, level after level
   void* fmid_lv = nullptr;   // pyramid levels 2..L: aligned features, level after level
+  void* u2 = nullptr;        // the t = 0 output's HR features and R'G'B' while it runs
+  float* hr2 = nullptr;      // beside the alignment (null: no overlap)
   size_t bytes = 0;
 };
 
@@ -351,6 +353,10 @@ struct nv_context {
   PackedConv off1, off2, dcn, up, hr;
   // feature pyramid: levels L, and for level l = 2..L (index l - 2) the conv after the
   // 2x2 mean pool and the level's offset head and DCN
+  // side stream for the t = 0 output of a group, which needs no alignment and runs
+  // beside it (fork / join events on the caller's stream)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int levels = 1;
   std::vector<PackedConv> down;
   struct LevelFusion {
@@ -750,6 +756,8 @@ void free_workspace(Workspace& ws) {
   free_raw(ws.fmid);
   dev_free(ws.offs_lv);
   free_raw(ws.fmid_lv);
+  free_raw(ws.u2);
+  dev_free(ws.hr2);
   free_raw(ws.u);
   dev_free(ws.hr);
   for (int i = 0; i < 2; ++i) {
@@ -788,6 +796,8 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   const size_t up = upper_levels_px(ctx, nh, nw);
   if (e == hipSuccess && up) e = dev_alloc(&n.offs_lv, up * ctx->ldo);
   if (e == hipSuccess && up) e = dev_malloc(&n.fmid_lv, up * C * fb);
+  if (e == hipSuccess && ctx->side) e = dev_malloc(&n.u2, r2 * px * C * fb);
+  if (e == hipSuccess && ctx->side) e = dev_alloc(&n.hr2, 3 * r2 * px);
   if (e != hipSuccess) {
     free_workspace(n);
     return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "workspace of %dx%d: %s", nw, nh,
@@ -796,7 +806,8 @@ nv_status ensure_workspace(nv_context* ctx, int hp, int wp) {
   n.hp = nh;
   n.wp = nw;
   n.bytes = px * (C * fb * (2 + r2) + 4 * C + 4 * (size_t)ctx->ldo + 12 * r2 + 24) +
-            2 * feat_bytes(ctx, nh, nw) + up * (4 * (size_t)ctx->ldo + C * fb);
+            2 * feat_bytes(ctx, nh, nw) + up * (4 * (size_t)ctx->ldo + C * fb) +
+            (ctx->side ? px * r2 * (C * fb + 12) : 0);
   ws = n;
   return NV_OK;
 }
@@ -952,6 +963,48 @@ nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const fl
   const int C = ctx->C, G = ctx->G, ft = ctx->ft;
   float* offs = offs_out ? offs_out : ws.offs;
   void* fmid = fmid_out ? fmid_out : ws.fmid;
+  // The t = 0 output needs only frame a, so with the alignment to compute it runs on the
+  // side stream beside it (its own HR buffers), joined before the call returns.
+  // output t: the pixel-shuffle conv of its features, the HR conv plus the base, the pack
+  auto recon = [&](int t, hipStream_t st, void* ub, float* hrb) -> nv_status {
+    const void* g = t == 0 ? fa : (t == 1 ? fmid : fb);
+    const void* alt = t == 2 ? fa : nullptr;
+    const int tsel = t == 0 ? 0 : (t == 1 ? 2 : 1);
+    const ConvImg iu = conv_img(g, nullptr, sel, alt, nullptr, nullptr, ub, hp, wp);
+    if (ctx->calibrating && ctx->ut == DT_F8)
+      NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks + 1, {g}, (size_t)hp * wp * C, st));
+    // scale 1 in both directions: the conv before the (absent) shuffle is a plain conv
+    const int r2 = ctx->sv * ctx->sh;
+    NV_TRY(timed(ctx, NV_K_UP, st, "up", [&] {
+      return launch_conv(ctx->up, CONV_BULK, r2 > 1 ? EPI_SHUFFLE : EPI_LRELU, ft, ctx->tune.pb_up, iu, r2 * C, 0, st);
+    }));
+    float* hr = hr_out && hr_out[t] ? hr_out[t] : hrb;
+    HrImg hi;
+    hi.u = ub;
+    hi.rgb_a = rgb_a;
+    hi.rgb_b = rgb_b;
+    hi.sel = sel;
+    hi.dst = hr;
+    hi.H = hp;
+    hi.W = wp;
+    hi.tsel = tsel;
+    hi.item_begin = 0;
+    hi.sv = ctx->sv;
+    hi.sh = ctx->sh;
+    NV_TRY(timed(ctx, NV_K_HR, st, "hr", [&] { return launch_hr(ctx->hr, ft, hi, st); }));
+    if (pack_fmt && pack_out && pack_out[t]) {
+      const FrameOut fo = to_frame_out(pack_fmt, pack_out[t]);
+      NV_TRY(timed(ctx, NV_K_PACK, st, "pack", [&] { return launch_pack(fo, hr, ctx->sv * hp, ctx->sh * wp, st); }));
+    }
+    return NV_OK;
+  };
+  const bool fork = (mask & 1u) && (mask & 6u) && ws.u2 && ws.hr2 && ctx->side && !ctx->calibrating;
+  if (fork) {
+    HIP_TRY(hipEventRecord(ctx->fork_ev, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+    NV_TRY(recon(0, ctx->side, ws.u2, ws.hr2));
+    HIP_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+  }
   if (mask & 2u) {
     // alignment, coarsest pyramid level first: level l's offsets add twice the x2
     // resize of level l+1's, and its aligned features the x2 resize of level l+1's
@@ -998,39 +1051,9 @@ nv_status fuse_impl(nv_context* ctx, Workspace& ws, const float* rgb_a, const fl
                      [&] { return launch_up2_add(ft, fmid_l, C, fmid_at(l + 1), C, h, w, C, 1.0f, s); }));
     }
   }
-  for (int t = 0; t < 3; ++t) {
-    if (!(mask & (1u << t))) continue;
-    const void* g = t == 0 ? fa : (t == 1 ? fmid : fb);
-    const void* alt = t == 2 ? fa : nullptr;
-    const int tsel = t == 0 ? 0 : (t == 1 ? 2 : 1);
-    const ConvImg iu = conv_img(g, nullptr, sel, alt, nullptr, nullptr, ws.u, hp, wp);
-    if (ctx->calibrating && ctx->ut == DT_F8)
-      NV_TRY(calib_layer(ctx, 2 * ctx->cfg.res_blocks + 1, {g}, (size_t)hp * wp * C, s));
-    // scale 1 in both directions: the conv before the (absent) shuffle is a plain conv
-    const int r2 = ctx->sv * ctx->sh;
-    NV_TRY(timed(ctx, NV_K_UP, s, "up", [&] {
-      return launch_conv(ctx->up, CONV_BULK, r2 > 1 ? EPI_SHUFFLE : EPI_LRELU, ft, ctx->tune.pb_up, iu, r2 * C, 0, s);
-    }));
-    float* hr = hr_out && hr_out[t] ? hr_out[t] : ws.hr;
-    HrImg hi;
-    hi.u = ws.u;
-    hi.rgb_a = rgb_a;
-    hi.rgb_b = rgb_b;
-    hi.sel = sel;
-    hi.dst = hr;
-    hi.H = hp;
-    hi.W = wp;
-    hi.tsel = tsel;
-    hi.item_begin = 0;
-    hi.sv = ctx->sv;
-    hi.sh = ctx->sh;
-    NV_TRY(timed(ctx, NV_K_HR, s, "hr", [&] { return launch_hr(ctx->hr, ft, hi, s); }));
-    if (pack_fmt && pack_out && pack_out[t]) {
-      const FrameOut fo = to_frame_out(pack_fmt, pack_out[t]);
-      NV_TRY(timed(ctx, NV_K_PACK, s, "pack",
-                   [&] { return launch_pack(fo, hr, ctx->sv * hp, ctx->sh * wp, s); }));
-    }
-  }
+  for (int t = 0; t < 3; ++t)
+    if ((mask & (1u << t)) && !(fork && t == 0)) NV_TRY(recon(t, s, ws.u, ws.hr));
+  if (fork) HIP_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
   return NV_OK;
 }
 
@@ -1086,6 +1109,15 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   ctx->sh = scale_h(*cfg);
   ctx->interp = interpolating(*cfg);
   ctx->dbl = doubling(*cfg);
+  if (ctx->interp && ctx->dbl) {   // groups emit t = 0 beside the interpolated frame
+    hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      nv_context_destroy(ctx);
+      return fail(e == hipErrorOutOfMemory ? NV_E_NOMEM : NV_E_DEVICE, "side stream: %s", hipGetErrorString(e));
+    }
+  }
   ctx->ft = cfg->precision == NV_FP16 || cfg->precision == NV_FP8_E4M3
                 ? DT_F16
                 : (cfg->precision == NV_BF16 ? DT_BF16 : DT_F32);
@@ -1170,6 +1202,9 @@ extern "C" nv_status nv_context_destroy(nv_context* ctx) {
   batch_release(ctx->batch);
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
   return NV_OK;
 }

@@ -252,6 +252,15 @@ static void batch_nomem_stream_usable() {
   nv_context_destroy(ctx);
 }
 
+// The waits between the caller's HIP streams a and b (the context's own fork / join with
+// its side stream is internal to one call and ordered by the caller's stream).
+static std::vector<fake::Wait> caller_waits(int a, int b) {
+  std::vector<fake::Wait> v;
+  for (const auto& w : fake::waits())
+    if ((w.waiter == a || w.waiter == b) && (w.recorded_on == a || w.recorded_on == b)) v.push_back(w);
+  return v;
+}
+
 // Calls on different HIP streams: the second stream waits for the event recorded after
 // the last call that used the shared workspace or the clip stream's state.
 static void ordering_across_streams() {
@@ -270,20 +279,20 @@ static void ordering_across_streams() {
   int32_t n = 0;
   fake::clear_waits();
   EXPECT(nv_stream_push(s1, &in[0].p, -1, po, &n, A) == NV_OK);
-  EXPECT(fake::waits().empty());                   // first use: nothing to wait for
+  EXPECT(caller_waits(a, b).empty());                   // first use: nothing to wait for
   EXPECT(nv_stream_push(s2, &in[1].p, -1, po, &n, B) == NV_OK);
   // s2's own state is new; the context workspace was last used on A
-  EXPECT(fake::waits().size() == 1 && fake::waits()[0].waiter == b && fake::waits()[0].recorded_on == a);
+  EXPECT(caller_waits(a, b).size() == 1 && caller_waits(a, b)[0].waiter == b && caller_waits(a, b)[0].recorded_on == a);
   fake::clear_waits();
   EXPECT(nv_stream_push(s2, &in[2].p, -1, po, &n, B) == NV_OK);
-  EXPECT(fake::waits().empty());                   // same stream: ordered by the stream
+  EXPECT(caller_waits(a, b).empty());                   // same stream: ordered by the stream
   EXPECT(nv_stream_push(s1, &in[3].p, -1, po, &n, B) == NV_OK);
   // s1 was last pushed on A: B waits for it (the workspace was last used on B itself)
-  EXPECT(fake::waits().size() == 1 && fake::waits()[0].waiter == b && fake::waits()[0].recorded_on == a);
+  EXPECT(caller_waits(a, b).size() == 1 && caller_waits(a, b)[0].waiter == b && caller_waits(a, b)[0].recorded_on == a);
   fake::clear_waits();
   uint32_t cuts[2];
   EXPECT(nv_stream_cuts(s1, cuts, 2, A) == NV_OK);
-  EXPECT(fake::waits().size() == 1 && fake::waits()[0].waiter == a && fake::waits()[0].recorded_on == b);
+  EXPECT(caller_waits(a, b).size() == 1 && caller_waits(a, b)[0].waiter == a && caller_waits(a, b)[0].recorded_on == b);
   nv_stream_close(s1);
   nv_stream_close(s2);
   hipStreamDestroy(A);
