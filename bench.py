@@ -402,10 +402,14 @@ def batching_bench(B, synth, torch, reps=3):
     return res
 
 
-def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=120, max_batch_mpx=16.0):
+def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=240, tight_budget_gb=96,
+                  max_batch_mpx=16.0):
     """16 streams (540p/1080p, 8/10-bit 4:2:0, 30-300 frames, cuts every 10-60 frames)
     whose frames arrive as Poisson processes totalling `rate` groups/s, truncated at
-    `duration` seconds of arrivals; FP16 network C=64, R=10; admission by HBM footprint."""
+    `duration` seconds of arrivals; FP16 network C=64, R=10; admission by HBM footprint
+    (stream state plus a full chain's share of the batch pools).  With budget_gb (most of
+    the 288 GB card) every stream is admitted on arrival; the same arrivals under
+    tight_budget_gb show the admission queue at work."""
     from paper_2308_03121_amd.serving import GpuExecutor, Server, poisson_workload
 
     specs = poisson_workload(n_streams=16, rate_total=rate, seed=3, max_time=duration)
@@ -424,11 +428,12 @@ def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=120, max_
                     precision="fp16")
     ctx.autotune(544, 960)
     out = {}
-    for label, sp in (("poisson", specs), ("saturation", [type(s)(s.sid, s.width, s.height, s.bits, s.chroma,
-                                                                    [0.0] * s.n_frames, s.scene_starts)
-                                                               for s in specs])):
+    saturation = [type(s)(s.sid, s.width, s.height, s.bits, s.chroma, [0.0] * s.n_frames, s.scene_starts)
+                  for s in specs]
+    for label, sp, gb in (("poisson", specs, budget_gb), ("saturation", saturation, budget_gb),
+                          ("poisson_tight_budget", specs, tight_budget_gb)):
         ex = GpuExecutor(ctx, source, max_chain=4)   # admission counts the batch pools too
-        srv = Server(ex, hbm_budget=int(budget_gb * 2 ** 30), max_chain=4, max_batch_px=int(max_batch_mpx * 1e6))
+        srv = Server(ex, hbm_budget=int(gb * 2 ** 30), max_chain=4, max_batch_px=int(max_batch_mpx * 1e6))
         rep = srv.run(sp)
         torch.cuda.synchronize()
         ex.shutdown()
@@ -437,6 +442,7 @@ def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=120, max_
     out["frames"] = sum(s.n_frames for s in specs)
     out["arrival_rate_groups_per_s"] = rate
     out["hbm_budget_gb"] = budget_gb
+    out["tight_hbm_budget_gb"] = tight_budget_gb
     out["max_batch_lr_mpx"] = max_batch_mpx
     ctx.close()
     return out
@@ -460,7 +466,7 @@ def main():
                     help="only run a device copy of MIB MiB 10 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the path needs no collective and this build runs on a "
+        print(f"bench.py measures one GPU: the path needs no collective and runs on a "
               f"single MI355X (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

@@ -654,7 +654,7 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
   delete x;
   return hipSuccess;
 }
-// device-side statics are host statics in this build: the symbol's address is the array's
+// device-side statics are host statics in the simulation: the symbol's address is the array's
 hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
   *p = const_cast<void*>(symbol);
   return hipSuccess;
