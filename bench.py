@@ -402,6 +402,96 @@ def batching_bench(B, synth, torch, reps=3):
     return res
 
 
+def next_rows_bench(B, synth, torch, n_frames=12, reps=3):
+    """Throughput of the wider rows on a 12-frame 960x540 clip (cut at frame 8), FP16
+    network C=64, R=10, G=8, tiles tuned per context: the feature pyramid (2 and 3
+    levels) and the task modes through clip streams, a BT.2020 full-range 10-bit clip
+    through the network of its colourspace, and a general-n clip (n = 3, b = 2); each
+    against the same clip through the one-level space-time network."""
+    clip8 = synth.gen_clip(960, 540, n_frames, seed=5, scene_starts=[8])
+    clip10 = synth.gen_clip(960, 540, n_frames, bits=10, seed=5, scene_starts=[8])
+    f8 = [B.to_device_frame(*clip8.frame(t)) for t in range(n_frames)]
+    f10 = [B.to_device_frame(*clip10.frame(t)) for t in range(n_frames)]
+    w, h = 960, 540
+    res = {"workload": f"{n_frames}-frame 960x540 4:2:0 clip, cut at 8, FP16 C=64 R=10 G=8"}
+
+    def timed(go):
+        go()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            go()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def stream_run(ctx, fmt, frames):
+        st = ctx.open_stream(fmt)
+
+        def go():
+            st.reset()
+            n = 0
+            for f in frames:
+                n += len(st.push(f))
+            n += len(st.end())
+            return n
+        dt = timed(go)
+        n_out = go()
+        torch.cuda.synchronize()
+        st.close()
+        return dt, n_out
+
+    def record(name, dt, n_out, sv, sh, extra=None):
+        mpix = n_out * sv * h * sh * w / 1e6
+        res[name] = {"mpix_per_s": round(mpix / dt, 1), "ms_per_input_frame": round(1000 * dt / n_frames, 3),
+                     "outputs": n_out}
+        if extra:
+            res[name].update(extra)
+
+    blob_cache = {}
+
+    def context(**kw):
+        levels = kw.get("levels", 1)
+        cfg = synth.NetConfig(64, 10, 8, scale=kw.get("scale", 2), scale_v=kw.get("scale_v", 0),
+                              interp=kw.get("interp", True), double=kw.get("double", True), levels=levels)
+        if cfg not in blob_cache:
+            blob_cache[cfg] = synth.gen_weights(cfg, seed=1)
+        ctx = B.Context(64, 10, 8, blob_cache[cfg], precision="fp16", **kw)
+        ctx.autotune(544, 960)
+        return ctx, cfg
+
+    fmt8 = B.fmt_struct(w, h, 8, 420)
+    for name, kw in (("space_time", {}), ("pyramid_2_levels", {"levels": 2}), ("pyramid_3_levels", {"levels": 3}),
+                     ("denoise_x1", {"scale": 1, "interp": False}), ("sr_x2", {"scale": 2, "interp": False}),
+                     ("deinterlace", {"scale": 1, "scale_v": 2, "interp": False}),
+                     ("interp_pass_through", {"scale": 1, "double": False})):
+        ctx, cfg = context(**kw)
+        dt, n_out = stream_run(ctx, fmt8, f8)
+        record(name, dt, n_out, cfg.sv, cfg.sh)
+        if name == "space_time":
+            # the general-n clip: n = 3 frames per run, b = 2 groups per batch
+            def go_clip(cl):
+                n = 0
+                for f in f8:
+                    n += len(cl.push(f))
+                return n + len(cl.end())
+            for timed_run in (False, True):      # a warm-up clip, then a timed one
+                cl = B.Clip(ctx, fmt8, 3, 2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                n_clip = go_clip(cl)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                cl.close()
+            record("general_n3_b2", dt, n_clip, 2, 2)
+        ctx.close()
+    ctx = B.Context(64, 10, 8, blob_cache[synth.NetConfig(64, 10, 8)], precision="fp16", matrix=2020, full=True)
+    ctx.autotune(544, 960)
+    dt, n_out = stream_run(ctx, B.fmt_struct(w, h, 10, 420, matrix=2020, full=True), f10)
+    record("bt2020_full_range_10bit", dt, n_out, 2, 2)
+    ctx.close()
+    return res
+
+
 def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=240, tight_budget_gb=96,
                   max_batch_mpx=16.0):
     """16 streams (540p/1080p, 8/10-bit 4:2:0, 30-300 frames, cuts every 10-60 frames)
@@ -461,6 +551,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 1080p 10-bit per-precision run")
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-group batching run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the pyramid / task-mode / colourspace / general-n throughput leg")
     ap.add_argument("--serving-seconds", type=float, default=20.0)
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB 10 times (HBM counter calibration)")
@@ -638,6 +730,13 @@ def main():
         except Exception as e:  # report, keep the main measurement
             rec["batching"] = {"error": f"{type(e).__name__}: {e}"}
         print("# batching: " + json.dumps(rec["batching"]), file=sys.stderr, flush=True)
+    if not args.no_next:
+        print("# wider rows: pyramid, task modes, colourspace, general n", file=sys.stderr, flush=True)
+        try:
+            rec["next_rows"] = next_rows_bench(B, synth, torch)
+        except Exception as e:
+            rec["next_rows"] = {"error": f"{type(e).__name__}: {e}"}
+        print("# next rows: " + json.dumps(rec["next_rows"]), file=sys.stderr, flush=True)
     if not args.no_serving:
         print("# serving: Poisson arrivals of 16 streams", file=sys.stderr, flush=True)
         try:
