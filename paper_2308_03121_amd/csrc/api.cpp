@@ -2469,9 +2469,22 @@ std::string tile_name(int code) {
   return b;
 }
 
+// The DCN tile codes the tuner times for a network: rows per wave, the windowed forms
+// and the staged form where the maps and offset groups allow them.
+std::vector<int> dcn_tiles(int ft, int tc, int C, int groups) {
+  std::vector<int> v{1, 2};
+  if (dcn_window_supported(ft, tc, C, groups)) {
+    v.push_back(1 | kDcnWindow);
+    v.push_back(2 | kDcnWindow);
+  }
+  if (dcn_staged_supported(ft, tc, C, groups)) v.push_back(1 | kDcnStaged);
+  return v;
+}
+
 std::string dcn_tile_name(int code) {
   char b[32];
-  snprintf(b, sizeof b, "pb%d%s", code & (kDcnWindow - 1), (code & kDcnWindow) ? "win" : "");
+  snprintf(b, sizeof b, "pb%d%s", code & (kDcnWindow - 1),
+           (code & kDcnWindow) ? "win" : (code & kDcnStaged) ? "stg" : "");
   return b;
 }
 
@@ -2583,9 +2596,7 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
     } cands[5] = {{"block", &ctx->tune.pb_block, block_tiles}, {"up", &ctx->tune.pb_up, up_tiles},
                   {"dcn", &ctx->tune.pb_dcn,
                    ctx->ut == DT_F8 ? std::vector<int>{1}
-                   : dcn_window_supported(ft, ctx->dcn.tc, C, ctx->G)
-                       ? std::vector<int>{1, 2, 1 | kDcnWindow, 2 | kDcnWindow}
-                       : std::vector<int>{1, 2}},
+                   : dcn_tiles(ft, ctx->dcn.tc, C, ctx->G)},
                   {"off1", &ctx->tune.off1, head_tiles(ctx->off1)}, {"off2", &ctx->tune.off2, head_tiles(ctx->off2)}};
     for (auto& cd : cands) {
       // networks that do not interpolate have no offset head and no alignment
@@ -2637,7 +2648,8 @@ extern "C" nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* 
         }
       }
       *cd.slot = best_pb;
-      snprintf(buf, sizeof buf, " -> %s; ", tile_name(best_pb).c_str());
+      snprintf(buf, sizeof buf, " -> %s; ",
+               (cd.slot == &ctx->tune.pb_dcn ? dcn_tile_name(best_pb) : tile_name(best_pb)).c_str());
       rep += buf;
     }
     // residual block: one fused launch against the two convs with the chosen tile

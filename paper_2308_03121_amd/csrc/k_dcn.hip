@@ -51,12 +51,15 @@ struct DcnSmem {
 
 // The DCN epilogue: bias, LReLU and the store of the tile's C output channels (through
 // the idle LDS buffer S of NS elements for float and 16-bit maps, so that each wave
-// stores whole pixels; FP8 outputs scaled per channel and stored directly).
-template <typename TF, typename TC, int C, int PB, int NS>
+// stores whole pixels; FP8 outputs scaled per channel and stored directly).  A wave's
+// accumulators acc[r][b] are pixel row wave * PB + r and channel block b, or with CS
+// (channel split: one block of 16 channels per wave) pixel row r of the PB-row tile and
+// channel block wave.
+template <typename TF, typename TC, int C, int PB, int NS, bool CS = false, int OB = C / 16>
 __device__ __forceinline__ void dcn_store(const DcnLayer& L, const DcnImg& im, int ty0, int tx0,
-                                          const f32x4 (&acc)[PB][C / 16], TC* S) {
-  constexpr int TH = 4 * PB;
-  constexpr int OB = C / 16;
+                                          const f32x4 (&acc)[PB][OB], TC* S) {
+  constexpr int TH = CS ? PB : 4 * PB;
+  static_assert(!CS || (OB == 1 && std::is_same<TF, TC>::value), "channel split: one block per wave, staged");
   constexpr bool kF8 = std::is_same<TC, f8>::value;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
@@ -70,10 +73,10 @@ __device__ __forceinline__ void dcn_store(const DcnLayer& L, const DcnImg& im, i
     __syncthreads();
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      const int r = wave * PB + pb;
+      const int r = CS ? pb : wave * PB + pb;
 #pragma unroll
       for (int ob = 0; ob < OB; ++ob) {
-        const int row = ob * 16 + 4 * q;
+        const int row = (CS ? wave : ob) * 16 + 4 * q;
         const f32x4 v = acc[pb][ob] + ld4(L.bias + row);
         store4f<TF>(&S[(r * kTW + j) * OLDP + row], lrelu4(v));
       }
@@ -102,6 +105,130 @@ __device__ __forceinline__ void dcn_store(const DcnLayer& L, const DcnImg& im, i
   }
 }
 
+// Float samples in 16-channel chunks: the four 16-byte pieces of chunk c sit rotated by
+// c / 2 inside the chunk, so that stores of consecutive taps (chunks 64 bytes apart) fall
+// in eight different 16-byte bank groups.
+template <typename TC, int CPG>
+constexpr bool dcn_rot() {
+  return std::is_same<TC, float>::value && DcnPhase<TC, CPG>::CW == 16;
+}
+template <bool ROT>
+__device__ __forceinline__ int dcn_piece(int c, int v4) {
+  return ROT ? ((v4 + (c >> 1)) & 3) : v4;
+}
+
+// The sampling position of one (pixel, tap) at integer base (by, bx) = pixel + tap - 1
+// plus the offset (dy, dx): the top-left corner (y0, x0) and the four bilinear weights
+// times the modulation m, zero for a corner outside the H x W map.  Positions are clamped
+// to [-2, H + 1] x [-2, W + 1]: beyond one pixel outside the map every sample is zero, and
+// the clamp keeps the integer conversion defined for any offset value.
+__device__ __forceinline__ void dcn_corners(int by, int bx, float dy, float dx, float m, int H, int W, int& y0,
+                                            int& x0, float (&cw)[4]) {
+  const float py = fminf(fmaxf((float)by + dy, -2.0f), (float)H + 1.0f);
+  const float px = fminf(fmaxf((float)bx + dx, -2.0f), (float)W + 1.0f);
+  const float y0f = floorf(py), x0f = floorf(px);
+  const float ly = py - y0f, lx = px - x0f;
+  y0 = (int)y0f;
+  x0 = (int)x0f;
+#pragma unroll
+  for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+    for (int cx = 0; cx < 2; ++cx) {
+      const int yy = y0 + cy, xx = x0 + cx;
+      const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      cw[2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
+    }
+}
+
+// The weighted sum of the four corners' CW channels (raw vectors of 8 channels), rounded
+// to TC and stored at sp: chunk-contiguous, or rotated pieces (ROT) for chunk c.
+template <typename TF, typename TC, int NV8, bool ROT>
+__device__ __forceinline__ void dcn_blend_store(const Raw8<TF> (&raw)[4][NV8], const float (&cw)[4], TC* sp, int c) {
+#pragma unroll
+  for (int v = 0; v < NV8; ++v) {
+    f32x4 lo = zero4(), hi = zero4();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      f32x4 a, b;
+      raw[k][v].to_f32(a, b);
+      lo += cw[k] * a;
+      hi += cw[k] * b;
+    }
+    if constexpr (ROT) {
+      store4f<TC>(sp + 4 * dcn_piece<ROT>(c, 2 * v), lo);
+      store4f<TC>(sp + 4 * dcn_piece<ROT>(c, 2 * v + 1), hi);
+    } else {
+      store8f<TC>(sp + 8 * v, lo, hi);
+    }
+  }
+}
+
+// One phase's nine MFMA steps: the phase's weight fragments of channel blocks ob0 ..
+// ob0 + OB - 1 times the samples of PB pixel rows of the sample buffer (from sbase),
+// accumulated into acc; over two register buffers, step i + 1 loading while step i
+// multiplies.
+template <typename TC, int CPG, int PB, int OB>
+__device__ __forceinline__ void dcn_phase_mfma(const DcnLayer& L, int ph, const TC* sbase, int ob0,
+                                               f32x4 (&acc)[PB][OB]) {
+  using Ph = DcnPhase<TC, CPG>;
+  using Frag = typename Mma<TC>::Frag;
+  constexpr int KG = Ph::KG, LDS_P = Ph::LDS_P;
+  constexpr bool ROT = dcn_rot<TC, CPG>();
+  const int lane = threadIdx.x & 63, q = lane >> 4;
+  const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot + ob0) * 64 + lane;
+  Frag wa0[OB], xb0[PB], wa1[OB], xb1[PB];
+  auto fetch = [&](int st, Frag (&wa)[OB], Frag (&xb)[PB]) {
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[((size_t)st * L.obtot + ob) * 64];
+    // float: step st is chunk st (KG = CW = 16), quarter q its piece q
+    const int so = ROT ? KG * st + 4 * dcn_piece<ROT>(st, q) : KG * st;
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + so);
+  };
+  auto mma = [&](const Frag (&wa)[OB], const Frag (&xb)[PB]) {
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
+  };
+#if NV_DCN_PRELOAD
+  if constexpr (OB == 1) {
+    // one block of output channels: all nine steps' weight fragments in one round trip
+    Frag wall[9];
+#pragma unroll
+    for (int st = 0; st < 9; ++st) wall[st] = wbase[(size_t)st * L.obtot * 64];
+    auto ldb = [&](int st, Frag (&xb)[PB]) {
+      const int so = ROT ? KG * st + 4 * dcn_piece<ROT>(st, q) : KG * st;
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + so);
+    };
+    ldb(0, xb0);
+#pragma unroll
+    for (int st = 0; st < 9; st += 2) {
+      if (st + 1 < 9) ldb(st + 1, xb1);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) acc[pb][0] = Mma<TC>::step(wall[st], xb0[pb], acc[pb][0]);
+      if (st + 1 < 9) {
+        if (st + 2 < 9) ldb(st + 2, xb0);
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) acc[pb][0] = Mma<TC>::step(wall[st + 1], xb1[pb], acc[pb][0]);
+      }
+    }
+    return;
+  }
+#endif
+  fetch(0, wa0, xb0);
+#pragma unroll 1
+  for (int st = 0; st < 9; st += 2) {
+    if (st + 1 < 9) fetch(st + 1, wa1, xb1);
+    mma(wa0, xb0);
+    if (st + 1 < 9) {
+      if (st + 2 < 9) fetch(st + 2, wa0, xb0);
+      mma(wa1, xb1);
+    }
+  }
+}
+
 template <typename TF, typename TC, int C, int CPG, int PB>
 __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, int ty0, int tx0, TC* S) {
   using Ph = DcnPhase<TC, CPG>;
@@ -119,7 +246,6 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, j = lane & 15;
   constexpr bool kF8 = std::is_same<TC, f8>::value;
-  using Frag = typename Mma<TC>::Frag;
   const TF* fa = static_cast<const TF*>(im.fa);
   const TF* fb = (im.sel != nullptr && *im.sel != 0u) ? fa : static_cast<const TF*>(im.fb);
   const float hmax = (float)im.H, wmax = (float)im.W;
@@ -132,11 +258,7 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = zero4();
 
-  // float with 16-channel chunks: the four 16-byte pieces of chunk c sit rotated by
-  // c / 2 inside the chunk, so that the gather's stores of consecutive taps (chunks 64
-  // bytes apart) fall in eight different 16-byte bank groups
-  constexpr bool ROT = std::is_same<TC, float>::value && CW == 16;
-  auto piece = [](int c, int v4) { return ROT ? ((v4 + (c >> 1)) & 3) : v4; };
+  constexpr bool ROT = dcn_rot<TC, CPG>();
   const TC* sbase = ROT ? &S[((wave * PB) * kTW + j) * LDS_P] : &S[((wave * PB) * kTW + j) * LDS_P + QE * q];
 
   // gather: item = (pixel, chunk in phase, tap), tap fastest; S[p][(gi*9 + tap)*CW + c].
@@ -207,13 +329,9 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
           const int ky = ip.tap / 3, kx = ip.tap - 3 * ky;
           float m = od[r & 1][uu][2];
           if (kF8) m *= qs;
-          // beyond one pixel outside the map every sample is zero; the clamp keeps the
-          // integer conversion defined for any offset value
-          const float py = fminf(fmaxf((float)(ip.gy + ky - 1) + od[r & 1][uu][0], -2.0f), hmax + 1.0f);
-          const float px = fminf(fmaxf((float)(ip.gx + kx - 1) + od[r & 1][uu][1], -2.0f), wmax + 1.0f);
-          const float y0f = floorf(py), x0f = floorf(px);
-          const float ly = py - y0f, lx = px - x0f;
-          const int y0 = (int)y0f, x0 = (int)x0f;
+          int y0, x0;
+          dcn_corners(ip.gy + ky - 1, ip.gx + kx - 1, od[r & 1][uu][0], od[r & 1][uu][1], m, im.H, im.W, y0, x0,
+                      cw[uu]);
           const int ci = u * CW;
           const TF* src = ci < C ? fa : fb;
           const int cl = ci < C ? ci : ci - C;
@@ -221,10 +339,7 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
           for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
-              const int yy = y0 + cy, xx = x0 + cx;
-              const bool ok = yy >= 0 && yy < im.H && xx >= 0 && xx < im.W;
-              const int yc = min(max(yy, 0), im.H - 1), xc = min(max(xx, 0), im.W - 1);
-              cw[uu][2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
+              const int yc = min(max(y0 + cy, 0), im.H - 1), xc = min(max(x0 + cx, 0), im.W - 1);
               const TF* cp = src + ((size_t)yc * im.W + xc) * C + cl;
 #pragma unroll
               for (int v = 0; v < NV8; ++v) raw[uu][2 * cy + cx][v].load(cp + 8 * v);
@@ -234,24 +349,9 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
           if (sp[uu] == nullptr) continue;
-#pragma unroll
-          for (int v = 0; v < NV8; ++v) {
-            f32x4 lo = zero4(), hi = zero4();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              f32x4 a, b;
-              raw[uu][k][v].to_f32(a, b);
-              lo += cw[uu][k] * a;
-              hi += cw[uu][k] * b;
-            }
-            if constexpr (ROT) {
-              const int c = (int)((sp[uu] - S) % LDS_P) / CW;   // chunk index within the pixel row
-              store4f<TC>(sp[uu] + 4 * piece(c, 2 * v), lo);
-              store4f<TC>(sp[uu] + 4 * piece(c, 2 * v + 1), hi);
-            } else {
-              store8f<TC>(sp[uu] + 8 * v, lo, hi);
-            }
-          }
+          // the chunk index within the pixel row (rotation of float 16-channel chunks)
+          const int c = ROT ? (int)((sp[uu] - S) % LDS_P) / CW : 0;
+          dcn_blend_store<TF, TC, NV8, ROT>(raw[uu], cw[uu], sp[uu], c);
         }
         __builtin_amdgcn_sched_barrier(0);   // keep each round's loads in their round
       }
@@ -296,34 +396,7 @@ __device__ __forceinline__ void dcn_tile(const DcnLayer& L, const DcnImg& im, in
     }
     __syncthreads();
     if (ph + 1 < NPHASE) load_offs(ph + 1, 0, od_next);
-
-    const Frag* wbase = static_cast<const Frag*>(L.wfrag) + ((size_t)ph * 9 * L.obtot) * 64 + lane;
-    // nine steps over two register buffers, step i+1 loading while step i multiplies
-    Frag wa0[OB], xb0[PB], wa1[OB], xb1[PB];
-    auto fetch = [&](int st, Frag (&wa)[OB], Frag (&xb)[PB]) {
-#pragma unroll
-      for (int ob = 0; ob < OB; ++ob) wa[ob] = wbase[((size_t)st * L.obtot + ob) * 64];
-      // float: step st is chunk st (KG = CW = 16), quarter q its piece q
-      const int so = ROT ? KG * st + 4 * piece(st, q) : KG * st;
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + so);
-    };
-    auto mma = [&](const Frag (&wa)[OB], const Frag (&xb)[PB]) {
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
-    };
-    fetch(0, wa0, xb0);
-#pragma unroll 1
-    for (int st = 0; st < 9; st += 2) {
-      if (st + 1 < 9) fetch(st + 1, wa1, xb1);
-      mma(wa0, xb0);
-      if (st + 1 < 9) {
-        if (st + 2 < 9) fetch(st + 2, wa0, xb0);
-        mma(wa1, xb1);
-      }
-    }
+    dcn_phase_mfma<TC, CPG, PB, OB>(L, ph, sbase, 0, acc);
   }
 
   dcn_store<TF, TC, C, PB, DcnSmem<TC, CPG, PB>::N>(L, im, ty0, tx0, acc, S);
@@ -632,6 +705,231 @@ __global__ __launch_bounds__(256, 3) void k_dcnw_batch(DcnLayer L, const DcnImg*
   }
 }
 
+// ---- staged form: the plain form's items and sample buffer, corners from LDS ----
+// Per phase the plain form's gather items (pixel, chunk, tap) first load their offsets and
+// form their sampling positions; the workgroup reduces the box of all their corners and,
+// when it fits FH x FW pixels, copies the phase's KG channels of that box from the map
+// into LDS with whole-pixel loads (coordinates clamped into the map, as the plain form
+// clamps its corner reads).  The items then read their four corners from that copy
+// instead of from global memory, blend them into the same sample buffer with the same
+// arithmetic, and the same MFMA steps follow: the output is bit-identical to the plain
+// form's.  A phase whose box does not fit reads its corners from the maps.
+template <typename T, int C, int CPG, int PB>
+struct DcnStaged {
+  static constexpr int KG = Mma<T>::KG;
+  static constexpr int TH = 4 * PB;
+  static constexpr int FH = TH + 7, FW = kTW + 6;      // samples within about 2.5 pixels of the tile
+  static constexpr int WP = KG;                        // window pixel stride (elements): 64 bytes
+  // window row stride: 16 bytes of padding, so that the nine taps of an item (three
+  // rows, three columns) fall in different LDS bank groups
+  static constexpr int WR = FW * WP + 16 / (int)sizeof(T);
+  static constexpr int NS = DcnSmem<T, CPG, PB>::N;    // the sample buffer (elements)
+  static constexpr int NWIN = FH * WR;
+  static constexpr int BYTES = (NS + NWIN) * (int)sizeof(T);
+  static_assert(NS * (int)sizeof(T) % 16 == 0, "the window starts 16-byte aligned");
+};
+
+template <typename T, int C, int CPG, int PB>
+__device__ __forceinline__ void dcns_tile(const DcnLayer& L, const DcnImg& im, int ty0, int tx0, T* S, T* Wn,
+                                          int* red) {
+  using Ph = DcnPhase<T, CPG>;
+  using D = DcnStaged<T, C, CPG, PB>;
+  constexpr int TH = 4 * PB, OB = C / 16, G = 2 * C / CPG;
+  constexpr int CW = Ph::CW, GP = Ph::GP, NCH = Ph::NCH, KG = Ph::KG, QE = KG / 4, LDS_P = Ph::LDS_P;
+  constexpr int NPHASE = 2 * C / KG;
+  constexpr int NPX = TH * kTW, NITEM = NPX * GP * 9, NR = (NITEM + 255) / 256, NV8 = CW / 8;
+  constexpr int FH = D::FH, FW = D::FW, WP = D::WP, WR = D::WR;
+  constexpr int E = 16 / (int)sizeof(T), PPX = KG / E;
+  constexpr bool ROT = dcn_rot<T, CPG>();
+  static_assert(CW % 8 == 0 && C % KG == 0, "chunks of whole 8-channel vectors; a phase in one map");
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, j = lane & 15;
+  const T* fa = static_cast<const T*>(im.fa);
+  const T* fb = (im.sel != nullptr && *im.sel != 0u) ? fa : static_cast<const T*>(im.fb);
+
+  // 64 channels: each wave multiplies one block of 16 output channels over all TH rows
+  // (a quarter of the phase's weight fragments per wave), else PB rows over all blocks
+  constexpr bool CS = OB == 4;
+  constexpr int AR = CS ? TH : PB, AB = CS ? 1 : OB;
+  f32x4 acc[AR][AB];
+#pragma unroll
+  for (int r = 0; r < AR; ++r)
+#pragma unroll
+    for (int b = 0; b < AB; ++b) acc[r][b] = zero4();
+  const int r0 = CS ? 0 : wave * PB;
+  const T* sbase = ROT ? &S[(r0 * kTW + j) * LDS_P] : &S[(r0 * kTW + j) * LDS_P + QE * q];
+
+  // item r of this thread: (pixel, chunk gi, tap) as in the plain form, tap fastest
+  auto item_of = [&](int r, int& tap, int& gi, int& p) {
+    const int item = r * 256 + (int)threadIdx.x;
+    tap = item % 9;
+    const int rest = item / 9;
+    gi = rest % GP;
+    p = rest / GP;
+    return item < NITEM;
+  };
+  // offsets (dy, dx) and mask of every item of phase ph, all rounds in flight at once
+  float od[NR][3];
+  auto load_offs = [&](int ph) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      int tap, gi, p;
+      od[r][0] = od[r][1] = od[r][2] = 0.0f;
+      if (!item_of(r, tap, gi, p)) continue;
+      const int g = (ph * GP + gi) / NCH;
+      const int gy = ty0 + p / kTW, gx = tx0 + p % kTW;
+      const float* orow = im.offs + ((size_t)min(gy, im.H - 1) * im.W + min(gx, im.W - 1)) * L.ldo;
+      od[r][0] = orow[2 * (9 * g + tap)];
+      od[r][1] = orow[2 * (9 * g + tap) + 1];
+      od[r][2] = gy < im.H && gx < im.W ? orow[18 * G + 9 * g + tap] : 0.0f;
+    }
+  };
+  load_offs(0);
+
+  for (int ph = 0; ph < NPHASE; ++ph) {
+    // the box of the phase's corners (rows y0 .. y0 + 1, columns x0 .. x0 + 1 of every item)
+    int ylo = 1 << 30, yhi = -(1 << 30), xlo = 1 << 30, xhi = -(1 << 30);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      int tap, gi, p;
+      if (!item_of(r, tap, gi, p)) continue;
+      const int ky = tap / 3, kx = tap - 3 * ky;
+      int y0, x0;
+      float cw[4];
+      dcn_corners(ty0 + p / kTW + ky - 1, tx0 + p % kTW + kx - 1, od[r][0], od[r][1], od[r][2], im.H, im.W, y0,
+                  x0, cw);
+      ylo = min(ylo, y0);
+      yhi = max(yhi, y0);
+      xlo = min(xlo, x0);
+      xhi = max(xhi, x0);
+    }
+    ylo = wave_min(ylo);
+    yhi = wave_max(yhi);
+    xlo = wave_min(xlo);
+    xhi = wave_max(xhi);
+    if (lane == 0) {
+      red[4 * wave] = ylo;
+      red[4 * wave + 1] = yhi;
+      red[4 * wave + 2] = xlo;
+      red[4 * wave + 3] = xhi;
+    }
+    // also: the previous phase's MFMA reads of the sample buffer are done
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      ylo = min(ylo, red[4 * w]);
+      yhi = max(yhi, red[4 * w + 1]);
+      xlo = min(xlo, red[4 * w + 2]);
+      xhi = max(xhi, red[4 * w + 3]);
+    }
+    const int wy0 = ylo, wx0 = xlo, nh = yhi - ylo + 2, nw = xhi - xlo + 2;
+    const bool win = nh <= FH && nw <= FW;
+    const T* map = ph * KG < C ? fa : fb;
+    const int cl0 = (ph * KG) % C;
+    if (win) {
+      constexpr int NPC = FH * FW * PPX, NIT = (NPC + 255) / 256;
+      u32x4 v[NIT];
+#pragma unroll
+      for (int k = 0; k < NIT; ++k) {
+        const int idx = (int)threadIdx.x + 256 * k;
+        const int px = idx / PPX, pc = idx - px * PPX;
+        const int r = px / FW, c = px - r * FW;
+        v[k] = u32x4{0u, 0u, 0u, 0u};
+        if (idx < NPC && r < nh && c < nw) {
+          const int yy = min(max(wy0 + r, 0), im.H - 1), xx = min(max(wx0 + c, 0), im.W - 1);
+          v[k] = ldu4(map + ((size_t)yy * im.W + xx) * C + cl0 + E * pc);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NIT; ++k) {
+        const int idx = (int)threadIdx.x + 256 * k;
+        const int px = idx / PPX, pc = idx - px * PPX;
+        const int r = px / FW, c = px - r * FW;
+        if (idx < NPC && r < nh && c < nw) stu4(&Wn[r * WR + c * WP + E * pc], v[k]);
+      }
+      // the window visible to every lane
+      __syncthreads();
+    }
+    // gather: the items' corners from the window (or the map), blended into S; one loop
+    // per source, so that the window reads are LDS reads
+    auto gather = [&](auto in_window) {
+      constexpr bool WIN = decltype(in_window)::value;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        int tap, gi, p;
+        if (!item_of(r, tap, gi, p)) continue;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        int y0, x0;
+        float cw[4];
+        dcn_corners(ty0 + p / kTW + ky - 1, tx0 + p % kTW + kx - 1, od[r][0], od[r][1], od[r][2], im.H, im.W, y0,
+                    x0, cw);
+        Raw8<T> raw[4][NV8];
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            if constexpr (WIN) {
+              const T* cp = &Wn[(y0 + cy - wy0) * WR + (x0 + cx - wx0) * WP + gi * CW];
+#pragma unroll
+              for (int v8 = 0; v8 < NV8; ++v8) raw[2 * cy + cx][v8].load(cp + 8 * v8);
+            } else {
+              const int yc = min(max(y0 + cy, 0), im.H - 1), xc = min(max(x0 + cx, 0), im.W - 1);
+              const T* cp = map + ((size_t)yc * im.W + xc) * C + cl0 + gi * CW;
+#pragma unroll
+              for (int v8 = 0; v8 < NV8; ++v8) raw[2 * cy + cx][v8].load(cp + 8 * v8);
+            }
+          }
+        const int chunk = gi * 9 + tap;   // the chunk index within the pixel row
+        dcn_blend_store<T, T, NV8, ROT>(raw, cw, &S[p * LDS_P + chunk * CW], chunk);
+      }
+    };
+    if (win) gather(std::true_type{});
+    else gather(std::false_type{});
+    // the samples visible to every wave
+    __syncthreads();
+    if (ph + 1 < NPHASE) load_offs(ph + 1);
+    dcn_phase_mfma<T, CPG, AR, AB>(L, ph, sbase, CS ? wave : 0, acc);
+  }
+  dcn_store<T, T, C, AR, D::NS, CS, AB>(L, im, ty0, tx0, acc, S);
+}
+
+// Three workgroups per CU where the registers allow it (up to five gather rounds of at
+// most 32 bytes per corner), else two.
+template <typename T, int C, int CPG, int PB>
+constexpr int dcns_waves() {
+  using Ph = DcnPhase<T, CPG>;
+  return 4 * PB * kTW * Ph::GP * 9 <= 5 * 256 && Ph::CW * (int)sizeof(T) <= 32 ? 3 : 2;
+}
+
+template <typename T, int C, int CPG, int PB>
+__global__ __launch_bounds__(256, (dcns_waves<T, C, CPG, PB>())) void k_dcns(DcnLayer L, DcnImg im) {
+  using D = DcnStaged<T, C, CPG, PB>;
+  __shared__ __attribute__((aligned(16))) T S[D::NS + D::NWIN];
+  __shared__ int red[16];
+  const int tiles_x = (im.W + kTW - 1) / kTW;
+  const int ntile = tiles_x * ((im.H + 4 * PB - 1) / (4 * PB));
+  const int t = xcd_tile(blockIdx.x, ntile);
+  dcns_tile<T, C, CPG, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S, S + D::NS, red);
+}
+
+template <typename T, int C, int CPG, int PB>
+__global__ __launch_bounds__(256, (dcns_waves<T, C, CPG, PB>())) void k_dcns_batch(DcnLayer L,
+                                                                                  const DcnImg* __restrict__ jobs,
+                                                                                  const int* __restrict__ count) {
+  using D = DcnStaged<T, C, CPG, PB>;
+  __shared__ __attribute__((aligned(16))) T S[D::NS + D::NWIN];
+  __shared__ int red[16];
+  const int njobs = count[0], total = count[1];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const DcnImg im = jobs[find_job(jobs, njobs, item)];
+    const int t = item - im.item_begin;
+    const int tiles_x = (im.W + kTW - 1) / kTW;
+    dcns_tile<T, C, CPG, PB>(L, im, (t / tiles_x) * 4 * PB, (t % tiles_x) * kTW, S, S + D::NS, red);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- dispatch ----
 
 template <typename TF, typename TC, int C, int CPG, int PB>
@@ -652,6 +950,42 @@ void run_dcnw(const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int
   } else {
     hipLaunchKernelGGL((k_dcnw_batch<T, C, CPG, PB>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
   }
+}
+
+template <typename T, int C, int CPG, int PB>
+void run_dcns(const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count, hipStream_t s) {
+  if (im) {
+    const int ntile = ((im->W + kTW - 1) / kTW) * ((im->H + 4 * PB - 1) / (4 * PB));
+    hipLaunchKernelGGL((k_dcns<T, C, CPG, PB>), dim3(ntile), dim3(256), 0, s, L, *im);
+  } else {
+    hipLaunchKernelGGL((k_dcns_batch<T, C, CPG, PB>), dim3(kBatchGrid), dim3(256), 0, s, L, jobs, count);
+  }
+}
+
+// Staged form: float and 16-bit maps with chunks of 8 or more channels (8 or more
+// channels per offset group).
+template <typename T, int PB>
+hipError_t dcns_c(int C, int cpg, const DcnLayer& L, const DcnImg* im, const DcnImg* jobs, const int* count,
+                  hipStream_t s) {
+  if (C == 64) {
+    switch (cpg) {
+      case 8: run_dcns<T, 64, 8, PB>(L, im, jobs, count, s); break;
+      case 16: run_dcns<T, 64, 16, PB>(L, im, jobs, count, s); break;
+      case 32: run_dcns<T, 64, 32, PB>(L, im, jobs, count, s); break;
+      case 64: run_dcns<T, 64, 64, PB>(L, im, jobs, count, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (C == 32) {
+    switch (cpg) {
+      case 8: run_dcns<T, 32, 8, PB>(L, im, jobs, count, s); break;
+      case 16: run_dcns<T, 32, 16, PB>(L, im, jobs, count, s); break;
+      case 32: run_dcns<T, 32, 32, PB>(L, im, jobs, count, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // Windowed form: float and 16-bit maps whose chunks hold at least one fragment's
@@ -736,6 +1070,7 @@ hipError_t dcn_pb(int pb, int C, int cpg, const DcnLayer& L, const DcnImg* im, c
   if (pb == 2) return dcn_c<TF, 2>(C, cpg, L, im, jobs, count, s);
   if (pb == (1 | kDcnWindow)) return dcnw_c<TF, 1>(C, cpg, L, im, jobs, count, s);
   if (pb == (2 | kDcnWindow)) return dcnw_c<TF, 2>(C, cpg, L, im, jobs, count, s);
+  if (pb == (1 | kDcnStaged)) return dcns_c<TF, 1>(C, cpg, L, im, jobs, count, s);
   return hipErrorInvalidValue;
 }
 

@@ -236,6 +236,14 @@ inline bool dcn_window_supported(int tf, int tc, int C, int groups) {
   const int cpg = 2 * C / groups;
   return tc == tf && tf != DT_F8 && (tf == DT_F32 ? cpg >= 4 : cpg >= 8);
 }
+// kDcnStaged (one row per wave only): the plain form's gather and sample buffer with the
+// corners read from an LDS copy of the phase's window (float and 16-bit maps with at least
+// 8 channels per offset group; bit-identical to the plain form).
+constexpr int kDcnStaged = 32;
+inline bool dcn_staged_supported(int tf, int tc, int C, int groups) {
+  const int cpg = 2 * C / groups;
+  return tc == tf && tf != DT_F8 && cpg >= 8 && (C == 32 || C == 64);
+}
 // HR conv C->3 plus the bilinear x2 base of frame a (tsel 0), b (1) or their mean (2).
 hipError_t launch_hr(const PackedConv& L, int tu, const HrImg& im, hipStream_t s);
 

@@ -113,11 +113,12 @@ def test_network_case_in_simulation(driver, tmp_path, C, R, G, H, W):
 @pytest.mark.parametrize("prec,off_gain", [(1, 1.0), (1, 12.0), (0, 1.0), (2, 12.0)],
                          ids=["fp16-window", "fp16-wide-offsets", "fp32-window", "bf16-wide-offsets"])
 def test_dcn_window_form_bit_identical_in_simulation(driver, tmp_path, prec, off_gain):
-    """The DCN form that reads a phase's sampling corners from an LDS copy of their
-    window (tile code 2 | 16, forced through the tuner's cache file) gives the same bits
-    as the plain form: with the generator's offsets (every phase fits its window) and
-    with the offset conv's weights scaled up (wide offsets: phases fall back to reading
-    the map), at a padded size with a ragged right tile."""
+    """The DCN forms that read a phase's sampling corners from an LDS copy of their
+    window (tile code 2 | 16, the windowed form, and 1 | 32, the staged form, forced
+    through the tuner's cache file) give the same bits as the plain form: with the
+    generator's offsets (every phase fits its window) and with the offset conv's weights
+    scaled up (wide offsets: phases fall back to reading the map), at a padded size with
+    a ragged right tile."""
     C, R, G, H, W = 64, 1, 8, 40, 56
     cfg = synth.NetConfig(C, R, G)
     blob = synth.gen_weights(cfg, seed=3)
@@ -127,7 +128,7 @@ def test_dcn_window_form_bit_identical_in_simulation(driver, tmp_path, prec, off
     ra = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
     rb = np.clip(ra + rng.normal(0, 0.05, ra.shape), 0, 1).astype(np.float32)
     outs = {}
-    for code in (2, 2 | 16):
+    for code in (2, 2 | 16, 1 | 32):
         d = tmp_path / f"t{code}"
         d.mkdir()
         blob.astype(np.float32).tofile(d / "weights.f32")
@@ -151,6 +152,7 @@ def test_dcn_window_form_bit_identical_in_simulation(driver, tmp_path, prec, off
     print("max |offset|", float(np.abs(offs).max()))
     for k in outs[2]:
         assert outs[2][k] == outs[2 | 16][k], k
+        assert outs[2][k] == outs[1 | 32][k], k
 
 
 def test_static_group_entry_in_simulation(driver):

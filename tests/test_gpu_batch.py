@@ -312,10 +312,11 @@ def test_fp32_two_wave_tiles_bit_identical(B, tmp_path, monkeypatch):
 @pytest.mark.parametrize("prec,off_gain", [("fp16", 1.0), ("fp16", 12.0), ("bf16", 1.0), ("fp32", 1.0),
                                            ("fp32", 12.0)])
 def test_dcn_window_tiles_bit_identical(B, prec, off_gain, tmp_path, monkeypatch):
-    """The DCN form that reads a phase's sampling corners from an LDS copy of their
-    window (forced through the tuner's cache file) gives the same bits as the plain
-    form, per stream and batched.  With the offset conv's weights scaled up, most phases
-    do not fit their window and read the maps directly."""
+    """The DCN forms that read a phase's sampling corners from an LDS copy of their
+    window (the windowed form, tile code 2 | 16, and the staged form, 1 | 32, forced
+    through the tuner's cache file) give the same bits as the plain form, per stream and
+    batched.  With the offset conv's weights scaled up, most phases do not fit their
+    window and read the maps directly."""
     say(f"DCN window tiles {prec} offsets x{off_gain}")
     cfg = synth.NetConfig(64, 1, 8)
     blob = synth.gen_weights(cfg, seed=9)
@@ -337,7 +338,9 @@ def test_dcn_window_tiles_bit_identical(B, prec, off_gain, tmp_path, monkeypatch
     ref_ctx = forced(2)
     ref = _per_stream(B, ref_ctx, clips, dev)
     ref_ctx.close()
-    ctx = forced(2 | 16)
-    _same(_per_stream(B, ctx, clips, dev), ref)
-    _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
-    ctx.close()
+    for form in (2 | 16, 1 | 32):
+        say(f"DCN tile code {form}")
+        ctx = forced(form)
+        _same(_per_stream(B, ctx, clips, dev), ref)
+        _same(_batched(B, ctx, clips, dev, [[3, 3], [1, 2, 3], [6], [2, 2, 2]]), ref)
+        ctx.close()
