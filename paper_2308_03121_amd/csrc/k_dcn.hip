@@ -191,32 +191,6 @@ __device__ __forceinline__ void dcn_phase_mfma(const DcnLayer& L, int ph, const 
 #pragma unroll
       for (int ob = 0; ob < OB; ++ob) acc[pb][ob] = Mma<TC>::step(wa[ob], xb[pb], acc[pb][ob]);
   };
-#if NV_DCN_PRELOAD
-  if constexpr (OB == 1) {
-    // one block of output channels: all nine steps' weight fragments in one round trip
-    Frag wall[9];
-#pragma unroll
-    for (int st = 0; st < 9; ++st) wall[st] = wbase[(size_t)st * L.obtot * 64];
-    auto ldb = [&](int st, Frag (&xb)[PB]) {
-      const int so = ROT ? KG * st + 4 * dcn_piece<ROT>(st, q) : KG * st;
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) xb[pb] = Mma<TC>::ld(sbase + pb * kTW * LDS_P + so);
-    };
-    ldb(0, xb0);
-#pragma unroll
-    for (int st = 0; st < 9; st += 2) {
-      if (st + 1 < 9) ldb(st + 1, xb1);
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) acc[pb][0] = Mma<TC>::step(wall[st], xb0[pb], acc[pb][0]);
-      if (st + 1 < 9) {
-        if (st + 2 < 9) ldb(st + 2, xb0);
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) acc[pb][0] = Mma<TC>::step(wall[st + 1], xb1[pb], acc[pb][0]);
-      }
-    }
-    return;
-  }
-#endif
   fetch(0, wa0, xb0);
 #pragma unroll 1
   for (int st = 0; st < 9; st += 2) {

@@ -1174,12 +1174,18 @@ struct HrLayer {
   const float* bias;     // [3]
 };
 
-constexpr int kHrT = 16, kHrRW = kHrT + 2, kHrNP = kHrRW * kHrRW, kHrNPB = (kHrNP + 15) / 16,
-              kHrLDR = 33;
+constexpr int kHrT = 16, kHrRW = kHrT + 2, kHrNP = kHrRW * kHrRW, kHrNPB = (kHrNP + 15) / 16;
+// R's row stride (floats): the 27 used response rows of a pixel, plus one for float maps.
+// An odd stride puts the column reads of the sums below in distinct banks; 16-bit maps
+// then fit four workgroups per CU (float maps measured faster at three).
+template <typename TU>
+constexpr int hr_ldr() {
+  return sizeof(TU) == 2 ? 27 : 33;
+}
 
 template <typename TU, int C>
 __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int ty0, int tx0, float* R) {
-  constexpr int T = kHrT, RW = kHrRW, NP = kHrNP, NPB = kHrNPB, LDR = kHrLDR;
+  constexpr int T = kHrT, RW = kHrRW, NP = kHrNP, NPB = kHrNPB, LDR = hr_ldr<TU>();
   constexpr int KG = Mma<TU>::KG, QE = KG / 4, NCG = C / KG;
   const int H2 = im.sv * im.H, W2 = im.sh * im.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1207,6 +1213,27 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) xb[k][cg] = ok ? ldu4(up + KG * cg) : zero;
   }
+  // this thread's output pixel and its bilinear base; for 16-bit maps the base is
+  // requested together with the tile's loads (both round trips overlap), for float maps
+  // (twice the registers in flight) after the responses
+  const int ly = threadIdx.x / T, lx = threadIdx.x - ly * T;
+  const int Y = ty0 + ly, X = tx0 + lx;
+  const bool out = Y < H2 && X < W2;
+  const size_t lpl = (size_t)im.H * im.W, hpl = (size_t)H2 * W2;
+  float base[3] = {0.0f, 0.0f, 0.0f};
+  auto base_at = [&] {
+    const float* rb = (im.sel != nullptr && *im.sel != 0u) ? im.rgb_a : im.rgb_b;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (im.tsel == 0) base[c] = up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
+      else if (im.tsel == 1) base[c] = up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
+      else
+        base[c] = 0.5f * (up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh) +
+                          up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh));
+    }
+  };
+  constexpr bool kEarlyBase = sizeof(TU) == 2;
+  if (kEarlyBase && out) base_at();
 #pragma unroll
   for (int k = 0; k < MAXB; ++k) {
     const int pbk = wave + 4 * k;
@@ -1222,13 +1249,13 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       rp[4 * q + r] = acc0[r];
-      rp[16 + 4 * q + r] = acc1[r];
+      // rows 27 .. 31 are padding (written where the stride leaves room for them)
+      if (LDR > 31 || 16 + 4 * q + r < 27) rp[16 + 4 * q + r] = acc1[r];
     }
   }
   __syncthreads();
-  const int ly = threadIdx.x / T, lx = threadIdx.x - ly * T;
-  const int Y = ty0 + ly, X = tx0 + lx;
-  if (Y >= H2 || X >= W2) return;
+  if (!out) return;
+  if (!kEarlyBase) base_at();
   float s0 = L.bias[0], s1 = L.bias[1], s2 = L.bias[2];
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
@@ -1238,17 +1265,6 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
     s1 += rp[1];
     s2 += rp[2];
   }
-  const size_t lpl = (size_t)im.H * im.W, hpl = (size_t)H2 * W2;
-  const float* rb = (im.sel != nullptr && *im.sel != 0u) ? im.rgb_a : im.rgb_b;
-  float base[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (im.tsel == 0) base[c] = up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
-    else if (im.tsel == 1) base[c] = up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh);
-    else
-      base[c] = 0.5f * (up_sample(im.rgb_a + c * lpl, im.H, im.W, Y, X, im.sv, im.sh) +
-                        up_sample(rb + c * lpl, im.H, im.W, Y, X, im.sv, im.sh));
-  }
   im.dst[(size_t)Y * W2 + X] = s0 + base[0];
   im.dst[hpl + (size_t)Y * W2 + X] = s1 + base[1];
   im.dst[2 * hpl + (size_t)Y * W2 + X] = s2 + base[2];
@@ -1256,7 +1272,7 @@ __device__ __forceinline__ void hr_tile(const HrLayer& L, const HrImg& im, int t
 
 template <typename TU, int C>
 __global__ __launch_bounds__(256) void k_hr(HrLayer L, HrImg im) {
-  __shared__ float R[kHrNPB * 16 * kHrLDR];
+  __shared__ float R[kHrNPB * 16 * hr_ldr<TU>()];
   const int tiles_x = (im.sh * im.W + kHrT - 1) / kHrT;
   const int ntile = tiles_x * ((im.sv * im.H + kHrT - 1) / kHrT);
   const int t = xcd_tile(blockIdx.x, ntile);
@@ -1266,7 +1282,7 @@ __global__ __launch_bounds__(256) void k_hr(HrLayer L, HrImg im) {
 template <typename TU, int C>
 __global__ __launch_bounds__(256) void k_hr_batch(HrLayer L, const HrImg* __restrict__ jobs,
                                                   const int* __restrict__ count) {
-  __shared__ float R[kHrNPB * 16 * kHrLDR];
+  __shared__ float R[kHrNPB * 16 * hr_ldr<TU>()];
   const int njobs = count[0], total = count[1];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const HrImg im = jobs[find_job(jobs, njobs, item)];
