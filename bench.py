@@ -28,14 +28,34 @@ if ROOT not in sys.path:
 # HBM bytes per launch of the FP32 residual-block conv (the two launch kinds of a block
 # averaged, as the kernel timing is), from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
 # scaled by a plain device copy's readings (x2.00 and x1.00); the command lines and the
-# per-kernel table are in profiles/c2_fp32_hbm_traffic.md.  Valid for the kernel source
-# the counters were taken on; retake them after changing it.
+# per-kernel table are in profiles/c2_fp32_hbm_traffic.md.  Valid only for the device
+# source the counters were taken on: "source" is the hash of the conv kernels' files
+# (conv_source_hash), and the bench reports no traffic when it differs.
 FP32_CONV_BLOCK_TRAFFIC = {
-    "first conv (LReLU)": {"fetch_kib": 69763, "write_kib": 130560},
-    "second conv (+ skip)": {"fetch_kib": 135404, "write_kib": 130560},
+    "first conv (LReLU)": {"fetch_kib": 69840, "write_kib": 130600},
+    "second conv (+ skip)": {"fetch_kib": 135500, "write_kib": 130600},
     "fetch_scale": 2.00, "write_scale": 1.00,
     "tile": "pb2w2",   # the tile the tuner chose for the counted launches
+    "source": "c23dfa6b5efa41a8",
 }
+CONV_SOURCES = ("k_net.hip", "nv_mma.h", "nv_device.h")
+
+
+def conv_source_hash():
+    """First 16 hex digits of the SHA-256 of the conv kernels' device sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in CONV_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2308_03121_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_valid(tuning_line):
+    """The stored counters apply: same device source and the same block tile."""
+    t = FP32_CONV_BLOCK_TRAFFIC
+    return t["source"] == conv_source_hash() and f"[block {t['tile']}," in tuning_line
 
 
 def conv_block_traffic():
@@ -670,7 +690,7 @@ def main():
                      "frac": round(achieved / PEAKS[args.precision], 4),
                      "traffic": (round(conv_block_traffic())
                                  if args.precision == "fp32" and dom == "conv_block"
-                                 and f"[block {FP32_CONV_BLOCK_TRAFFIC['tile']}," in tuning[args.precision]
+                                 and traffic_valid(tuning[args.precision])
                                  else None),
                      "traffic_algorithmic": (conv_block_bytes(hp, wp, cfg.channels) if dom == "conv_block"
                                              else None),

@@ -873,7 +873,7 @@ __device__ __forceinline__ void dcns_tile(const DcnLayer& L, const DcnImg& im, i
 template <typename T, int C, int CPG, int PB>
 constexpr int dcns_waves() {
   using Ph = DcnPhase<T, CPG>;
-  return 4 * PB * kTW * Ph::GP * 9 <= 5 * 256 && Ph::CW * (int)sizeof(T) <= 32 ? 3 : 2;
+  return 4 * PB * kTW * Ph::GP * 9 <= 5 * 256 && Ph::CW * (int)sizeof(T) <= 64 ? 3 : 2;
 }
 
 template <typename T, int C, int CPG, int PB>

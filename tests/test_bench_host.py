@@ -44,6 +44,19 @@ def test_counter_traffic_is_near_algorithmic():
     assert algo <= traffic <= 1.10 * algo
 
 
+def test_counter_traffic_needs_the_counted_source(monkeypatch):
+    """The stored counters are reported only for the device source and tile they were
+    taken on."""
+    t = dict(bench.FP32_CONV_BLOCK_TRAFFIC)
+    line = f"block: ... -> {t['tile']}; [block {t['tile']}, up pb2w2, dcn pb2win]"
+    monkeypatch.setattr(bench, "FP32_CONV_BLOCK_TRAFFIC", dict(t, source=bench.conv_source_hash()))
+    assert bench.traffic_valid(line)
+    assert not bench.traffic_valid(line.replace(f"[block {t['tile']},", "[block pb4,"))
+    monkeypatch.setattr(bench, "FP32_CONV_BLOCK_TRAFFIC", dict(t, source="0" * 16))
+    assert not bench.traffic_valid(line)
+    assert re.fullmatch(r"[0-9a-f]{16}", bench.conv_source_hash())
+
+
 def test_pixel_stage_bytes():
     # pack of one 3840x2160 10-bit 4:2:0 frame: float R'G'B' in, 1.5 codes of 2 B out
     assert bench.pixel_bytes("pack", 1920, 1080, 10, 420) == 4 * 1920 * 1080 * (12 + 3)
