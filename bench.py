@@ -523,14 +523,15 @@ def serving_bench(B, synth, torch, duration=20.0, rate=40.0, budget_gb=240, tigh
     from paper_2308_03121_amd.serving import GpuExecutor, Server, poisson_workload
 
     specs = poisson_workload(n_streams=16, rate_total=rate, seed=3, max_time=duration)
-    fmts = {(s.width, s.height, s.bits, s.chroma) for s in specs}
-    banks = {f: _frame_bank(B, synth, *f, scenes=2, per=4, seed=sum(f)) for f in fmts}
+    # each stream its own content: two generated scenes of six frames (its own fields,
+    # textures and motion), alternating at the stream's cuts, a scene's frames cycled
+    banks = {s.sid: _frame_bank(B, synth, s.width, s.height, s.bits, s.chroma, scenes=2, per=6, seed=100 + s.sid)
+             for s in specs}
 
     def source(spec, t):
         k = sum(1 for c in spec.scene_starts if c <= t)
         start = ([0] + [c for c in spec.scene_starts if c <= t])[-1]
-        bank = banks[(spec.width, spec.height, spec.bits, spec.chroma)]
-        scene = bank[(k + spec.sid) % len(bank)]
+        scene = banks[spec.sid][k % 2]
         return scene[(t - start) % len(scene)]
 
     cfg = synth.NET_C2
