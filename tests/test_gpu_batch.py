@@ -309,16 +309,17 @@ def test_fp32_two_wave_tiles_bit_identical(B, tmp_path, monkeypatch):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,off_gain", [("fp16", 1.0), ("fp16", 12.0), ("bf16", 1.0), ("fp32", 1.0),
-                                           ("fp32", 12.0)])
-def test_dcn_window_tiles_bit_identical(B, prec, off_gain, tmp_path, monkeypatch):
+@pytest.mark.parametrize("prec,off_gain,C,G", [("fp16", 1.0, 64, 8), ("fp16", 12.0, 64, 8), ("bf16", 1.0, 64, 8),
+                                               ("fp32", 1.0, 64, 8), ("fp32", 12.0, 64, 8), ("fp16", 1.0, 64, 16),
+                                               ("fp16", 1.0, 64, 4), ("fp16", 1.0, 32, 8), ("fp32", 1.0, 64, 16)])
+def test_dcn_window_tiles_bit_identical(B, prec, off_gain, C, G, tmp_path, monkeypatch):
     """The DCN forms that read a phase's sampling corners from an LDS copy of their
     window (the windowed form, tile code 2 | 16, and the staged form, 1 | 32, forced
     through the tuner's cache file) give the same bits as the plain form, per stream and
     batched.  With the offset conv's weights scaled up, most phases do not fit their
     window and read the maps directly."""
-    say(f"DCN window tiles {prec} offsets x{off_gain}")
-    cfg = synth.NetConfig(64, 1, 8)
+    say(f"DCN window tiles {prec} offsets x{off_gain} C={C} G={G}")
+    cfg = synth.NetConfig(C, 1, G)
     blob = synth.gen_weights(cfg, seed=9)
     synth.unpack_weights(cfg, blob)["off2"][0][...] *= off_gain
     clips = _clips()
@@ -327,7 +328,7 @@ def test_dcn_window_tiles_bit_identical(B, prec, off_gain, tmp_path, monkeypatch
 
     def forced(dcn):
         cache = tmp_path / f"tune{dcn}.txt"
-        cache.write_text(f"prec={code} C=64 R=1 size=64x48 | 2 2 {dcn} 2 2 0\n")
+        cache.write_text(f"prec={code} C={C} R=1 size=64x48 | 2 2 {dcn} 2 2 0\n")
         ctx = B.Context(cfg.channels, cfg.res_blocks, cfg.offset_groups, blob, precision=prec)
         monkeypatch.setenv("NNVISR_TUNE_CACHE", str(cache))
         rep = ctx.autotune(48, 64)
