@@ -1124,6 +1124,8 @@ extern "C" nv_status nv_context_create(int32_t device, const nv_net_config* cfg,
   ctx->bt = cfg->precision == NV_FP8_E4M3 ? DT_F8 : ctx->ft;
   ctx->ut = (cfg->flags & NV_FLAG_FP8_FUSION) ? DT_F8 : ctx->ft;
   if (ctx->ut == DT_F8) ctx->tune.pb_dcn = 1;   // the FP8 DCN tile is one row per wave
+  // the staged DCN form (the tuner's pick wherever it was timed) is the default tile
+  else if (dcn_staged_supported(ctx->ft, ctx->ut, ctx->C, ctx->G)) ctx->tune.pb_dcn = 1 | kDcnStaged;
   std::vector<std::vector<float>> wscales;      // FP8 row scales in calibration order
   std::vector<float> dcn_ws, up_ws;
   const auto specs = layer_specs(*cfg);
