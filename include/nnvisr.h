@@ -411,11 +411,15 @@ nv_status nv_batch_bytes_per_px(const nv_context* ctx, size_t* per_group, size_t
 /* Device bytes of batch workspace currently held by ctx. */
 nv_status nv_batch_footprint(const nv_context* ctx, size_t* bytes);
 
-/* Autotuner: times each candidate workgroup tile (rows per wave) of the residual-block
- * conv, the pixel-shuffle conv and the DCN on an hp x wp frame and keeps the fastest in
- * ctx.  When the environment variable NNVISR_TUNE_CACHE names a file, results are
- * looked up there first (key: precision, channels, hp, wp) and appended after timing.
- * A human-readable summary is written to report (HOST, may be NULL). */
+/* Autotuner: times each candidate workgroup tile (rows per wave, waves along the output
+ * channels) of the residual-block conv, the pixel-shuffle conv, the offset head and the
+ * DCN on an hp x wp frame and keeps the fastest in ctx.  The DCN candidates include its
+ * forms that read the sampling corners from an LDS copy of their window (all forms give
+ * bit-identical results); before any tuning a context uses default tiles, for the DCN
+ * the staged form wherever it applies.  When the environment variable
+ * NNVISR_TUNE_CACHE names a file, results are looked up there first (key: precision,
+ * channels, hp, wp) and appended after timing.  A human-readable summary is written to
+ * report (HOST, may be NULL). */
 nv_status nv_autotune(nv_context* ctx, int32_t hp, int32_t wp, void* stream, char* report,
                       size_t report_len);
 
