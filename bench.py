@@ -570,6 +570,8 @@ def main():
     ap.add_argument("--also", default="fp16,bf16,fp8",
                     help="other precisions timed on the same clip after the main run ('' for none)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 1080p 10-bit per-precision run")
+    ap.add_argument("--c3-precisions", default="fp32,fp16,bf16,fp8,fp8-fusion",
+                    help="precisions of the 1080p 10-bit run (comma list)")
     ap.add_argument("--no-batching", action="store_true", help="skip the 64-group batching run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-next", action="store_true",
@@ -740,7 +742,8 @@ def main():
     if not args.no_c3:
         print("# precisions on the 48-frame 1920x1080 10-bit clip", file=sys.stderr, flush=True)
         try:
-            rec["c3_precisions"] = c3_precision_bench(B, synth, torch, cfg, blob)
+            rec["c3_precisions"] = c3_precision_bench(B, synth, torch, cfg, blob,
+                                                      precs=tuple(p for p in args.c3_precisions.split(",") if p))
         except Exception as e:
             rec["c3_precisions"] = {"error": f"{type(e).__name__}: {e}"}
         print("# c3: " + json.dumps(rec["c3_precisions"]), file=sys.stderr, flush=True)
