@@ -130,14 +130,18 @@ __device__ __forceinline__ void dcn_corners(int by, int bx, float dy, float dx, 
   const float ly = py - y0f, lx = px - x0f;
   y0 = (int)y0f;
   x0 = (int)x0f;
+  // a corner is inside when its row and its column are (each tested once)
+  bool rok[2], cok[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    rok[k] = (unsigned)(y0 + k) < (unsigned)H;
+    cok[k] = (unsigned)(x0 + k) < (unsigned)W;
+  }
 #pragma unroll
   for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      const int yy = y0 + cy, xx = x0 + cx;
-      const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      cw[2 * cy + cx] = ok ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
-    }
+    for (int cx = 0; cx < 2; ++cx)
+      cw[2 * cy + cx] = rok[cy] && cok[cx] ? (cy ? ly : 1.0f - ly) * (cx ? lx : 1.0f - lx) * m : 0.0f;
 }
 
 // The weighted sum of the four corners' CW channels (raw vectors of 8 channels), rounded
@@ -741,7 +745,7 @@ __device__ __forceinline__ void dcns_tile(const DcnLayer& L, const DcnImg& im, i
     const int rest = item / 9;
     gi = rest % GP;
     p = rest / GP;
-    return item < NITEM;
+    return (r + 1) * 256 <= NITEM || item < NITEM;   // rounds below NITEM / 256 are full
   };
   // offsets (dy, dx) and mask of every item of phase ph, all rounds in flight at once
   float od[NR][3];
