@@ -658,8 +658,14 @@ __device__ __forceinline__ void dcnw_tile(const DcnLayer& L, const DcnImg& im, i
   dcn_store<T, T, C, PB, D::BYTES / (int)sizeof(T)>(L, im, ty0, tx0, acc, reinterpret_cast<T*>(smem));
 }
 
+// Three workgroups per CU where their LDS fits three times, else two.
 template <typename T, int C, int CPG, int PB>
-__global__ __launch_bounds__(256, 3) void k_dcnw(DcnLayer L, DcnImg im) {
+constexpr int dcnw_waves() {
+  return 3 * (DcnWin<T, C, CPG, PB>::BYTES + 128) <= 163840 ? 3 : 2;
+}
+
+template <typename T, int C, int CPG, int PB>
+__global__ __launch_bounds__(256, (dcnw_waves<T, C, CPG, PB>())) void k_dcnw(DcnLayer L, DcnImg im) {
   __shared__ __attribute__((aligned(16))) uint8_t Wn[DcnWin<T, C, CPG, PB>::BYTES];
   __shared__ int red[2][16];
   const int tiles_x = (im.W + kTW - 1) / kTW;
@@ -669,8 +675,9 @@ __global__ __launch_bounds__(256, 3) void k_dcnw(DcnLayer L, DcnImg im) {
 }
 
 template <typename T, int C, int CPG, int PB>
-__global__ __launch_bounds__(256, 3) void k_dcnw_batch(DcnLayer L, const DcnImg* __restrict__ jobs,
-                                                    const int* __restrict__ count) {
+__global__ __launch_bounds__(256, (dcnw_waves<T, C, CPG, PB>())) void k_dcnw_batch(DcnLayer L,
+                                                                                  const DcnImg* __restrict__ jobs,
+                                                                                  const int* __restrict__ count) {
   __shared__ __attribute__((aligned(16))) uint8_t Wn[DcnWin<T, C, CPG, PB>::BYTES];
   __shared__ int red[2][16];
   const int njobs = count[0], total = count[1];
