@@ -93,18 +93,45 @@ def kernel_work(kind, hp, wp, C, G, bits_out_bytes):
     return None, None
 
 
+def mfma_peak(kind, prec):
+    """Dense peak (TFLOP/s) of the MFMA type a conv kind runs on in a precision mode: FP32
+    everything on float MFMA; 16-bit modes on their 16-bit MFMA (the offset head too, as
+    float-class products of float16 parts); FP8 puts the residual-block convs on e4m3 and
+    the rest on float16, FP8-fusion also the DCN and the pixel-shuffle conv."""
+    if prec == "fp32":
+        return PEAKS["fp32"]
+    if prec == "fp8" and kind == "conv_block":
+        return PEAKS["fp8"]
+    if prec == "fp8-fusion" and kind in ("conv_block", "dcn", "up"):
+        return PEAKS["fp8"]
+    return PEAKS["fp16"]
+
+
+MFMA_KINDS = ("conv_block", "off1", "off2", "dcn", "up", "hr")
+
+
 def mfma_share(pr, kind, hp, wp, C, G, prec):
     """Achieved TFLOP/s of one kernel kind from a profile (launches, ms) and its share of
-    the precision's dense MFMA peak."""
+    the dense peak of the MFMA type it runs on."""
     n, tot = pr.get(kind, (0, 0.0))
     flop, unit = kernel_work(kind, hp, wp, C, G, 0)
     if not n or unit != "flop":
         return None
     us = 1000.0 * tot / n
     tf = flop / (us * 1e-6) / 1e12
-    peak = PEAKS[prec.split("-")[0]]
+    peak = mfma_peak(kind, prec)
     return {"kernel": kind, "avg_launch_us": round(us, 2), "achieved": round(tf, 2), "peak": peak,
             "unit": "TFLOP/s", "frac": round(tf / peak, 4)}
+
+
+def mfma_shares(pr, hp, wp, C, G, prec):
+    """mfma_share of every MFMA conv kind in the profile: {kind: frac}."""
+    out = {}
+    for kind in MFMA_KINDS:
+        r = mfma_share(pr, kind, hp, wp, C, G, prec)
+        if r is not None:
+            out[kind] = r["frac"]
+    return out
 
 
 def pixel_bytes(kind, w, h, bits, chroma):
@@ -319,6 +346,7 @@ def c3_precision_bench(B, synth, torch, cfg, blob, precs=("fp32", "fp16", "bf16"
                      "cuts": cuts,
                      "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]},
                      "conv_block_mfma": mfma_share(pr, "conv_block", hp, wp, cfg.channels, cfg.offset_groups, prec),
+                     "mfma_frac": mfma_shares(pr, hp, wp, cfg.channels, cfg.offset_groups, prec),
                      "meets_50db_bar": prec != "fp8-fusion"}
         if prec == "fp8-fusion":
             res[prec]["note"] = ("below the 50 dB PSNR bar against the FP64 oracle (worst 1920x1080 window "
@@ -727,7 +755,8 @@ def main():
                         "speedup_vs_" + args.precision: round(ms / ms2, 3),
                         "kernel_ms_per_step": {k: round(v[1], 2) for k, v in pr.items() if v[0]},
                         "conv_block_mfma": mfma_share(pr, "conv_block", hp, wp, cfg.channels, cfg.offset_groups,
-                                                      prec)}
+                                                      prec),
+                        "mfma_frac": mfma_shares(pr, hp, wp, cfg.channels, cfg.offset_groups, prec)}
         st2.close()
         c2.close()
     rec["tuning"] = tuning

@@ -57,6 +57,26 @@ def test_counter_traffic_needs_the_counted_source(monkeypatch):
     assert re.fullmatch(r"[0-9a-f]{16}", bench.conv_source_hash())
 
 
+def test_mfma_fraction_per_kind_uses_the_kind_s_mfma_type():
+    """Per-kind MFMA fractions take the peak of the MFMA type each kind runs on: FP8 runs
+    only the residual-block convs on e4m3 (FP8-fusion also the DCN and pixel-shuffle
+    conv), the offset head stays on float16 MFMA in every reduced-precision mode."""
+    hp, wp, C, G = 544, 960, 64, 8
+    us = {"conv_block": 42.0, "off1": 116.0, "off2": 499.0, "dcn": 318.0, "up": 210.0, "hr": 91.0}
+    pr = {k: (10, 10 * v / 1000.0) for k, v in us.items()}          # (launches, total ms)
+    for prec, want in (("fp8", {"conv_block": 5000.0, "dcn": 2500.0, "up": 2500.0, "off2": 2500.0}),
+                       ("fp8-fusion", {"conv_block": 5000.0, "dcn": 5000.0, "up": 5000.0, "hr": 2500.0}),
+                       ("fp16", {k: 2500.0 for k in us}), ("fp32", {k: 157.3 for k in us})):
+        for kind, peak in want.items():
+            r = bench.mfma_share(pr, kind, hp, wp, C, G, prec)
+            flop, _ = bench.kernel_work(kind, hp, wp, C, G, 0)
+            assert r["peak"] == peak, (prec, kind)
+            assert abs(r["frac"] - flop / (us[kind] * 1e-6) / 1e12 / peak) < 1e-4
+    fr = bench.mfma_shares(pr, hp, wp, C, G, "fp16")
+    assert set(fr) == set(bench.MFMA_KINDS)
+    assert abs(fr["conv_block"] - 2 * 9 * 64 * 64 * hp * wp / 42e-6 / 1e12 / 2500.0) < 1e-4
+
+
 def test_pixel_stage_bytes():
     # pack of one 3840x2160 10-bit 4:2:0 frame: float R'G'B' in, 1.5 codes of 2 B out
     assert bench.pixel_bytes("pack", 1920, 1080, 10, 420) == 4 * 1920 * 1080 * (12 + 3)
